@@ -1,0 +1,431 @@
+"""Classic and pipelined preconditioned BiCGStab, step by step (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Both solvers follow the paper's listings in their order of operations:
+
+* ``classic_bicgstab``   -- Algorithm 1 (Section 2.1).
+* ``pipelined_bicgstab`` -- Algorithm 2 (Section 3), with the auxiliary
+  quantities of eq:auxvars, and the periodic residual replacement of
+  Section 3.6 (eq:rr, performed right after the w-update of the iteration).
+
+Every vector expression is written with the brackets of eq:auxrec0 /
+eq:auxrec and is evaluated left to right with one rounding per operation
+(NumPy never contracts into fused multiply-adds), which is the
+floating-point model of Section 2.
+
+Readings of points the paper leaves open (each is listed in the design doc):
+
+* The preconditioner is applied on the right exactly as the listings do:
+  r = b - A x is the unpreconditioned residual and x is updated with
+  M^-1-preconditioned directions.  M^-1 is either the identity or the
+  Jacobi diagonal ``dinv`` (elementwise product).
+* In iteration 0 the listing refers to g, s, l, z, n, v and omega of
+  iteration -1; they are taken as zero (beta_0 = 0 makes the terms vanish).
+* Stopping: ||r_i|| <= tol * ||b|| on the recursively computed residual
+  (Section 3.5 keeps the unpreconditioned residual norm); (r, r) is
+  reduced together with the second global reduction.  A recursive
+  convergence is confirmed by the true residual ||b - A x||; if that fails
+  and residual replacement is enabled, a replacement is performed and the
+  iteration continues, otherwise the solve reports TRUE_RES_NOT_MET.
+* Periodic replacement: in iteration i, after the w-update, when
+  (i+1) mod P == 0 and the last reduced ||r_i|| >= tau * ||r_0|| (tau =
+  sqrt(eps), eps = unit roundoff 2^-53), recompute r, k, w from x_{i+1}
+  and s, l, z from g_i (the six quantities of eq:rr; n and v are not
+  recomputed, the shadow residual r_0 is never replaced).
+* Scalars are evaluated left to right as printed:
+  beta = ((alpha/omega) * rho') / rho and
+  alpha' = rho' / ((rw + beta*rs) - (beta*omega)*rz).
+* Breakdowns: rho' = 0 or a zero alpha-denominator -> BREAKDOWN_RHO;
+  omega = 0 (including (y, y) = 0, where omega is set to 0 and the update
+  x + alpha g, r = q is still performed) -> BREAKDOWN_OMEGA unless that
+  update meets the tolerance; a non-finite reduction -> NONFINITE.
+
+Pins: exact-rational equality of the classic and pipelined iterates with and
+without replacement (the abstract and Section 3: identical iterates in exact
+arithmetic); agreement with SciPy's textbook BiCGStab; the dense LU solution
+at convergence; the local error bounds eq:errbounds1-4 and the exact gap
+identities eq:Dr-eq:Dz (``oracle.gaps``); a hand-derived 2x2 iteration
+(tests/golden).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from fractions import Fraction
+from typing import Optional
+
+import numpy as np
+
+# Status codes (numerically the same as the solver library's; declared here
+# independently so the oracle imports nothing from the library).
+STATUS = {
+    "CONVERGED": 0,
+    "MAXIT": 1,
+    "BREAKDOWN_RHO": 2,
+    "BREAKDOWN_OMEGA": 3,
+    "NONFINITE": 4,
+    "TRUE_RES_NOT_MET": 5,
+}
+
+
+def unit_roundoff(dtype=np.float64) -> float:
+    """Unit roundoff u = 2^-(p) of a binary format with p-bit significand
+    (the epsilon of Section 2 read as u; 2^-53 for double)."""
+    return float(np.finfo(dtype).eps) / 2.0
+
+
+# -----------------------------------------------------------------------------
+# arithmetic backends
+# -----------------------------------------------------------------------------
+
+class Float64Ops:
+    """IEEE double arithmetic.
+
+    SPMV is SciPy's CSR product (each row summed sequentially in stored
+    column order, one rounding per multiply and per add), PREC is the
+    elementwise product with ``dinv`` (or a copy for M = I), DOTPR is
+    ``numpy.dot``."""
+
+    exact = False
+
+    def __init__(self, A, dinv: Optional[np.ndarray] = None):
+        import scipy.sparse as sp
+        self.A = sp.csr_matrix(A)
+        self.n = self.A.shape[0]
+        self.dinv = None if dinv is None else np.asarray(dinv, dtype=np.float64)
+
+    def spmv(self, v):
+        return self.A @ v
+
+    def prec(self, v):
+        return v.copy() if self.dinv is None else self.dinv * v
+
+    def dot(self, v, w):
+        return float(np.dot(v, w))
+
+    def norm(self, v):
+        return math.sqrt(self.dot(v, v))
+
+    def zeros(self):
+        return np.zeros(self.n)
+
+    def copy(self, v):
+        return np.array(v, dtype=np.float64, copy=True)
+
+    def finite(self, *vals):
+        return all(math.isfinite(float(a)) for a in vals)
+
+    def zero(self):
+        return 0.0
+
+    def scalar_sqrt(self, s):
+        return math.sqrt(s)
+
+
+class ExactOps:
+    """Exact rational arithmetic for tiny systems (vectors are NumPy object
+    arrays of ``fractions.Fraction``).  Norms used by stopping tests are
+    converted to float; everything that enters an iterate stays exact."""
+
+    exact = True
+
+    def __init__(self, A, dinv=None):
+        import scipy.sparse as sp
+        A = sp.csr_matrix(A)
+        self.n = A.shape[0]
+        self.rows = []
+        for i in range(self.n):
+            lo, hi = A.indptr[i], A.indptr[i + 1]
+            self.rows.append([(int(A.indices[j]), Fraction(float(A.data[j])))
+                              for j in range(lo, hi)])
+        self.dinv = None if dinv is None else self.vec(dinv)
+
+    def vec(self, a):
+        return np.array([x if isinstance(x, Fraction) else Fraction(float(x)) for x in a],
+                        dtype=object)
+
+    def spmv(self, v):
+        out = np.empty(self.n, dtype=object)
+        for i, row in enumerate(self.rows):
+            acc = Fraction(0)
+            for j, a in row:
+                acc += a * v[j]
+            out[i] = acc
+        return out
+
+    def prec(self, v):
+        return v.copy() if self.dinv is None else self.dinv * v
+
+    def dot(self, v, w):
+        acc = Fraction(0)
+        for a, b in zip(v, w):
+            acc += a * b
+        return acc
+
+    def norm(self, v):
+        return math.sqrt(float(self.dot(v, v)))
+
+    def zeros(self):
+        return np.array([Fraction(0)] * self.n, dtype=object)
+
+    def copy(self, v):
+        return self.vec(v)
+
+    def finite(self, *vals):
+        return True
+
+    def zero(self):
+        return Fraction(0)
+
+
+# -----------------------------------------------------------------------------
+# results
+# -----------------------------------------------------------------------------
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    status: int
+    iterations: int
+    replacements: int = 0
+    rnorm0: float = 0.0
+    bnorm: float = 0.0
+    alpha: list = field(default_factory=list)     # alpha_i used in iteration i
+    omega: list = field(default_factory=list)     # omega_i of iteration i
+    beta: list = field(default_factory=list)      # beta_{i+1} formed at the end of iteration i
+    rnorm: list = field(default_factory=list)     # ||r_{i+1}|| after iteration i
+    rr_iters: list = field(default_factory=list)  # iterations i in which a replacement ran
+    true_rel_res: Optional[float] = None
+    snapshots: list = field(default_factory=list)
+
+    @property
+    def status_name(self):
+        return {v: k for k, v in STATUS.items()}[self.status]
+
+
+def _finish(res, x, status, its, ops, b):
+    res.x = x
+    res.status = status
+    res.iterations = its
+    if not ops.exact and res.bnorm > 0:
+        res.true_rel_res = ops.norm(b - ops.spmv(x)) / res.bnorm
+    return res
+
+
+# -----------------------------------------------------------------------------
+# Algorithm 1: classic preconditioned BiCGStab
+# -----------------------------------------------------------------------------
+
+def classic_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, record=False):
+    """Algorithm 1 (classic preconditioned BiCGStab), Section 2.1.
+
+    Three global reductions per iteration: (r0, s_i); (q_i, y_i), (y_i, y_i);
+    (r0, r_{i+1}) together with (r_{i+1}, r_{i+1}) for the stopping test.
+    No residual replacement (Section 4.3 performs none for the classic
+    method)."""
+    b = ops.copy(b)
+    x = ops.zeros() if x0 is None else ops.copy(x0)
+    r = b - ops.spmv(x)                       # r_0 := b - A x_0
+    rhat = ops.copy(r)                        # the shadow residual r_0
+    p = ops.copy(r)                           # p_0 := r_0
+    rho = ops.dot(rhat, r)                    # (r_0, r_i)
+    nb = ops.norm(b)
+    rn0 = ops.norm(r)
+    res = SolveResult(x=x, status=STATUS["MAXIT"], iterations=0, rnorm0=rn0, bnorm=nb)
+    if nb == 0:
+        return _finish(res, ops.zeros(), STATUS["CONVERGED"], 0, ops, b)
+    if rn0 <= tol * nb:
+        return _finish(res, x, STATUS["CONVERGED"], 0, ops, b)
+    for i in range(maxit):
+        g = ops.prec(p)                       # g_i := M^-1 p_i
+        s = ops.spmv(g)                       # s_i := A g_i
+        sig = ops.dot(rhat, s)                # GLRED 1: (r_0, s_i)
+        if not ops.finite(sig):
+            return _finish(res, x, STATUS["NONFINITE"], i, ops, b)
+        if sig == 0:
+            return _finish(res, x, STATUS["BREAKDOWN_RHO"], i, ops, b)
+        alpha = rho / sig                     # alpha_i
+        q = r - alpha * s                     # q_i := r_i - alpha_i s_i
+        u = ops.prec(q)                       # u_i := M^-1 q_i
+        y = ops.spmv(u)                       # y_i := A u_i
+        sig1 = ops.dot(q, y)                  # GLRED 2: (q_i, y_i), (y_i, y_i)
+        sig2 = ops.dot(y, y)
+        if not ops.finite(sig1, sig2):
+            return _finish(res, x, STATUS["NONFINITE"], i, ops, b)
+        omega = sig1 / sig2 if sig2 != 0 else ops.zero()
+        x_in, r_in = x, r
+        x = (x + alpha * g) + omega * u       # x_{i+1}
+        r = q - omega * y                     # r_{i+1}
+        rho_new = ops.dot(rhat, r)            # GLRED 3: (r_0, r_{i+1}) and ||r_{i+1}||
+        rr = ops.dot(r, r)
+        if not ops.finite(rho_new, rr):
+            return _finish(res, x, STATUS["NONFINITE"], i + 1, ops, b)
+        rn = math.sqrt(float(rr))
+        res.alpha.append(alpha)
+        res.omega.append(omega)
+        res.rnorm.append(rn)
+        if record:
+            res.snapshots.append(dict(i=i, alpha=alpha, omega=omega, x=x_in, r=r_in, p=p,
+                                      g=g, s=s, q=q, u=u, y=y, x1=ops.copy(x),
+                                      r1=ops.copy(r)))
+        if rn <= tol * nb:
+            tr = ops.norm(b - ops.spmv(x))
+            st = STATUS["CONVERGED"] if tr <= tol * nb else STATUS["TRUE_RES_NOT_MET"]
+            return _finish(res, x, st, i + 1, ops, b)
+        if omega == 0:
+            return _finish(res, x, STATUS["BREAKDOWN_OMEGA"], i + 1, ops, b)
+        if rho_new == 0:
+            return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
+        beta = ((alpha / omega) * rho_new) / rho          # beta_i
+        res.beta.append(beta)
+        p = r + beta * (p - omega * s)                    # p_{i+1}
+        rho = rho_new
+    return _finish(res, x, STATUS["MAXIT"], maxit, ops, b)
+
+
+# -----------------------------------------------------------------------------
+# Algorithm 2: preconditioned pipelined BiCGStab, with residual replacement
+# -----------------------------------------------------------------------------
+
+def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
+                       rr_tau=None, record=False):
+    """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with the periodic
+    residual replacement of Section 3.6 (eq:rr) when ``rr_period > 0``.
+
+    Two global reductions per iteration, each overlapped (on parallel
+    hardware) by one PREC + SPMV: (q_i, y_i), (y_i, y_i) with
+    n_i = M^-1 z_i, v_i = A n_i; and (r0, r_{i+1}), (r0, w_{i+1}),
+    (r0, s_i), (r0, z_i) -- plus (r_{i+1}, r_{i+1}) for the stopping test --
+    with m_{i+1} = M^-1 w_{i+1}, t_{i+1} = A m_{i+1}."""
+    tau = math.sqrt(unit_roundoff()) if rr_tau is None else rr_tau
+    b = ops.copy(b)
+    x = ops.zeros() if x0 is None else ops.copy(x0)
+    # initialisation (the two lines before the loop of Algorithm 2)
+    r = b - ops.spmv(x)                       # r_0 := b - A x_0
+    rhat = ops.copy(r)                        # shadow residual r_0 (never replaced)
+    k = ops.prec(r)                           # k_0 := M^-1 r_0
+    w = ops.spmv(k)                           # w_0 := A k_0
+    m = ops.prec(w)                           # m_0 := M^-1 w_0
+    t = ops.spmv(m)                           # t_0 := A m_0
+    rho = ops.dot(rhat, r)                    # (r_0, r_0)
+    den = ops.dot(rhat, w)                    # (r_0, w_0)
+    nb = ops.norm(b)
+    rn0 = ops.norm(r)
+    rn = rn0
+    res = SolveResult(x=x, status=STATUS["MAXIT"], iterations=0, rnorm0=rn0, bnorm=nb)
+    if nb == 0:
+        return _finish(res, ops.zeros(), STATUS["CONVERGED"], 0, ops, b)
+    if rn0 <= tol * nb:
+        return _finish(res, x, STATUS["CONVERGED"], 0, ops, b)
+    if not ops.finite(rho, den):
+        return _finish(res, x, STATUS["NONFINITE"], 0, ops, b)
+    if den == 0:
+        return _finish(res, x, STATUS["BREAKDOWN_RHO"], 0, ops, b)
+    alpha = rho / den                         # alpha_0
+    beta = ops.zero()                         # beta_0 := 0
+    omega_prev = ops.zero()                   # omega_{-1} (taken as 0)
+    g, s, l, z, n, v = (ops.zeros() for _ in range(6))   # iteration -1 values (taken as 0)
+
+    def replace(x, g):
+        """eq:rr: explicit recomputation of r, k, w (from x) and s, l, z (from g)."""
+        r_ = b - ops.spmv(x)
+        k_ = ops.prec(r_)
+        w_ = ops.spmv(k_)
+        s_ = ops.spmv(g)
+        l_ = ops.prec(s_)
+        z_ = ops.spmv(l_)
+        return r_, k_, w_, s_, l_, z_
+
+    for i in range(maxit):
+        # recurrences for the auxiliary vectors (each uses iteration i-1 values)
+        g_new = k + beta * (g - omega_prev * l)        # g_i
+        s_new = w + beta * (s - omega_prev * z)        # s_i
+        l_new = m + beta * (l - omega_prev * n)        # l_i
+        z_new = t + beta * (z - omega_prev * v)        # z_i
+        g, s, l, z = g_new, s_new, l_new, z_new
+        q = r - alpha * s                              # q_i
+        u = k - alpha * l                              # u_i
+        y = w - alpha * z                              # y_i
+        sig1 = ops.dot(q, y)                           # GLRED 1 begins: (q_i, y_i), (y_i, y_i)
+        sig2 = ops.dot(y, y)
+        n = ops.prec(z)                                # n_i := M^-1 z_i   (overlaps GLRED 1)
+        v = ops.spmv(n)                                # v_i := A n_i
+        if not ops.finite(sig1, sig2):                 # GLRED 1 ends
+            return _finish(res, x, STATUS["NONFINITE"], i, ops, b)
+        omega = sig1 / sig2 if sig2 != 0 else ops.zero()   # omega_i
+        x_new = (x + alpha * g) + omega * u            # x_{i+1}
+        r_new = q - omega * y                          # r_{i+1}
+        k_new = u - omega * (m - alpha * n)            # k_{i+1}
+        w_new = y - omega * (t - alpha * v)            # w_{i+1}
+        snap = None
+        if record:
+            snap = dict(i=i, alpha=alpha, beta=beta, omega=omega, omega_prev=omega_prev,
+                        x=x, r=r, k=k, w=w, m=m, t=t, g=g, s=s, l=l, z=z, q=q, u=u, y=y,
+                        n=n, v=v, x1=x_new, r1=r_new, k1=k_new, w1=w_new, replaced=False)
+        x, r, k, w = x_new, r_new, k_new, w_new
+        replaced = False
+        if rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0:
+            r, k, w, s, l, z = replace(x, g)           # eq:rr, right after the w-update
+            res.replacements += 1
+            res.rr_iters.append(i)
+            replaced = True
+            if snap is not None:
+                snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
+        rho_new = ops.dot(rhat, r)                     # GLRED 2 begins: (r0, r_{i+1}),
+        rw = ops.dot(rhat, w)                          #   (r0, w_{i+1}), (r0, s_i),
+        rs = ops.dot(rhat, s)                          #   (r0, z_i) and (r_{i+1}, r_{i+1})
+        rz = ops.dot(rhat, z)
+        rr = ops.dot(r, r)
+        if not ops.finite(rho_new, rw, rs, rz, rr):
+            return _finish(res, x, STATUS["NONFINITE"], i + 1, ops, b)
+        rn = math.sqrt(float(rr))
+        if rn <= tol * nb:
+            tr = ops.norm(b - ops.spmv(x))
+            if tr <= tol * nb:
+                res.alpha.append(alpha)
+                res.omega.append(omega)
+                res.rnorm.append(rn)
+                if snap is not None:
+                    snap["replaced"] = replaced
+                    res.snapshots.append(snap)
+                return _finish(res, x, STATUS["CONVERGED"], i + 1, ops, b)
+            if rr_period <= 0:
+                res.alpha.append(alpha)
+                res.omega.append(omega)
+                res.rnorm.append(rn)
+                return _finish(res, x, STATUS["TRUE_RES_NOT_MET"], i + 1, ops, b)
+            r, k, w, s, l, z = replace(x, g)           # confirm failed: replace and go on
+            res.replacements += 1
+            res.rr_iters.append(i)
+            replaced = True
+            if snap is not None:
+                snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
+            rho_new = ops.dot(rhat, r)
+            rw = ops.dot(rhat, w)
+            rs = ops.dot(rhat, s)
+            rz = ops.dot(rhat, z)
+            rr = ops.dot(r, r)
+            rn = math.sqrt(float(rr))
+        res.alpha.append(alpha)
+        res.omega.append(omega)
+        res.rnorm.append(rn)
+        if snap is not None:
+            snap["replaced"] = replaced
+            res.snapshots.append(snap)
+        if omega == 0:
+            return _finish(res, x, STATUS["BREAKDOWN_OMEGA"], i + 1, ops, b)
+        m = ops.prec(w)                                # m_{i+1} := M^-1 w_{i+1} (overlaps GLRED 2)
+        t = ops.spmv(m)                                # t_{i+1} := A m_{i+1}
+        if rho_new == 0 or rho == 0:                   # GLRED 2 ends
+            return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
+        beta = ((alpha / omega) * rho_new) / rho       # beta_{i+1}
+        den = (rw + beta * rs) - (beta * omega) * rz
+        if den == 0:
+            return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
+        res.beta.append(beta)
+        alpha = rho_new / den                          # alpha_{i+1}
+        rho = rho_new
+        omega_prev = omega
+    return _finish(res, x, STATUS["MAXIT"], maxit, ops, b)

@@ -1,0 +1,285 @@
+"""Pins of the CPU oracle against facts fixed outside the oracle itself.
+
+* a hand-derived 2x2 iteration (tests/golden/bicgstab_2x2_worked.txt);
+* SciPy's textbook BiCGStab (same operation order as Algorithm 1 with right
+  preconditioning) iterate by iterate;
+* exact-rational equality of Algorithm 1, Algorithm 2 and Algorithm 2 with
+  residual replacement (identical iterates in exact arithmetic; eq:rr only
+  re-evaluates quantities that the recurrences already equal exactly);
+* finite termination in exact arithmetic and the dense LU solution;
+* closed-form special cases (Jacobi on a diagonal matrix, b = 0,
+  skew-symmetric breakdown, non-finite input).
+"""
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import (STATUS, ExactOps, Float64Ops, classic_bicgstab,
+                    pipelined_bicgstab, unit_roundoff)
+from workloads import (Stencil, convdiff2d_c1, random_dense_system,
+                       stencil_to_csr)
+
+
+def _load_golden(path):
+    vals = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        k, v = line.split("=")
+        vals[k.strip()] = [Fraction(t.strip()) for t in v.split(",")]
+    return vals
+
+
+A22 = sp.csr_matrix(np.array([[2.0, 1.0], [1.0, 3.0]]))
+B22 = np.array([1.0, 0.0])
+
+
+@pytest.mark.parametrize("method", ["classic", "pipelined"])
+def test_worked_2x2_exact(golden_dir, method):
+    g = _load_golden(f"{golden_dir}/bicgstab_2x2_worked.txt")
+    ops = ExactOps(A22)
+    fn = classic_bicgstab if method == "classic" else pipelined_bicgstab
+    res = fn(ops, B22, tol=0.0, maxit=5, record=True)
+    assert res.status == STATUS["CONVERGED"]
+    assert res.iterations == 2
+    assert res.alpha[0] == g["alpha0"][0]
+    assert res.omega[0] == g["omega0"][0]
+    assert res.beta[0] == g["beta1"][0]
+    assert res.alpha[1] == g["alpha1"][0]
+    assert res.omega[1] == 0
+    assert list(res.snapshots[0]["x1"]) == g["x1"]
+    assert list(res.snapshots[0]["r1"]) == g["r1"]
+    assert list(res.x) == g["x2"]
+
+
+def test_worked_2x2_float64(golden_dir):
+    g = _load_golden(f"{golden_dir}/bicgstab_2x2_worked.txt")
+    for fn in (classic_bicgstab, pipelined_bicgstab):
+        res = fn(Float64Ops(A22), B22, tol=1e-15, maxit=10)
+        assert res.status == STATUS["CONVERGED"]
+        assert abs(res.alpha[0] - 0.5) <= 1e-16
+        assert abs(res.omega[0] - 0.3) <= 1e-16
+        np.testing.assert_allclose(res.x, [float(v) for v in g["x2"]], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_classic_matches_scipy_bicgstab(jacobi):
+    """SciPy's bicgstab (van der Vorst's BiCGStab, right-preconditioned) and
+    Algorithm 1 share the operation order, so the early iterates agree."""
+    p = convdiff2d_c1(32)
+    A = p.scipy_csr()
+    dinv = 1.0 / A.diagonal() if jacobi else None
+    kw = {}
+    if jacobi:
+        kw["M"] = spla.LinearOperator(A.shape, matvec=lambda v: dinv * v)
+    xs = []
+    spla.bicgstab(A, p.b, rtol=1e-30, atol=0.0, maxiter=12,
+                  callback=lambda xk: xs.append(xk.copy()), **kw)
+    res = classic_bicgstab(Float64Ops(A, dinv), p.b, tol=0.0, maxit=12, record=True)
+    for i in range(10):
+        xi = res.snapshots[i]["x1"]
+        assert np.linalg.norm(xi - xs[i]) <= 1e-13 * np.linalg.norm(xs[i]), i
+
+
+def _exact_case(name):
+    if name == "dense6":
+        p = random_dense_system(6, 7, shift=6.0, integer=True)
+        A = p.scipy_csr()
+        return A, p.b, 1.0 / A.diagonal(), p.x_exact
+    st = Stencil("2d5", (4, 4), {"C": 4.0, "E": -2.0, "W": -1.0, "N": -1.0, "S": 0.5})
+    rowptr, col, val = stencil_to_csr(st)
+    A = sp.csr_matrix((val, col, rowptr))
+    xex = np.arange(16.0)
+    return A, A @ xex, None, xex
+
+
+@pytest.mark.parametrize("case", ["dense6", "stencil4x4"])
+def test_exact_classic_equals_pipelined(case):
+    A, b, dinv, xex = _exact_case(case)
+    its = 6 if case == "dense6" else 5
+    ops = ExactOps(A, dinv)
+    rc = classic_bicgstab(ops, b, tol=0.0, maxit=its, record=True)
+    rp = pipelined_bicgstab(ops, b, tol=0.0, maxit=its, record=True)
+    assert rc.iterations == rp.iterations
+    assert rc.alpha == rp.alpha
+    assert rc.omega == rp.omega
+    assert rc.beta == rp.beta
+    for sc, sp_ in zip(rc.snapshots, rp.snapshots):
+        assert list(sc["x1"]) == list(sp_["x1"])
+        assert list(sc["r1"]) == list(sp_["r1"])
+    # residual replacement is a no-op on exact iterates (eq:rr recomputes
+    # quantities the recurrences already equal exactly)
+    rr = pipelined_bicgstab(ops, b, tol=0.0, maxit=its, rr_period=2, rr_tau=0.0)
+    assert rr.replacements >= 2
+    assert list(rr.x) == list(rp.x)
+    assert rr.alpha == rp.alpha and rr.omega == rp.omega
+
+
+def test_exact_finite_termination():
+    A, b, dinv, xex = _exact_case("dense6")
+    res = pipelined_bicgstab(ExactOps(A, dinv), b, tol=0.0, maxit=12)
+    assert res.status == STATUS["CONVERGED"]
+    assert res.iterations <= 6
+    assert [float(v) for v in res.x] == list(xex)
+
+
+@pytest.mark.parametrize("method,rr", [("classic", 0), ("pipelined", 0), ("pipelined", 50)])
+def test_dense_lu_agreement(method, rr):
+    p = convdiff2d_c1(32)
+    A = p.scipy_csr()
+    x_lu = np.linalg.solve(A.toarray(), p.b)
+    kappa = np.linalg.cond(A.toarray())
+    ops = Float64Ops(A)
+    if method == "classic":
+        res = classic_bicgstab(ops, p.b, tol=1e-10, maxit=2000)
+    else:
+        res = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000, rr_period=rr)
+    assert res.status == STATUS["CONVERGED"]
+    assert res.true_rel_res <= 1e-10
+    fwd = np.linalg.norm(res.x - x_lu) / np.linalg.norm(x_lu)
+    assert fwd <= kappa * 1e-10
+    assert np.linalg.norm(x_lu - p.x_exact) <= 1e-12 * np.linalg.norm(p.x_exact)
+
+
+def test_jacobi_on_diagonal_matrix_one_step():
+    """M^-1 A = I: alpha_0 = 1, q_0 = 0, so x_1 = M^-1 b (closed form)."""
+    rng = np.random.default_rng(3)
+    d = 2.0 ** rng.integers(-3, 4, 50)      # powers of two: 1/d is exact
+    A = sp.diags(d).tocsr()
+    b = rng.uniform(-1, 1, 50)
+    for fn in (classic_bicgstab, pipelined_bicgstab):
+        res = fn(ExactOps(A, 1.0 / d), b, tol=0.0, maxit=3)
+        assert res.status == STATUS["CONVERGED"] and res.iterations == 1
+        assert res.alpha[0] == 1
+        assert all(res.x[i] * Fraction(float(d[i])) == Fraction(float(b[i])) for i in range(50))
+        resf = fn(Float64Ops(A, 1.0 / d), b, tol=1e-14, maxit=3)
+        assert resf.status == STATUS["CONVERGED"]
+        np.testing.assert_allclose(resf.x, b / d, rtol=1e-15)
+
+
+@pytest.mark.parametrize("fn", [classic_bicgstab, pipelined_bicgstab])
+def test_zero_rhs(fn):
+    p = convdiff2d_c1(8)
+    res = fn(Float64Ops(p.scipy_csr()), np.zeros(p.n), tol=1e-10, maxit=10)
+    assert res.status == STATUS["CONVERGED"] and res.iterations == 0
+    assert not np.any(res.x)
+
+
+@pytest.mark.parametrize("fn", [classic_bicgstab, pipelined_bicgstab])
+def test_skew_symmetric_breakdown(fn):
+    """(r0, A r0) = 0 for skew-symmetric A: the first alpha is undefined."""
+    rng = np.random.default_rng(5)
+    S = rng.integers(-3, 4, size=(8, 8)).astype(float)
+    A = sp.csr_matrix(S - S.T)
+    b = rng.integers(-3, 4, size=8).astype(float)
+    res = fn(ExactOps(A), b, tol=1e-10, maxit=10)
+    assert res.status == STATUS["BREAKDOWN_RHO"] and res.iterations == 0
+    A2 = sp.csr_matrix(np.array([[0.0, 1.0], [-1.0, 0.0]]))
+    res = fn(Float64Ops(A2), np.array([1.0, 1.0]), tol=1e-10, maxit=10)
+    assert res.status == STATUS["BREAKDOWN_RHO"] and res.iterations == 0
+
+
+@pytest.mark.parametrize("fn", [classic_bicgstab, pipelined_bicgstab])
+def test_nonfinite(fn):
+    p = convdiff2d_c1(8)
+    b = p.b.copy()
+    b[3] = np.nan
+    res = fn(Float64Ops(p.scipy_csr()), b, tol=1e-10, maxit=10)
+    assert res.status == STATUS["NONFINITE"]
+
+
+def test_maxit_and_true_residual_not_met():
+    p = convdiff2d_c1(16)
+    ops = Float64Ops(p.scipy_csr())
+    res = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=5)
+    assert res.status == STATUS["MAXIT"] and res.iterations == 5
+    # a tolerance below the attainable accuracy: the recursive residual keeps
+    # falling while the true residual stagnates (Section 2.2, Figure captions)
+    p = convdiff2d_c1(6)
+    ops = Float64Ops(p.scipy_csr())
+    res = pipelined_bicgstab(ops, p.b, tol=1e-14, maxit=2000)
+    assert res.status == STATUS["TRUE_RES_NOT_MET"]
+    assert res.rnorm[-1] <= 1e-14 * res.bnorm
+    assert res.true_rel_res > 1e-14
+
+
+def test_replacement_schedule():
+    """Replacements only when (i+1) mod P == 0 and the last reduced
+    ||r_i|| >= sqrt(u) ||r_0|| (Section 3.6, periodic setting)."""
+    p = convdiff2d_c1(32)
+    ops = Float64Ops(p.scipy_csr())
+    P = 7
+    res = pipelined_bicgstab(ops, p.b, tol=1e-12, maxit=2000, rr_period=P)
+    tau = math.sqrt(unit_roundoff())
+    rn = [res.rnorm0] + res.rnorm
+    periodic = [i for i in res.rr_iters if (i + 1) % P == 0]
+    assert periodic, "expected periodic replacements"
+    for i in periodic:
+        assert rn[i] >= tau * res.rnorm0
+    for i in range(len(res.rnorm)):
+        if (i + 1) % P == 0 and rn[i] >= tau * res.rnorm0 and i < res.iterations - 1:
+            assert i in res.rr_iters
+
+
+def test_replacement_recomputes_true_quantities():
+    """After a replacement (eq:rr) r, k, w come from x_{i+1} and s, l, z from
+    g_i; their gaps are then single rounding errors, bounded as in Section 2
+    and Section 3.2 (initial-gap bound ((mu sqrt(N)+1)||A|| ||x|| + ||b||) eps,
+    SPMV bound mu sqrt(N) ||A|| ||v|| eps)."""
+    from oracle.gaps import ExactMatrix, exact_norm, to_exact
+    p = convdiff2d_c1(10)
+    A = p.scipy_csr()
+    dinv = 1.0 / A.diagonal()
+    res = pipelined_bicgstab(Float64Ops(A, dinv), p.b, tol=1e-13, maxit=400,
+                             rr_period=10, record=True)
+    eps = unit_roundoff()
+    N = p.n
+    mu = int(np.max(np.diff(A.indptr)))
+    nA = np.linalg.norm(A.toarray(), 2)
+    Ax = ExactMatrix(A)
+    D = to_exact(dinv)
+    checked = 0
+    for sn in res.snapshots:
+        if not sn["replaced"]:
+            continue
+        rep = sn["rep"]
+        x1, g = to_exact(sn["x1"]), to_exact(sn["g"])
+        r, k, w, s, l, z = (to_exact(rep[c]) for c in "rkwslz")
+        gap_r = exact_norm((to_exact(p.b) - Ax @ x1) - r)
+        assert gap_r <= ((mu * math.sqrt(N) + 1) * nA * np.linalg.norm(sn["x1"])
+                         + np.linalg.norm(p.b)) * eps
+        assert exact_norm(k - D * r) <= np.linalg.norm(rep["k"]) * eps
+        assert exact_norm(Ax @ k - w) <= mu * math.sqrt(N) * nA * np.linalg.norm(rep["k"]) * eps
+        assert exact_norm(Ax @ g - s) <= mu * math.sqrt(N) * nA * np.linalg.norm(sn["g"]) * eps
+        assert exact_norm(l - D * s) <= np.linalg.norm(rep["l"]) * eps
+        assert exact_norm(Ax @ l - z) <= mu * math.sqrt(N) * nA * np.linalg.norm(rep["l"]) * eps
+        checked += 1
+    assert checked >= 2
+    assert res.status == STATUS["CONVERGED"]
+
+
+def test_attainable_accuracy_ordering():
+    """Section 4 (Figures 1-4): p-BiCGStab attains a markedly worse true
+    residual than classic BiCGStab, and periodic residual replacement brings
+    it back to the classic level."""
+    p = convdiff2d_c1(32)
+    A = p.scipy_csr()
+    ops = Float64Ops(A)
+    nb = np.linalg.norm(p.b)
+
+    def best_true(res):
+        return min(np.linalg.norm(p.b - A @ s["x1"]) / nb for s in res.snapshots)
+
+    cl = best_true(classic_bicgstab(ops, p.b, tol=1e-30, maxit=400, record=True))
+    pi = best_true(pipelined_bicgstab(ops, p.b, tol=1e-30, maxit=400, record=True))
+    rr = best_true(pipelined_bicgstab(ops, p.b, tol=1e-30, maxit=400, rr_period=20,
+                                      record=True))
+    assert cl < 1e-13
+    assert pi > 10 * cl
+    assert rr < 3 * cl
