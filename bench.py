@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X pipelined BiCGStab library.
+
+One *step* is one pbicgstab_solve call of 1000 iterations on the 2D Poisson
+workload (1000 x 1000 grid, N = 1e6, 5-point stencil, FP64, Jacobi
+preconditioner, residual replacement every 50 iterations, tolerance 1e-10
+on the relative residual): initialisation, 1000 iterations of Algorithm 2
+(phase A, PREC+SPMV with the GLRED 1 final, phase B, the 20 replacements,
+PREC+SPMV with the GLRED 2 final, the device-side stopping test) and the
+final FP64 true residual.  The tolerance is not reached within 1000
+iterations (the workload needs ~2400 classic or ~3900 pipelined iterations,
+and with replacement every 50 the pipelined iteration does not reach 1e-10
+at all), so every step performs exactly 1000 full iterations.  Full solves
+to 1e-10 are reported separately (`solve_to_tol`).  The right-hand side
+lives in HBM before the timed region starts.
+
+Printed (one JSON line):
+  value        p-BiCGStab iterations per second (iterations of the K timed
+               solves / their wall time)
+  roofline     the phase B kernel (the largest HBM stream of the iteration),
+               algorithmic bytes per launch / average launch duration, timed
+               live with HIP events on the library's stream
+  cpu_baseline the CPU oracle (NumPy/SciPy FP64, one thread) on the first
+               iterations of the same solve
+  mixed_vs_fp64  time to a 1e-10 relative true residual on the 200^3
+               convection-diffusion workload, FP32 storage + FP64 reductions
+               and replacement versus all FP64 (both replacement period 50)
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+ITERS_PER_STEP = 1000
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle baseline")
+    ap.add_argument("--skip-mixed", action="store_true", help="omit the 200^3 mixed-vs-FP64 runs")
+    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--graph", type=int, default=1, help="replay iteration chunks from HIP graphs")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, iters):
+    """Oracle p-BiCGStab (Algorithm 2) on the host, one thread, `iters`
+    iterations of the same solve (the full solve takes minutes)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import Float64Ops, pipelined_bicgstab
+    A = prob.scipy_csr()
+    ops = Float64Ops(A, 1.0 / A.diagonal())
+    with threadpool_limits(limits=1):
+        pipelined_bicgstab(ops, prob.b, tol=0.0, maxit=2, rr_period=50)   # warm-up
+        t0 = time.perf_counter()
+        res = pipelined_bicgstab(ops, prob.b, tol=0.0, maxit=iters, rr_period=50)
+        dt = time.perf_counter() - t0
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": res.iterations / dt, "unit": "iter/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {res.iterations} iterations of the same 1000x1000 solve "
+                      f"(NumPy/SciPy FP64, 1 thread, {dt:.1f} s)",
+            "host_cpus": os.cpu_count(), "cpu_model": cpu}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1809_01948_amd.solver import Solver
+    from workloads import convdiff3d_c3, poisson2d_c2
+
+    dev = torch.device("cuda:0")
+    log("generating 1000x1000 Poisson workload")
+    prob = poisson2d_c2(1000, with_csr=not args.skip_cpu)
+    b = torch.from_numpy(prob.b).to(dev)
+    S = Solver.from_problem(prob, form="stencil", precision="fp64", precond="jacobi")
+    opts = dict(tol=1e-10, maxit=ITERS_PER_STEP, rr_period=50, use_graph=bool(args.graph))
+
+    for w in range(args.warmup):
+        x, st = S.solve(b, **opts)
+        log(f"warmup {w}: {st['status_name']} its={st['iterations']} "
+            f"true={st['rel_res_true']:.2e} {st['elapsed_ms']:.1f} ms")
+    torch.cuda.synchronize()
+    its = 0
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        x, st = S.solve(b, **opts)
+        its += st["iterations"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for k, st in enumerate(stats):
+        log(f"step {k}: {st['status_name']} its={st['iterations']} rr={st['replacements']} "
+            f"true={st['rel_res_true']:.2e} {st['elapsed_ms']:.1f} ms")
+    if any(st["iterations"] != ITERS_PER_STEP for st in stats):
+        log("a timed solve stopped early")
+    value = its / dt
+    ms_per_step = 1000.0 * dt / args.steps
+    n = prob.n
+    # algorithmic HBM bytes per iteration (FP64, constant-diagonal Jacobi):
+    # phase A 13 streams, SPMV 2 streams, phase B 15 streams, SPMV 2 streams
+    bytes_per_iter = 32 * 8 * n
+    eff_gbs = bytes_per_iter * its / dt / 1e9
+
+    # roofline of the dominant kernel: phase B (15 FP64 streams per row)
+    phaseB_bytes = 15 * 8 * n
+    ms_b = S.time_kernel("phaseB", reps=100)
+    ms_a = S.time_kernel("phaseA", reps=100)
+    ms_s = S.time_kernel("spmv1", reps=100)
+    ms_it = S.time_kernel("iteration", reps=50)
+    achieved = phaseB_bytes / (ms_b * 1e-3) / 1e9
+    kernels = {
+        "phaseA": {"ms": ms_a, "GBps": 13 * 8 * n / (ms_a * 1e-3) / 1e9},
+        "phaseB": {"ms": ms_b, "GBps": achieved},
+        "spmv": {"ms": ms_s, "GBps": 2 * 8 * n / (ms_s * 1e-3) / 1e9},
+        "iteration_kernels_only_ms": ms_it,
+    }
+    log(f"kernels: {json.dumps(kernels)}")
+
+    # full solves of the same workload to a 1e-10 true residual
+    sol = {}
+    for name, kw in (("pipelined_rr200", dict(rr_period=200, method="pipelined")),
+                     ("classic", dict(method="classic"))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = S.solve(b, tol=1e-10, maxit=20000, use_graph=bool(args.graph), **kw)
+        torch.cuda.synchronize()
+        sol[name] = {"seconds": time.perf_counter() - t0, "iterations": st["iterations"],
+                     "status": st["status_name"], "rel_res_true": st["rel_res_true"],
+                     "replacements": st["replacements"]}
+        log(f"to tol {name}: {sol[name]}")
+    S.close()
+
+    out = {
+        "metric": "p-BiCGStab iter/s + HBM GB/s; time to 1e-10 true residual, mixed vs FP64",
+        "value": value,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "poisson2d 1000x1000 5-point stencil, N=1e6, Jacobi, "
+                               "residual replacement every 50, 1000 iterations per step",
+                   "n": n, "form": "stencil", "precision": "fp64",
+                   "iterations_per_solve": stats[-1]["iterations"],
+                   "replacements_per_solve": stats[-1]["replacements"],
+                   "status": stats[-1]["status_name"],
+                   "graph": bool(args.graph)},
+        "hbm_gbps_effective": eff_gbs,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "phaseB", "algorithmic_bytes_per_launch": phaseB_bytes,
+                     "avg_launch_ms": ms_b},
+        "kernels": kernels,
+        "solve_to_tol": sol,
+    }
+
+    if not args.skip_mixed:
+        log("200^3 convection-diffusion: FP64 vs mixed to 1e-10")
+        p3 = convdiff3d_c3(200)
+        b3 = torch.from_numpy(p3.b).to(dev)
+        mv = {}
+        for prec, P in (("fp64", 50), ("fp64", 100), ("mixed", 50), ("mixed", 100)):
+            S3 = Solver.from_problem(p3, form="stencil", precision=prec, precond="jacobi")
+            S3.solve(b3, tol=1e-10, maxit=300, rr_period=P, use_graph=bool(args.graph))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x3, st3 = S3.solve(b3, tol=1e-10, maxit=20000, rr_period=P,
+                               use_graph=bool(args.graph))
+            torch.cuda.synchronize()
+            t3 = time.perf_counter() - t0
+            xerr = float(torch.linalg.norm(x3 - torch.from_numpy(p3.x_exact).to(dev)) /
+                         np.linalg.norm(p3.x_exact))
+            key = f"{prec}_rr{P}"
+            mv[key] = {"seconds": t3, "iterations": st3["iterations"],
+                       "replacements": st3["replacements"], "status": st3["status_name"],
+                       "rel_res_true": st3["rel_res_true"], "rel_err_vs_exact": xerr,
+                       "iter_per_s": st3["iterations"] / t3}
+            log(f"{key}: {mv[key]}")
+            S3.close()
+
+        def best(prefix):
+            ok = [v["seconds"] for k, v in mv.items()
+                  if k.startswith(prefix) and v["status"] == "CONVERGED"]
+            return min(ok) if ok else None
+        bf, bm = best("fp64"), best("mixed")
+        mv["best_fp64_seconds"] = bf
+        mv["best_mixed_seconds"] = bm
+        mv["speedup_mixed_over_fp64"] = (bf / bm) if (bf and bm) else None
+        out["mixed_vs_fp64"] = {"workload": "convdiff3d 200^3, c=(10,5,1), Jacobi, "
+                                            "tol 1e-10 true residual", **mv}
+
+    if not args.skip_cpu:
+        log(f"CPU oracle baseline ({args.cpu_iters} iterations)")
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

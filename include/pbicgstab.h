@@ -1,0 +1,237 @@
+/*
+ * pbicgstab.h -- C ABI of the MI355X (gfx950) pipelined BiCGStab library.
+ *
+ * The library solves A x = b for a sparse, nonsingular N x N matrix A
+ * (Section 1 of Cools, "Analyzing and improving maximal attainable accuracy
+ * in the communication hiding pipelined BiCGStab method") with
+ *
+ *   - the preconditioned pipelined BiCGStab method, Algorithm 2, with the
+ *     periodic residual replacement of Section 3.6 (eq:rr), and
+ *   - the classic preconditioned BiCGStab method, Algorithm 1, for
+ *     comparison,
+ *
+ * both with the identity or the Jacobi (diagonal) preconditioner applied as
+ * the listings do (right preconditioning: r = b - A x is the unpreconditioned
+ * residual, x is updated with M^-1-preconditioned directions).
+ *
+ * Conventions for every function
+ *   - Return value: 0 (PBCG_CONVERGED) or a positive solver outcome from a
+ *     solve, 0 (PBCG_OK) from other calls, or a negative error code.  After an
+ *     error, pbicgstab_last_error() returns a message (per thread).
+ *   - "host" pointers are CPU memory, "device" pointers are GPU memory of the
+ *     device that was current when the handle was created.  All device
+ *     vectors are FP64 and hold exactly N elements unless stated otherwise.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is ordered after everything already queued on `stream`, and
+ *     `stream` is made to wait for the library's own work before a call
+ *     returns, so device buffers may be reused on `stream` right away.
+ *   - The handle owns its device memory (matrix layouts, solver vectors,
+ *     reduction scratch) and one internal stream; it is not thread safe, but
+ *     separate handles may be used concurrently.  Input arrays passed to
+ *     create/update calls are copied and may be freed after the call.
+ */
+#ifndef PBICGSTAB_H
+#define PBICGSTAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbcg_solver* pbcg_handle;
+
+/* storage precision */
+enum {
+  PBCG_FP64 = 0,  /* everything in FP64 */
+  PBCG_MIXED = 1  /* matrix and recurrence vectors stored and updated in FP32 (SPMV and
+                     AXPYs in FP32); dot products accumulated in FP64, scalars alpha,
+                     beta, omega in FP64, x and b in FP64, residual replacement and
+                     true residuals computed in FP64 */
+};
+
+/* preconditioner M */
+enum { PBCG_PC_NONE = 0, PBCG_PC_JACOBI = 1 /* M = diag(A) */ };
+
+/* structured operators */
+enum {
+  PBCG_ST_2D5 = 0,  /* constant 5-point stencil, dims {nx, ny}: coef[5] = S, W, C, E, N */
+  PBCG_ST_3D7 = 1,  /* constant 7-point stencil, dims {nx, ny, nz}: coef[7] = D, S, W, C, E, N, U */
+  PBCG_ST_DIA5 = 2  /* variable 5-point coefficients, dims {nx, ny}: coef[5*N], row d = S, W, C, E, N */
+};
+
+/* outcomes (>= 0) and errors (< 0) */
+enum {
+  PBCG_OK = 0,
+  PBCG_CONVERGED = 0,         /* ||b - A x|| <= tol ||b||, confirmed on the true residual */
+  PBCG_MAXIT = 1,             /* maxit iterations done; x holds the last iterate */
+  PBCG_BREAKDOWN_RHO = 2,     /* (r0, r_{i+1}) = 0 or a zero denominator of alpha */
+  PBCG_BREAKDOWN_OMEGA = 3,   /* omega_i = 0 and the update did not meet the tolerance */
+  PBCG_NONFINITE = 4,         /* a reduction produced NaN or Inf */
+  PBCG_TRUE_RES_NOT_MET = 5,  /* the recursive residual met tol but the true one did not
+                                 (and residual replacement is disabled) */
+  PBCG_ERR_INVALID_ARG = -1,
+  PBCG_ERR_HIP = -2,          /* a HIP runtime call failed */
+  PBCG_ERR_ZERO_DIAG = -3,    /* Jacobi requested but a diagonal entry is zero or missing */
+  PBCG_ERR_UNSUPPORTED = -5
+};
+
+typedef struct {
+  double tol;            /* stop when ||r_i|| <= tol * ||b|| (recursive residual, Section 3.5),
+                            confirmed by the true residual ||b - A x_i|| */
+  int32_t maxit;         /* maximum number of iterations (>= 1) */
+  int32_t rr_period;     /* P > 0: residual replacement (eq:rr) in iteration i when
+                            (i+1) mod P == 0 and ||r_i|| >= rr_tau ||r_0||; also used when the
+                            true residual fails the confirmation.  0 disables it.
+                            Ignored by classic_bicgstab_solve. */
+  double rr_tau;         /* replacement cutoff; 0 selects sqrt(2^-53) */
+  int32_t check_every;   /* iterations between host polls of the device state (0: default) */
+  int32_t transpose;     /* nonzero: solve A^T x = b (the adjoint system) */
+  double* history;       /* optional device buffer of 4*history_len doubles; row i (0-based)
+                            holds the scalars of iteration i: ||r_{i+1}||, alpha_i,
+                            omega_i, beta_{i+1} (0 when the iteration stopped before beta) */
+  int32_t history_len;   /* rows */
+  int32_t gap_every;     /* > 0: after every gap_every-th iteration store the residual gap
+                            ||(b - A x_{i+1}) - r_{i+1}|| (eq:res_gap) in gap_history */
+  double* gap_history;   /* device buffer of gap_len doubles */
+  int32_t gap_len;
+  int32_t use_graph;     /* nonzero: replay chunks of iterations from captured HIP graphs */
+  void* stream;          /* hipStream_t */
+} pbcg_opts;
+
+typedef struct {
+  int32_t status;            /* outcome code, same as the return value */
+  int32_t iterations;        /* completed iterations */
+  int32_t replacements;      /* residual replacements performed */
+  int32_t spmvs;             /* sparse matrix-vector products issued */
+  double rel_res_recursive;  /* ||r|| / ||b|| of the recursively computed residual */
+  double rel_res_true;       /* ||b - A x|| / ||b||, computed in FP64 at the end */
+  double elapsed_ms;         /* device time from the first to the last kernel of the solve */
+  double rnorm0;             /* ||r_0|| */
+  double bnorm;              /* ||b|| */
+} pbcg_stats;
+
+/* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
+ * check_every 0, transpose 0, no history, use_graph 0, stream NULL. */
+void pbicgstab_default_opts(pbcg_opts* opt);
+
+/*
+ * Create a solver for a CSR matrix (Section 1: A sparse, N x N).
+ *   n, nnz          : dimension and number of stored entries (n >= 1)
+ *   rowptr, col, val: host arrays, rowptr[n+1] (rowptr[0] = 0, nondecreasing,
+ *                     rowptr[n] = nnz), col[nnz] in [0, n), val[nnz]; duplicate
+ *                     entries are kept and summed in stored order
+ *   precision       : PBCG_FP64 or PBCG_MIXED (values rounded once to FP32)
+ *   precond         : PBCG_PC_NONE or PBCG_PC_JACOBI (M^-1 = 1/diag, the
+ *                     diagonal being the sum of the entries with col == row;
+ *                     PBCG_ERR_ZERO_DIAG if one is zero)
+ * The matrix is stored on the device as sliced ELLPACK (slice height 64) in
+ * the stored column order of each row.
+ */
+int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
+                         const int32_t* col, const double* val, int precision, int precond,
+                         void* stream);
+
+/*
+ * Create a solver for a structured operator on a lexicographically ordered
+ * grid (p = ix + nx*iy + nx*ny*iz; neighbours outside the grid have no entry,
+ * i.e. homogeneous Dirichlet boundaries).
+ *   kind : PBCG_ST_2D5, PBCG_ST_3D7 or PBCG_ST_DIA5
+ *   dims : host int64[2] or int64[3]
+ *   coef : host array, see the kind enum (coefficients in ascending column order)
+ */
+int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, const double* coef,
+                             int precision, int precond, void* stream);
+
+/*
+ * Solve A x = b (or A^T x = b) with pipelined BiCGStab, Algorithm 2, and
+ * periodic residual replacement (Section 3.6).
+ *   b : device FP64 [n]       right-hand side
+ *   x : device FP64 [n]       in: x_0, out: the last iterate
+ *   opt: host, see pbcg_opts (NULL = defaults); st: host, may be NULL
+ * Blocks the calling thread until the solve has finished.
+ */
+int pbicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
+                    pbcg_stats* st);
+
+/* Same interface with classic BiCGStab, Algorithm 1 (three global reductions
+ * per iteration on the critical path; rr_period is ignored). */
+int classic_bicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
+                           pbcg_stats* st);
+
+/* y = A x (or A^T x) with FP64 accumulation; x, y device FP64 [n]. */
+int pbicgstab_apply(pbcg_handle h, const double* x, double* y, int transpose, void* stream);
+
+/*
+ * Gradient of a loss with respect to the stored matrix values, given the
+ * adjoint lambda (solution of A^T lambda = dL/dx) and the solution x:
+ * dL/da_ij = -lambda_i x_j (from d(A^-1) = -A^-1 dA A^-1).  Output (device FP64):
+ *   CSR handle : grad[nnz] in the stored CSR order
+ *   DIA5       : grad[5*n], row d = S, W, C, E, N, 0 where the entry does not exist
+ *   2D5 / 3D7  : grad[5] / grad[7], the derivative with respect to each
+ *                constant stencil coefficient (sum over the rows having it)
+ */
+int pbicgstab_grad_values(pbcg_handle h, const double* lambda, const double* x, double* grad,
+                          void* stream);
+
+/*
+ * Replace the matrix values, keeping the pattern (the Jacobi diagonal and the
+ * transposed layout follow).  values: CSR order [nnz] (CSR handle), [5*n]
+ * (DIA5) or [5]/[7] (stencils); on_device selects a device or host pointer.
+ */
+int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, void* stream);
+
+/*
+ * Coefficient-field operators (DIA5 handles): assemble
+ * -div(kappa grad u) + (cx, cy).grad u, scaled by h^2, from node values
+ * kappa (device FP64 [n]): face coefficient = mean of the two node values, a
+ * boundary face takes the node's own value; E/W get +/- cx h/2, N/S +/- cy h/2.
+ */
+int pbicgstab_dia5_assemble_kappa(pbcg_handle h, const double* kappa, double cx, double cy,
+                                  double hgrid, void* stream);
+
+/*
+ * dL/dkappa (device FP64 [n]) for the assembly above, from lambda and x:
+ * an interior face contributes -(lambda_p - lambda_q)(x_p - x_q)/2 to each of
+ * its nodes, a boundary face -lambda_p x_p to its node.
+ */
+int pbicgstab_dia5_kappa_grad(pbcg_handle h, const double* lambda, const double* x,
+                              double* grad_kappa, void* stream);
+
+/*
+ * Copy an internal solver vector to `out` (device FP64 [n]) for diagnostics:
+ * 0 r0 (shadow residual), 1 r, 2 g, 3 s, 4 l, 5 z, 6 k, 7 w, 8 t, 9 v,
+ * 10 x (the iterate), 11 dinv (Jacobi diagonal, 1 without preconditioner).
+ * For classic solves 2 holds p, 3 s and 9 y.
+ */
+int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream);
+
+/*
+ * Kernel timing for roofline measurements.  Launches one kernel of the
+ * Algorithm 2 iteration `reps` times back to back on the handle's stream and
+ * returns the average duration per launch, measured with HIP events recorded
+ * on that stream:
+ *   0 phase A (g, s, l, z recurrences + GLRED 1 partials)
+ *   1 PREC + SPMV  v = A M^-1 z  (with the GLRED 1 final block)
+ *   2 phase B (x, r, k, w recurrences + GLRED 2 partials)
+ *   3 PREC + SPMV  t = A M^-1 w  (with the GLRED 2 final block)
+ *   4 one full iteration (0-3)
+ * The solver vectors are overwritten (run it after, not between, the solves
+ * whose results are needed); every later solve reinitialises them.
+ */
+int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, void* stream);
+
+/* Problem size, stored entries, and device bytes held by the handle. */
+int pbicgstab_info(pbcg_handle h, int64_t* n, int64_t* nnz, int64_t* device_bytes);
+
+void pbicgstab_destroy(pbcg_handle h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* pbicgstab_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBICGSTAB_H */

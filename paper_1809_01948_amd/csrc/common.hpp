@@ -1,0 +1,198 @@
+// Shared device-side definitions of the pipelined BiCGStab library (gfx950).
+//
+// Layout conventions
+//   * Every solver vector lives in one device arena, padded to a multiple of
+//     kPadElems elements with zeros.  The padding stays zero through every
+//     recurrence of Algorithm 2 (all inputs of a padded element are zero and
+//     operator kernels never write padded rows), so streaming kernels need no
+//     bounds checks and can use 16-byte vector loads throughout.
+//   * Global reductions (the GLRED phases) are two-level: each block of a
+//     streaming kernel writes one FP64 partial per dot product into
+//     partials[slot * kMaxBlocks + block]; a single "final" block then sums
+//     the partials of each slot in a fixed order and updates the device
+//     scalar block.  The summation tree is fixed, so results are bitwise
+//     reproducible run to run.
+//   * All scalar recurrences (alpha, beta, omega, rho) live in FP64 in a
+//     device-resident DevScalars block; the host only reads it when polling.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pbcg {
+
+constexpr int kBlock = 256;          // threads per block (4 wave64)
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxBlocks = 2048;     // max blocks of a streaming kernel = partials per slot
+constexpr int kNumSlots = 8;         // partial slots
+constexpr int64_t kPadElems = 2048;  // vector padding granularity (elements)
+constexpr int kXcds = 8;             // MI355X: workgroups are dispatched round-robin over 8 XCDs
+constexpr int kSellC = 64;           // SELL slice height = one wavefront
+
+// partial slots
+enum Slot : int {
+  SL_QY = 0,    // (q_i, y_i)                      GLRED 1
+  SL_YY = 1,    // (y_i, y_i)
+  SL_RR0 = 2,   // (r_0, r_{i+1})                  GLRED 2
+  SL_RW0 = 3,   // (r_0, w_{i+1})
+  SL_RS0 = 4,   // (r_0, s_i)
+  SL_RZ0 = 5,   // (r_0, z_i)
+  SL_RR = 6,    // (r_{i+1}, r_{i+1})  (stopping test)
+  SL_BB = 7,    // (b, b)              (initialisation)
+};
+
+// final-reduction modes (run by one extra block of an operator kernel, or by
+// a one-block kernel)
+enum FinalMode : int {
+  FIN_NONE = 0,
+  FIN_INIT = 1,      // rho_0, alpha_0, ||r_0||, ||b||           (Algorithm 2 initialisation)
+  FIN_OMEGA = 2,     // omega_i = (q,y)/(y,y)                    (GLRED 1)
+  FIN_BETA = 3,      // beta_{i+1}, alpha_{i+1}, stopping test   (GLRED 2)
+  FIN_REDO = 4,      // FIN_BETA after a forced replacement (iteration count unchanged)
+  FIN_TRUE = 5,      // ||b - A x|| from slot SL_RR
+  FIN_GAP = 6,       // ||(b - A x) - r|| from slot SL_RR into the gap history
+  FIN_C_INIT = 7,    // classic: rho_0 = (r0, r0), ||r_0||, ||b||
+  FIN_C_ALPHA = 8,   // classic: alpha_i = rho_i / (r0, s_i)
+  FIN_C_OMEGA = 9,   // classic: omega_i
+  FIN_C_BETA = 10,   // classic: beta_i, stopping test
+  FIN_SUM = 11,      // plain sums of slots 0..nslot-1 into DevScalars::sums
+};
+
+// done flag values
+enum Done : int { RUNNING = 0, RECURSIVE_CONVERGED = 1, STOPPED = 2 };
+
+// status codes (same numbering as the C ABI)
+enum Status : int {
+  ST_CONVERGED = 0, ST_MAXIT = 1, ST_BREAKDOWN_RHO = 2, ST_BREAKDOWN_OMEGA = 3,
+  ST_NONFINITE = 4, ST_TRUE_RES_NOT_MET = 5,
+};
+
+struct DevScalars {
+  double alpha, beta, omega, omega_prev, rho;
+  double rn, rn0, nb, tol, tau;
+  double tr, gap;                  // last true residual norm / last gap norm
+  double sig[kNumSlots];           // last reduced sums (diagnostics)
+  double sums[kNumSlots];          // FIN_SUM output
+  int32_t iter;                    // completed iterations
+  int32_t done;                    // Done
+  int32_t status;                  // Status (valid when done == STOPPED)
+  int32_t rr_count;                // replacements performed
+  int32_t rr_period, maxit;
+  int32_t hist_len, gap_len;
+  int32_t gap_idx;                 // next free gap-history slot
+  int32_t bad_diag;                // set by value-update kernels on a zero diagonal
+  int32_t n_saved;                 // 1: the iteration's pre-replacement z is in the spare vector
+  int32_t pad_;
+  double* history;                 // optional ||r_{i+1}|| per iteration
+  double* gap_history;             // optional gap norms
+};
+
+// ----------------------------------------------------------------------------
+// reductions
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-level sum of ND per-thread accumulators; thread d < ND writes the
+// block's partial of dot d into partials[slot[d] * kMaxBlocks + blk].
+template <int ND>
+__device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&slot)[ND],
+                                               double* __restrict__ partials, int blk) {
+  __shared__ double red[ND][kWaves];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double v = wave_sum(acc[d]);
+    if (lane == 0) red[d][wid] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < ND) {
+    const int d = threadIdx.x;
+    double s = red[d][0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s += red[d][w];
+    partials[slot[d] * kMaxBlocks + blk] = s;
+  }
+}
+
+// Sum of the first nblk partials of one slot, computed by one whole block in
+// a fixed order; every thread returns the result.
+__device__ __forceinline__ double block_sum_slot(const double* __restrict__ partials, int slot,
+                                                 int nblk) {
+  __shared__ double red[kWaves];
+  __shared__ double total;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < nblk; j += kBlock) s += partials[slot * kMaxBlocks + j];
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < kWaves; ++w) t += red[w];
+    total = t;
+  }
+  __syncthreads();
+  double r = total;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// ----------------------------------------------------------------------------
+// tile scheduling
+// ----------------------------------------------------------------------------
+
+// XCD-aware tile walk.  Block b runs on XCD b % 8; XCD x owns the contiguous
+// tile range [x*T/8, (x+1)*T/8) and its blocks stride through it together, so
+// tiles that share stencil halo rows are processed by one XCD and hit in its
+// L2.  `nwork` must be a multiple of kXcds.
+struct XcdWalk {
+  int64_t t, end, step;
+  __device__ XcdWalk(int64_t ntiles, int blk, int nwork) {
+    const int x = blk % kXcds;
+    const int j = blk / kXcds;
+    const int per = nwork / kXcds;
+    const int64_t lo = (ntiles * x) / kXcds;
+    end = (ntiles * (x + 1)) / kXcds;
+    t = lo + j;
+    step = per;
+  }
+};
+
+// ----------------------------------------------------------------------------
+// vector helpers
+// ----------------------------------------------------------------------------
+
+template <typename T> struct V16;                 // 16-byte vector of T
+template <> struct V16<double> { typedef double2 type; static constexpr int n = 2; };
+template <> struct V16<float> { typedef float4 type; static constexpr int n = 4; };
+
+template <typename T>
+__device__ __forceinline__ void ld16(const T* __restrict__ p, T (&v)[V16<T>::n]) {
+  typedef typename V16<T>::type VT;
+  VT t = *reinterpret_cast<const VT*>(p);
+  const T* e = reinterpret_cast<const T*>(&t);
+#pragma unroll
+  for (int k = 0; k < V16<T>::n; ++k) v[k] = e[k];
+}
+
+template <typename T>
+__device__ __forceinline__ void st16(T* __restrict__ p, const T (&v)[V16<T>::n]) {
+  typedef typename V16<T>::type VT;
+  VT t;
+  T* e = reinterpret_cast<T*>(&t);
+#pragma unroll
+  for (int k = 0; k < V16<T>::n; ++k) e[k] = v[k];
+  *reinterpret_cast<VT*>(p) = t;
+}
+
+// preconditioner kinds (compile-time)
+enum PcKind : int { PC_NONE = 0, PC_SCALAR = 1, PC_VECTOR = 2 };
+
+}  // namespace pbcg

@@ -1,0 +1,996 @@
+// Host engine of the pipelined BiCGStab library: layouts, the solve loops
+// and the exported C ABI (include/pbicgstab.h).
+//
+// Iteration schedule of Algorithm 2 on one GPU (one stream, 4 kernels per
+// iteration, no host synchronisation inside the loop):
+//   phaseA   g, s, l, z recurrences; partials (q,y), (y,y)           [GLRED 1 begins]
+//   spmv     v = A M^-1 z; its block 0 reduces GLRED 1 -> omega_i    [GLRED 1 ends]
+//   phaseB   x, r, k, w recurrences; partials of GLRED 2             [GLRED 2 begins]
+//   (rr1, rr2: residual replacement, predicated on the device)
+//   spmv     t = A M^-1 w; its block 0 reduces GLRED 2 -> beta, alpha [GLRED 2 ends]
+// All scalars stay on the device.  The host launches chunks of iterations
+// and reads the device status block (pinned copy) one chunk behind, so the
+// GPU never waits for the host; kernels of an already finished solve exit at
+// their first instruction.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pbicgstab.h"
+#include "solver.hpp"
+
+namespace pbcg {
+void launch_dia5_transpose(Solver& S, hipStream_t st);
+}
+
+using namespace pbcg;
+
+struct pbcg_solver {
+  Solver S;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct PbcgError : std::runtime_error {
+  int code;
+  PbcgError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw PbcgError(code, msg); }
+
+void hipck(hipError_t e, const char* what) {
+  if (e != hipSuccess)
+    fail(PBCG_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const PbcgError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PBCG_ERR_HIP;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return PBCG_ERR_INVALID_ARG;
+  }
+}
+
+void* dalloc(Solver& S, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipck(hipMalloc(&p, bytes), "hipMalloc");
+  S.allocations.push_back(p);
+  hipck(hipMemset(p, 0, bytes), "hipMemset");
+  return p;
+}
+
+int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+void common_setup(Solver& S, int precision, int precond) {
+  if (precision != PBCG_FP64 && precision != PBCG_MIXED) fail(PBCG_ERR_INVALID_ARG, "precision must be PBCG_FP64 or PBCG_MIXED");
+  if (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI) fail(PBCG_ERR_INVALID_ARG, "precond must be PBCG_PC_NONE or PBCG_PC_JACOBI");
+  if (S.n > (int64_t)2000000000) fail(PBCG_ERR_UNSUPPORTED, "n exceeds the int32 index range");
+  S.precision = precision;
+  S.precond = precond;
+  S.tsize = precision == PBCG_FP64 ? 8 : 4;
+  S.npad = round_up(S.n, kPadElems);
+  const int vw = (int)(16 / S.tsize);
+  S.vtiles = S.npad / (kBlock * vw);
+  S.rtiles = (S.n + kBlock - 1) / kBlock;
+  int64_t nb = std::min<int64_t>(kMaxBlocks, std::max<int64_t>(S.vtiles, S.rtiles));
+  nb = round_up(std::max<int64_t>(nb, kXcds), kXcds);
+  if (nb > kMaxBlocks) nb = kMaxBlocks;
+  S.nblk = (int)nb;
+  hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
+  hipck(hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming), "hipEventCreate");
+  hipck(hipEventCreateWithFlags(&S.ev_out, hipEventDisableTiming), "hipEventCreate");
+  hipck(hipEventCreateWithFlags(&S.ev_poll[0], hipEventDisableTiming), "hipEventCreate");
+  hipck(hipEventCreateWithFlags(&S.ev_poll[1], hipEventDisableTiming), "hipEventCreate");
+  hipck(hipEventCreate(&S.ev_t0), "hipEventCreate");
+  hipck(hipEventCreate(&S.ev_t1), "hipEventCreate");
+  for (int v = 0; v < V_COUNT; ++v) S.vec[v] = dalloc(S, S.npad * S.tsize);
+  S.x = (double*)dalloc(S, S.npad * 8);
+  S.b = (double*)dalloc(S, S.npad * 8);
+  S.partials = (double*)dalloc(S, sizeof(double) * kNumSlots * kMaxBlocks);
+  S.sc = (DevScalars*)dalloc(S, sizeof(DevScalars));
+  hipck(hipHostMalloc((void**)&S.h_sc, 3 * sizeof(DevScalars), hipHostMallocDefault),
+        "hipHostMalloc");
+  std::memset(S.h_sc, 0, 3 * sizeof(DevScalars));
+}
+
+// CSR -> SELL-64 on the host; pos[k] = SELL slot of CSR entry k
+void build_sell(int64_t n, const int32_t* rowptr, const int32_t* col, const double* val,
+                std::vector<int64_t>& sptr, std::vector<int32_t>& scol, std::vector<double>& sval,
+                std::vector<int64_t>& pos, int& max_width) {
+  const int64_t ns = (n + kSellC - 1) / kSellC;
+  sptr.assign(ns + 1, 0);
+  max_width = 0;
+  for (int64_t s = 0; s < ns; ++s) {
+    int w = 0;
+    for (int64_t i = s * kSellC; i < std::min<int64_t>(n, (s + 1) * kSellC); ++i)
+      w = std::max<int>(w, rowptr[i + 1] - rowptr[i]);
+    max_width = std::max(max_width, w);
+    sptr[s + 1] = sptr[s] + (int64_t)w * kSellC;
+  }
+  scol.assign(sptr[ns], -1);
+  sval.assign(sptr[ns], 0.0);
+  pos.assign(rowptr[n], 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t s = i / kSellC, lane = i % kSellC;
+    int j = 0;
+    for (int64_t kk = rowptr[i]; kk < rowptr[i + 1]; ++kk, ++j) {
+      const int64_t p = sptr[s] + (int64_t)j * kSellC + lane;
+      scol[p] = col[kk];
+      sval[p] = val[kk];
+      pos[kk] = p;
+    }
+  }
+}
+
+template <typename T>
+void upload_vals(Solver& S, void* dst, const std::vector<double>& v) {
+  std::vector<T> t(v.size());
+  for (size_t i = 0; i < v.size(); ++i) t[i] = (T)v[i];
+  hipck(hipMemcpy(dst, t.data(), t.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+void upload_sell(Solver& S, OpData& o, const std::vector<int64_t>& sptr,
+                 const std::vector<int32_t>& scol, const std::vector<double>& sval, int mw) {
+  o.kind = OP_SELL;
+  o.nslices = (int64_t)sptr.size() - 1;
+  o.sell_elems = sptr.back();
+  o.max_width = mw;
+  o.sptr = (int64_t*)dalloc(S, sptr.size() * 8);
+  o.col = (int32_t*)dalloc(S, scol.size() * 4);
+  o.val = dalloc(S, sval.size() * S.tsize);
+  hipck(hipMemcpy(o.sptr, sptr.data(), sptr.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
+  hipck(hipMemcpy(o.col, scol.data(), scol.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  if (S.precision == PBCG_FP64) upload_vals<double>(S, o.val, sval);
+  else upload_vals<float>(S, o.val, sval);
+}
+
+// Jacobi diagonal (sum of the entries with col == row) from the host CSR
+void set_dinv_csr(Solver& S) {
+  std::vector<double> d(S.npad, 0.0);
+  std::vector<int64_t> dpos(S.n, -1);
+  for (int64_t i = 0; i < S.n; ++i) {
+    double s = 0.0;
+    for (int64_t kk = S.h_rowptr[i]; kk < S.h_rowptr[i + 1]; ++kk)
+      if (S.h_col[kk] == i) {
+        s += S.h_val[kk];
+        if (dpos[i] < 0) dpos[i] = kk;
+      }
+    d[i] = s;
+  }
+  S.d_diagpos = (int64_t*)dalloc(S, S.n * 8);
+  hipck(hipMemcpy(S.d_diagpos, dpos.data(), S.n * 8, hipMemcpyHostToDevice), "hipMemcpy");
+  if (!S.precond) return;
+  S.pc = PC_VECTOR;
+  S.dinv = dalloc(S, S.npad * S.tsize);
+  if (S.precision == PBCG_FP64) {
+    std::vector<double> di(S.npad, 0.0);
+    for (int64_t i = 0; i < S.n; ++i) {
+      if (d[i] == 0.0) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal entry in row " + std::to_string(i));
+      di[i] = 1.0 / d[i];
+    }
+    hipck(hipMemcpy(S.dinv, di.data(), S.npad * 8, hipMemcpyHostToDevice), "hipMemcpy");
+  } else {
+    std::vector<float> di(S.npad, 0.0f);
+    for (int64_t i = 0; i < S.n; ++i) {
+      const float df = (float)d[i];
+      if (df == 0.0f) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal entry in row " + std::to_string(i));
+      di[i] = 1.0f / df;
+    }
+    hipck(hipMemcpy(S.dinv, di.data(), S.npad * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  }
+}
+
+void build_transpose(Solver& S) {
+  if (S.have_AT) return;
+  if (S.kind == OP_SELL) {
+    const int64_t n = S.n, nnz = S.nnz;
+    std::vector<int32_t> trp(n + 1, 0), tcol(nnz);
+    std::vector<double> tval(nnz);
+    std::vector<int64_t> where(nnz);  // CSR entry -> position in the transposed CSR
+    for (int64_t kk = 0; kk < nnz; ++kk) trp[S.h_col[kk] + 1]++;
+    for (int64_t i = 0; i < n; ++i) trp[i + 1] += trp[i];
+    std::vector<int32_t> fillp(trp.begin(), trp.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t kk = S.h_rowptr[i]; kk < S.h_rowptr[i + 1]; ++kk) {
+        const int32_t j = S.h_col[kk];
+        const int64_t q = fillp[j]++;
+        tcol[q] = (int32_t)i;
+        tval[q] = S.h_val[kk];
+        where[kk] = q;
+      }
+    std::vector<int64_t> sptr, pos;
+    std::vector<int32_t> scol;
+    std::vector<double> sval;
+    int mw = 0;
+    build_sell(n, trp.data(), tcol.data(), tval.data(), sptr, scol, sval, pos, mw);
+    upload_sell(S, S.AT, sptr, scol, sval, mw);
+    std::vector<int64_t> posAT(nnz);
+    for (int64_t kk = 0; kk < nnz; ++kk) posAT[kk] = pos[where[kk]];
+    S.d_posAT = (int64_t*)dalloc(S, std::max<int64_t>(nnz, 1) * 8);
+    hipck(hipMemcpy(S.d_posAT, posAT.data(), nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
+  } else if (S.kind == OP_ST2D5 || S.kind == OP_ST3D7) {
+    S.AT = S.A;
+    const int nd = S.kind == OP_ST2D5 ? 5 : 7;
+    for (int d = 0; d < nd; ++d) {
+      S.AT.c64[d] = S.A.c64[nd - 1 - d];
+      S.AT.c32[d] = S.A.c32[nd - 1 - d];
+    }
+  } else {
+    S.AT = S.A;
+    S.AT.dia = dalloc(S, 5 * S.npad * S.tsize);
+    launch_dia5_transpose(S, S.s1);
+    hipck(hipGetLastError(), "dia5 transpose launch");
+    hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+  }
+  S.have_AT = true;
+}
+
+DevScalars initial_scalars(const pbcg_opts& o) {
+  DevScalars d;
+  std::memset(&d, 0, sizeof(d));
+  d.tol = o.tol;
+  d.tau = o.rr_tau > 0 ? o.rr_tau : std::sqrt(std::ldexp(1.0, -53));
+  d.maxit = o.maxit;
+  d.rr_period = o.rr_period;
+  d.history = o.history;
+  d.hist_len = o.history ? o.history_len : 0;
+  d.gap_history = o.gap_history;
+  d.gap_len = o.gap_history ? o.gap_len : 0;
+  return d;
+}
+
+void validate_opts(const pbcg_opts& o) {
+  if (!(o.tol >= 0.0)) fail(PBCG_ERR_INVALID_ARG, "tol must be >= 0");
+  if (o.maxit < 1) fail(PBCG_ERR_INVALID_ARG, "maxit must be >= 1");
+  if (o.rr_period < 0) fail(PBCG_ERR_INVALID_ARG, "rr_period must be >= 0");
+  if (o.rr_tau < 0) fail(PBCG_ERR_INVALID_ARG, "rr_tau must be >= 0");
+  if (o.check_every < 0) fail(PBCG_ERR_INVALID_ARG, "check_every must be >= 0");
+  if (o.history_len < 0 || o.gap_len < 0 || o.gap_every < 0)
+    fail(PBCG_ERR_INVALID_ARG, "negative history length");
+}
+
+// Upload scalars, copy b and x0 into the padded internal vectors.
+void begin_solve(Solver& S, const double* b, const double* x, const pbcg_opts& o,
+                 hipStream_t cs) {
+  if (!b || !x) fail(PBCG_ERR_INVALID_ARG, "b and x must be device pointers");
+  hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+  hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+  S.h_sc[2] = initial_scalars(o);
+  hipck(hipMemcpyAsync(S.sc, &S.h_sc[2], sizeof(DevScalars), hipMemcpyHostToDevice, S.s1),
+        "hipMemcpyAsync");
+  hipck(hipMemcpyAsync(S.b, b, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  hipck(hipMemcpyAsync(S.x, x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  hipck(hipEventRecord(S.ev_t0, S.s1), "hipEventRecord");
+}
+
+void end_solve(Solver& S, double* x, hipStream_t cs) {
+  hipck(hipMemcpyAsync(x, S.x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+  hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+}
+
+// synchronous read of the device scalars
+DevScalars read_scalars(Solver& S) {
+  hipck(hipMemcpyAsync(&S.h_sc[0], S.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, S.s1),
+        "hipMemcpyAsync");
+  hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+  return S.h_sc[0];
+}
+
+double true_residual(Solver& S, bool tr) {
+  launch_true_res(S, tr, S.s1);
+  launch_final(S, FIN_TRUE, 0, S.s1);
+  hipck(hipGetLastError(), "true residual launch");
+  return read_scalars(S).tr;
+}
+
+// one iteration of Algorithm 2 (index i) on stream st
+void enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_t st) {
+  launch_phaseA(S, st);
+  launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
+  launch_phaseB(S, st);
+  if (o.rr_period > 0 && (i + 1) % o.rr_period == 0) {
+    launch_rr1(S, tr, false, st);
+    launch_rr2(S, tr, false, st);
+  }
+  launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
+  if (o.gap_every > 0 && (i + 1) % o.gap_every == 0) {
+    launch_gap(S, tr, st);
+    launch_final(S, FIN_GAP, 0, st);
+  }
+}
+
+hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_opts& o) {
+  const int off = o.rr_period > 0 ? start % o.rr_period : 0;
+  const std::string key = std::to_string(tr) + "/" + std::to_string(len) + "/" +
+                          std::to_string(off) + "/" + std::to_string(o.rr_period) + "/" +
+                          std::to_string(o.gap_every > 0 ? start % o.gap_every : 0) + "/" +
+                          std::to_string(o.gap_every);
+  auto it = S.graphs.find(key);
+  if (it != S.graphs.end()) return it->second;
+  hipGraph_t g = nullptr;
+  hipck(hipStreamBeginCapture(S.s1, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  for (int j = 0; j < len; ++j) enqueue_iteration(S, tr, start + j, o, S.s1);
+  hipck(hipStreamEndCapture(S.s1, &g), "hipStreamEndCapture");
+  hipGraphExec_t ge = nullptr;
+  hipck(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+  hipck(hipGraphDestroy(g), "hipGraphDestroy");
+  S.graphs[key] = ge;
+  return ge;
+}
+
+// Runs iterations until the device reports done or `maxit` iterations have
+// been completed.  Returns the device scalars after draining the stream.
+DevScalars run_iterations(Solver& S, bool tr, int start, const pbcg_opts& o) {
+  int K = o.check_every > 0 ? o.check_every : (o.use_graph ? 16 : 8);
+  if (o.use_graph && o.rr_period > 0) {
+    // chunk length dividing the replacement period keeps the captured variants few
+    int best = 1;
+    for (int d = 1; d <= std::min(o.rr_period, 64); ++d)
+      if (o.rr_period % d == 0 && std::abs(d - K) < std::abs(best - K)) best = d;
+    K = best;
+  }
+  int it = start;
+  int chunk = 0;
+  bool outstanding = false;
+  while (it < o.maxit) {
+    const int len = std::min(K, o.maxit - it);
+    if (o.use_graph) {
+      hipGraphExec_t ge = chunk_graph(S, tr, it, len, o);
+      hipck(hipGraphLaunch(ge, S.s1), "hipGraphLaunch");
+    } else {
+      for (int j = 0; j < len; ++j) enqueue_iteration(S, tr, it + j, o, S.s1);
+    }
+    hipck(hipGetLastError(), "iteration launch");
+    it += len;
+    const int slot = chunk & 1;
+    hipck(hipMemcpyAsync(&S.h_sc[slot], S.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, S.s1),
+          "hipMemcpyAsync");
+    hipck(hipEventRecord(S.ev_poll[slot], S.s1), "hipEventRecord");
+    if (outstanding) {
+      const int prev = (chunk - 1) & 1;
+      hipck(hipEventSynchronize(S.ev_poll[prev]), "hipEventSynchronize");
+      if (S.h_sc[prev].done != RUNNING) break;
+    }
+    outstanding = true;
+    ++chunk;
+  }
+  return read_scalars(S);
+}
+
+int finish_stats(Solver& S, bool tr, const DevScalars& d, int status, pbcg_stats* st,
+                 double tr_norm, int spmvs) {
+  hipck(hipEventRecord(S.ev_t1, S.s1), "hipEventRecord");
+  hipck(hipEventSynchronize(S.ev_t1), "hipEventSynchronize");
+  float ms = 0.0f;
+  hipck(hipEventElapsedTime(&ms, S.ev_t0, S.ev_t1), "hipEventElapsedTime");
+  if (st) {
+    st->status = status;
+    st->iterations = d.iter;
+    st->replacements = d.rr_count;
+    st->spmvs = spmvs;
+    st->bnorm = d.nb;
+    st->rnorm0 = d.rn0;
+    st->rel_res_recursive = d.nb > 0 ? d.rn / d.nb : 0.0;
+    st->rel_res_true = d.nb > 0 ? tr_norm / d.nb : 0.0;
+    st->elapsed_ms = ms;
+  }
+  (void)tr;
+  return status;
+}
+
+int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, pbcg_stats* st) {
+  validate_opts(o);
+  const bool tr = o.transpose != 0;
+  if (tr) build_transpose(S);
+  hipStream_t cs = (hipStream_t)o.stream;
+  begin_solve(S, b, x, o, cs);
+  // Algorithm 2 initialisation
+  launch_init_res(S, tr, S.s1);
+  launch_spmv(S, tr, S.vec[V_R], S.vec[V_W], FIN_NONE, true, S.s1);
+  launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_INIT, false, S.s1);
+  hipck(hipGetLastError(), "init launch");
+  DevScalars d = read_scalars(S);
+  int status = -1;
+  double trn = 0.0;
+  int forced = 0;
+  int start = 0;
+  if (d.done == STOPPED) {
+    status = d.status;
+    if (d.nb == 0.0) launch_fill_zero(S, S.x, S.n, 8, S.s1);
+  }
+  while (status < 0) {
+    d = run_iterations(S, tr, start, o);
+    if (d.done == STOPPED) {
+      status = d.status;
+      break;
+    }
+    if (d.done == RUNNING) {  // maxit reached without a device-side stop
+      status = PBCG_MAXIT;
+      break;
+    }
+    // recursive residual met the tolerance: confirm on the true residual
+    trn = true_residual(S, tr);
+    d = read_scalars(S);
+    if (trn <= o.tol * d.nb) {
+      status = PBCG_CONVERGED;
+      break;
+    }
+    if (o.rr_period <= 0 || forced >= 3) {
+      status = PBCG_TRUE_RES_NOT_MET;
+      break;
+    }
+    // replace (eq:rr) and recompute GLRED 2, then continue
+    ++forced;
+    launch_set_done(S, RUNNING, S.s1);
+    launch_rr1(S, tr, true, S.s1);
+    launch_rr2(S, tr, true, S.s1);
+    launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_REDO, false, S.s1);
+    hipck(hipGetLastError(), "replacement launch");
+    d = read_scalars(S);
+    if (d.done == STOPPED) {
+      status = d.status;
+      break;
+    }
+    if (d.done == RECURSIVE_CONVERGED) {
+      status = PBCG_TRUE_RES_NOT_MET;
+      break;
+    }
+    start = d.iter;
+    if (start >= o.maxit) {
+      status = PBCG_MAXIT;
+      break;
+    }
+  }
+  trn = true_residual(S, tr);
+  d = read_scalars(S);
+  const int spmvs = 3 + 2 * d.iter + 4 * d.rr_count + 1;
+  end_solve(S, x, cs);
+  return finish_stats(S, tr, d, status, st, trn, spmvs);
+}
+
+int solve_classic(Solver& S, const double* b, double* x, const pbcg_opts& o, pbcg_stats* st) {
+  validate_opts(o);
+  const bool tr = o.transpose != 0;
+  if (tr) build_transpose(S);
+  hipStream_t cs = (hipStream_t)o.stream;
+  begin_solve(S, b, x, o, cs);
+  launch_cl_init(S, tr, S.s1);
+  launch_final(S, FIN_C_INIT, 0, S.s1);
+  hipck(hipGetLastError(), "init launch");
+  DevScalars d = read_scalars(S);
+  int status = -1;
+  if (d.done == STOPPED) {
+    status = d.status;
+    if (d.nb == 0.0) launch_fill_zero(S, S.x, S.n, 8, S.s1);
+  } else {
+    const int K = o.check_every > 0 ? o.check_every : 8;
+    int it = 0, chunk = 0;
+    bool outstanding = false;
+    while (it < o.maxit) {
+      const int len = std::min(K, o.maxit - it);
+      for (int j = 0; j < len; ++j) {
+        launch_cl_spmv_s(S, tr, S.s1);
+        launch_final(S, FIN_C_ALPHA, 0, S.s1);
+        launch_cl_spmv_y(S, tr, S.s1);
+        launch_final(S, FIN_C_OMEGA, 0, S.s1);
+        launch_cl_update(S, S.s1);
+        launch_final(S, FIN_C_BETA, 0, S.s1);
+        launch_cl_p(S, S.s1);
+      }
+      hipck(hipGetLastError(), "iteration launch");
+      it += len;
+      const int slot = chunk & 1;
+      hipck(hipMemcpyAsync(&S.h_sc[slot], S.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, S.s1),
+            "hipMemcpyAsync");
+      hipck(hipEventRecord(S.ev_poll[slot], S.s1), "hipEventRecord");
+      if (outstanding) {
+        const int prev = (chunk - 1) & 1;
+        hipck(hipEventSynchronize(S.ev_poll[prev]), "hipEventSynchronize");
+        if (S.h_sc[prev].done != RUNNING) break;
+      }
+      outstanding = true;
+      ++chunk;
+    }
+    d = read_scalars(S);
+    if (d.done == STOPPED) status = d.status;
+    else if (d.done == RUNNING) status = PBCG_MAXIT;
+    else {
+      const double trn = true_residual(S, tr);
+      d = read_scalars(S);
+      status = trn <= o.tol * d.nb ? PBCG_CONVERGED : PBCG_TRUE_RES_NOT_MET;
+    }
+  }
+  const double trn = true_residual(S, tr);
+  d = read_scalars(S);
+  end_solve(S, x, cs);
+  return finish_stats(S, tr, d, status, st, trn, 1 + 2 * d.iter + 1);
+}
+
+pbcg_opts defaults() {
+  pbcg_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.tol = 1e-10;
+  o.maxit = 10000;
+  return o;
+}
+
+Solver& H(pbcg_handle h) {
+  if (!h) fail(PBCG_ERR_INVALID_ARG, "null handle");
+  return h->S;
+}
+
+void destroy_solver(pbcg_solver* p) {
+  if (!p) return;
+  Solver& S = p->S;
+  for (auto& kv : S.graphs) (void)hipGraphExecDestroy(kv.second);
+  if (S.s1) (void)hipStreamSynchronize(S.s1);
+  for (void* a : S.allocations) (void)hipFree(a);
+  if (S.h_sc) (void)hipHostFree(S.h_sc);
+  hipEvent_t evs[] = {S.ev_in, S.ev_out, S.ev_t0, S.ev_t1, S.ev_poll[0], S.ev_poll[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (S.s1) (void)hipStreamDestroy(S.s1);
+  delete p;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+
+extern "C" {
+
+void pbicgstab_default_opts(pbcg_opts* opt) {
+  if (opt) *opt = defaults();
+}
+
+int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
+                         const int32_t* col, const double* val, int precision, int precond,
+                         void* stream) {
+  return guarded([&]() -> int {
+    if (!out) fail(PBCG_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (n < 1) fail(PBCG_ERR_INVALID_ARG, "n must be >= 1");
+    if (nnz < 0 || nnz > (int64_t)2000000000) fail(PBCG_ERR_INVALID_ARG, "nnz out of range");
+    if (!rowptr || (nnz > 0 && (!col || !val))) fail(PBCG_ERR_INVALID_ARG, "null CSR array");
+    if (rowptr[0] != 0 || rowptr[n] != nnz) fail(PBCG_ERR_INVALID_ARG, "rowptr[0] must be 0 and rowptr[n] == nnz");
+    for (int64_t i = 0; i < n; ++i)
+      if (rowptr[i + 1] < rowptr[i]) fail(PBCG_ERR_INVALID_ARG, "rowptr must be nondecreasing");
+    for (int64_t kk = 0; kk < nnz; ++kk)
+      if (col[kk] < 0 || col[kk] >= n) fail(PBCG_ERR_INVALID_ARG, "column index out of range");
+    hipStream_t cs = (hipStream_t)stream;
+    if (cs) hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    auto* p = new pbcg_solver();
+    try {
+      Solver& S = p->S;
+      S.n = n;
+      S.nnz = nnz;
+      S.kind = OP_SELL;
+      common_setup(S, precision, precond);
+      S.h_rowptr.assign(rowptr, rowptr + n + 1);
+      S.h_col.assign(col, col + nnz);
+      S.h_val.assign(val, val + nnz);
+      std::vector<int64_t> sptr, pos;
+      std::vector<int32_t> scol;
+      std::vector<double> sval;
+      int mw = 0;
+      build_sell(n, rowptr, col, val, sptr, scol, sval, pos, mw);
+      upload_sell(S, S.A, sptr, scol, sval, mw);
+      S.d_posA = (int64_t*)dalloc(S, std::max<int64_t>(nnz, 1) * 8);
+      hipck(hipMemcpy(S.d_posA, pos.data(), nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
+      S.d_rowptr = (int32_t*)dalloc(S, (n + 1) * 4);
+      S.d_col = (int32_t*)dalloc(S, std::max<int64_t>(nnz, 1) * 4);
+      hipck(hipMemcpy(S.d_rowptr, rowptr, (n + 1) * 4, hipMemcpyHostToDevice), "hipMemcpy");
+      hipck(hipMemcpy(S.d_col, col, nnz * 4, hipMemcpyHostToDevice), "hipMemcpy");
+      set_dinv_csr(S);
+      hipck(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    } catch (...) {
+      destroy_solver(p);
+      throw;
+    }
+    *out = p;
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, const double* coef,
+                             int precision, int precond, void* stream) {
+  return guarded([&]() -> int {
+    if (!out) fail(PBCG_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!dims || !coef) fail(PBCG_ERR_INVALID_ARG, "dims and coef are required");
+    const int nd = kind == PBCG_ST_3D7 ? 3 : 2;
+    if (kind != PBCG_ST_2D5 && kind != PBCG_ST_3D7 && kind != PBCG_ST_DIA5)
+      fail(PBCG_ERR_INVALID_ARG, "unknown stencil kind");
+    int64_t n = 1;
+    for (int d = 0; d < nd; ++d) {
+      if (dims[d] < 1 || dims[d] > 2000000000) fail(PBCG_ERR_INVALID_ARG, "grid dimension out of range");
+      n *= dims[d];
+    }
+    hipStream_t cs = (hipStream_t)stream;
+    if (cs) hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    auto* p = new pbcg_solver();
+    try {
+      Solver& S = p->S;
+      S.n = n;
+      S.kind = kind == PBCG_ST_2D5 ? OP_ST2D5 : kind == PBCG_ST_3D7 ? OP_ST3D7 : OP_DIA5;
+      common_setup(S, precision, precond);
+      OpData& o = S.A;
+      o.kind = S.kind;
+      for (int d = 0; d < nd; ++d) o.dims[d] = (int)dims[d];
+      const int64_t nx = dims[0], ny = dims[1], nz = nd == 3 ? dims[2] : 1;
+      if (S.kind == OP_ST2D5 || S.kind == OP_ST3D7) {
+        const int nc = S.kind == OP_ST2D5 ? 5 : 7;
+        for (int d = 0; d < nc; ++d) {
+          o.c64[d] = coef[d];
+          o.c32[d] = (float)coef[d];
+        }
+        S.nnz = S.kind == OP_ST2D5 ? 5 * n - 2 * ny - 2 * nx
+                                   : 7 * n - 2 * ny * nz - 2 * nx * nz - 2 * nx * ny;
+        const double c = coef[S.kind == OP_ST2D5 ? 2 : 3];
+        if (precond) {
+          if (precision == PBCG_FP64) {
+            if (c == 0.0) fail(PBCG_ERR_ZERO_DIAG, "zero stencil centre");
+            S.dinv_s = 1.0 / c;
+          } else {
+            if ((float)c == 0.0f) fail(PBCG_ERR_ZERO_DIAG, "zero stencil centre");
+            S.dinv_s = (double)(1.0f / (float)c);
+          }
+          S.pc = PC_SCALAR;
+        }
+      } else {
+        // DIA5 coefficients, one row of n per direction
+        S.h_dia.assign(coef, coef + 5 * n);
+        std::vector<double> padded(5 * S.npad, 0.0);
+        int64_t nnz = 0;
+        for (int d = 0; d < 5; ++d)
+          for (int64_t i = 0; i < n; ++i) padded[d * S.npad + i] = coef[d * n + i];
+        for (int64_t i = 0; i < n; ++i) {
+          const int64_t iy = i / nx, ix = i % nx;
+          nnz += 1 + (iy > 0) + (ix > 0) + (ix < nx - 1) + (iy < ny - 1);
+        }
+        S.nnz = nnz;
+        o.dia = dalloc(S, 5 * S.npad * S.tsize);
+        if (precision == PBCG_FP64) upload_vals<double>(S, o.dia, padded);
+        else upload_vals<float>(S, o.dia, padded);
+        if (precond) {
+          S.pc = PC_VECTOR;
+          S.dinv = dalloc(S, S.npad * S.tsize);
+          if (precision == PBCG_FP64) {
+            std::vector<double> di(S.npad, 0.0);
+            for (int64_t i = 0; i < n; ++i) {
+              const double c = coef[2 * n + i];
+              if (c == 0.0) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal in row " + std::to_string(i));
+              di[i] = 1.0 / c;
+            }
+            hipck(hipMemcpy(S.dinv, di.data(), S.npad * 8, hipMemcpyHostToDevice), "hipMemcpy");
+          } else {
+            std::vector<float> di(S.npad, 0.0f);
+            for (int64_t i = 0; i < n; ++i) {
+              const float c = (float)coef[2 * n + i];
+              if (c == 0.0f) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal in row " + std::to_string(i));
+              di[i] = 1.0f / c;
+            }
+            hipck(hipMemcpy(S.dinv, di.data(), S.npad * 4, hipMemcpyHostToDevice), "hipMemcpy");
+          }
+        }
+      }
+      (void)nz;
+      hipck(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    } catch (...) {
+      destroy_solver(p);
+      throw;
+    }
+    *out = p;
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
+                    pbcg_stats* st) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    const pbcg_opts o = opt ? *opt : defaults();
+    return solve_pipelined(S, b, x, o, st);
+  });
+}
+
+int classic_bicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
+                           pbcg_stats* st) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    pbcg_opts o = opt ? *opt : defaults();
+    o.rr_period = 0;
+    o.gap_every = 0;
+    o.use_graph = 0;
+    return solve_classic(S, b, x, o, st);
+  });
+}
+
+int pbicgstab_apply(pbcg_handle h, const double* x, double* y, int transpose, void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (!x || !y) fail(PBCG_ERR_INVALID_ARG, "null vector");
+    if (transpose) build_transpose(S);
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    launch_apply(S, transpose != 0, x, y, S.s1);
+    hipck(hipGetLastError(), "apply launch");
+    hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+    hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_grad_values(pbcg_handle h, const double* lambda, const double* x, double* grad,
+                          void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (!lambda || !x || !grad) fail(PBCG_ERR_INVALID_ARG, "null vector");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    launch_grad(S, lambda, x, grad, S.s1);
+    if (S.kind == OP_ST2D5 || S.kind == OP_ST3D7) {
+      const int nc = S.kind == OP_ST2D5 ? 5 : 7;
+      launch_final(S, FIN_SUM, nc, S.s1);
+      hipck(hipMemcpyAsync(grad, &S.sc->sums[0], nc * sizeof(double), hipMemcpyDeviceToDevice,
+                           S.s1), "hipMemcpyAsync");
+    }
+    hipck(hipGetLastError(), "grad launch");
+    hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+    hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (!values) fail(PBCG_ERR_INVALID_ARG, "null values");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+    if (S.kind == OP_SELL) {
+      double* dv = nullptr;
+      if (!on_device) {
+        hipck(hipMalloc(&dv, std::max<int64_t>(S.nnz, 1) * 8), "hipMalloc");
+        hipck(hipMemcpy(dv, values, S.nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
+      }
+      const double* src = on_device ? values : dv;
+      hipck(hipMemsetAsync(&S.sc->bad_diag, 0, sizeof(int32_t), S.s1), "hipMemsetAsync");
+      launch_update_sell(S, src, S.s1);
+      hipck(hipGetLastError(), "update launch");
+      hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+      // keep the host copy current for a later transpose build
+      hipck(hipMemcpy(S.h_val.data(), src, S.nnz * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+      if (dv) (void)hipFree(dv);
+      int32_t bad = 0;
+      hipck(hipMemcpy(&bad, &S.sc->bad_diag, 4, hipMemcpyDeviceToHost), "hipMemcpy");
+      if (bad) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
+      return PBCG_OK;
+    }
+    if (S.kind == OP_ST2D5 || S.kind == OP_ST3D7) {
+      const int nc = S.kind == OP_ST2D5 ? 5 : 7;
+      double c[7];
+      if (on_device) hipck(hipMemcpy(c, values, nc * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+      else std::memcpy(c, values, nc * 8);
+      const double centre = c[nc / 2];
+      if (S.precond && (S.precision == PBCG_FP64 ? centre == 0.0 : (float)centre == 0.0f))
+        fail(PBCG_ERR_ZERO_DIAG, "zero stencil centre");
+      for (int d = 0; d < nc; ++d) {
+        S.A.c64[d] = c[d];
+        S.A.c32[d] = (float)c[d];
+      }
+      if (S.precond)
+        S.dinv_s = S.precision == PBCG_FP64 ? 1.0 / centre : (double)(1.0f / (float)centre);
+      if (S.have_AT) {
+        S.have_AT = false;
+        build_transpose(S);
+      }
+      for (auto& kv : S.graphs) (void)hipGraphExecDestroy(kv.second);
+      S.graphs.clear();
+      return PBCG_OK;
+    }
+    // DIA5
+    std::vector<double> host(5 * S.n);
+    if (on_device) hipck(hipMemcpy(host.data(), values, 5 * S.n * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+    else std::memcpy(host.data(), values, 5 * S.n * 8);
+    std::vector<double> padded(5 * S.npad, 0.0);
+    for (int d = 0; d < 5; ++d)
+      for (int64_t i = 0; i < S.n; ++i) padded[d * S.npad + i] = host[d * S.n + i];
+    if (S.precision == PBCG_FP64) upload_vals<double>(S, S.A.dia, padded);
+    else upload_vals<float>(S, S.A.dia, padded);
+    if (S.precond) {
+      std::vector<double> di(S.npad, 0.0);
+      for (int64_t i = 0; i < S.n; ++i) {
+        const double c = host[2 * S.n + i];
+        if (S.precision == PBCG_FP64) {
+          if (c == 0.0) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
+          di[i] = 1.0 / c;
+        } else {
+          if ((float)c == 0.0f) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
+          di[i] = (double)(1.0f / (float)c);
+        }
+      }
+      if (S.precision == PBCG_FP64) upload_vals<double>(S, S.dinv, di);
+      else upload_vals<float>(S, S.dinv, di);
+    }
+    S.h_dia = host;
+    if (S.have_AT) {
+      launch_dia5_transpose(S, S.s1);
+      hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+    }
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_dia5_assemble_kappa(pbcg_handle h, const double* kappa, double cx, double cy,
+                                  double hgrid, void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (S.kind != OP_DIA5) fail(PBCG_ERR_UNSUPPORTED, "not a DIA5 handle");
+    if (!kappa) fail(PBCG_ERR_INVALID_ARG, "null kappa");
+    if (S.precond && !S.dinv) fail(PBCG_ERR_INVALID_ARG, "no Jacobi diagonal");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    hipck(hipMemsetAsync(&S.sc->bad_diag, 0, sizeof(int32_t), S.s1), "hipMemsetAsync");
+    void* keep = S.dinv;
+    if (!S.precond) S.dinv = S.vec[V_TMP];  // assembled diagonal goes to scratch, unused
+    launch_kappa_assemble(S, kappa, cx, cy, hgrid, S.s1);
+    S.dinv = keep;
+    hipck(hipGetLastError(), "assemble launch");
+    int32_t bad = 0;
+    hipck(hipMemcpyAsync(&bad, &S.sc->bad_diag, 4, hipMemcpyDeviceToHost, S.s1), "hipMemcpyAsync");
+    hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+    if (bad && S.precond) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after assembly");
+    hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+    hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_dia5_kappa_grad(pbcg_handle h, const double* lambda, const double* x,
+                              double* grad_kappa, void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (S.kind != OP_DIA5) fail(PBCG_ERR_UNSUPPORTED, "not a DIA5 handle");
+    if (!lambda || !x || !grad_kappa) fail(PBCG_ERR_INVALID_ARG, "null vector");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    launch_kappa_grad(S, lambda, x, grad_kappa, S.s1);
+    hipck(hipGetLastError(), "kappa grad launch");
+    hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+    hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (!out) fail(PBCG_ERR_INVALID_ARG, "null output");
+    if (which < 0 || which > 11) fail(PBCG_ERR_INVALID_ARG, "unknown vector id");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    if (which <= 9) {
+      launch_to_double(S, S.vec[which], out, S.n, S.s1);
+    } else if (which == 10) {
+      hipck(hipMemcpyAsync(out, S.x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+    } else {
+      if (S.pc == PC_VECTOR) {
+        launch_to_double(S, S.dinv, out, S.n, S.s1);
+      } else {
+        std::vector<double> v(S.n, S.pc == PC_SCALAR ? S.dinv_s : 1.0);
+        hipck(hipMemcpyAsync(out, v.data(), S.n * 8, hipMemcpyHostToDevice, S.s1), "hipMemcpyAsync");
+        hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+      }
+    }
+    hipck(hipGetLastError(), "get_vector launch");
+    hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+    hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, void* stream) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (kernel < 0 || kernel > 4 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    // a state in which every kernel does its full work: scalars of a running
+    // iteration with a large tolerance-free budget
+    pbcg_opts o = defaults();
+    o.tol = 0.0;
+    o.maxit = 1 << 30;
+    S.h_sc[2] = initial_scalars(o);
+    S.h_sc[2].alpha = 0.5;
+    S.h_sc[2].beta = 0.5;
+    S.h_sc[2].omega = 0.5;
+    S.h_sc[2].omega_prev = 0.5;
+    S.h_sc[2].rho = 1.0;
+    S.h_sc[2].nb = 1.0;
+    hipck(hipMemcpyAsync(S.sc, &S.h_sc[2], sizeof(DevScalars), hipMemcpyHostToDevice, S.s1),
+          "hipMemcpyAsync");
+    auto one = [&](int kk) {
+      switch (kk) {
+        case 0: launch_phaseA(S, S.s1); break;
+        case 1: launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, S.s1); break;
+        case 2: launch_phaseB(S, S.s1); break;
+        case 3: launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_NONE, false, S.s1); break;
+      }
+    };
+    auto launch = [&]() {
+      if (kernel == 4) for (int kk = 0; kk < 4; ++kk) one(kk);
+      else one(kernel);
+    };
+    launch();  // warm-up
+    hipck(hipEventRecord(S.ev_t0, S.s1), "hipEventRecord");
+    for (int r = 0; r < reps; ++r) launch();
+    hipck(hipEventRecord(S.ev_t1, S.s1), "hipEventRecord");
+    hipck(hipGetLastError(), "timing launch");
+    hipck(hipEventSynchronize(S.ev_t1), "hipEventSynchronize");
+    float ms = 0.0f;
+    hipck(hipEventElapsedTime(&ms, S.ev_t0, S.ev_t1), "hipEventElapsedTime");
+    *avg_ms = (double)ms / reps;
+    hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
+    hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
+    return PBCG_OK;
+  });
+}
+
+int pbicgstab_info(pbcg_handle h, int64_t* n, int64_t* nnz, int64_t* device_bytes) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    if (n) *n = S.n;
+    if (nnz) *nnz = S.nnz;
+    if (device_bytes) {
+      int64_t b = 0;
+      b += V_COUNT * S.npad * (int64_t)S.tsize + 2 * S.npad * 8;
+      if (S.dinv) b += S.npad * S.tsize;
+      auto opb = [&](const OpData& o) {
+        int64_t r = 0;
+        if (o.kind == OP_SELL) r += (o.nslices + 1) * 8 + o.sell_elems * (4 + (int64_t)S.tsize);
+        if (o.kind == OP_DIA5 && o.dia) r += 5 * S.npad * (int64_t)S.tsize;
+        return r;
+      };
+      b += opb(S.A);
+      if (S.have_AT && S.AT.kind != OP_ST2D5 && S.AT.kind != OP_ST3D7) b += opb(S.AT);
+      *device_bytes = b;
+    }
+    return PBCG_OK;
+  });
+}
+
+void pbicgstab_destroy(pbcg_handle h) { destroy_solver(h); }
+
+const char* pbicgstab_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,743 @@
+// Operator kernels of pipelined BiCGStab.
+//
+// Every kernel walks rows in tiles of 256 with the XCD-aware mapping of
+// XcdWalk and applies the operator through a row visitor (ops.hpp).
+//
+// The SPMV kernel carries the global-reduction "final" as its block 0: the
+// GLRED of Algorithm 2 is reduced and turned into omega_i (or beta_{i+1},
+// alpha_{i+1}) by that one block while the other blocks compute the SPMV that
+// the reduction is meant to hide behind (the PREC + SPMV between
+// "begin global reduction" and "end reduction").  Block 0 is dispatched first,
+// so the reduction overlaps the whole product.
+
+#include "solver.hpp"
+
+namespace pbcg {
+
+// ----------------------------------------------------------------------------
+// visitors
+// ----------------------------------------------------------------------------
+
+template <typename T, int PC>
+__device__ __forceinline__ T prec1(T zj, const T* __restrict__ dinv, T ds, int64_t j) {
+  if (PC == PC_NONE) return zj;
+  if (PC == PC_SCALAR) return ds * zj;
+  return dinv[j] * zj;
+}
+
+// sum_j a_ij (M^-1 z)_j in the storage precision
+template <typename T, int PC>
+struct SpmvVis {
+  const T* __restrict__ z;
+  const T* __restrict__ dinv;
+  T ds;
+  T sum;
+  __device__ __forceinline__ void operator()(T a, int64_t j) {
+    sum += a * prec1<T, PC>(z[j], dinv, ds, j);
+  }
+};
+
+// sum_j a_ij x_j in FP64 (x FP64)
+template <typename T>
+struct ResVis {
+  const double* __restrict__ x;
+  double sum;
+  __device__ __forceinline__ void operator()(T a, int64_t j) { sum += (double)a * x[j]; }
+};
+
+// two FP64 products sharing the matrix loads: sum a_ij x_j and sum a_ij y_j
+template <typename T, typename X, typename Y>
+struct Res2Vis {
+  const X* __restrict__ x;
+  const Y* __restrict__ y;
+  double sx, sy;
+  __device__ __forceinline__ void operator()(T a, int64_t j) {
+    const double ad = (double)a;
+    sx += ad * (double)x[j];
+    sy += ad * (double)y[j];
+  }
+};
+
+// classic method: y_i = sum_j a_ij M^-1 (r_j - alpha s_j)
+template <typename T, int PC>
+struct QVis {
+  const T* __restrict__ r;
+  const T* __restrict__ s;
+  const T* __restrict__ dinv;
+  T ds, a;
+  T sum;
+  __device__ __forceinline__ void operator()(T c, int64_t j) {
+    const T q = r[j] - a * s[j];
+    sum += c * prec1<T, PC>(q, dinv, ds, j);
+  }
+};
+
+// ----------------------------------------------------------------------------
+// kernels
+// ----------------------------------------------------------------------------
+
+// out = A (M^-1 in); optional partial (r0, out); block 0 runs `fin_mode`.
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in, T* __restrict__ out,
+                                                 const T* __restrict__ dinv, T ds,
+                                                 const T* __restrict__ rhat, int64_t n, int64_t ntiles,
+                                                 int nwork, DevScalars* __restrict__ sc,
+                                                 double* __restrict__ partials, int fin_mode,
+                                                 int dot_rhat) {
+  if (blockIdx.x == 0) {
+    if (fin_mode != FIN_NONE && (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done))
+      run_final(fin_mode, sc, partials, nwork, 0);
+    return;
+  }
+  if (sc->done) return;
+  const int blk = blockIdx.x - 1;
+  double acc[1] = {0.0};
+  for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      SpmvVis<T, PC> vis{in, dinv, ds, T(0)};
+      op.row(i, vis);
+      out[i] = vis.sum;
+      if (dot_rhat) acc[0] += (double)rhat[i] * (double)vis.sum;
+    }
+  }
+  if (dot_rhat) {
+    const int slots[1] = {SL_RW0};
+    block_partials<1>(acc, slots, partials, blk);
+  }
+}
+
+// Algorithm 2 initialisation, first part: r_0 = b - A x_0 (FP64), r0 := r_0,
+// k_0 = M^-1 r_0, the iteration -1 vectors g, s, l, z, v set to zero, and the
+// partials (r0, r_0), (r_0, r_0), (b, b).
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_init_res(Op op, const double* __restrict__ x,
+                                                     const double* __restrict__ b, T* __restrict__ r,
+                                                     T* __restrict__ rhat, T* __restrict__ k,
+                                                     T* __restrict__ g, T* __restrict__ s,
+                                                     T* __restrict__ l, T* __restrict__ z,
+                                                     T* __restrict__ v, const T* __restrict__ dinv,
+                                                     T ds, int64_t n, int64_t ntiles, int nwork,
+                                                     double* __restrict__ partials) {
+  const int blk = blockIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      ResVis<T> vis{x, 0.0};
+      op.row(i, vis);
+      const T ri = (T)(b[i] - vis.sum);
+      r[i] = ri;
+      rhat[i] = ri;
+      k[i] = prec1<T, PC>(ri, dinv, ds, i);
+      g[i] = T(0); s[i] = T(0); l[i] = T(0); z[i] = T(0); v[i] = T(0);
+      acc[0] += (double)ri * (double)ri;
+      acc[1] += (double)ri * (double)ri;
+      acc[2] += b[i] * b[i];
+    }
+  }
+  const int slots[3] = {SL_RR0, SL_RR, SL_BB};
+  block_partials<3>(acc, slots, partials, blk);
+}
+
+__device__ __forceinline__ bool rr_due(const DevScalars* __restrict__ sc) {
+  if (sc->done) return false;
+  const int P = sc->rr_period;
+  if (P <= 0 || ((sc->iter + 1) % P) != 0) return false;
+  return sc->rn >= sc->tau * sc->rn0;
+}
+
+// Residual replacement (eq:rr), first half: r = b - A x_{i+1}, k = M^-1 r,
+// s = A g_i, l = M^-1 s.  FP64 products; stored results rounded to T.
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict__ x,
+                                                const T* __restrict__ g, const double* __restrict__ b,
+                                                T* __restrict__ r, T* __restrict__ k, T* __restrict__ s,
+                                                T* __restrict__ l, const T* __restrict__ dinv, T ds,
+                                                int64_t n, int64_t ntiles, int nwork,
+                                                DevScalars* __restrict__ sc, int force) {
+  if (!force && !rr_due(sc)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->rr_count += 1;
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      Res2Vis<T, double, T> vis{x, g, 0.0, 0.0};
+      op.row(i, vis);
+      const T ri = (T)(b[i] - vis.sx);
+      const T si = (T)vis.sy;
+      r[i] = ri;
+      k[i] = prec1<T, PC>(ri, dinv, ds, i);
+      s[i] = si;
+      l[i] = prec1<T, PC>(si, dinv, ds, i);
+    }
+  }
+}
+
+// Residual replacement, second half: w = A k, z = A l (FP64 products), and
+// the GLRED 2 partials recomputed from the replaced vectors.  The explicitly
+// computed n_i = M^-1 z_i of this iteration is not replaced (only the six
+// quantities of eq:rr are), and v_i = A n_i keeps its value; so the
+// pre-replacement z_i is kept in `zsave` for the next phase A, which forms
+// n_i from it.
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, const T* __restrict__ l,
+                                                T* __restrict__ w, T* __restrict__ z,
+                                                T* __restrict__ zsave,
+                                                const T* __restrict__ rhat, const T* __restrict__ r,
+                                                const T* __restrict__ s, int64_t n, int64_t ntiles,
+                                                int nwork, DevScalars* __restrict__ sc,
+                                                double* __restrict__ partials, int force) {
+  if (!force && !rr_due(sc)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->n_saved = 1;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (XcdWalk wk(ntiles, blockIdx.x, nwork); wk.t < wk.end; wk.t += wk.step) {
+    const int64_t i = wk.t * kBlock + threadIdx.x;
+    if (i < n) {
+      Res2Vis<T, T, T> vis{k, l, 0.0, 0.0};
+      op.row(i, vis);
+      const T wi = (T)vis.sx;
+      const T zi = (T)vis.sy;
+      zsave[i] = z[i];
+      w[i] = wi;
+      z[i] = zi;
+      const double rh = (double)rhat[i], ri = (double)r[i];
+      acc[0] += rh * ri;
+      acc[1] += rh * (double)wi;
+      acc[2] += rh * (double)s[i];
+      acc[3] += rh * (double)zi;
+      acc[4] += ri * ri;
+    }
+  }
+  const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+  block_partials<5>(acc, slots, partials, blockIdx.x);
+}
+
+// partial of ||b - A x||^2 (FP64)
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_true_res(Op op, const double* __restrict__ x,
+                                                     const double* __restrict__ b, int64_t n,
+                                                     int64_t ntiles, int nwork,
+                                                     double* __restrict__ partials) {
+  double acc[1] = {0.0};
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      ResVis<T> vis{x, 0.0};
+      op.row(i, vis);
+      const double ri = b[i] - vis.sum;
+      acc[0] += ri * ri;
+    }
+  }
+  const int slots[1] = {SL_RR};
+  block_partials<1>(acc, slots, partials, blockIdx.x);
+}
+
+// partial of ||(b - A x) - r||^2, the residual gap of eq:res_gap
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_gap(Op op, const double* __restrict__ x,
+                                                const double* __restrict__ b, const T* __restrict__ r,
+                                                int64_t n, int64_t ntiles, int nwork,
+                                                DevScalars* __restrict__ sc,
+                                                double* __restrict__ partials) {
+  if (sc->done) return;
+  double acc[1] = {0.0};
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      ResVis<T> vis{x, 0.0};
+      op.row(i, vis);
+      const double gi = (b[i] - vis.sum) - (double)r[i];
+      acc[0] += gi * gi;
+    }
+  }
+  const int slots[1] = {SL_RR};
+  block_partials<1>(acc, slots, partials, blockIdx.x);
+}
+
+// Algorithm 1 initialisation: r_0 = b - A x_0, r0 := r_0, p_0 := r_0
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_cl_init(Op op, const double* __restrict__ x,
+                                                    const double* __restrict__ b, T* __restrict__ r,
+                                                    T* __restrict__ rhat, T* __restrict__ p, int64_t n,
+                                                    int64_t ntiles, int nwork,
+                                                    double* __restrict__ partials) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      ResVis<T> vis{x, 0.0};
+      op.row(i, vis);
+      const T ri = (T)(b[i] - vis.sum);
+      r[i] = ri; rhat[i] = ri; p[i] = ri;
+      acc[0] += (double)ri * (double)ri;
+      acc[1] += (double)ri * (double)ri;
+      acc[2] += b[i] * b[i];
+    }
+  }
+  const int slots[3] = {SL_RR0, SL_RR, SL_BB};
+  block_partials<3>(acc, slots, partials, blockIdx.x);
+}
+
+// Algorithm 1: s_i = A M^-1 p_i and the partial (r0, s_i)
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_cl_spmv_s(Op op, const T* __restrict__ p, T* __restrict__ s,
+                                                      const T* __restrict__ rhat,
+                                                      const T* __restrict__ dinv, T ds, int64_t n,
+                                                      int64_t ntiles, int nwork,
+                                                      const DevScalars* __restrict__ sc,
+                                                      double* __restrict__ partials) {
+  if (sc->done) return;
+  double acc[1] = {0.0};
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      SpmvVis<T, PC> vis{p, dinv, ds, T(0)};
+      op.row(i, vis);
+      s[i] = vis.sum;
+      acc[0] += (double)rhat[i] * (double)vis.sum;
+    }
+  }
+  const int slots[1] = {SL_RS0};
+  block_partials<1>(acc, slots, partials, blockIdx.x);
+}
+
+// Algorithm 1: y_i = A M^-1 q_i with q = r - alpha s formed on the fly, and
+// the partials (q_i, y_i), (y_i, y_i)
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_cl_spmv_y(Op op, const T* __restrict__ r,
+                                                      const T* __restrict__ s, T* __restrict__ y,
+                                                      const T* __restrict__ dinv, T ds, int64_t n,
+                                                      int64_t ntiles, int nwork,
+                                                      const DevScalars* __restrict__ sc,
+                                                      double* __restrict__ partials) {
+  if (sc->done) return;
+  const T a = (T)sc->alpha;
+  double acc[2] = {0.0, 0.0};
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      QVis<T, PC> vis{r, s, dinv, ds, a, T(0)};
+      op.row(i, vis);
+      y[i] = vis.sum;
+      const T qi = r[i] - a * s[i];
+      acc[0] += (double)qi * (double)vis.sum;
+      acc[1] += (double)vis.sum * (double)vis.sum;
+    }
+  }
+  const int slots[2] = {SL_QY, SL_YY};
+  block_partials<2>(acc, slots, partials, blockIdx.x);
+}
+
+// y = A x with FP64 accumulation (user buffers of length n)
+template <typename T, class Op>
+__global__ __launch_bounds__(kBlock) void k_apply(Op op, const double* __restrict__ x,
+                                                  double* __restrict__ y, int64_t n, int64_t ntiles,
+                                                  int nwork) {
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      ResVis<T> vis{x, 0.0};
+      op.row(i, vis);
+      y[i] = vis.sum;
+    }
+  }
+}
+
+// dL/da_ij = -lambda_i x_j on the CSR pattern (stored order)
+__global__ __launch_bounds__(kBlock) void k_grad_csr(const int32_t* __restrict__ rowptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const double* __restrict__ lam,
+                                                     const double* __restrict__ x,
+                                                     double* __restrict__ grad, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double li = lam[i];
+    for (int32_t kk = rowptr[i]; kk < rowptr[i + 1]; ++kk) grad[kk] = -li * x[col[kk]];
+  }
+}
+
+// DIA5 pattern: grad[d * n + p] = -lambda_p x_{p + off_d} (0 where the entry does not exist)
+__global__ __launch_bounds__(kBlock) void k_grad_dia5(int nx, int ny, const double* __restrict__ lam,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ grad, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const int p = (int)i;
+    const int iy = p / nx, ix = p - iy * nx;
+    const double li = -lam[i];
+    grad[i] = iy > 0 ? li * x[p - nx] : 0.0;
+    grad[n + i] = ix > 0 ? li * x[p - 1] : 0.0;
+    grad[2 * n + i] = li * x[p];
+    grad[3 * n + i] = ix < nx - 1 ? li * x[p + 1] : 0.0;
+    grad[4 * n + i] = iy < ny - 1 ? li * x[p + nx] : 0.0;
+  }
+}
+
+// constant stencil: dL/dc_d = sum_p -lambda_p x_{p + off_d} over existing entries
+struct GradStVis {
+  const double* __restrict__ x;
+  double lam;
+  double acc[7];
+  int d;
+  __device__ __forceinline__ void operator()(double, int64_t j) { acc[d++] += -lam * x[j]; }
+};
+
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_grad_st(int nx, int ny, int nz,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ x, int64_t n,
+                                                    int64_t ntiles, int nwork,
+                                                    double* __restrict__ partials) {
+  constexpr int ND = KIND == OP_ST2D5 ? 5 : 7;
+  double acc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) acc[d] = 0.0;
+  for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t i = w.t * kBlock + threadIdx.x;
+    if (i < n) {
+      const int p = (int)i;
+      const double li = -lam[i];
+      if (KIND == OP_ST2D5) {
+        const int iy = p / nx, ix = p - iy * nx;
+        if (iy > 0) acc[0] += li * x[p - nx];
+        if (ix > 0) acc[1] += li * x[p - 1];
+        acc[2] += li * x[p];
+        if (ix < nx - 1) acc[3] += li * x[p + 1];
+        if (iy < ny - 1) acc[4] += li * x[p + nx];
+      } else {
+        const int nxy = nx * ny;
+        const int iz = p / nxy, rem = p - iz * nxy, iy = rem / nx, ix = rem - iy * nx;
+        if (iz > 0) acc[0] += li * x[p - nxy];
+        if (iy > 0) acc[1] += li * x[p - nx];
+        if (ix > 0) acc[2] += li * x[p - 1];
+        acc[3] += li * x[p];
+        if (ix < nx - 1) acc[4] += li * x[p + 1];
+        if (iy < ny - 1) acc[5] += li * x[p + nx];
+        if (iz < nz - 1) acc[6] += li * x[p + nxy];
+      }
+    }
+  }
+  int slots[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) slots[d] = d;
+  block_partials<ND>(acc, slots, partials, blockIdx.x);
+}
+
+// value update of a SELL operator from CSR-ordered values, and Jacobi diagonal
+template <typename T>
+__global__ void k_update_sell(const double* __restrict__ val, int64_t nnz,
+                              const int64_t* __restrict__ pos, T* __restrict__ sv) {
+  for (int64_t kk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; kk < nnz;
+       kk += (int64_t)gridDim.x * blockDim.x)
+    sv[pos[kk]] = (T)val[kk];
+}
+
+template <typename T>
+__global__ void k_update_dinv(const double* __restrict__ val, const int64_t* __restrict__ diagpos,
+                              T* __restrict__ dinv, int64_t n, int32_t* __restrict__ bad) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t dp = diagpos[i];
+    const T d = dp >= 0 ? (T)val[dp] : T(0);
+    if (d == T(0)) {
+      *bad = 1;
+      dinv[i] = T(0);
+    } else {
+      dinv[i] = T(1) / d;
+    }
+  }
+}
+
+// DIA5 coefficients of -div(kappa grad u) + (cx, cy).grad u (h^2-scaled),
+// face value = mean of the two node values, own value on a boundary face;
+// also the transposed DIA5 and the Jacobi diagonal.
+template <typename T>
+__global__ void k_kappa_assemble(const double* __restrict__ kap, int nx, int ny, double cx,
+                                 double cy, double h, T* __restrict__ dia, T* __restrict__ diaT,
+                                 int64_t ld, T* __restrict__ dinv, int32_t* __restrict__ bad) {
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)i;
+    const int iy = p / nx, ix = p - iy * nx;
+    const double kp = kap[p];
+    const double ke = ix < nx - 1 ? 0.5 * (kp + kap[p + 1]) : kp;
+    const double kw = ix > 0 ? 0.5 * (kp + kap[p - 1]) : kp;
+    const double kn = iy < ny - 1 ? 0.5 * (kp + kap[p + nx]) : kp;
+    const double ks = iy > 0 ? 0.5 * (kp + kap[p - nx]) : kp;
+    const double C = ((ke + kw) + kn) + ks;
+    const double E = ix < nx - 1 ? -ke + cx * h / 2.0 : 0.0;
+    const double W = ix > 0 ? -kw - cx * h / 2.0 : 0.0;
+    const double N = iy < ny - 1 ? -kn + cy * h / 2.0 : 0.0;
+    const double S = iy > 0 ? -ks - cy * h / 2.0 : 0.0;
+    dia[i] = (T)S; dia[ld + i] = (T)W; dia[2 * ld + i] = (T)C; dia[3 * ld + i] = (T)E;
+    dia[4 * ld + i] = (T)N;
+    const T Ct = (T)C;
+    if (Ct == T(0)) { *bad = 1; dinv[i] = T(0); } else { dinv[i] = T(1) / Ct; }
+  }
+  (void)diaT;
+}
+
+// transposed DIA5: A^T(p, p-nx) = A(p-nx, p) = N of row p-nx, etc.
+template <typename T>
+__global__ void k_dia5_transpose(const T* __restrict__ dia, T* __restrict__ diaT, int nx, int ny,
+                                 int64_t ld) {
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)i;
+    const int iy = p / nx, ix = p - iy * nx;
+    diaT[i] = iy > 0 ? dia[4 * ld + (p - nx)] : T(0);
+    diaT[ld + i] = ix > 0 ? dia[3 * ld + (p - 1)] : T(0);
+    diaT[2 * ld + i] = dia[2 * ld + i];
+    diaT[3 * ld + i] = ix < nx - 1 ? dia[ld + (p + 1)] : T(0);
+    diaT[4 * ld + i] = iy < ny - 1 ? dia[(p + nx)] : T(0);
+  }
+}
+
+// dL/dkappa from the face gradients -(lam_p - lam_q)(x_p - x_q) (interior
+// faces, half to each node) and -lam_p x_p (boundary faces)
+__global__ void k_kappa_grad(const double* __restrict__ lam, const double* __restrict__ x, int nx,
+                             int ny, double* __restrict__ gk) {
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)i;
+    const int iy = p / nx, ix = p - iy * nx;
+    const double lp = lam[p], xp = x[p];
+    double g = 0.0;
+    if (ix < nx - 1) g += 0.5 * (-(lp - lam[p + 1]) * (xp - x[p + 1]));
+    if (ix > 0) g += 0.5 * (-(lam[p - 1] - lp) * (x[p - 1] - xp));
+    if (iy < ny - 1) g += 0.5 * (-(lp - lam[p + nx]) * (xp - x[p + nx]));
+    if (iy > 0) g += 0.5 * (-(lam[p - nx] - lp) * (x[p - nx] - xp));
+    const double own = -lp * xp;
+    if (ix == 0) g += own;
+    if (ix == nx - 1) g += own;
+    if (iy == 0) g += own;
+    if (iy == ny - 1) g += own;
+    gk[i] = g;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// dispatch
+// ----------------------------------------------------------------------------
+
+const OpData& op_of(Solver& S, bool transpose) { return transpose ? S.AT : S.A; }
+
+template <typename T, class F>
+static void with_op_t(Solver& S, const OpData& o, bool use_pc, F& f) {
+  switch (o.kind) {
+    case OP_SELL: {
+      SellOp<T> op{o.sptr, o.col, (const T*)o.val};
+      if (use_pc && S.pc == PC_VECTOR) f.template operator()<T, PC_VECTOR>(op);
+      else f.template operator()<T, PC_NONE>(op);
+      break;
+    }
+    case OP_ST2D5: {
+      St2d5Op<T> op;
+      op.nx = o.dims[0]; op.ny = o.dims[1];
+      for (int d = 0; d < 5; ++d) op.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
+      if (use_pc && S.pc == PC_SCALAR) f.template operator()<T, PC_SCALAR>(op);
+      else f.template operator()<T, PC_NONE>(op);
+      break;
+    }
+    case OP_ST3D7: {
+      St3d7Op<T> op;
+      op.nx = o.dims[0]; op.ny = o.dims[1]; op.nz = o.dims[2];
+      for (int d = 0; d < 7; ++d) op.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
+      if (use_pc && S.pc == PC_SCALAR) f.template operator()<T, PC_SCALAR>(op);
+      else f.template operator()<T, PC_NONE>(op);
+      break;
+    }
+    case OP_DIA5: {
+      Dia5Op<T> op;
+      op.nx = o.dims[0]; op.ny = o.dims[1]; op.ld = S.npad; op.dia = (const T*)o.dia;
+      if (use_pc && S.pc == PC_VECTOR) f.template operator()<T, PC_VECTOR>(op);
+      else f.template operator()<T, PC_NONE>(op);
+      break;
+    }
+  }
+}
+
+template <class F>
+static void with_op(Solver& S, bool tr, bool use_pc, F&& f) {
+  const OpData& o = op_of(S, tr);
+  if (S.precision == 0) with_op_t<double>(S, o, use_pc, f);
+  else with_op_t<float>(S, o, use_pc, f);
+}
+
+#define PBCG_GRID_OP dim3(S.nblk), dim3(kBlock), 0, st
+
+void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
+                 hipStream_t st) {
+  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(S.nblk + 1), dim3(kBlock), 0, st, op,
+                       (const T*)in, (T*)out, (const T*)S.dinv, (T)S.dinv_s,
+                       (const T*)S.vec[V_RHAT], S.n, S.rtiles, S.nblk, S.sc, S.partials, fin_mode,
+                       dot_rhat ? 1 : 0);
+  });
+}
+
+void launch_init_res(Solver& S, bool tr, hipStream_t st) {
+  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_init_res<T, PC, Op>), PBCG_GRID_OP, op, (const double*)S.x,
+                       (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_RHAT], (T*)S.vec[V_K],
+                       (T*)S.vec[V_G], (T*)S.vec[V_S], (T*)S.vec[V_L], (T*)S.vec[V_Z],
+                       (T*)S.vec[V_V], (const T*)S.dinv, (T)S.dinv_s, S.n, S.rtiles, S.nblk,
+                       S.partials);
+  });
+}
+
+void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st) {
+  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_rr1<T, PC, Op>), PBCG_GRID_OP, op, (const double*)S.x,
+                       (const T*)S.vec[V_G], (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_K],
+                       (T*)S.vec[V_S], (T*)S.vec[V_L], (const T*)S.dinv, (T)S.dinv_s, S.n,
+                       S.rtiles, S.nblk, S.sc, force ? 1 : 0);
+  });
+}
+
+void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st) {
+  with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_rr2<T, PC, Op>), PBCG_GRID_OP, op, (const T*)S.vec[V_K],
+                       (const T*)S.vec[V_L], (T*)S.vec[V_W], (T*)S.vec[V_Z], (T*)S.vec[V_TMP],
+                       (const T*)S.vec[V_RHAT], (const T*)S.vec[V_R], (const T*)S.vec[V_S], S.n,
+                       S.rtiles, S.nblk, S.sc, S.partials, force ? 1 : 0);
+  });
+}
+
+void launch_true_res(Solver& S, bool tr, hipStream_t st) {
+  with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_true_res<T, Op>), PBCG_GRID_OP, op, (const double*)S.x,
+                       (const double*)S.b, S.n, S.rtiles, S.nblk, S.partials);
+  });
+}
+
+void launch_gap(Solver& S, bool tr, hipStream_t st) {
+  with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_gap<T, Op>), PBCG_GRID_OP, op, (const double*)S.x, (const double*)S.b,
+                       (const T*)S.vec[V_R], S.n, S.rtiles, S.nblk, S.sc, S.partials);
+  });
+}
+
+void launch_cl_init(Solver& S, bool tr, hipStream_t st) {
+  with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_cl_init<T, Op>), PBCG_GRID_OP, op, (const double*)S.x,
+                       (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_RHAT], (T*)S.vec[V_G], S.n,
+                       S.rtiles, S.nblk, S.partials);
+  });
+}
+
+void launch_cl_spmv_s(Solver& S, bool tr, hipStream_t st) {
+  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_cl_spmv_s<T, PC, Op>), PBCG_GRID_OP, op, (const T*)S.vec[V_G],
+                       (T*)S.vec[V_S], (const T*)S.vec[V_RHAT], (const T*)S.dinv, (T)S.dinv_s,
+                       S.n, S.rtiles, S.nblk, S.sc, S.partials);
+  });
+}
+
+void launch_cl_spmv_y(Solver& S, bool tr, hipStream_t st) {
+  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_cl_spmv_y<T, PC, Op>), PBCG_GRID_OP, op, (const T*)S.vec[V_R],
+                       (const T*)S.vec[V_S], (T*)S.vec[V_V], (const T*)S.dinv, (T)S.dinv_s, S.n,
+                       S.rtiles, S.nblk, S.sc, S.partials);
+  });
+}
+
+void launch_apply(Solver& S, bool tr, const double* x, double* y, hipStream_t st) {
+  with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_apply<T, Op>), PBCG_GRID_OP, op, x, y, S.n, S.rtiles, S.nblk);
+  });
+}
+
+static int grid_for(int64_t count) {
+  int64_t b = (count + kBlock - 1) / kBlock;
+  if (b > 8192) b = 8192;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+void launch_grad(Solver& S, const double* lam, const double* x, double* grad, hipStream_t st) {
+  switch (S.kind) {
+    case OP_SELL:
+      hipLaunchKernelGGL(k_grad_csr, dim3(grid_for(S.n)), dim3(kBlock), 0, st, S.d_rowptr,
+                         S.d_col, lam, x, grad, S.n);
+      break;
+    case OP_DIA5:
+      hipLaunchKernelGGL(k_grad_dia5, dim3(grid_for(S.n)), dim3(kBlock), 0, st, S.A.dims[0],
+                         S.A.dims[1], lam, x, grad, S.n);
+      break;
+    case OP_ST2D5:
+      hipLaunchKernelGGL(k_grad_st<OP_ST2D5>, PBCG_GRID_OP, S.A.dims[0], S.A.dims[1], 1, lam, x,
+                         S.n, S.rtiles, S.nblk, S.partials);
+      break;
+    case OP_ST3D7:
+      hipLaunchKernelGGL(k_grad_st<OP_ST3D7>, PBCG_GRID_OP, S.A.dims[0], S.A.dims[1], S.A.dims[2],
+                         lam, x, S.n, S.rtiles, S.nblk, S.partials);
+      break;
+  }
+}
+
+void launch_update_sell(Solver& S, const double* val_dev, hipStream_t st) {
+  int32_t* bad = &S.sc->bad_diag;
+  if (S.precision == 0) {
+    hipLaunchKernelGGL(k_update_sell<double>, dim3(grid_for(S.nnz)), dim3(kBlock), 0, st, val_dev,
+                       S.nnz, S.d_posA, (double*)S.A.val);
+    if (S.have_AT)
+      hipLaunchKernelGGL(k_update_sell<double>, dim3(grid_for(S.nnz)), dim3(kBlock), 0, st,
+                         val_dev, S.nnz, S.d_posAT, (double*)S.AT.val);
+    if (S.precond)
+      hipLaunchKernelGGL(k_update_dinv<double>, dim3(grid_for(S.n)), dim3(kBlock), 0, st, val_dev,
+                         S.d_diagpos, (double*)S.dinv, S.n, bad);
+  } else {
+    hipLaunchKernelGGL(k_update_sell<float>, dim3(grid_for(S.nnz)), dim3(kBlock), 0, st, val_dev,
+                       S.nnz, S.d_posA, (float*)S.A.val);
+    if (S.have_AT)
+      hipLaunchKernelGGL(k_update_sell<float>, dim3(grid_for(S.nnz)), dim3(kBlock), 0, st,
+                         val_dev, S.nnz, S.d_posAT, (float*)S.AT.val);
+    if (S.precond)
+      hipLaunchKernelGGL(k_update_dinv<float>, dim3(grid_for(S.n)), dim3(kBlock), 0, st, val_dev,
+                         S.d_diagpos, (float*)S.dinv, S.n, bad);
+  }
+}
+
+void launch_kappa_assemble(Solver& S, const double* kappa, double cx, double cy, double h,
+                           hipStream_t st) {
+  int32_t* bad = &S.sc->bad_diag;
+  const int nx = S.A.dims[0], ny = S.A.dims[1];
+  if (S.precision == 0) {
+    hipLaunchKernelGGL(k_kappa_assemble<double>, dim3(grid_for(S.n)), dim3(kBlock), 0, st, kappa,
+                       nx, ny, cx, cy, h, (double*)S.A.dia, (double*)nullptr, S.npad,
+                       (double*)S.dinv, bad);
+    if (S.have_AT)
+      hipLaunchKernelGGL(k_dia5_transpose<double>, dim3(grid_for(S.n)), dim3(kBlock), 0, st,
+                         (const double*)S.A.dia, (double*)S.AT.dia, nx, ny, S.npad);
+  } else {
+    hipLaunchKernelGGL(k_kappa_assemble<float>, dim3(grid_for(S.n)), dim3(kBlock), 0, st, kappa,
+                       nx, ny, cx, cy, h, (float*)S.A.dia, (float*)nullptr, S.npad,
+                       (float*)S.dinv, bad);
+    if (S.have_AT)
+      hipLaunchKernelGGL(k_dia5_transpose<float>, dim3(grid_for(S.n)), dim3(kBlock), 0, st,
+                         (const float*)S.A.dia, (float*)S.AT.dia, nx, ny, S.npad);
+  }
+}
+
+void launch_kappa_grad(Solver& S, const double* lam, const double* x, double* gk,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_kappa_grad, dim3(grid_for(S.n)), dim3(kBlock), 0, st, lam, x, S.A.dims[0],
+                     S.A.dims[1], gk);
+}
+
+// transpose of a DIA5 operator, used by the engine when the transpose is built
+void launch_dia5_transpose(Solver& S, hipStream_t st) {
+  const int nx = S.A.dims[0], ny = S.A.dims[1];
+  if (S.precision == 0)
+    hipLaunchKernelGGL(k_dia5_transpose<double>, dim3(grid_for(S.n)), dim3(kBlock), 0, st,
+                       (const double*)S.A.dia, (double*)S.AT.dia, nx, ny, S.npad);
+  else
+    hipLaunchKernelGGL(k_dia5_transpose<float>, dim3(grid_for(S.n)), dim3(kBlock), 0, st,
+                       (const float*)S.A.dia, (float*)S.AT.dia, nx, ny, S.npad);
+}
+
+}  // namespace pbcg

@@ -1,0 +1,369 @@
+// Streaming kernels of pipelined BiCGStab: the two fused multi-AXPY passes
+// (with their dot-product partials), the classic method's vector updates,
+// and the one-block final reduction kernel.
+//
+// Each thread owns one 16-byte chunk (2 doubles or 4 floats) per tile, so a
+// wave moves 1 KiB per vector per tile with fully coalesced dwordx4 accesses.
+// Vectors are zero-padded to whole tiles: no bounds checks.
+
+#include "solver.hpp"
+
+namespace pbcg {
+
+template <typename T>
+struct PhaseAArgs {
+  const T* __restrict__ k;
+  const T* __restrict__ w;
+  const T* __restrict__ t;
+  const T* __restrict__ r;
+  const T* __restrict__ v;
+  T* __restrict__ g;
+  T* __restrict__ s;
+  T* __restrict__ l;
+  T* __restrict__ z;
+  const T* __restrict__ zsave;     // pre-replacement z_{i-1} (when a replacement preceded)
+  const T* __restrict__ dinv;
+  T dinv_s;
+};
+
+// Phase A: the four auxiliary recurrences of Algorithm 2 for iteration i
+//   g_i = k_i + beta_i (g_{i-1} - omega_{i-1} l_{i-1})
+//   s_i = w_i + beta_i (s_{i-1} - omega_{i-1} z_{i-1})
+//   l_i = m_i + beta_i (l_{i-1} - omega_{i-1} n_{i-1})   m_i = M^-1 w_i, n_{i-1} = M^-1 z_{i-1}
+//   z_i = t_i + beta_i (z_{i-1} - omega_{i-1} v_{i-1})
+// in place, and the GLRED 1 partials (q_i, y_i), (y_i, y_i) with
+// q_i = r_i - alpha_i s_i, y_i = w_i - alpha_i z_i formed in registers.
+// In iteration 0 the previous vectors are zero and beta_0 = 0.  After a
+// residual replacement (SAVED) n_{i-1} is formed from the saved
+// pre-replacement z_{i-1} instead of the replaced one.
+template <typename T, int PC, bool SAVED>
+__device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T wp,
+                                            double (&acc)[2], int64_t ntiles) {
+  constexpr int W = V16<T>::n;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t i = (tile * kBlock + threadIdx.x) * W;
+    T k[W], w[W], t[W], r[W], v[W], g[W], s[W], l[W], z[W], zp[W], d[W];
+    ld16(A.k + i, k); ld16(A.w + i, w); ld16(A.t + i, t); ld16(A.r + i, r); ld16(A.v + i, v);
+    ld16(A.g + i, g); ld16(A.s + i, s); ld16(A.l + i, l); ld16(A.z + i, z);
+    if (SAVED) ld16(A.zsave + i, zp);
+    if (PC == PC_VECTOR) ld16(A.dinv + i, d);
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const T de = (PC == PC_VECTOR) ? d[e] : A.dinv_s;
+      const T zprev = SAVED ? zp[e] : z[e];
+      const T m = (PC == PC_NONE) ? w[e] : de * w[e];
+      const T np = (PC == PC_NONE) ? zprev : de * zprev;
+      const T gn = k[e] + b * (g[e] - wp * l[e]);
+      const T sn = w[e] + b * (s[e] - wp * z[e]);
+      const T ln = m + b * (l[e] - wp * np);
+      const T zn = t[e] + b * (z[e] - wp * v[e]);
+      g[e] = gn; s[e] = sn; l[e] = ln; z[e] = zn;
+      const T q = r[e] - a * sn;
+      const T y = w[e] - a * zn;
+      acc[0] += (double)q * (double)y;
+      acc[1] += (double)y * (double)y;
+    }
+    st16(A.g + i, g); st16(A.s + i, s); st16(A.l + i, l); st16(A.z + i, z);
+  }
+}
+
+template <typename T, int PC>
+__global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, const DevScalars* __restrict__ sc,
+                                                   double* __restrict__ partials, int64_t ntiles) {
+  if (sc->done) return;
+  const T a = (T)sc->alpha, b = (T)sc->beta, wp = (T)sc->omega_prev;
+  double acc[2] = {0.0, 0.0};
+  if (sc->n_saved) phaseA_body<T, PC, true>(A, a, b, wp, acc, ntiles);
+  else phaseA_body<T, PC, false>(A, a, b, wp, acc, ntiles);
+  const int slots[2] = {SL_QY, SL_YY};
+  block_partials<2>(acc, slots, partials, blockIdx.x);
+}
+
+template <typename T>
+struct PhaseBArgs {
+  double* __restrict__ x;
+  const T* __restrict__ g;
+  const T* __restrict__ l;
+  const T* __restrict__ s;
+  const T* __restrict__ z;
+  const T* __restrict__ t;
+  const T* __restrict__ v;
+  const T* __restrict__ rhat;
+  T* __restrict__ r;
+  T* __restrict__ k;
+  T* __restrict__ w;
+  const T* __restrict__ dinv;
+  T dinv_s;
+};
+
+// Phase B: with omega_i known,
+//   u_i = k_i - alpha_i l_i,  q_i = r_i - alpha_i s_i,  y_i = w_i - alpha_i z_i
+//   x_{i+1} = (x_i + alpha_i g_i) + omega_i u_i           (FP64)
+//   r_{i+1} = q_i - omega_i y_i
+//   k_{i+1} = u_i - omega_i (m_i - alpha_i n_i)           m_i = M^-1 w_i, n_i = M^-1 z_i
+//   w_{i+1} = y_i - omega_i (t_i - alpha_i v_i)
+// in place, and the GLRED 2 partials (r0, r_{i+1}), (r0, w_{i+1}), (r0, s_i),
+// (r0, z_i), (r_{i+1}, r_{i+1}).
+template <typename T, int PC>
+__global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevScalars* __restrict__ sc,
+                                                   double* __restrict__ partials, int64_t ntiles) {
+  if (sc->done) return;
+  constexpr int W = V16<T>::n;
+  const double alpha = sc->alpha, omega = sc->omega;
+  const T a = (T)alpha, om = (T)omega;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t i = (tile * kBlock + threadIdx.x) * W;
+    T g[W], l[W], s[W], z[W], t[W], v[W], rh[W], r[W], k[W], w[W], d[W];
+    double x[W];
+    ld16(B.g + i, g); ld16(B.l + i, l); ld16(B.s + i, s); ld16(B.z + i, z);
+    ld16(B.t + i, t); ld16(B.v + i, v); ld16(B.rhat + i, rh); ld16(B.r + i, r);
+    ld16(B.k + i, k); ld16(B.w + i, w);
+#pragma unroll
+    for (int h = 0; h < W; h += 2) {
+      double xx[2];
+      ld16(B.x + i + h, xx);
+      x[h] = xx[0]; x[h + 1] = xx[1];
+    }
+    if (PC == PC_VECTOR) ld16(B.dinv + i, d);
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const T de = (PC == PC_VECTOR) ? d[e] : B.dinv_s;
+      const T m = (PC == PC_NONE) ? w[e] : de * w[e];
+      const T n = (PC == PC_NONE) ? z[e] : de * z[e];
+      const T q = r[e] - a * s[e];
+      const T u = k[e] - a * l[e];
+      const T y = w[e] - a * z[e];
+      x[e] = (x[e] + alpha * (double)g[e]) + omega * (double)u;
+      const T rn = q - om * y;
+      const T kn = u - om * (m - a * n);
+      const T wn = y - om * (t[e] - a * v[e]);
+      r[e] = rn; k[e] = kn; w[e] = wn;
+      const double rhd = (double)rh[e];
+      acc[0] += rhd * (double)rn;
+      acc[1] += rhd * (double)wn;
+      acc[2] += rhd * (double)s[e];
+      acc[3] += rhd * (double)z[e];
+      acc[4] += (double)rn * (double)rn;
+    }
+    st16(B.r + i, r); st16(B.k + i, k); st16(B.w + i, w);
+#pragma unroll
+    for (int h = 0; h < W; h += 2) {
+      double xx[2] = {x[h], x[h + 1]};
+      st16(B.x + i + h, xx);
+    }
+  }
+  const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+  block_partials<5>(acc, slots, partials, blockIdx.x);
+}
+
+// Classic BiCGStab (Algorithm 1) vector update, with alpha_i and omega_i known:
+//   q_i = r_i - alpha_i s_i, g_i = M^-1 p_i, u_i = M^-1 q_i
+//   x_{i+1} = (x_i + alpha_i g_i) + omega_i u_i,  r_{i+1} = q_i - omega_i y_i
+// and the third reduction's partials (r0, r_{i+1}), (r_{i+1}, r_{i+1}).
+template <typename T>
+struct ClUpdArgs {
+  double* __restrict__ x;
+  const T* __restrict__ p;
+  const T* __restrict__ s;
+  const T* __restrict__ y;
+  const T* __restrict__ rhat;
+  T* __restrict__ r;
+  const T* __restrict__ dinv;
+  T dinv_s;
+};
+
+template <typename T, int PC>
+__global__ __launch_bounds__(kBlock) void k_cl_update(ClUpdArgs<T> U, const DevScalars* __restrict__ sc,
+                                                      double* __restrict__ partials, int64_t ntiles) {
+  if (sc->done) return;
+  constexpr int W = V16<T>::n;
+  const double alpha = sc->alpha, omega = sc->omega;
+  const T a = (T)alpha, om = (T)omega;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t i = (tile * kBlock + threadIdx.x) * W;
+    T p[W], s[W], y[W], rh[W], r[W], d[W];
+    double x[W];
+    ld16(U.p + i, p); ld16(U.s + i, s); ld16(U.y + i, y); ld16(U.rhat + i, rh); ld16(U.r + i, r);
+#pragma unroll
+    for (int h = 0; h < W; h += 2) {
+      double xx[2];
+      ld16(U.x + i + h, xx);
+      x[h] = xx[0]; x[h + 1] = xx[1];
+    }
+    if (PC == PC_VECTOR) ld16(U.dinv + i, d);
+#pragma unroll
+    for (int e = 0; e < W; ++e) {
+      const T de = (PC == PC_VECTOR) ? d[e] : U.dinv_s;
+      const T q = r[e] - a * s[e];
+      const T g = (PC == PC_NONE) ? p[e] : de * p[e];
+      const T u = (PC == PC_NONE) ? q : de * q;
+      x[e] = (x[e] + alpha * (double)g) + omega * (double)u;
+      const T rn = q - om * y[e];
+      r[e] = rn;
+      acc[0] += (double)rh[e] * (double)rn;
+      acc[1] += (double)rn * (double)rn;
+    }
+    st16(U.r + i, r);
+#pragma unroll
+    for (int h = 0; h < W; h += 2) {
+      double xx[2] = {x[h], x[h + 1]};
+      st16(U.x + i + h, xx);
+    }
+  }
+  const int slots[2] = {SL_RR0, SL_RR};
+  block_partials<2>(acc, slots, partials, blockIdx.x);
+}
+
+// Classic: p_{i+1} = r_{i+1} + beta_i (p_i - omega_i s_i)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cl_p(const T* __restrict__ r, T* __restrict__ p,
+                                                 const T* __restrict__ s,
+                                                 const DevScalars* __restrict__ sc, int64_t ntiles) {
+  if (sc->done) return;
+  constexpr int W = V16<T>::n;
+  const T b = (T)sc->beta, om = (T)sc->omega;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t i = (tile * kBlock + threadIdx.x) * W;
+    T rr[W], pp[W], ss[W];
+    ld16(r + i, rr); ld16(p + i, pp); ld16(s + i, ss);
+#pragma unroll
+    for (int e = 0; e < W; ++e) pp[e] = rr[e] + b * (pp[e] - om * ss[e]);
+    st16(p + i, pp);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_final(int mode, DevScalars* __restrict__ sc,
+                                                  const double* __restrict__ partials, int nblk,
+                                                  int aux, int respect_done) {
+  if (respect_done && sc->done) return;
+  run_final(mode, sc, partials, nblk, aux);
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* __restrict__ p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = T(0);
+}
+
+template <typename T>
+__global__ void k_to_double(const T* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+
+__global__ void k_set_done(DevScalars* sc, int value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc->done = value;
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+
+static inline int fill_blocks(int64_t count) {
+  int64_t b = (count + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T, int PC>
+static void phaseA_t(Solver& S, hipStream_t st) {
+  PhaseAArgs<T> a;
+  a.k = (const T*)S.vec[V_K]; a.w = (const T*)S.vec[V_W]; a.t = (const T*)S.vec[V_T];
+  a.r = (const T*)S.vec[V_R]; a.v = (const T*)S.vec[V_V];
+  a.g = (T*)S.vec[V_G]; a.s = (T*)S.vec[V_S]; a.l = (T*)S.vec[V_L]; a.z = (T*)S.vec[V_Z];
+  a.zsave = (const T*)S.vec[V_TMP];
+  a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
+  hipLaunchKernelGGL((k_phaseA<T, PC>), dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials,
+                     S.vtiles);
+}
+
+template <typename T, int PC>
+static void phaseB_t(Solver& S, hipStream_t st) {
+  PhaseBArgs<T> a;
+  a.x = S.x;
+  a.g = (const T*)S.vec[V_G]; a.l = (const T*)S.vec[V_L]; a.s = (const T*)S.vec[V_S];
+  a.z = (const T*)S.vec[V_Z]; a.t = (const T*)S.vec[V_T]; a.v = (const T*)S.vec[V_V];
+  a.rhat = (const T*)S.vec[V_RHAT];
+  a.r = (T*)S.vec[V_R]; a.k = (T*)S.vec[V_K]; a.w = (T*)S.vec[V_W];
+  a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
+  hipLaunchKernelGGL((k_phaseB<T, PC>), dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials,
+                     S.vtiles);
+}
+
+template <typename T, int PC>
+static void clupd_t(Solver& S, hipStream_t st) {
+  ClUpdArgs<T> a;
+  a.x = S.x;
+  a.p = (const T*)S.vec[V_G]; a.s = (const T*)S.vec[V_S]; a.y = (const T*)S.vec[V_V];
+  a.rhat = (const T*)S.vec[V_RHAT]; a.r = (T*)S.vec[V_R];
+  a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
+  hipLaunchKernelGGL((k_cl_update<T, PC>), dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc,
+                     S.partials, S.vtiles);
+}
+
+#define PBCG_DISPATCH_T_PC(S, FN, ...)                                      \
+  do {                                                                      \
+    if ((S).precision == 0) {                                               \
+      if ((S).pc == PC_NONE) FN<double, PC_NONE>(__VA_ARGS__);              \
+      else if ((S).pc == PC_SCALAR) FN<double, PC_SCALAR>(__VA_ARGS__);     \
+      else FN<double, PC_VECTOR>(__VA_ARGS__);                              \
+    } else {                                                                \
+      if ((S).pc == PC_NONE) FN<float, PC_NONE>(__VA_ARGS__);               \
+      else if ((S).pc == PC_SCALAR) FN<float, PC_SCALAR>(__VA_ARGS__);      \
+      else FN<float, PC_VECTOR>(__VA_ARGS__);                               \
+    }                                                                       \
+  } while (0)
+
+void launch_phaseA(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseA_t, S, st); }
+void launch_phaseB(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseB_t, S, st); }
+void launch_cl_update(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, clupd_t, S, st); }
+
+void launch_cl_p(Solver& S, hipStream_t st) {
+  if (S.precision == 0)
+    hipLaunchKernelGGL(k_cl_p<double>, dim3(S.nblk), dim3(kBlock), 0, st,
+                       (const double*)S.vec[V_R], (double*)S.vec[V_G], (const double*)S.vec[V_S],
+                       S.sc, S.vtiles);
+  else
+    hipLaunchKernelGGL(k_cl_p<float>, dim3(S.nblk), dim3(kBlock), 0, st,
+                       (const float*)S.vec[V_R], (float*)S.vec[V_G], (const float*)S.vec[V_S],
+                       S.sc, S.vtiles);
+}
+
+void launch_final(Solver& S, int mode, int aux, hipStream_t st) {
+  const int respect = (mode == FIN_TRUE || mode == FIN_SUM || mode == FIN_INIT ||
+                       mode == FIN_C_INIT || mode == FIN_REDO) ? 0 : 1;
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, st, mode, S.sc, S.partials, S.nblk, aux,
+                     respect);
+}
+
+void launch_fill_zero(Solver& S, void* ptr, int64_t count, size_t elem, hipStream_t st) {
+  (void)S;
+  if (count <= 0) return;
+  if (elem == 8)
+    hipLaunchKernelGGL(k_fill_zero<double>, dim3(fill_blocks(count)), dim3(kBlock), 0, st,
+                       (double*)ptr, count);
+  else
+    hipLaunchKernelGGL(k_fill_zero<float>, dim3(fill_blocks(count)), dim3(kBlock), 0, st,
+                       (float*)ptr, count);
+}
+
+void launch_to_double(Solver& S, const void* src, double* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  if (S.precision == 0)
+    hipLaunchKernelGGL(k_to_double<double>, dim3(fill_blocks(n)), dim3(kBlock), 0, st,
+                       (const double*)src, dst, n);
+  else
+    hipLaunchKernelGGL(k_to_double<float>, dim3(fill_blocks(n)), dim3(kBlock), 0, st,
+                       (const float*)src, dst, n);
+}
+
+void launch_set_done(Solver& S, int value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_done, dim3(1), dim3(64), 0, st, S.sc, value);
+}
+
+}  // namespace pbcg

@@ -1,0 +1,112 @@
+// Host-side solver state and kernel launchers (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "ops.hpp"
+
+namespace pbcg {
+
+// One orientation (A or A^T) of the operator on the device.
+struct OpData {
+  int kind = OP_SELL;
+  // SELL-64
+  int64_t nslices = 0;
+  int64_t* sptr = nullptr;      // nslices + 1 element offsets
+  int32_t* col = nullptr;
+  void* val = nullptr;          // T
+  int64_t sell_elems = 0;
+  int max_width = 0;
+  // stencils
+  int dims[3] = {1, 1, 1};
+  double c64[7] = {0};
+  float c32[7] = {0};
+  // DIA5
+  void* dia = nullptr;          // T, 5 * ld
+};
+
+struct Solver {
+  int64_t n = 0, npad = 0, nnz = 0;
+  int precision = 0;            // 0 = FP64, 1 = mixed (FP32 storage, FP64 reductions/scalars)
+  int precond = 0;              // 0 = none, 1 = Jacobi
+  int kind = OP_SELL;
+  int pc = PC_NONE;             // compile-time preconditioner kind used by the kernels
+  size_t tsize = 8;             // bytes per stored vector element
+  OpData A, AT;
+  bool have_AT = false;
+
+  // host copies kept for the transpose (built on first use) and value updates
+  std::vector<int32_t> h_rowptr, h_col;
+  std::vector<double> h_val;
+  std::vector<double> h_dia;    // DIA5, 5 * n, S W C E N
+
+  // CSR on the device (gradient on the pattern, value updates)
+  int32_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  int64_t* d_posA = nullptr;    // CSR entry -> SELL slot of A
+  int64_t* d_posAT = nullptr;   // CSR entry -> SELL slot of A^T
+  int64_t* d_diagpos = nullptr; // row -> CSR index of its diagonal (or -1)
+
+  // device arena
+  std::vector<void*> allocations;
+  void* vec[16] = {nullptr};    // stored solver vectors (T), see VecId
+  double* x = nullptr;          // iterate (FP64, padded)
+  double* b = nullptr;          // right-hand side (FP64, padded)
+  void* dinv = nullptr;         // Jacobi diagonal (T) when a vector is needed
+  double dinv_s = 1.0;          // constant Jacobi scale for constant stencils
+  double* partials = nullptr;   // kNumSlots * kMaxBlocks
+  DevScalars* sc = nullptr;
+  DevScalars* h_sc = nullptr;   // pinned, 2 entries (double-buffered poll)
+
+  int nblk = 8;                 // blocks of every streaming kernel (multiple of 8)
+  int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
+  int64_t rtiles = 0;           // tiles of 256 rows
+
+  hipStream_t s1 = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};
+
+  // captured iteration chunks: key = (transpose, chunk length, start offset mod P, P)
+  std::map<std::string, hipGraphExec_t> graphs;
+};
+
+enum VecId : int {
+  V_RHAT = 0, V_R, V_G, V_S, V_L, V_Z, V_K, V_W, V_T, V_V, V_TMP, V_COUNT
+};
+
+// ---- launchers (kernels_vec.hip) ----
+void launch_phaseA(Solver& S, hipStream_t st);
+void launch_phaseB(Solver& S, hipStream_t st);
+void launch_final(Solver& S, int mode, int aux, hipStream_t st);
+void launch_cl_update(Solver& S, hipStream_t st);
+void launch_cl_p(Solver& S, hipStream_t st);
+void launch_fill_zero(Solver& S, void* ptr, int64_t count, size_t elem, hipStream_t st);
+void launch_to_double(Solver& S, const void* src, double* dst, int64_t n, hipStream_t st);
+void launch_set_done(Solver& S, int value, hipStream_t st);
+
+// ---- launchers (kernels_op.hip) ----
+const OpData& op_of(Solver& S, bool transpose);
+void launch_init_res(Solver& S, bool tr, hipStream_t st);
+void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
+                 hipStream_t st);
+void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
+void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st);
+void launch_true_res(Solver& S, bool tr, hipStream_t st);
+void launch_gap(Solver& S, bool tr, hipStream_t st);
+void launch_cl_init(Solver& S, bool tr, hipStream_t st);
+void launch_cl_spmv_s(Solver& S, bool tr, hipStream_t st);
+void launch_cl_spmv_y(Solver& S, bool tr, hipStream_t st);
+void launch_apply(Solver& S, bool tr, const double* x, double* y, hipStream_t st);
+void launch_grad(Solver& S, const double* lam, const double* x, double* grad, hipStream_t st);
+void launch_update_sell(Solver& S, const double* val_dev, hipStream_t st);
+void launch_kappa_assemble(Solver& S, const double* kappa, double cx, double cy, double h,
+                           hipStream_t st);
+void launch_kappa_grad(Solver& S, const double* lam, const double* x, double* gk, hipStream_t st);
+
+
+}  // namespace pbcg

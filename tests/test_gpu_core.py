@@ -1,0 +1,318 @@
+"""GPU parity of the HIP path against the CPU oracle (core cases).
+
+Iteration counts are compared with a 20% margin: p-BiCGStab amplifies
+rounding differences (Section 3.3), and changing nothing but the summation
+order of the oracle's dot products already moves the 32^2 convection-diffusion
+solve between 75 and 86 iterations.
+
+Every call goes through the C ABI (libpbicgstab.so) via the ctypes binding.
+Tolerances: the library is built without FMA contraction and sums each SPMV
+row in stored column order, so SPMV results are bitwise equal to the
+oracle's; the only other difference is the summation tree of the dot
+products (a few ulp on each reduced scalar), hence the scalar trace of the
+first iterations agrees to ~1e-13 and is tested at the 1e-10 bound.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from gpu_util import dev, history_buffer, host, oracle_ops, rel, split_history
+from oracle import STATUS, Float64Ops, classic_bicgstab, pipelined_bicgstab
+from workloads import (Stencil, convdiff2d_c1, convdiff3d_c3, dia5_from_kappa, dia5_to_csr,
+                       kappa_field_c5, poisson2d_c2, random_banded_c4, stencil_to_csr)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    from paper_1809_01948_amd.solver import Solver as S
+    return S
+
+
+# -----------------------------------------------------------------------------
+# SPMV (pbicgstab_apply) bitwise against the oracle's CSR product
+# -----------------------------------------------------------------------------
+
+def _apply_cases():
+    out = []
+    p = convdiff2d_c1(32)
+    out.append(("c1-csr", p, "csr"))
+    out.append(("c1-stencil", p, "stencil"))
+    out.append(("ragged-2d", convdiff2d_c1(37, conv=(3.0, -2.0)), "stencil"))
+    out.append(("3d-small", convdiff3d_c3(13, with_csr=True), "stencil"))
+    out.append(("3d-csr", convdiff3d_c3(11, with_csr=True), "csr"))
+    out.append(("c4-small", random_banded_c4(N=5000, nnz_row=27, band=300, seed=4), "csr"))
+    return out
+
+
+_CASES = _apply_cases()
+
+
+@pytest.mark.parametrize("name,prob,form", _CASES, ids=[c[0] for c in _CASES])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_bitwise(Solver, name, prob, form, transpose):
+    S = Solver.from_problem(prob, form=form, precond="none")
+    A = prob.scipy_csr()
+    x = np.random.default_rng(1).standard_normal(prob.n)
+    y = host(S.apply(dev(x), transpose=transpose))
+    ref = (sp.csr_matrix(A.T) if transpose else A) @ x
+    assert np.array_equal(y, ref)
+    S.close()
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_apply_dia5_bitwise(Solver, transpose):
+    n = 45
+    h = 1.0 / (n + 1)
+    dia = dia5_from_kappa(kappa_field_c5(n, seed=5, sigma=4.0), h)
+    S = Solver.from_stencil("dia5", (n, n), dia, precond="none")
+    rp, col, val = dia5_to_csr((n, n), dia)
+    A = sp.csr_matrix((val, col, rp), shape=(n * n, n * n))
+    x = np.random.default_rng(2).standard_normal(n * n)
+    y = host(S.apply(dev(x), transpose=transpose))
+    assert np.array_equal(y, (sp.csr_matrix(A.T) if transpose else A) @ x)
+    S.close()
+
+
+# -----------------------------------------------------------------------------
+# the first iterations of Algorithm 2 against the oracle
+# -----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form,precond", [("csr", "none"), ("stencil", "none"),
+                                          ("csr", "jacobi"), ("stencil", "jacobi")])
+def test_trace_c1(Solver, form, precond):
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, precond)
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000)
+    S = Solver.from_problem(p, form=form, precond=precond)
+    hist = history_buffer(2000)
+    x, st = S.solve(dev(p.b), tol=1e-10, maxit=2000, history=hist)
+    its = st["iterations"]
+    rn, al, om, be = split_history(hist, its)
+    k = 12
+    assert np.all(rel(al[:k], ref.alpha[:k]) <= 1e-10)
+    assert np.all(rel(om[:k], ref.omega[:k]) <= 1e-10)
+    assert np.all(rel(be[:k], ref.beta[:k]) <= 1e-10)
+    assert np.all(rel(rn[:k], ref.rnorm[:k]) <= 1e-10)
+    assert st["status"] == 0 and ref.status == 0
+    assert abs(its - ref.iterations) <= max(3, 0.2 * ref.iterations)
+    xh = host(x)
+    assert np.linalg.norm(p.b - A @ xh) <= 1e-10 * np.linalg.norm(p.b)
+    assert np.linalg.norm(xh - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    S.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7])
+def test_vectors_after_k_iterations(Solver, k):
+    """x, r, k, w, g, s, l, z and v after k iterations equal the oracle's up to
+    the dot-product summation order."""
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, "jacobi")
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, record=True)
+    sn = ref.snapshots[-1]
+    S = Solver.from_problem(p, form="csr", precond="jacobi")
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k)
+    assert st["status"] == STATUS["MAXIT"] and st["iterations"] == k
+    pairs = {"x": sn["x1"], "r": sn["r1"], "k": sn["k1"], "w": sn["w1"], "g": sn["g"],
+             "s": sn["s"], "l": sn["l"], "z": sn["z"], "v": sn["v"]}
+    for name, want in pairs.items():
+        got = host(S.get_vector(name))
+        assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want), name
+    assert np.array_equal(host(x), host(S.get_vector("x")))
+    S.close()
+
+
+@pytest.mark.parametrize("method,rr", [("classic", 0), ("pipelined", 0), ("pipelined", 50),
+                                       ("pipelined", 7)])
+def test_solve_c1(Solver, method, rr):
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p)
+    if method == "classic":
+        ref = classic_bicgstab(ops, p.b, tol=1e-10, maxit=2000)
+    else:
+        ref = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000, rr_period=rr)
+    S = Solver.from_problem(p, form="csr")
+    hist = history_buffer(2000)
+    x, st = S.solve(dev(p.b), tol=1e-10, maxit=2000, rr_period=rr, method=method, history=hist)
+    assert st["status"] == 0, st
+    assert abs(st["iterations"] - ref.iterations) <= max(3, 0.2 * ref.iterations)
+    rn, al, om, be = split_history(hist, st["iterations"])
+    assert np.all(rel(al[:10], ref.alpha[:10]) <= 1e-10)
+    assert np.all(rel(om[:10], ref.omega[:10]) <= 1e-10)
+    xh = host(x)
+    assert np.linalg.norm(p.b - A @ xh) <= 1e-10 * np.linalg.norm(p.b)
+    assert np.linalg.norm(xh - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    assert np.linalg.norm(xh - p.x_exact) <= 1e-6 * np.linalg.norm(p.x_exact)
+    if rr:
+        assert st["replacements"] >= 1
+    S.close()
+
+
+# -----------------------------------------------------------------------------
+# the 1000^2 Poisson workload: stencil form == CSR form, bitwise
+# -----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c2():
+    return poisson2d_c2(1000)
+
+
+def test_c2_stencil_equals_csr_and_oracle(Solver, c2):
+    """300 iterations with replacement every 50: the stencil and CSR forms
+    give bitwise identical iterates (same SPMV sums, same reduction tree);
+    the scalar trace matches the oracle over the first 15 iterations.  Past
+    ~20 iterations any two correct implementations diverge on this workload:
+    the oracle against itself with a pairwise dot-product summation differs
+    by 1e-10 at iteration 20 and 1e-1 at iteration 40."""
+    A, ops = oracle_ops(c2)
+    ref = pipelined_bicgstab(ops, c2.b, tol=0.0, maxit=15)
+    res = {}
+    for form in ("stencil", "csr"):
+        S = Solver.from_problem(c2, form=form)
+        hist = history_buffer(300)
+        x, st = S.solve(dev(c2.b), tol=0.0, maxit=300, rr_period=50, history=hist)
+        res[form] = (host(x), st, host(hist))
+        S.close()
+    xs, sts, hs = res["stencil"]
+    xc, stc, hc = res["csr"]
+    assert sts["status"] == STATUS["MAXIT"] and stc["status"] == STATUS["MAXIT"]
+    assert sts["iterations"] == stc["iterations"] == 300
+    assert sts["replacements"] == stc["replacements"] == 6
+    assert np.array_equal(xs, xc)
+    assert np.array_equal(hs, hc)
+    rn, al, om, be = split_history(torch.from_numpy(hs), 15)
+    assert np.all(rel(al[:10], ref.alpha[:10]) <= 1e-12)
+    assert np.all(rel(om[:10], ref.omega[:10]) <= 1e-12)
+    assert np.all(rel(al, ref.alpha) <= 1e-9)
+    assert np.all(rel(om, ref.omega) <= 1e-9)
+    assert np.all(rel(be, ref.beta) <= 1e-9)
+    assert np.all(rel(rn, ref.rnorm) <= 1e-9)
+
+
+@pytest.mark.parametrize("k", [1, 5])
+def test_c2_vectors_after_k(Solver, c2, k):
+    A, ops = oracle_ops(c2)
+    ref = pipelined_bicgstab(ops, c2.b, tol=0.0, maxit=k, record=True)
+    sn = ref.snapshots[-1]
+    S = Solver.from_problem(c2, form="stencil")
+    x, st = S.solve(dev(c2.b), tol=0.0, maxit=k)
+    for name, want in {"x": sn["x1"], "r": sn["r1"], "k": sn["k1"], "w": sn["w1"],
+                       "g": sn["g"], "s": sn["s"], "l": sn["l"], "z": sn["z"],
+                       "v": sn["v"]}.items():
+        got = host(S.get_vector(name))
+        assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want), name
+    S.close()
+
+
+@pytest.mark.parametrize("method,rr", [("pipelined", 200), ("classic", 0)])
+def test_c2_converges(Solver, c2, method, rr):
+    """Full solves to 1e-10, the true residual recomputed by the oracle's
+    SPMV.  (Replacement every 50 or 100 iterations does not reach 1e-10 on
+    this workload -- neither on the GPU nor in the oracle on scaled-down
+    grids, where 400^2 with period 50 breaks down after ~2950 iterations.)"""
+    A, _ = oracle_ops(c2)
+    S = Solver.from_problem(c2, form="stencil")
+    x, st = S.solve(dev(c2.b), tol=1e-10, maxit=20000, rr_period=rr, method=method)
+    assert st["status"] == 0, st
+    xh = host(x)
+    assert np.linalg.norm(c2.b - A @ xh) <= 1e-10 * np.linalg.norm(c2.b)
+    S.close()
+
+
+def test_determinism_and_graph_replay(Solver, c2):
+    S = Solver.from_problem(c2, form="stencil")
+    b = dev(c2.b)
+    outs = []
+    for use_graph in (False, False, True, True):
+        hist = history_buffer(400)
+        x, st = S.solve(b, tol=0.0, maxit=400, rr_period=50, history=hist,
+                        use_graph=use_graph)
+        outs.append((host(x), st["iterations"], host(hist), st["replacements"]))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert o[1] == outs[0][1] == 400
+        assert o[3] == outs[0][3] == 8
+        assert np.array_equal(o[2], outs[0][2])
+    S.close()
+
+
+# -----------------------------------------------------------------------------
+# edge cases and failure handling
+# -----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("method", ["pipelined", "classic"])
+def test_zero_rhs(Solver, method):
+    p = convdiff2d_c1(8)
+    S = Solver.from_problem(p, form="csr")
+    x0 = dev(np.ones(p.n))
+    x, st = S.solve(dev(np.zeros(p.n)), x0=x0, method=method)
+    assert st["status"] == 0 and st["iterations"] == 0
+    assert not np.any(host(x))
+    S.close()
+
+
+@pytest.mark.parametrize("method", ["pipelined", "classic"])
+def test_nonfinite(Solver, method):
+    p = convdiff2d_c1(8)
+    b = p.b.copy()
+    b[5] = np.nan
+    S = Solver.from_problem(p, form="csr")
+    x, st = S.solve(dev(b), method=method)
+    assert st["status"] == STATUS["NONFINITE"]
+    S.close()
+
+
+@pytest.mark.parametrize("method", ["pipelined", "classic"])
+def test_maxit(Solver, method):
+    p = convdiff2d_c1(16)
+    S = Solver.from_problem(p, form="csr")
+    x, st = S.solve(dev(p.b), maxit=5, method=method)
+    assert st["status"] == STATUS["MAXIT"] and st["iterations"] == 5
+    S.close()
+
+
+@pytest.mark.parametrize("method", ["pipelined", "classic"])
+def test_breakdown(Solver, method):
+    rowptr = np.array([0, 1, 2], dtype=np.int32)
+    col = np.array([1, 0], dtype=np.int32)
+    val = np.array([1.0, -1.0])
+    S = Solver.from_csr(rowptr, col, val, precond="none")
+    x, st = S.solve(dev(np.array([1.0, 1.0])), method=method)
+    assert st["status"] == STATUS["BREAKDOWN_RHO"] and st["iterations"] == 0
+    S.close()
+
+
+def test_one_by_one_and_diagonal(Solver):
+    S = Solver.from_csr(np.array([0, 1]), np.array([0]), np.array([4.0]), precond="jacobi")
+    x, st = S.solve(dev(np.array([2.0])))
+    assert st["status"] == 0 and host(x)[0] == 0.5
+    S.close()
+    d = 2.0 ** np.random.default_rng(3).integers(-3, 4, 300)
+    A = sp.diags(d).tocsr()
+    b = np.random.default_rng(4).uniform(-1, 1, 300)
+    S = Solver.from_csr(A.indptr, A.indices, A.data, precond="jacobi")
+    x, st = S.solve(dev(b), tol=1e-14)
+    assert st["status"] == 0 and st["iterations"] == 1
+    np.testing.assert_allclose(host(x), b / d, rtol=1e-15)
+    S.close()
+
+
+def test_errors(Solver):
+    from paper_1809_01948_amd import PbcgError
+    with pytest.raises(PbcgError) as e:
+        Solver.from_csr(np.array([0, 1, 2]), np.array([1, 0]), np.array([1.0, 1.0]),
+                        precond="jacobi")
+    assert e.value.code == -3
+    with pytest.raises(PbcgError) as e:
+        Solver.from_csr(np.array([0, 1, 2]), np.array([1, 5]), np.array([1.0, 1.0]),
+                        precond="none")
+    assert e.value.code == -1
+    p = convdiff2d_c1(8)
+    S = Solver.from_problem(p, form="csr")
+    with pytest.raises(PbcgError) as e:
+        S.solve(dev(p.b), maxit=0)
+    assert e.value.code == -1
+    S.close()
