@@ -56,6 +56,7 @@ enum FinalMode : int {
   FIN_C_OMEGA = 9,   // classic: omega_i
   FIN_C_BETA = 10,   // classic: beta_i, stopping test
   FIN_SUM = 11,      // plain sums of slots 0..nslot-1 into DevScalars::sums
+  FIN_PROBE = 12,    // the GLRED 2 reduction only (into sig), for kernel timing
 };
 
 // done flag values
@@ -119,27 +120,51 @@ __device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&sl
   }
 }
 
-// Sum of the first nblk partials of one slot, computed by one whole block in
-// a fixed order; every thread returns the result.
-__device__ __forceinline__ double block_sum_slot(const double* __restrict__ partials, int slot,
-                                                 int nblk) {
-  __shared__ double red[kWaves];
-  __shared__ double total;
-  double s = 0.0;
-  for (int j = threadIdx.x; j < nblk; j += kBlock) s += partials[slot * kMaxBlocks + j];
-  s = wave_sum(s);
+// Sums of the first nblk partials of NS slots, computed by one whole block in
+// a fixed order (per thread: ascending j; then the wave tree; then the 4 wave
+// sums left to right); every thread returns the results.  All loads of all
+// slots are issued before any reduction, so the cost is one memory round
+// trip however many slots are reduced.
+template <int NS>
+__device__ __forceinline__ void block_sum_slots(const double* __restrict__ partials,
+                                                const int (&slot)[NS], int nblk,
+                                                double (&out)[NS]) {
+  __shared__ double red[NS][kWaves];
+  double s[NS];
+#pragma unroll
+  for (int d = 0; d < NS; ++d) s[d] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxBlocks / kBlock; ++u) {
+    const int j = u * kBlock + threadIdx.x;
+    if (j < nblk) {
+#pragma unroll
+      for (int d = 0; d < NS; ++d) s[d] += partials[slot[d] * kMaxBlocks + j];
+    }
+  }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = red[0];
-    for (int w = 1; w < kWaves; ++w) t += red[w];
-    total = t;
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    const double v = wave_sum(s[d]);
+    if (lane == 0) red[d][wid] = v;
   }
   __syncthreads();
-  double r = total;
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    double t = red[d][0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t += red[d][w];
+    out[d] = t;
+  }
   __syncthreads();
-  return r;
+}
+
+// Sum of the first nblk partials of one slot (see block_sum_slots).
+__device__ __forceinline__ double block_sum_slot(const double* __restrict__ partials, int slot,
+                                                 int nblk) {
+  const int sl[1] = {slot};
+  double v[1];
+  block_sum_slots<1>(partials, sl, nblk, v);
+  return v[0];
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
@@ -169,9 +194,11 @@ struct XcdWalk {
 // vector helpers
 // ----------------------------------------------------------------------------
 
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf4 __attribute__((ext_vector_type(4)));
 template <typename T> struct V16;                 // 16-byte vector of T
-template <> struct V16<double> { typedef double2 type; static constexpr int n = 2; };
-template <> struct V16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct V16<double> { typedef nd2 type; static constexpr int n = 2; };
+template <> struct V16<float> { typedef nf4 type; static constexpr int n = 4; };
 
 template <typename T>
 __device__ __forceinline__ void ld16(const T* __restrict__ p, T (&v)[V16<T>::n]) {
@@ -190,6 +217,37 @@ __device__ __forceinline__ void st16(T* __restrict__ p, const T (&v)[V16<T>::n])
 #pragma unroll
   for (int k = 0; k < V16<T>::n; ++k) e[k] = v[k];
   *reinterpret_cast<VT*>(p) = t;
+}
+
+// Streaming access of C consecutive elements (C a multiple of the 16-byte
+// width), optionally with the non-temporal hint (data used once per kernel).
+template <typename T, int C, bool NT>
+__device__ __forceinline__ void ldc(const T* __restrict__ p, T (&v)[C]) {
+  constexpr int W = V16<T>::n;
+  typedef typename V16<T>::type VT;
+#pragma unroll
+  for (int h = 0; h < C / W; ++h) {
+    VT t = NT ? __builtin_nontemporal_load(reinterpret_cast<const VT*>(p) + h)
+              : reinterpret_cast<const VT*>(p)[h];
+    const T* e = reinterpret_cast<const T*>(&t);
+#pragma unroll
+    for (int k = 0; k < W; ++k) v[h * W + k] = e[k];
+  }
+}
+
+template <typename T, int C, bool NT>
+__device__ __forceinline__ void stc(T* __restrict__ p, const T (&v)[C]) {
+  constexpr int W = V16<T>::n;
+  typedef typename V16<T>::type VT;
+#pragma unroll
+  for (int h = 0; h < C / W; ++h) {
+    VT t;
+    T* e = reinterpret_cast<T*>(&t);
+#pragma unroll
+    for (int k = 0; k < W; ++k) e[k] = v[h * W + k];
+    if (NT) __builtin_nontemporal_store(t, reinterpret_cast<VT*>(p) + h);
+    else reinterpret_cast<VT*>(p)[h] = t;
+  }
 }
 
 // preconditioner kinds (compile-time)

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -92,9 +93,22 @@ void common_setup(Solver& S, int precision, int precond) {
   S.vtiles = S.npad / (kBlock * vw);
   S.rtiles = (S.n + kBlock - 1) / kBlock;
   int64_t nb = std::min<int64_t>(kMaxBlocks, std::max<int64_t>(S.vtiles, S.rtiles));
+  if (const char* env = std::getenv("PBCG_NBLK")) {   // tuning override
+    const long v = std::strtol(env, nullptr, 10);
+    if (v > 0) nb = v;
+  }
   nb = round_up(std::max<int64_t>(nb, kXcds), kXcds);
   if (nb > kMaxBlocks) nb = kMaxBlocks;
   S.nblk = (int)nb;
+  // Non-temporal streaming pays once the solver's vectors no longer fit the
+  // 256 MB Infinity Cache (measured: phase B on 8e6 FP64 rows 190 -> 144 us);
+  // below that it costs a little.  Mixed-precision phase A is faster with
+  // cached accesses at every size measured.
+  const int64_t footprint = (int64_t)(V_COUNT * S.tsize + 16) * S.npad;
+  if (footprint > ((int64_t)192 << 20)) S.vnt = precision == PBCG_FP64 ? 3 : 2;
+  if (const char* env = std::getenv("PBCG_VEC_UNROLL")) S.vunroll = std::atoi(env) == 2 ? 2 : 1;
+  if (const char* env = std::getenv("PBCG_VEC_NT")) S.vnt = std::atoi(env) & 3;
+  if (const char* env = std::getenv("PBCG_SPMV_TILED")) S.spmv_tiled = std::atoi(env) != 0;
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
   hipck(hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming), "hipEventCreate");
   hipck(hipEventCreateWithFlags(&S.ev_out, hipEventDisableTiming), "hipEventCreate");
@@ -921,7 +935,7 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream) {
 int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, void* stream) {
   return guarded([&]() -> int {
     Solver& S = H(h);
-    if (kernel < 0 || kernel > 4 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
+    if (kernel < 0 || kernel > 5 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
     hipStream_t cs = (hipStream_t)stream;
     hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
     hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
@@ -944,7 +958,8 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
         case 0: launch_phaseA(S, S.s1); break;
         case 1: launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, S.s1); break;
         case 2: launch_phaseB(S, S.s1); break;
-        case 3: launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_NONE, false, S.s1); break;
+        case 3: launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_PROBE, false, S.s1); break;
+        case 5: launch_copy(S, S.x, S.b, S.s1); break;
       }
     };
     auto launch = [&]() {

@@ -28,48 +28,58 @@ __device__ __forceinline__ T prec1(T zj, const T* __restrict__ dinv, T ds, int64
 // sum_j a_ij (M^-1 z)_j in the storage precision
 template <typename T, int PC>
 struct SpmvVis {
+  typedef T V;
   const T* __restrict__ z;
   const T* __restrict__ dinv;
   T ds;
   T sum;
-  __device__ __forceinline__ void operator()(T a, int64_t j) {
-    sum += a * prec1<T, PC>(z[j], dinv, ds, j);
-  }
+  __device__ __forceinline__ V load(int64_t j) const { return prec1<T, PC>(z[j], dinv, ds, j); }
+  __device__ __forceinline__ void add(T a, V x) { sum += a * x; }
 };
 
 // sum_j a_ij x_j in FP64 (x FP64)
 template <typename T>
 struct ResVis {
+  typedef double V;
   const double* __restrict__ x;
   double sum;
-  __device__ __forceinline__ void operator()(T a, int64_t j) { sum += (double)a * x[j]; }
+  __device__ __forceinline__ V load(int64_t j) const { return x[j]; }
+  __device__ __forceinline__ void add(T a, V v) { sum += (double)a * v; }
+};
+
+struct D2 {
+  double x, y;
 };
 
 // two FP64 products sharing the matrix loads: sum a_ij x_j and sum a_ij y_j
 template <typename T, typename X, typename Y>
 struct Res2Vis {
+  typedef D2 V;
   const X* __restrict__ x;
   const Y* __restrict__ y;
   double sx, sy;
-  __device__ __forceinline__ void operator()(T a, int64_t j) {
+  __device__ __forceinline__ V load(int64_t j) const { return D2{(double)x[j], (double)y[j]}; }
+  __device__ __forceinline__ void add(T a, V v) {
     const double ad = (double)a;
-    sx += ad * (double)x[j];
-    sy += ad * (double)y[j];
+    sx += ad * v.x;
+    sy += ad * v.y;
   }
 };
 
 // classic method: y_i = sum_j a_ij M^-1 (r_j - alpha s_j)
 template <typename T, int PC>
 struct QVis {
+  typedef T V;
   const T* __restrict__ r;
   const T* __restrict__ s;
   const T* __restrict__ dinv;
   T ds, a;
   T sum;
-  __device__ __forceinline__ void operator()(T c, int64_t j) {
+  __device__ __forceinline__ V load(int64_t j) const {
     const T q = r[j] - a * s[j];
-    sum += c * prec1<T, PC>(q, dinv, ds, j);
+    return prec1<T, PC>(q, dinv, ds, j);
   }
+  __device__ __forceinline__ void add(T c, V v) { sum += c * v; }
 };
 
 // ----------------------------------------------------------------------------
@@ -104,6 +114,127 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
   if (dot_rhat) {
     const int slots[1] = {SL_RW0};
     block_partials<1>(acc, slots, partials, blk);
+  }
+}
+
+// ----------------------------------------------------------------------------
+// structured SPMV, R consecutive rows per thread
+// ----------------------------------------------------------------------------
+//
+// For the stencil and DIA5 operators with nx a multiple of R = 16 bytes /
+// sizeof(T), the R rows of a thread lie on one grid line, so the centre,
+// S/N (and D/U) neighbours of all R rows are aligned 16-byte chunks and the
+// W/E neighbours are the centre chunk shifted by one plus one scalar at each
+// end.  Each row is still summed in ascending column order, exactly as the
+// row-per-thread kernel does.
+
+template <typename T, int PC>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ z, const T* __restrict__ dinv, T ds,
+                                           int64_t j, T (&v)[V16<T>::n]) {
+  ld16(z + j, v);
+  if (PC == PC_SCALAR) {
+#pragma unroll
+    for (int e = 0; e < V16<T>::n; ++e) v[e] = ds * v[e];
+  } else if (PC == PC_VECTOR) {
+    T d[V16<T>::n];
+    ld16(dinv + j, d);
+#pragma unroll
+    for (int e = 0; e < V16<T>::n; ++e) v[e] = d[e] * v[e];
+  }
+}
+
+template <typename T>
+struct StParams {
+  int kind;          // OP_ST2D5, OP_ST3D7 or OP_DIA5
+  int nx, ny, nz;
+  T c[7];            // constant coefficients (ascending column order)
+  const T* __restrict__ dia;
+  int64_t ld;
+};
+
+template <typename T, int PC, int KIND>
+__global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __restrict__ in,
+                                                    T* __restrict__ out, const T* __restrict__ dinv,
+                                                    T ds, int64_t n, int64_t ntiles, int nwork,
+                                                    DevScalars* __restrict__ sc,
+                                                    double* __restrict__ partials, int fin_mode,
+                                                    int nblk_partials) {
+  if (blockIdx.x == 0) {
+    if (fin_mode != FIN_NONE && (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done))
+      run_final(fin_mode, sc, partials, nblk_partials, 0);
+    return;
+  }
+  if (sc->done) return;
+  constexpr int R = V16<T>::n;
+  constexpr bool THREE = KIND == OP_ST3D7;
+  const int blk = blockIdx.x - 1;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int nxy = nx * ny;
+  for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t p0 = (w.t * kBlock + threadIdx.x) * R;
+    if (p0 >= n) continue;
+    const int p = (int)p0;
+    int ix, iy, iz = 0;
+    if (THREE) {
+      iz = p / nxy;
+      const int rem = p - iz * nxy;
+      iy = rem / nx;
+      ix = rem - iy * nx;
+    } else {
+      iy = p / nx;
+      ix = p - iy * nx;
+    }
+    const bool hS = iy > 0, hN = iy < ny - 1;
+    const bool hD = THREE && iz > 0, hU = THREE && iz < nz - 1;
+    const bool hW0 = ix > 0, hEl = ix + R < nx;
+    T xc[R], xs[R], xn[R], xd[R], xu[R];
+    load_chunk<T, PC>(in, dinv, ds, p, xc);
+    load_chunk<T, PC>(in, dinv, ds, hS ? p - nx : p, xs);
+    load_chunk<T, PC>(in, dinv, ds, hN ? p + nx : p, xn);
+    if (THREE) {
+      load_chunk<T, PC>(in, dinv, ds, hD ? p - nxy : p, xd);
+      load_chunk<T, PC>(in, dinv, ds, hU ? p + nxy : p, xu);
+    }
+    const int jw = hW0 ? p - 1 : p, je = hEl ? p + R : p;
+    const T xw0 = prec1<T, PC>(in[jw], dinv, ds, jw);
+    const T xeR = prec1<T, PC>(in[je], dinv, ds, je);
+    T cS[R], cW[R], cC[R], cE[R], cN[R];
+    if (KIND == OP_DIA5) {
+      ld16(P.dia + p, cS); ld16(P.dia + P.ld + p, cW); ld16(P.dia + 2 * P.ld + p, cC);
+      ld16(P.dia + 3 * P.ld + p, cE); ld16(P.dia + 4 * P.ld + p, cN);
+    }
+    T res[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) {
+      const T xw = e == 0 ? xw0 : xc[e - 1];
+      const T xe = e == R - 1 ? xeR : xc[e + 1];
+      const bool vw = e == 0 ? hW0 : true;
+      const bool ve = e == R - 1 ? hEl : true;
+      T sum = T(0);
+      if (KIND == OP_DIA5) {
+        if (hS) sum += cS[e] * xs[e];
+        if (vw) sum += cW[e] * xw;
+        sum += cC[e] * xc[e];
+        if (ve) sum += cE[e] * xe;
+        if (hN) sum += cN[e] * xn[e];
+      } else if (THREE) {
+        if (hD) sum += P.c[0] * xd[e];
+        if (hS) sum += P.c[1] * xs[e];
+        if (vw) sum += P.c[2] * xw;
+        sum += P.c[3] * xc[e];
+        if (ve) sum += P.c[4] * xe;
+        if (hN) sum += P.c[5] * xn[e];
+        if (hU) sum += P.c[6] * xu[e];
+      } else {
+        if (hS) sum += P.c[0] * xs[e];
+        if (vw) sum += P.c[1] * xw;
+        sum += P.c[2] * xc[e];
+        if (ve) sum += P.c[3] * xe;
+        if (hN) sum += P.c[4] * xn[e];
+      }
+      res[e] = sum;
+    }
+    st16(out + p, res);
   }
 }
 
@@ -374,14 +505,6 @@ __global__ __launch_bounds__(kBlock) void k_grad_dia5(int nx, int ny, const doub
 }
 
 // constant stencil: dL/dc_d = sum_p -lambda_p x_{p + off_d} over existing entries
-struct GradStVis {
-  const double* __restrict__ x;
-  double lam;
-  double acc[7];
-  int d;
-  __device__ __forceinline__ void operator()(double, int64_t j) { acc[d++] += -lam * x[j]; }
-};
-
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_grad_st(int nx, int ny, int nz,
                                                     const double* __restrict__ lam,
@@ -569,8 +692,46 @@ static void with_op(Solver& S, bool tr, bool use_pc, F&& f) {
 
 #define PBCG_GRID_OP dim3(S.nblk), dim3(kBlock), 0, st
 
+template <typename T>
+static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* out, int fin_mode,
+                            hipStream_t st) {
+  constexpr int R = V16<T>::n;
+  if (o.kind == OP_SELL || o.dims[0] % R != 0) return false;
+  StParams<T> P;
+  P.kind = o.kind;
+  P.nx = o.dims[0]; P.ny = o.dims[1]; P.nz = o.dims[2];
+  for (int d = 0; d < 7; ++d) P.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
+  P.dia = (const T*)o.dia;
+  P.ld = S.npad;
+  const int64_t ntiles = (S.n + (int64_t)kBlock * R - 1) / ((int64_t)kBlock * R);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(S.nblk + 1), dim3(kBlock), 0, st, P, (const T*)in, (T*)out,
+                       (const T*)S.dinv, (T)S.dinv_s, S.n, ntiles, S.nblk, S.sc, S.partials,
+                       fin_mode, S.nblk);
+  };
+  const bool pc = S.pc != PC_NONE;
+  switch (o.kind) {
+    case OP_ST2D5:
+      if (pc) go(k_spmv_st<T, PC_SCALAR, OP_ST2D5>); else go(k_spmv_st<T, PC_NONE, OP_ST2D5>);
+      break;
+    case OP_ST3D7:
+      if (pc) go(k_spmv_st<T, PC_SCALAR, OP_ST3D7>); else go(k_spmv_st<T, PC_NONE, OP_ST3D7>);
+      break;
+    case OP_DIA5:
+      if (pc) go(k_spmv_st<T, PC_VECTOR, OP_DIA5>); else go(k_spmv_st<T, PC_NONE, OP_DIA5>);
+      break;
+  }
+  return true;
+}
+
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
                  hipStream_t st) {
+  if (!dot_rhat && S.spmv_tiled) {
+    const OpData& o = op_of(S, tr);
+    const bool done = S.precision == 0 ? spmv_structured<double>(S, o, in, out, fin_mode, st)
+                                       : spmv_structured<float>(S, o, in, out, fin_mode, st);
+    if (done) return;
+  }
   with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
     hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(S.nblk + 1), dim3(kBlock), 0, st, op,
                        (const T*)in, (T*)out, (const T*)S.dinv, (T)S.dinv_s,

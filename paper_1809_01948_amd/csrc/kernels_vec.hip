@@ -36,19 +36,22 @@ struct PhaseAArgs {
 // In iteration 0 the previous vectors are zero and beta_0 = 0.  After a
 // residual replacement (SAVED) n_{i-1} is formed from the saved
 // pre-replacement z_{i-1} instead of the replaced one.
-template <typename T, int PC, bool SAVED>
+// Each thread handles C = U * (16 bytes / sizeof(T)) consecutive elements per
+// tile; NT selects non-temporal loads and stores.
+template <typename T, int PC, int U, bool NT, bool SAVED>
 __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T wp,
                                             double (&acc)[2], int64_t ntiles) {
-  constexpr int W = V16<T>::n;
+  constexpr int C = U * V16<T>::n;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t i = (tile * kBlock + threadIdx.x) * W;
-    T k[W], w[W], t[W], r[W], v[W], g[W], s[W], l[W], z[W], zp[W], d[W];
-    ld16(A.k + i, k); ld16(A.w + i, w); ld16(A.t + i, t); ld16(A.r + i, r); ld16(A.v + i, v);
-    ld16(A.g + i, g); ld16(A.s + i, s); ld16(A.l + i, l); ld16(A.z + i, z);
-    if (SAVED) ld16(A.zsave + i, zp);
-    if (PC == PC_VECTOR) ld16(A.dinv + i, d);
+    const int64_t i = (tile * kBlock + threadIdx.x) * C;
+    T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C];
+    ldc<T, C, NT>(A.k + i, k); ldc<T, C, NT>(A.w + i, w); ldc<T, C, NT>(A.t + i, t);
+    ldc<T, C, NT>(A.r + i, r); ldc<T, C, NT>(A.v + i, v); ldc<T, C, NT>(A.g + i, g);
+    ldc<T, C, NT>(A.s + i, s); ldc<T, C, NT>(A.l + i, l); ldc<T, C, NT>(A.z + i, z);
+    if (SAVED) ldc<T, C, NT>(A.zsave + i, zp);
+    if (PC == PC_VECTOR) ldc<T, C, NT>(A.dinv + i, d);
 #pragma unroll
-    for (int e = 0; e < W; ++e) {
+    for (int e = 0; e < C; ++e) {
       const T de = (PC == PC_VECTOR) ? d[e] : A.dinv_s;
       const T zprev = SAVED ? zp[e] : z[e];
       const T m = (PC == PC_NONE) ? w[e] : de * w[e];
@@ -63,18 +66,19 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T 
       acc[0] += (double)q * (double)y;
       acc[1] += (double)y * (double)y;
     }
-    st16(A.g + i, g); st16(A.s + i, s); st16(A.l + i, l); st16(A.z + i, z);
+    stc<T, C, NT>(A.g + i, g); stc<T, C, NT>(A.s + i, s); stc<T, C, NT>(A.l + i, l);
+    stc<T, C, NT>(A.z + i, z);
   }
 }
 
-template <typename T, int PC>
+template <typename T, int PC, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, const DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
   if (sc->done) return;
   const T a = (T)sc->alpha, b = (T)sc->beta, wp = (T)sc->omega_prev;
   double acc[2] = {0.0, 0.0};
-  if (sc->n_saved) phaseA_body<T, PC, true>(A, a, b, wp, acc, ntiles);
-  else phaseA_body<T, PC, false>(A, a, b, wp, acc, ntiles);
+  if (sc->n_saved) phaseA_body<T, PC, U, NT, true>(A, a, b, wp, acc, ntiles);
+  else phaseA_body<T, PC, U, NT, false>(A, a, b, wp, acc, ntiles);
   const int slots[2] = {SL_QY, SL_YY};
   block_partials<2>(acc, slots, partials, blockIdx.x);
 }
@@ -104,30 +108,26 @@ struct PhaseBArgs {
 //   w_{i+1} = y_i - omega_i (t_i - alpha_i v_i)
 // in place, and the GLRED 2 partials (r0, r_{i+1}), (r0, w_{i+1}), (r0, s_i),
 // (r0, z_i), (r_{i+1}, r_{i+1}).
-template <typename T, int PC>
+template <typename T, int PC, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
   if (sc->done) return;
-  constexpr int W = V16<T>::n;
+  constexpr int C = U * V16<T>::n;
   const double alpha = sc->alpha, omega = sc->omega;
   const T a = (T)alpha, om = (T)omega;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t i = (tile * kBlock + threadIdx.x) * W;
-    T g[W], l[W], s[W], z[W], t[W], v[W], rh[W], r[W], k[W], w[W], d[W];
-    double x[W];
-    ld16(B.g + i, g); ld16(B.l + i, l); ld16(B.s + i, s); ld16(B.z + i, z);
-    ld16(B.t + i, t); ld16(B.v + i, v); ld16(B.rhat + i, rh); ld16(B.r + i, r);
-    ld16(B.k + i, k); ld16(B.w + i, w);
+    const int64_t i = (tile * kBlock + threadIdx.x) * C;
+    T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C];
+    double x[C];
+    ldc<T, C, NT>(B.g + i, g); ldc<T, C, NT>(B.l + i, l); ldc<T, C, NT>(B.s + i, s);
+    ldc<T, C, NT>(B.z + i, z); ldc<T, C, NT>(B.t + i, t); ldc<T, C, NT>(B.v + i, v);
+    ldc<T, C, NT>(B.rhat + i, rh); ldc<T, C, NT>(B.r + i, r); ldc<T, C, NT>(B.k + i, k);
+    ldc<T, C, NT>(B.w + i, w);
+    ldc<double, C, NT>(B.x + i, x);
+    if (PC == PC_VECTOR) ldc<T, C, NT>(B.dinv + i, d);
 #pragma unroll
-    for (int h = 0; h < W; h += 2) {
-      double xx[2];
-      ld16(B.x + i + h, xx);
-      x[h] = xx[0]; x[h + 1] = xx[1];
-    }
-    if (PC == PC_VECTOR) ld16(B.dinv + i, d);
-#pragma unroll
-    for (int e = 0; e < W; ++e) {
+    for (int e = 0; e < C; ++e) {
       const T de = (PC == PC_VECTOR) ? d[e] : B.dinv_s;
       const T m = (PC == PC_NONE) ? w[e] : de * w[e];
       const T n = (PC == PC_NONE) ? z[e] : de * z[e];
@@ -146,12 +146,8 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevSca
       acc[3] += rhd * (double)z[e];
       acc[4] += (double)rn * (double)rn;
     }
-    st16(B.r + i, r); st16(B.k + i, k); st16(B.w + i, w);
-#pragma unroll
-    for (int h = 0; h < W; h += 2) {
-      double xx[2] = {x[h], x[h + 1]};
-      st16(B.x + i + h, xx);
-    }
+    stc<T, C, NT>(B.r + i, r); stc<T, C, NT>(B.k + i, k); stc<T, C, NT>(B.w + i, w);
+    stc<double, C, NT>(B.x + i, x);
   }
   const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
   block_partials<5>(acc, slots, partials, blockIdx.x);
@@ -255,6 +251,21 @@ __global__ void k_to_double(const T* __restrict__ src, double* __restrict__ dst,
     dst[i] = (double)src[i];
 }
 
+// plain FP64 copy with the same tiling as the phase kernels (bandwidth calibration)
+__global__ __launch_bounds__(kBlock) void k_copy(const double* __restrict__ src,
+                                                 double* __restrict__ dst, int64_t ntiles) {
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t i = (tile * kBlock + threadIdx.x) * 2;
+    double v[2];
+    ld16(src + i, v);
+    st16(dst + i, v);
+  }
+}
+
+void launch_copy(Solver& S, const double* src, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(S.nblk), dim3(kBlock), 0, st, src, dst, S.npad / (kBlock * 2));
+}
+
 __global__ void k_set_done(DevScalars* sc, int value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sc->done = value;
 }
@@ -278,8 +289,16 @@ static void phaseA_t(Solver& S, hipStream_t st) {
   a.g = (T*)S.vec[V_G]; a.s = (T*)S.vec[V_S]; a.l = (T*)S.vec[V_L]; a.z = (T*)S.vec[V_Z];
   a.zsave = (const T*)S.vec[V_TMP];
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
-  hipLaunchKernelGGL((k_phaseA<T, PC>), dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials,
-                     S.vtiles);
+  const int64_t nt = S.npad / (kBlock * S.vunroll * V16<T>::n);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials, nt);
+  };
+  const bool ntm = (S.vnt & 1) != 0;
+  if (S.vunroll == 2) {
+    if (ntm) go(k_phaseA<T, PC, 2, true>); else go(k_phaseA<T, PC, 2, false>);
+  } else {
+    if (ntm) go(k_phaseA<T, PC, 1, true>); else go(k_phaseA<T, PC, 1, false>);
+  }
 }
 
 template <typename T, int PC>
@@ -291,8 +310,16 @@ static void phaseB_t(Solver& S, hipStream_t st) {
   a.rhat = (const T*)S.vec[V_RHAT];
   a.r = (T*)S.vec[V_R]; a.k = (T*)S.vec[V_K]; a.w = (T*)S.vec[V_W];
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
-  hipLaunchKernelGGL((k_phaseB<T, PC>), dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials,
-                     S.vtiles);
+  const int64_t nt = S.npad / (kBlock * S.vunroll * V16<T>::n);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials, nt);
+  };
+  const bool ntm = (S.vnt & 2) != 0;
+  if (S.vunroll == 2) {
+    if (ntm) go(k_phaseB<T, PC, 2, true>); else go(k_phaseB<T, PC, 2, false>);
+  } else {
+    if (ntm) go(k_phaseB<T, PC, 1, true>); else go(k_phaseB<T, PC, 1, false>);
+  }
 }
 
 template <typename T, int PC>

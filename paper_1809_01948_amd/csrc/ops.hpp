@@ -1,12 +1,15 @@
 // Sparse operators of the library, as row visitors.
 //
-// Each operator exposes `row(i, vis)`, which calls `vis(a_ij, j)` for the
-// stored entries of row i in ascending column order.  The visitor decides
-// what is computed (an SPMV with the Jacobi preconditioner fused into the
-// input, two products at once for residual replacement, a residual in FP64,
-// a gradient ...).  Summing in ascending column order, one rounding per
-// multiply and per add (the library is compiled without FMA contraction),
-// reproduces a sequential CSR product exactly.
+// Each operator exposes `row(i, vis)`.  A visitor provides
+//   V load(j)        the input value(s) needed from column j, and
+//   add(a_ij, v)     accumulation of one stored entry,
+// and the operator calls add() for the stored entries of row i in ascending
+// column order.  Every load of a row is issued before the first add (loads of
+// entries that do not exist are redirected to the row itself and their adds
+// skipped), so a row costs one memory round trip instead of one per entry.
+// Summing in ascending column order, one rounding per multiply and per add
+// (the library is compiled without FMA contraction), reproduces a sequential
+// CSR product exactly.
 #pragma once
 
 #include "common.hpp"
@@ -23,6 +26,7 @@ struct SellOp {
   const int64_t* __restrict__ sptr;
   const int32_t* __restrict__ col;
   const T* __restrict__ val;
+  static constexpr int kGroup = 8;   // entries whose loads are issued together
   template <class Vis>
   __device__ __forceinline__ void row(int64_t i, Vis& vis) const {
     const int64_t s = i >> 6;
@@ -31,9 +35,21 @@ struct SellOp {
     const int w = (int)((sptr[s + 1] - off) >> 6);
     const int32_t* c = col + off + lane;
     const T* a = val + off + lane;
-    for (int j = 0; j < w; ++j) {
-      const int32_t cj = c[(int64_t)j * kSellC];
-      if (cj >= 0) vis(a[(int64_t)j * kSellC], (int64_t)cj);
+    for (int j0 = 0; j0 < w; j0 += kGroup) {
+      int32_t cj[kGroup];
+      T aj[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) {
+        const int jj = min(j0 + u, w - 1);
+        cj[u] = c[(int64_t)jj * kSellC];
+        aj[u] = a[(int64_t)jj * kSellC];
+      }
+      typename Vis::V xv[kGroup];
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u) xv[u] = vis.load(cj[u] >= 0 ? (int64_t)cj[u] : i);
+#pragma unroll
+      for (int u = 0; u < kGroup; ++u)
+        if (j0 + u < w && cj[u] >= 0) vis.add(aj[u], xv[u]);
     }
   }
 };
@@ -49,11 +65,17 @@ struct St2d5Op {
     const int p = (int)i;
     const int iy = p / nx;
     const int ix = p - iy * nx;
-    if (iy > 0) vis(c[0], (int64_t)(p - nx));
-    if (ix > 0) vis(c[1], (int64_t)(p - 1));
-    vis(c[2], (int64_t)p);
-    if (ix < nx - 1) vis(c[3], (int64_t)(p + 1));
-    if (iy < ny - 1) vis(c[4], (int64_t)(p + nx));
+    const bool hS = iy > 0, hW = ix > 0, hE = ix < nx - 1, hN = iy < ny - 1;
+    const auto xS = vis.load((int64_t)(hS ? p - nx : p));
+    const auto xW = vis.load((int64_t)(hW ? p - 1 : p));
+    const auto xC = vis.load((int64_t)p);
+    const auto xE = vis.load((int64_t)(hE ? p + 1 : p));
+    const auto xN = vis.load((int64_t)(hN ? p + nx : p));
+    if (hS) vis.add(c[0], xS);
+    if (hW) vis.add(c[1], xW);
+    vis.add(c[2], xC);
+    if (hE) vis.add(c[3], xE);
+    if (hN) vis.add(c[4], xN);
   }
 };
 
@@ -71,13 +93,22 @@ struct St3d7Op {
     const int rem = p - iz * nxy;
     const int iy = rem / nx;
     const int ix = rem - iy * nx;
-    if (iz > 0) vis(c[0], (int64_t)(p - nxy));
-    if (iy > 0) vis(c[1], (int64_t)(p - nx));
-    if (ix > 0) vis(c[2], (int64_t)(p - 1));
-    vis(c[3], (int64_t)p);
-    if (ix < nx - 1) vis(c[4], (int64_t)(p + 1));
-    if (iy < ny - 1) vis(c[5], (int64_t)(p + nx));
-    if (iz < nz - 1) vis(c[6], (int64_t)(p + nxy));
+    const bool hD = iz > 0, hS = iy > 0, hW = ix > 0, hE = ix < nx - 1, hN = iy < ny - 1,
+               hU = iz < nz - 1;
+    const auto xD = vis.load((int64_t)(hD ? p - nxy : p));
+    const auto xS = vis.load((int64_t)(hS ? p - nx : p));
+    const auto xW = vis.load((int64_t)(hW ? p - 1 : p));
+    const auto xC = vis.load((int64_t)p);
+    const auto xE = vis.load((int64_t)(hE ? p + 1 : p));
+    const auto xN = vis.load((int64_t)(hN ? p + nx : p));
+    const auto xU = vis.load((int64_t)(hU ? p + nxy : p));
+    if (hD) vis.add(c[0], xD);
+    if (hS) vis.add(c[1], xS);
+    if (hW) vis.add(c[2], xW);
+    vis.add(c[3], xC);
+    if (hE) vis.add(c[4], xE);
+    if (hN) vis.add(c[5], xN);
+    if (hU) vis.add(c[6], xU);
   }
 };
 
@@ -93,11 +124,19 @@ struct Dia5Op {
     const int p = (int)i;
     const int iy = p / nx;
     const int ix = p - iy * nx;
-    if (iy > 0) vis(dia[i], (int64_t)(p - nx));
-    if (ix > 0) vis(dia[ld + i], (int64_t)(p - 1));
-    vis(dia[2 * ld + i], (int64_t)p);
-    if (ix < nx - 1) vis(dia[3 * ld + i], (int64_t)(p + 1));
-    if (iy < ny - 1) vis(dia[4 * ld + i], (int64_t)(p + nx));
+    const bool hS = iy > 0, hW = ix > 0, hE = ix < nx - 1, hN = iy < ny - 1;
+    const T cS = dia[i], cW = dia[ld + i], cC = dia[2 * ld + i], cE = dia[3 * ld + i],
+            cN = dia[4 * ld + i];
+    const auto xS = vis.load((int64_t)(hS ? p - nx : p));
+    const auto xW = vis.load((int64_t)(hW ? p - 1 : p));
+    const auto xC = vis.load((int64_t)p);
+    const auto xE = vis.load((int64_t)(hE ? p + 1 : p));
+    const auto xN = vis.load((int64_t)(hN ? p + nx : p));
+    if (hS) vis.add(cS, xS);
+    if (hW) vis.add(cW, xW);
+    vis.add(cC, xC);
+    if (hE) vis.add(cE, xE);
+    if (hN) vis.add(cN, xN);
   }
 };
 
@@ -118,10 +157,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
   switch (mode) {
     case FIN_INIT: {
       // Algorithm 2 initialisation: rho_0 = (r0, r0), alpha_0 = rho_0 / (r0, w0)
-      const double rho = block_sum_slot(partials, SL_RR0, nblk);
-      const double rw = block_sum_slot(partials, SL_RW0, nblk);
-      const double rr = block_sum_slot(partials, SL_RR, nblk);
-      const double bb = block_sum_slot(partials, SL_BB, nblk);
+      const int sl[4] = {SL_RR0, SL_RW0, SL_RR, SL_BB};
+      double v[4];
+      block_sum_slots<4>(partials, sl, nblk, v);
+      const double rho = v[0], rw = v[1], rr = v[2], bb = v[3];
       if (t0) {
         sc->sig[SL_RR0] = rho; sc->sig[SL_RW0] = rw; sc->sig[SL_RR] = rr; sc->sig[SL_BB] = bb;
         sc->rho = rho;
@@ -143,8 +182,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
     case FIN_OMEGA:
     case FIN_C_OMEGA: {
       // omega_i = (q_i, y_i) / (y_i, y_i); (y, y) = 0 gives omega = 0
-      const double s1 = block_sum_slot(partials, SL_QY, nblk);
-      const double s2 = block_sum_slot(partials, SL_YY, nblk);
+      const int sl[2] = {SL_QY, SL_YY};
+      double v[2];
+      block_sum_slots<2>(partials, sl, nblk, v);
+      const double s1 = v[0], s2 = v[1];
       if (t0) {
         sc->sig[SL_QY] = s1; sc->sig[SL_YY] = s2;
         sc->n_saved = 0;                       // phase A of this iteration has consumed it
@@ -157,11 +198,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
     case FIN_REDO: {
       // GLRED 2: beta_{i+1} = (alpha_i/omega_i) (r0,r_{i+1})/(r0,r_i),
       // alpha_{i+1} = (r0,r_{i+1}) / ((r0,w_{i+1}) + beta (r0,s_i) - beta omega (r0,z_i))
-      const double rho1 = block_sum_slot(partials, SL_RR0, nblk);
-      const double rw = block_sum_slot(partials, SL_RW0, nblk);
-      const double rs = block_sum_slot(partials, SL_RS0, nblk);
-      const double rz = block_sum_slot(partials, SL_RZ0, nblk);
-      const double rr = block_sum_slot(partials, SL_RR, nblk);
+      const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+      double v[5];
+      block_sum_slots<5>(partials, sl, nblk, v);
+      const double rho1 = v[0], rw = v[1], rs = v[2], rz = v[3], rr = v[4];
       if (t0) {
         sc->sig[SL_RR0] = rho1; sc->sig[SL_RW0] = rw; sc->sig[SL_RS0] = rs;
         sc->sig[SL_RZ0] = rz; sc->sig[SL_RR] = rr;
@@ -216,9 +256,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
     }
     case FIN_C_INIT: {
       // Algorithm 1 initialisation: rho_0 = (r0, r0)
-      const double rho = block_sum_slot(partials, SL_RR0, nblk);
-      const double rr = block_sum_slot(partials, SL_RR, nblk);
-      const double bb = block_sum_slot(partials, SL_BB, nblk);
+      const int sl[3] = {SL_RR0, SL_RR, SL_BB};
+      double v[3];
+      block_sum_slots<3>(partials, sl, nblk, v);
+      const double rho = v[0], rr = v[1], bb = v[2];
       if (t0) {
         sc->rho = rho;
         sc->rn0 = sqrt(rr);
@@ -243,8 +284,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       break;
     }
     case FIN_C_BETA: {
-      const double rho1 = block_sum_slot(partials, SL_RR0, nblk);
-      const double rr = block_sum_slot(partials, SL_RR, nblk);
+      const int sl[2] = {SL_RR0, SL_RR};
+      double v[2];
+      block_sum_slots<2>(partials, sl, nblk, v);
+      const double rho1 = v[0], rr = v[1];
       if (t0) {
         sc->sig[SL_RR0] = rho1; sc->sig[SL_RR] = rr;
         const int its = ++sc->iter;
@@ -273,11 +316,20 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       }
       break;
     }
+    case FIN_PROBE: {
+      const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+      double v[5];
+      block_sum_slots<5>(partials, sl, nblk, v);
+      if (t0)
+        for (int d = 0; d < 5; ++d) sc->sig[sl[d]] = v[d];
+      break;
+    }
     case FIN_SUM: {
-      for (int j = 0; j < aux; ++j) {
-        const double v = block_sum_slot(partials, j, nblk);
-        if (t0) sc->sums[j] = v;
-      }
+      const int sl[kNumSlots] = {0, 1, 2, 3, 4, 5, 6, 7};
+      double v[kNumSlots];
+      block_sum_slots<kNumSlots>(partials, sl, nblk, v);
+      if (t0)
+        for (int j = 0; j < aux && j < kNumSlots; ++j) sc->sums[j] = v[j];
       break;
     }
     default:

@@ -64,6 +64,9 @@ struct Solver {
   DevScalars* h_sc = nullptr;   // pinned, 2 entries (double-buffered poll)
 
   int nblk = 8;                 // blocks of every streaming kernel (multiple of 8)
+  int vunroll = 1;              // 16-byte chunks per thread and tile in the phase kernels
+  int vnt = 0;                  // non-temporal loads/stores: bit 0 phase A, bit 1 phase B
+  bool spmv_tiled = true;       // several consecutive rows per thread for structured operators
   int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
   int64_t rtiles = 0;           // tiles of 256 rows
 
@@ -88,6 +91,7 @@ void launch_cl_p(Solver& S, hipStream_t st);
 void launch_fill_zero(Solver& S, void* ptr, int64_t count, size_t elem, hipStream_t st);
 void launch_to_double(Solver& S, const void* src, double* dst, int64_t n, hipStream_t st);
 void launch_set_done(Solver& S, int value, hipStream_t st);
+void launch_copy(Solver& S, const double* src, double* dst, hipStream_t st);
 
 // ---- launchers (kernels_op.hip) ----
 const OpData& op_of(Solver& S, bool transpose);
