@@ -102,6 +102,19 @@ class Float64Ops:
     def prec(self, v):
         return v.copy() if self.dinv is None else self.dinv * v
 
+    def norm_bound_A(self):
+        """Upper bound sqrt(||A||_1 ||A||_inf) of ||A||_2."""
+        absA = abs(self.A)
+        n1 = float(np.max(np.asarray(absA.sum(axis=0)).ravel()))
+        ninf = float(np.max(np.asarray(absA.sum(axis=1)).ravel()))
+        return math.sqrt(n1 * ninf)
+
+    def max_row_nnz(self):
+        return int(np.max(np.diff(self.A.indptr)))
+
+    def norm_bound_M(self):
+        return 1.0 if self.dinv is None else float(np.max(np.abs(self.dinv)))
+
     def dot(self, v, w):
         return float(np.dot(v, w))
 
@@ -197,6 +210,7 @@ class SolveResult:
     beta: list = field(default_factory=list)      # beta_{i+1} formed at the end of iteration i
     rnorm: list = field(default_factory=list)     # ||r_{i+1}|| after iteration i
     rr_iters: list = field(default_factory=list)  # iterations i in which a replacement ran
+    fr: list = field(default_factory=list)        # f^r_{i+1} after iteration i (automated mode)
     true_rel_res: Optional[float] = None
     snapshots: list = field(default_factory=list)
 
@@ -289,17 +303,95 @@ def classic_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, record=False):
 # Algorithm 2: preconditioned pipelined BiCGStab, with residual replacement
 # -----------------------------------------------------------------------------
 
+class _GapBound:
+    """Running bound f^r on the residual gap (Section 3.6, eq:DDr_bound).
+
+    The local rounding errors of iteration i are bounded with
+    eq:errbounds1-4 (epsilon = `eps`, mu = max nonzeros per row of A,
+    mu~ = 1 for a diagonal M^-1, ||A|| and ||M^-1|| upper bounds), the gap
+    norms ||Delta^s||, ||Delta^w||, ||Delta^z|| by the triangle inequality
+    applied to eq:Ds, eq:Dw, eq:Dz, and f^r accumulates them as eq:DDr_bound
+    does, one iteration at a time.  A replacement resets the bounds to the
+    errors of the explicit recomputation (the initial-gap bounds of
+    Section 3.2)."""
+
+    def __init__(self, N, mu, nA, nM, eps, nb):
+        self.N, self.mu, self.nA, self.nM, self.eps, self.nb = N, mu, nA, nM, eps, nb
+        self.smu = mu * math.sqrt(N) * nA          # mu sqrt(N) ||A||
+        self.smut = math.sqrt(N) * nM              # mu~ sqrt(N) ||M^-1||, mu~ = 1
+        self.prev = dict(g=0.0, s=0.0, l=0.0, z=0.0, n=0.0, v=0.0)
+        self.ds_prev = 0.0
+        self.dz_prev = 0.0
+
+    def start(self, nx, nk):
+        """f^r_0 and ||Delta^w_0|| for r_0 = b - A x_0, w_0 = A k_0."""
+        self.f = ((self.mu * math.sqrt(self.N) + 1.0) * self.nA * nx + self.nb) * self.eps
+        self.dw = self.smu * nk * self.eps
+        return self.f
+
+    def step(self, a, b, w, wp, nm):
+        """Advance over iteration i.  `nm` holds the norms of the iteration-i
+        vectors x, g, u, q, y, r, s, k, l, w, z, m, t, n, v; a, b, w, wp are
+        |alpha_i|, |beta_i|, |omega_i|, |omega_{i-1}|.  Returns f^r_{i+1}."""
+        e, nA, smu, smut = self.eps, self.nA, self.smu, self.smut
+        P = self.prev
+        d_x = (2 * nm["x"] + 3 * a * nm["g"] + 2 * w * nm["u"]) * e
+        d_r = (nm["q"] + 2 * w * nm["y"]) * e
+        d_q = (nm["r"] + 2 * a * nm["s"]) * e
+        d_u = (nm["k"] + 2 * a * nm["l"]) * e
+        d_y = (nm["w"] + 2 * a * nm["z"]) * e
+        d_g = (nm["k"] + 3 * b * P["g"] + 4 * b * wp * P["l"]) * e
+        d_s = (nm["w"] + 3 * b * P["s"] + 4 * b * wp * P["z"]) * e
+        d_l = (nm["m"] + smut * nm["w"] + 3 * b * P["l"] + 4 * b * wp * P["n"]
+               + smut * b * wp * P["z"]) * e
+        d_z = (nm["t"] + smu * nm["m"] + smut * nA * nm["w"] + 3 * b * P["z"]
+               + 4 * b * wp * P["v"] + smu * b * wp * P["n"] + smut * nA * b * wp * P["z"]) * e
+        d_k = (nm["u"] + 3 * w * nm["m"] + smut * w * nm["w"] + 4 * w * a * nm["n"]
+               + smut * w * a * nm["z"]) * e
+        d_w = (nm["y"] + 3 * w * nm["t"] + smu * w * nm["m"] + smut * nA * w * nm["w"]
+               + 4 * w * a * nm["v"] + smu * w * a * nm["n"] + smut * nA * w * a * nm["z"]) * e
+        dz = b * self.dz_prev + nA * d_l + d_z                                   # eq:Dz
+        ds = self.dw + b * self.ds_prev + b * wp * self.dz_prev + nA * d_g + d_s  # eq:Ds
+        f = (self.f + a * ds + w * self.dw + w * a * dz + nA * d_x + d_r          # eq:Dr
+             + w * nA * d_u + d_q + w * d_y)
+        dw = self.dw + a * dz + nA * d_k + d_w + nA * d_u + d_y                  # eq:Dw
+        self.f, self.dw, self.ds_prev, self.dz_prev = f, dw, ds, dz
+        self.prev = dict(g=nm["g"], s=nm["s"], l=nm["l"], z=nm["z"], n=nm["n"], v=nm["v"])
+        return f
+
+    def reset(self, nx, nk, ng, nl):
+        """After a replacement (eq:rr) from x_{i+1} and g_i."""
+        self.f = ((self.mu * math.sqrt(self.N) + 1.0) * self.nA * nx + self.nb) * self.eps
+        self.dw = self.smu * nk * self.eps
+        self.ds_prev = self.smu * ng * self.eps
+        self.dz_prev = self.smu * nl * self.eps
+        return self.f
+
+
 def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
-                       rr_tau=None, record=False):
-    """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with the periodic
-    residual replacement of Section 3.6 (eq:rr) when ``rr_period > 0``.
+                       rr_tau=None, rr_mode="periodic", rr_eps=None, record=False):
+    """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with residual
+    replacement (Section 3.6, eq:rr):
+
+    * ``rr_mode="periodic"``: every ``rr_period`` iterations while
+      ||r_i|| >= tau ||r_0|| (tau = sqrt(eps) by default);
+    * ``rr_mode="auto"``: the automated strategy -- the running bound f^r of
+      eq:DDr_bound (``_GapBound``, epsilon = ``rr_eps``, default the unit
+      roundoff) and the criterion eq:criterion: replace in step i when
+      f^r_{i-1} <= tau ||r_{i-1}|| and f^r_i > tau ||r_i||, tau = sqrt(eps).
 
     Two global reductions per iteration, each overlapped (on parallel
     hardware) by one PREC + SPMV: (q_i, y_i), (y_i, y_i) with
     n_i = M^-1 z_i, v_i = A n_i; and (r0, r_{i+1}), (r0, w_{i+1}),
     (r0, s_i), (r0, z_i) -- plus (r_{i+1}, r_{i+1}) for the stopping test --
-    with m_{i+1} = M^-1 w_{i+1}, t_{i+1} = A m_{i+1}."""
-    tau = math.sqrt(unit_roundoff()) if rr_tau is None else rr_tau
+    with m_{i+1} = M^-1 w_{i+1}, t_{i+1} = A m_{i+1}.  In automated mode the
+    norms entering the bound are reduced with the second global reduction
+    (Section 3.6: no extra synchronisation)."""
+    auto = rr_mode == "auto"
+    if rr_mode not in ("periodic", "auto"):
+        raise ValueError(rr_mode)
+    eps = unit_roundoff() if rr_eps is None else rr_eps
+    tau = math.sqrt(eps if auto else unit_roundoff()) if rr_tau is None else rr_tau
     b = ops.copy(b)
     x = ops.zeros() if x0 is None else ops.copy(x0)
     # initialisation (the two lines before the loop of Algorithm 2)
@@ -327,6 +419,12 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     beta = ops.zero()                         # beta_0 := 0
     omega_prev = ops.zero()                   # omega_{-1} (taken as 0)
     g, s, l, z, n, v = (ops.zeros() for _ in range(6))   # iteration -1 values (taken as 0)
+    gb = None
+    rr_next = False
+    if auto:
+        gb = _GapBound(ops.n, ops.max_row_nnz(), ops.norm_bound_A(), ops.norm_bound_M(), eps, nb)
+        f_cur = gb.start(ops.norm(x), ops.norm(k))
+        f_ok_prev = f_cur <= tau * rn0
 
     def replace(x, g):
         """eq:rr: explicit recomputation of r, k, w (from x) and s, l, z (from g)."""
@@ -355,6 +453,11 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
         if not ops.finite(sig1, sig2):                 # GLRED 1 ends
             return _finish(res, x, STATUS["NONFINITE"], i, ops, b)
         omega = sig1 / sig2 if sig2 != 0 else ops.zero()   # omega_i
+        if auto:   # norms of the iteration-i vectors (reduced with GLRED 2)
+            nm = {key: ops.norm(vec) for key, vec in
+                  (("x", x), ("g", g), ("u", u), ("q", q), ("y", y), ("r", r), ("s", s),
+                   ("k", k), ("l", l), ("w", w), ("z", z), ("m", m), ("t", t), ("n", n),
+                   ("v", v))}
         x_new = (x + alpha * g) + omega * u            # x_{i+1}
         r_new = q - omega * y                          # r_{i+1}
         k_new = u - omega * (m - alpha * n)            # k_{i+1}
@@ -366,13 +469,20 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                         n=n, v=v, x1=x_new, r1=r_new, k1=k_new, w1=w_new, replaced=False)
         x, r, k, w = x_new, r_new, k_new, w_new
         replaced = False
-        if rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0:
+        if auto:
+            f_next = gb.step(abs(float(alpha)), abs(float(beta)), abs(float(omega)),
+                             abs(float(omega_prev)), nm)
+        due = (rr_next if auto else
+               (rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0))
+        if due:
             r, k, w, s, l, z = replace(x, g)           # eq:rr, right after the w-update
             res.replacements += 1
             res.rr_iters.append(i)
             replaced = True
             if snap is not None:
                 snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
+            if auto:
+                f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l))
         rho_new = ops.dot(rhat, r)                     # GLRED 2 begins: (r0, r_{i+1}),
         rw = ops.dot(rhat, w)                          #   (r0, w_{i+1}), (r0, s_i),
         rs = ops.dot(rhat, s)                          #   (r0, z_i) and (r_{i+1}, r_{i+1})
@@ -387,11 +497,13 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                 res.alpha.append(alpha)
                 res.omega.append(omega)
                 res.rnorm.append(rn)
+                if auto:
+                    res.fr.append(f_next)
                 if snap is not None:
                     snap["replaced"] = replaced
                     res.snapshots.append(snap)
                 return _finish(res, x, STATUS["CONVERGED"], i + 1, ops, b)
-            if rr_period <= 0:
+            if rr_period <= 0 and not auto:
                 res.alpha.append(alpha)
                 res.omega.append(omega)
                 res.rnorm.append(rn)
@@ -402,12 +514,19 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
             replaced = True
             if snap is not None:
                 snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
+            if auto:
+                f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l))
             rho_new = ops.dot(rhat, r)
             rw = ops.dot(rhat, w)
             rs = ops.dot(rhat, s)
             rz = ops.dot(rhat, z)
             rr = ops.dot(r, r)
             rn = math.sqrt(float(rr))
+        if auto:   # eq:criterion for step i+1
+            f_ok = f_next <= tau * rn
+            rr_next = f_ok_prev and not f_ok
+            f_ok_prev = f_ok
+            res.fr.append(f_next)
         res.alpha.append(alpha)
         res.omega.append(omega)
         res.rnorm.append(rn)

@@ -110,3 +110,34 @@ def test_wrong_wiring_is_caught():
     errs = gaps.pipelined_local_errors(A, p.b, snaps)
     bounds = gaps.pipelined_error_bounds(A, errs, snaps)
     assert any(nv > bv for bd in bounds[1:] for (nv, bv) in [bd["d_g"]])
+
+
+def test_automated_bound_dominates_exact_gap():
+    """f^r of Section 3.6 (eq:DDr_bound) is an upper bound of the residual gap
+    ||(b - A x_i) - r_i||, here evaluated exactly in rational arithmetic
+    (rr_tau = 0 disables the replacements so the gap is never reset)."""
+    p = convdiff2d_c1(6)
+    A = p.scipy_csr()
+    d = 1.0 / A.diagonal()
+    res = pipelined_bicgstab(Float64Ops(A, d), p.b, tol=0.0, maxit=20, rr_mode="auto",
+                             rr_tau=0.0, record=True)
+    assert res.replacements == 0
+    errs = gaps.pipelined_local_errors(A, p.b, res.snapshots)
+    ratios = [gaps.exact_norm(e["Dr1"]) / f for e, f in zip(errs, res.fr)]
+    assert len(ratios) == 20
+    assert max(ratios) <= 1.0
+    assert min(ratios) > 0.0
+
+
+def test_automated_bound_after_replacements():
+    """With replacements the bound restarts from the recomputation error and
+    still dominates the exact gap in every later iteration."""
+    p = random_dense_system(9, 3, shift=5.0)
+    A = p.scipy_csr()
+    res = pipelined_bicgstab(Float64Ops(A), p.b, tol=0.0, maxit=14, rr_mode="auto",
+                             rr_tau=1e-3, record=True)
+    assert res.replacements >= 1
+    errs = gaps.pipelined_local_errors(A, p.b, res.snapshots)
+    for e, f, sn in zip(errs, res.fr, res.snapshots):
+        if not sn["replaced"]:
+            assert gaps.exact_norm(e["Dr1"]) <= f

@@ -283,3 +283,34 @@ def test_attainable_accuracy_ordering():
     assert cl < 1e-13
     assert pi > 10 * cl
     assert rr < 3 * cl
+
+
+def test_automated_replacement_behaviour():
+    """Section 4.5: with the automated criterion few replacements are made,
+    early in the iteration, and the attainable accuracy is that of classic
+    BiCGStab (compare test_attainable_accuracy_ordering)."""
+    p = convdiff2d_c1(32)
+    A = p.scipy_csr()
+    ops = Float64Ops(A)
+    nb = np.linalg.norm(p.b)
+    cl = classic_bicgstab(ops, p.b, tol=1e-30, maxit=300, record=True)
+    au = pipelined_bicgstab(ops, p.b, tol=1e-30, maxit=300, rr_mode="auto", record=True)
+    best = lambda r: min(np.linalg.norm(p.b - A @ s["x1"]) / nb for s in r.snapshots)
+    assert 1 <= au.replacements <= 10
+    assert max(au.rr_iters) < 100
+    assert best(au) < 3 * best(cl)
+    res = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000, rr_mode="auto")
+    assert res.status == STATUS["CONVERGED"] and res.true_rel_res <= 1e-10
+
+
+def test_automated_replacement_paper_tp2():
+    """The unsymmetric model problem of Table tab:specs (TP2), normalised to
+    ||A||_2 = 1, b = A 1/sqrt(N): with automated replacement p-BiCGStab
+    reaches a 1e-13 relative residual (Section 4.5 reports a few to ten
+    replacements on this problem at 1000^2; here 300^2)."""
+    from workloads import tp2_unsymmetric
+    p = tp2_unsymmetric(300)
+    ops = Float64Ops(p.scipy_csr())
+    res = pipelined_bicgstab(ops, p.b, tol=1e-13, maxit=3000, rr_mode="auto")
+    assert res.status == STATUS["CONVERGED"] and res.true_rel_res <= 1e-13
+    assert 1 <= res.replacements <= 20
