@@ -24,7 +24,8 @@ Printed (one JSON line):
                iterations of the same solve
   mixed_vs_fp64  time to a 1e-10 relative true residual on the 200^3
                convection-diffusion workload, FP32 storage + FP64 reductions
-               and replacement versus all FP64 (both replacement period 50)
+               and replacement versus all FP64 (periodic and automated
+               replacement)
 """
 
 from __future__ import annotations
@@ -52,11 +53,112 @@ def parse():
     ap.add_argument("--skip-mixed", action="store_true", help="omit the 200^3 mixed-vs-FP64 runs")
     ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--graph", type=int, default=1, help="replay iteration chunks from HIP graphs")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only launch phase B and the copy kernel on the workload (the short "
+                         "program that the rocprofv3 counter runs profile)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "--kernels-only into the traffic summary under profiles/")
     return ap.parse_args()
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "phaseB_poisson1000_fp64_traffic.txt")
+KERNEL_SOURCES = ("paper_1809_01948_amd/csrc/kernels_vec.hip", "paper_1809_01948_amd/csrc/common.hpp")
+KERNELS_ONLY_REPS = 20
+
+
+def kernel_source_hash():
+    """Hash of the sources phase B and the copy kernel are built from: a
+    stored counter reading is used only while they are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_pmc_dir(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc CSV run:
+    {kernel name: [value per dispatch]}."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {path}")
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir, n):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of phase B and of the
+    plain copy kernel; the copy's known bytes calibrate each counter."""
+    fetch = read_pmc_dir(fetch_dir, "FETCH_SIZE")
+    write = read_pmc_dir(write_dir, "WRITE_SIZE")
+
+    def pick(d, key):
+        vals = [v for k, vs in d.items() if key in k for v in vs]
+        if not vals:
+            raise SystemExit(f"no dispatch of {key} in the counter output")
+        return sum(vals) / len(vals), len(vals)
+
+    npad = (n + 2047) // 2048 * 2048
+    copy_bytes = 8 * npad                               # read once, written once
+    f_b, nf = pick(fetch, "k_phaseB")
+    w_b, nw = pick(write, "k_phaseB")
+    f_c, _ = pick(fetch, "k_copy")
+    w_c, _ = pick(write, "k_copy")
+    kf = copy_bytes / (f_c * 1024.0)
+    kw = copy_bytes / (w_c * 1024.0)
+    traffic = f_b * 1024.0 * kf + w_b * 1024.0 * kw
+    algo = 15 * 8 * npad
+    lines = [
+        "# phase B, Poisson 1000x1000 FP64 stencil + scalar Jacobi: HBM traffic per launch",
+        f"source_hash {kernel_source_hash()}",
+        "commands (from the repository root):",
+        "  rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -- python bench.py --kernels-only",
+        "  rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -- python bench.py --kernels-only",
+        "  python bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write",
+        f"dispatches phaseB fetch {nf} write {nw}",
+        f"FETCH_SIZE_KiB phaseB {f_b:.1f} copy {f_c:.1f}",
+        f"WRITE_SIZE_KiB phaseB {w_b:.1f} copy {w_c:.1f}",
+        f"copy_algorithmic_bytes_each_way {copy_bytes}",
+        f"calibration_fetch {kf:.4f}",
+        f"calibration_write {kw:.4f}",
+        f"phaseB_algorithmic_bytes {algo}",
+        f"phaseB_traffic_bytes {traffic:.0f}",
+        f"traffic_over_algorithmic {traffic / algo:.4f}",
+    ]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def stored_traffic():
+    """Calibrated HBM bytes per phase B launch, or None when no counter
+    reading exists for the current kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) == 2:
+                    kv[parts[0]] = parts[1]
+        if kv.get("source_hash") != kernel_source_hash():
+            return None
+        return float(kv["phaseB_traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(prob, iters):
@@ -88,6 +190,9 @@ def cpu_baseline(prob, iters):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], 1000 * 1000)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
@@ -99,9 +204,17 @@ def main():
 
     dev = torch.device("cuda:0")
     log("generating 1000x1000 Poisson workload")
-    prob = poisson2d_c2(1000, with_csr=not args.skip_cpu)
+    prob = poisson2d_c2(1000, with_csr=not (args.skip_cpu or args.kernels_only))
     b = torch.from_numpy(prob.b).to(dev)
     S = Solver.from_problem(prob, form="stencil", precision="fp64", precond="jacobi")
+    if args.kernels_only:
+        S.solve(b, tol=1e-10, maxit=50, rr_period=50)      # realistic vector contents
+        ms_b = S.time_kernel("phaseB", reps=KERNELS_ONLY_REPS)
+        ms_c = S.time_kernel("copy", reps=KERNELS_ONLY_REPS)
+        print(json.dumps({"phaseB_ms": ms_b, "copy_ms": ms_c, "reps": KERNELS_ONLY_REPS}),
+              flush=True)
+        S.close()
+        return
     opts = dict(tol=1e-10, maxit=ITERS_PER_STEP, rr_period=50, use_graph=bool(args.graph))
 
     for w in range(args.warmup):
@@ -148,7 +261,7 @@ def main():
 
     # full solves of the same workload to a 1e-10 true residual
     sol = {}
-    for name, kw in (("pipelined_rr200", dict(rr_period=200, method="pipelined")),
+    for name, kw in (("pipelined_auto_rr", dict(rr_auto=True, method="pipelined")),
                      ("classic", dict(method="classic"))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -182,7 +295,7 @@ def main():
                    "graph": bool(args.graph)},
         "hbm_gbps_effective": eff_gbs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
                      "kernel": "phaseB", "algorithmic_bytes_per_launch": phaseB_bytes,
                      "avg_launch_ms": ms_b},
         "kernels": kernels,
@@ -194,18 +307,19 @@ def main():
         p3 = convdiff3d_c3(200)
         b3 = torch.from_numpy(p3.b).to(dev)
         mv = {}
-        for prec, P in (("fp64", 50), ("fp64", 100), ("mixed", 50), ("mixed", 100)):
+        for prec, P in (("fp64", 50), ("fp64", 100), ("fp64", "auto"),
+                        ("mixed", 10), ("mixed", 25), ("mixed", "auto")):
             S3 = Solver.from_problem(p3, form="stencil", precision=prec, precond="jacobi")
-            S3.solve(b3, tol=1e-10, maxit=300, rr_period=P, use_graph=bool(args.graph))
+            rr = dict(rr_auto=True) if P == "auto" else dict(rr_period=P)
+            S3.solve(b3, tol=1e-10, maxit=300, use_graph=bool(args.graph), **rr)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x3, st3 = S3.solve(b3, tol=1e-10, maxit=20000, rr_period=P,
-                               use_graph=bool(args.graph))
+            x3, st3 = S3.solve(b3, tol=1e-10, maxit=20000, use_graph=bool(args.graph), **rr)
             torch.cuda.synchronize()
             t3 = time.perf_counter() - t0
             xerr = float(torch.linalg.norm(x3 - torch.from_numpy(p3.x_exact).to(dev)) /
                          np.linalg.norm(p3.x_exact))
-            key = f"{prec}_rr{P}"
+            key = f"{prec}_rr_{P}"
             mv[key] = {"seconds": t3, "iterations": st3["iterations"],
                        "replacements": st3["replacements"], "status": st3["status_name"],
                        "rel_res_true": st3["rel_res_true"], "rel_err_vs_exact": xerr,

@@ -98,6 +98,17 @@ typedef struct {
   int32_t gap_len;
   int32_t use_graph;     /* nonzero: replay chunks of iterations from captured HIP graphs */
   void* stream;          /* hipStream_t */
+  int32_t rr_auto;       /* automated residual replacement (Section 3.6) instead of rr_period:
+                            the running bound f^r of eq:DDr_bound on the residual gap, built
+                            from the local error bounds eq:errbounds1-4 with epsilon rr_eps
+                            (the bound restarts after a replacement with the FP64 unit
+                            roundoff, the arithmetic of the replacement), replaces in step i
+                            when f^r_{i-1} <= tau ||r_{i-1}|| and f^r_i > tau ||r_i||
+                            (eq:criterion), tau = rr_tau or sqrt(rr_eps).
+                            1: the worst-case bound; 2: its square-root estimate (mu sqrt(N)
+                            -> sqrt(mu), mu~ sqrt(N) -> 1); 0: periodic replacement */
+  double rr_eps;         /* epsilon of the bound; 0 selects the unit roundoff of the storage
+                            precision (2^-53 FP64, 2^-24 mixed) */
 } pbcg_opts;
 
 typedef struct {
@@ -113,7 +124,8 @@ typedef struct {
 } pbcg_stats;
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
- * check_every 0, transpose 0, no history, use_graph 0, stream NULL. */
+ * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
+ * rr_eps 0. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

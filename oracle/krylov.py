@@ -315,19 +315,22 @@ class _GapBound:
     errors of the explicit recomputation (the initial-gap bounds of
     Section 3.2)."""
 
-    def __init__(self, N, mu, nA, nM, eps, nb):
+    def __init__(self, N, mu, nA, nM, eps, nb, estimate=False, eps_replace=None):
         self.N, self.mu, self.nA, self.nM, self.eps, self.nb = N, mu, nA, nM, eps, nb
-        self.smu = mu * math.sqrt(N) * nA          # mu sqrt(N) ||A||
-        self.smut = math.sqrt(N) * nM              # mu~ sqrt(N) ||M^-1||, mu~ = 1
+        self.eps_r = eps if eps_replace is None else eps_replace
+        # worst-case factors of eq:errbounds1-4, or their square-root estimates
+        # (the typical size of accumulated rounding errors, Section 3.6)
+        self.cmu = math.sqrt(mu) if estimate else mu * math.sqrt(N)    # mu sqrt(N)
+        self.cmut = 1.0 if estimate else math.sqrt(N)                   # mu~ sqrt(N), mu~ = 1
+        self.smu = self.cmu * nA
+        self.smut = self.cmut * nM
         self.prev = dict(g=0.0, s=0.0, l=0.0, z=0.0, n=0.0, v=0.0)
         self.ds_prev = 0.0
         self.dz_prev = 0.0
 
     def start(self, nx, nk):
         """f^r_0 and ||Delta^w_0|| for r_0 = b - A x_0, w_0 = A k_0."""
-        self.f = ((self.mu * math.sqrt(self.N) + 1.0) * self.nA * nx + self.nb) * self.eps
-        self.dw = self.smu * nk * self.eps
-        return self.f
+        return self.reset(nx, nk, 0.0, 0.0)
 
     def step(self, a, b, w, wp, nm):
         """Advance over iteration i.  `nm` holds the norms of the iteration-i
@@ -360,16 +363,20 @@ class _GapBound:
         return f
 
     def reset(self, nx, nk, ng, nl):
-        """After a replacement (eq:rr) from x_{i+1} and g_i."""
-        self.f = ((self.mu * math.sqrt(self.N) + 1.0) * self.nA * nx + self.nb) * self.eps
-        self.dw = self.smu * nk * self.eps
-        self.ds_prev = self.smu * ng * self.eps
-        self.dz_prev = self.smu * nl * self.eps
+        """After a replacement (eq:rr) from x_{i+1} and g_i: the errors of the
+        explicit recomputation, in the arithmetic of the recomputation
+        (epsilon ``eps_replace``)."""
+        e = self.eps_r
+        self.f = ((self.cmu + 1.0) * self.nA * nx + self.nb) * e
+        self.dw = self.smu * nk * e
+        self.ds_prev = self.smu * ng * e
+        self.dz_prev = self.smu * nl * e
         return self.f
 
 
 def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
-                       rr_tau=None, rr_mode="periodic", rr_eps=None, record=False):
+                       rr_tau=None, rr_mode="periodic", rr_eps=None, rr_estimate=False,
+                       record=False):
     """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with residual
     replacement (Section 3.6, eq:rr):
 
@@ -378,7 +385,9 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     * ``rr_mode="auto"``: the automated strategy -- the running bound f^r of
       eq:DDr_bound (``_GapBound``, epsilon = ``rr_eps``, default the unit
       roundoff) and the criterion eq:criterion: replace in step i when
-      f^r_{i-1} <= tau ||r_{i-1}|| and f^r_i > tau ||r_i||, tau = sqrt(eps).
+      f^r_{i-1} <= tau ||r_{i-1}|| and f^r_i > tau ||r_i||, tau = sqrt(eps);
+      with ``rr_estimate`` the square-root estimate of the bound (Section
+      3.6 suggests it as a less pessimistic alternative).
 
     Two global reductions per iteration, each overlapped (on parallel
     hardware) by one PREC + SPMV: (q_i, y_i), (y_i, y_i) with
@@ -422,7 +431,8 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     gb = None
     rr_next = False
     if auto:
-        gb = _GapBound(ops.n, ops.max_row_nnz(), ops.norm_bound_A(), ops.norm_bound_M(), eps, nb)
+        gb = _GapBound(ops.n, ops.max_row_nnz(), ops.norm_bound_A(), ops.norm_bound_M(), eps, nb,
+                       estimate=rr_estimate)
         f_cur = gb.start(ops.norm(x), ops.norm(k))
         f_ok_prev = f_cur <= tau * rn0
 

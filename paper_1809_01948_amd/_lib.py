@@ -58,6 +58,8 @@ class Opts(ctypes.Structure):
         ("gap_len", _c.c_int32),
         ("use_graph", _c.c_int32),
         ("stream", _P),
+        ("rr_auto", _c.c_int32),
+        ("rr_eps", _c.c_double),
     ]
 
 

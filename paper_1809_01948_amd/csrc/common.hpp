@@ -24,7 +24,7 @@ namespace pbcg {
 constexpr int kBlock = 256;          // threads per block (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxBlocks = 2048;     // max blocks of a streaming kernel = partials per slot
-constexpr int kNumSlots = 8;         // partial slots
+constexpr int kNumSlots = 32;        // partial slots
 constexpr int64_t kPadElems = 2048;  // vector padding granularity (elements)
 constexpr int kXcds = 8;             // MI355X: workgroups are dispatched round-robin over 8 XCDs
 constexpr int kSellC = 64;           // SELL slice height = one wavefront
@@ -39,6 +39,11 @@ enum Slot : int {
   SL_RZ0 = 5,   // (r_0, z_i)
   SL_RR = 6,    // (r_{i+1}, r_{i+1})  (stopping test)
   SL_BB = 7,    // (b, b)              (initialisation)
+  // squared norms for the automated replacement bound (Section 3.6)
+  SL_K2 = 8, SL_W2 = 9, SL_T2 = 10, SL_M2 = 11, SL_G2 = 12, SL_S2 = 13, SL_L2 = 14,
+  SL_Z2 = 15, SL_Q2 = 16, SL_Y2 = 17,          // phase A: k, w, t, m, g, s, l, z, q, y
+  SL_X2 = 18, SL_U2 = 19, SL_N2 = 20, SL_V2 = 21,  // phase B: x, u, n, v
+  SL_RX2 = 22, SL_RK2 = 23, SL_RL2 = 24,           // replacement: x, k, l after eq:rr
 };
 
 // final-reduction modes (run by one extra block of an operator kernel, or by
@@ -72,8 +77,8 @@ struct DevScalars {
   double alpha, beta, omega, omega_prev, rho;
   double rn, rn0, nb, tol, tau;
   double tr, gap;                  // last true residual norm / last gap norm
-  double sig[kNumSlots];           // last reduced sums (diagnostics)
-  double sums[kNumSlots];          // FIN_SUM output
+  double sig[8];                   // last reduced sums (diagnostics)
+  double sums[8];                  // FIN_SUM output
   int32_t iter;                    // completed iterations
   int32_t done;                    // Done
   int32_t status;                  // Status (valid when done == STOPPED)
@@ -83,7 +88,16 @@ struct DevScalars {
   int32_t gap_idx;                 // next free gap-history slot
   int32_t bad_diag;                // set by value-update kernels on a zero diagonal
   int32_t n_saved;                 // 1: the iteration's pre-replacement z is in the spare vector
-  int32_t pad_;
+  // automated residual replacement (running gap bound f^r and eq:criterion)
+  int32_t rr_auto;                 // 1: automated strategy instead of the period
+  int32_t rr_next;                 // replacement due in the current iteration
+  int32_t rr_hit;                  // a replacement ran in the current iteration
+  int32_t f_ok_prev;               // f^r_i <= tau ||r_i|| at the previous reduction
+  int32_t rr_est;                  // 1: square-root estimate instead of the worst-case bound
+  double eps_b, eps_r;             // epsilon of the recurrences / of a replacement
+  double nA, nM, mu, nN;           // ||A||, ||M^-1|| bounds, max nnz per row, N
+  double fr, dw, ds_prev, dz_prev; // f^r and the gap-norm bounds
+  double pg, ps, pl, pz, pn, pv;   // norms of the iteration i-1 vectors
   double* history;                 // optional ||r_{i+1}|| per iteration
   double* gap_history;             // optional gap norms
 };

@@ -106,7 +106,6 @@ void common_setup(Solver& S, int precision, int precond) {
   // cached accesses at every size measured.
   const int64_t footprint = (int64_t)(V_COUNT * S.tsize + 16) * S.npad;
   if (footprint > ((int64_t)192 << 20)) S.vnt = precision == PBCG_FP64 ? 3 : 2;
-  if (const char* env = std::getenv("PBCG_VEC_UNROLL")) S.vunroll = std::atoi(env) == 2 ? 2 : 1;
   if (const char* env = std::getenv("PBCG_VEC_NT")) S.vnt = std::atoi(env) & 3;
   if (const char* env = std::getenv("PBCG_SPMV_TILED")) S.spmv_tiled = std::atoi(env) != 0;
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
@@ -213,6 +212,61 @@ void set_dinv_csr(Solver& S) {
   }
 }
 
+// ||A||_2 <= sqrt(||A||_1 ||A||_inf) and the maximum stored entries per row
+// and per column, from host data (the automated replacement bound).
+void set_norm_bounds(Solver& S, const std::vector<double>& rowsum,
+                     const std::vector<double>& colsum, int mu_row, int mu_col) {
+  double r = 0.0, c = 0.0;
+  for (double v : rowsum) r = std::max(r, v);
+  for (double v : colsum) c = std::max(c, v);
+  S.normA = std::sqrt(c * r);
+  S.mu_row = mu_row;
+  S.mu_col = mu_col;
+}
+
+void norms_csr(Solver& S) {
+  std::vector<double> rs(S.n, 0.0), cs(S.n, 0.0);
+  std::vector<int> cc(S.n, 0);
+  int mr = 0;
+  for (int64_t i = 0; i < S.n; ++i) {
+    mr = std::max<int>(mr, S.h_rowptr[i + 1] - S.h_rowptr[i]);
+    for (int64_t kk = S.h_rowptr[i]; kk < S.h_rowptr[i + 1]; ++kk) {
+      rs[i] += std::fabs(S.h_val[kk]);
+      cs[S.h_col[kk]] += std::fabs(S.h_val[kk]);
+      cc[S.h_col[kk]] += 1;
+    }
+  }
+  int mc = 0;
+  for (int v : cc) mc = std::max(mc, v);
+  set_norm_bounds(S, rs, cs, mr, mc);
+}
+
+// constant stencils and DIA5: row and column sums over the actual grid
+void norms_grid(Solver& S, const double* dia /* 5*n or null */) {
+  const OpData& o = S.A;
+  const int nd = S.kind == OP_ST3D7 ? 7 : 5;
+  const int64_t nx = o.dims[0], ny = o.dims[1], nz = S.kind == OP_ST3D7 ? o.dims[2] : 1;
+  const int64_t off[7] = {-nx * ny, -nx, -1, 0, 1, nx, nx * ny};
+  const int base = nd == 7 ? 0 : 1;   // 2D uses off[1..5]
+  std::vector<double> rs(S.n, 0.0), cs(S.n, 0.0);
+  int mr = 0;
+  for (int64_t p = 0; p < S.n; ++p) {
+    const int64_t iz = p / (nx * ny), rem = p % (nx * ny), iy = rem / nx, ix = rem % nx;
+    const bool has[7] = {iz > 0, iy > 0, ix > 0, true, ix < nx - 1, iy < ny - 1, iz < nz - 1};
+    int cnt = 0;
+    for (int d = 0; d < nd; ++d) {
+      const int dd = base + d;
+      if (!has[dd]) continue;
+      const double a = dia ? dia[d * S.n + p] : o.c64[d];
+      rs[p] += std::fabs(a);
+      cs[p + off[dd]] += std::fabs(a);
+      ++cnt;
+    }
+    mr = std::max(mr, cnt);
+  }
+  set_norm_bounds(S, rs, cs, mr, mr);
+}
+
 void build_transpose(Solver& S) {
   if (S.have_AT) return;
   if (S.kind == OP_SELL) {
@@ -258,11 +312,20 @@ void build_transpose(Solver& S) {
   S.have_AT = true;
 }
 
-DevScalars initial_scalars(const pbcg_opts& o) {
+DevScalars initial_scalars(const Solver& S, const pbcg_opts& o, bool tr) {
   DevScalars d;
   std::memset(&d, 0, sizeof(d));
   d.tol = o.tol;
   d.tau = o.rr_tau > 0 ? o.rr_tau : std::sqrt(std::ldexp(1.0, -53));
+  d.rr_auto = o.rr_auto ? 1 : 0;
+  d.rr_est = o.rr_auto == 2 ? 1 : 0;
+  d.eps_b = o.rr_eps > 0 ? o.rr_eps : std::ldexp(1.0, S.precision == PBCG_FP64 ? -53 : -24);
+  d.eps_r = std::ldexp(1.0, -53);     // replacements are computed in FP64
+  if (o.rr_auto && !(o.rr_tau > 0)) d.tau = std::sqrt(d.eps_b);
+  d.nA = S.normA;
+  d.nM = S.normM;
+  d.mu = tr ? S.mu_col : S.mu_row;
+  d.nN = (double)S.n;
   d.maxit = o.maxit;
   d.rr_period = o.rr_period;
   d.history = o.history;
@@ -288,7 +351,7 @@ void begin_solve(Solver& S, const double* b, const double* x, const pbcg_opts& o
   if (!b || !x) fail(PBCG_ERR_INVALID_ARG, "b and x must be device pointers");
   hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
   hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
-  S.h_sc[2] = initial_scalars(o);
+  S.h_sc[2] = initial_scalars(S, o, o.transpose != 0);
   hipck(hipMemcpyAsync(S.sc, &S.h_sc[2], sizeof(DevScalars), hipMemcpyHostToDevice, S.s1),
         "hipMemcpyAsync");
   hipck(hipMemcpyAsync(S.b, b, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
@@ -322,8 +385,8 @@ void enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_
   launch_phaseA(S, st);
   launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
   launch_phaseB(S, st);
-  if (o.rr_period > 0 && (i + 1) % o.rr_period == 0) {
-    launch_rr1(S, tr, false, st);
+  if (o.rr_auto || (o.rr_period > 0 && (i + 1) % o.rr_period == 0)) {
+    launch_rr1(S, tr, false, st);      // predicated on the device (eq:criterion or the period)
     launch_rr2(S, tr, false, st);
   }
   launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
@@ -334,8 +397,9 @@ void enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_
 }
 
 hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_opts& o) {
-  const int off = o.rr_period > 0 ? start % o.rr_period : 0;
-  const std::string key = std::to_string(tr) + "/" + std::to_string(len) + "/" +
+  const int off = (o.rr_period > 0 && !o.rr_auto) ? start % o.rr_period : 0;
+  const std::string key = std::to_string(tr) + "/" + std::to_string(o.rr_auto) + "/" +
+                          std::to_string(len) + "/" +
                           std::to_string(off) + "/" + std::to_string(o.rr_period) + "/" +
                           std::to_string(o.gap_every > 0 ? start % o.gap_every : 0) + "/" +
                           std::to_string(o.gap_every);
@@ -356,7 +420,7 @@ hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_op
 // been completed.  Returns the device scalars after draining the stream.
 DevScalars run_iterations(Solver& S, bool tr, int start, const pbcg_opts& o) {
   int K = o.check_every > 0 ? o.check_every : (o.use_graph ? 16 : 8);
-  if (o.use_graph && o.rr_period > 0) {
+  if (o.use_graph && o.rr_period > 0 && !o.rr_auto) {
     // chunk length dividing the replacement period keeps the captured variants few
     int best = 1;
     for (int d = 1; d <= std::min(o.rr_period, 64); ++d)
@@ -415,6 +479,7 @@ int finish_stats(Solver& S, bool tr, const DevScalars& d, int status, pbcg_stats
 int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, pbcg_stats* st) {
   validate_opts(o);
   const bool tr = o.transpose != 0;
+  S.auto_rr = o.rr_auto != 0;
   if (tr) build_transpose(S);
   hipStream_t cs = (hipStream_t)o.stream;
   begin_solve(S, b, x, o, cs);
@@ -449,7 +514,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
       status = PBCG_CONVERGED;
       break;
     }
-    if (o.rr_period <= 0 || forced >= 3) {
+    if ((o.rr_period <= 0 && !o.rr_auto) || forced >= 3) {
       status = PBCG_TRUE_RES_NOT_MET;
       break;
     }
@@ -484,6 +549,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
 
 int solve_classic(Solver& S, const double* b, double* x, const pbcg_opts& o, pbcg_stats* st) {
   validate_opts(o);
+  S.auto_rr = false;
   const bool tr = o.transpose != 0;
   if (tr) build_transpose(S);
   hipStream_t cs = (hipStream_t)o.stream;
@@ -618,6 +684,17 @@ int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t
       hipck(hipMemcpy(S.d_rowptr, rowptr, (n + 1) * 4, hipMemcpyHostToDevice), "hipMemcpy");
       hipck(hipMemcpy(S.d_col, col, nnz * 4, hipMemcpyHostToDevice), "hipMemcpy");
       set_dinv_csr(S);
+      norms_csr(S);
+      if (S.dinv) {
+        double m = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+          double d = 0.0;
+          for (int64_t kk = rowptr[i]; kk < rowptr[i + 1]; ++kk)
+            if (col[kk] == i) d += val[kk];
+          m = std::max(m, std::fabs(1.0 / d));
+        }
+        S.normM = m;
+      }
       hipck(hipDeviceSynchronize(), "hipDeviceSynchronize");
     } catch (...) {
       destroy_solver(p);
@@ -711,6 +788,16 @@ int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, co
         }
       }
       (void)nz;
+      norms_grid(S, S.kind == OP_DIA5 ? coef : nullptr);
+      if (precond) {
+        if (S.kind == OP_DIA5) {
+          double m = 0.0;
+          for (int64_t i = 0; i < n; ++i) m = std::max(m, std::fabs(1.0 / coef[2 * n + i]));
+          S.normM = m;
+        } else {
+          S.normM = std::fabs(1.0 / coef[S.kind == OP_ST2D5 ? 2 : 3]);
+        }
+      }
       hipck(hipDeviceSynchronize(), "hipDeviceSynchronize");
     } catch (...) {
       destroy_solver(p);
@@ -736,6 +823,7 @@ int classic_bicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg
     Solver& S = H(h);
     pbcg_opts o = opt ? *opt : defaults();
     o.rr_period = 0;
+    o.rr_auto = 0;
     o.gap_every = 0;
     o.use_graph = 0;
     return solve_classic(S, b, x, o, st);
@@ -798,9 +886,10 @@ int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, 
       launch_update_sell(S, src, S.s1);
       hipck(hipGetLastError(), "update launch");
       hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
-      // keep the host copy current for a later transpose build
+      // keep the host copy current for a later transpose build and the norm bounds
       hipck(hipMemcpy(S.h_val.data(), src, S.nnz * 8, hipMemcpyDeviceToHost), "hipMemcpy");
       if (dv) (void)hipFree(dv);
+      norms_csr(S);
       int32_t bad = 0;
       hipck(hipMemcpy(&bad, &S.sc->bad_diag, 4, hipMemcpyDeviceToHost), "hipMemcpy");
       if (bad) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
@@ -818,8 +907,11 @@ int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, 
         S.A.c64[d] = c[d];
         S.A.c32[d] = (float)c[d];
       }
-      if (S.precond)
+      if (S.precond) {
         S.dinv_s = S.precision == PBCG_FP64 ? 1.0 / centre : (double)(1.0f / (float)centre);
+        S.normM = std::fabs(1.0 / centre);
+      }
+      norms_grid(S, nullptr);
       if (S.have_AT) {
         S.have_AT = false;
         build_transpose(S);
@@ -853,6 +945,7 @@ int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, 
       else upload_vals<float>(S, S.dinv, di);
     }
     S.h_dia = host;
+    norms_grid(S, S.h_dia.data());
     if (S.have_AT) {
       launch_dia5_transpose(S, S.s1);
       hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
@@ -944,7 +1037,8 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
     pbcg_opts o = defaults();
     o.tol = 0.0;
     o.maxit = 1 << 30;
-    S.h_sc[2] = initial_scalars(o);
+    S.auto_rr = false;
+    S.h_sc[2] = initial_scalars(S, o, false);
     S.h_sc[2].alpha = 0.5;
     S.h_sc[2].beta = 0.5;
     S.h_sc[2].omega = 0.5;

@@ -251,44 +251,55 @@ __global__ __launch_bounds__(kBlock) void k_init_res(Op op, const double* __rest
                                                      T ds, int64_t n, int64_t ntiles, int nwork,
                                                      double* __restrict__ partials) {
   const int blk = blockIdx.x;
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
     const int64_t i = w.t * kBlock + threadIdx.x;
     if (i < n) {
       ResVis<T> vis{x, 0.0};
       op.row(i, vis);
       const T ri = (T)(b[i] - vis.sum);
+      const T ki = prec1<T, PC>(ri, dinv, ds, i);
       r[i] = ri;
       rhat[i] = ri;
-      k[i] = prec1<T, PC>(ri, dinv, ds, i);
+      k[i] = ki;
       g[i] = T(0); s[i] = T(0); l[i] = T(0); z[i] = T(0); v[i] = T(0);
       acc[0] += (double)ri * (double)ri;
       acc[1] += (double)ri * (double)ri;
       acc[2] += b[i] * b[i];
+      acc[3] += x[i] * x[i];
+      acc[4] += (double)ki * (double)ki;
     }
   }
-  const int slots[3] = {SL_RR0, SL_RR, SL_BB};
-  block_partials<3>(acc, slots, partials, blk);
+  const int slots[5] = {SL_RR0, SL_RR, SL_BB, SL_X2, SL_K2};
+  block_partials<5>(acc, slots, partials, blk);
 }
 
 __device__ __forceinline__ bool rr_due(const DevScalars* __restrict__ sc) {
   if (sc->done) return false;
+  if (sc->rr_auto) return sc->rr_next != 0;       // eq:criterion, decided at the last GLRED 2
   const int P = sc->rr_period;
   if (P <= 0 || ((sc->iter + 1) % P) != 0) return false;
   return sc->rn >= sc->tau * sc->rn0;
 }
 
 // Residual replacement (eq:rr), first half: r = b - A x_{i+1}, k = M^-1 r,
-// s = A g_i, l = M^-1 s.  FP64 products; stored results rounded to T.
+// s = A g_i, l = M^-1 s.  FP64 products; stored results rounded to T.  Also
+// the partials of ||x_{i+1}||^2, ||k||^2, ||l||^2 that restart the automated
+// replacement bound.
 template <typename T, int PC, class Op>
 __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict__ x,
                                                 const T* __restrict__ g, const double* __restrict__ b,
                                                 T* __restrict__ r, T* __restrict__ k, T* __restrict__ s,
                                                 T* __restrict__ l, const T* __restrict__ dinv, T ds,
                                                 int64_t n, int64_t ntiles, int nwork,
-                                                DevScalars* __restrict__ sc, int force) {
+                                                DevScalars* __restrict__ sc,
+                                                double* __restrict__ partials, int force) {
   if (!force && !rr_due(sc)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->rr_count += 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->rr_count += 1;
+    sc->rr_hit = 1;
+  }
+  double acc[3] = {0.0, 0.0, 0.0};
   for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
     const int64_t i = w.t * kBlock + threadIdx.x;
     if (i < n) {
@@ -296,12 +307,19 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
       op.row(i, vis);
       const T ri = (T)(b[i] - vis.sx);
       const T si = (T)vis.sy;
+      const T ki = prec1<T, PC>(ri, dinv, ds, i);
+      const T li = prec1<T, PC>(si, dinv, ds, i);
       r[i] = ri;
-      k[i] = prec1<T, PC>(ri, dinv, ds, i);
+      k[i] = ki;
       s[i] = si;
-      l[i] = prec1<T, PC>(si, dinv, ds, i);
+      l[i] = li;
+      acc[0] += x[i] * x[i];
+      acc[1] += (double)ki * (double)ki;
+      acc[2] += (double)li * (double)li;
     }
   }
+  const int slots[3] = {SL_RX2, SL_RK2, SL_RL2};
+  block_partials<3>(acc, slots, partials, blockIdx.x);
 }
 
 // Residual replacement, second half: w = A k, z = A l (FP64 products), and
@@ -755,7 +773,7 @@ void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st) {
     hipLaunchKernelGGL((k_rr1<T, PC, Op>), PBCG_GRID_OP, op, (const double*)S.x,
                        (const T*)S.vec[V_G], (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_K],
                        (T*)S.vec[V_S], (T*)S.vec[V_L], (const T*)S.dinv, (T)S.dinv_s, S.n,
-                       S.rtiles, S.nblk, S.sc, force ? 1 : 0);
+                       S.rtiles, S.nblk, S.sc, S.partials, force ? 1 : 0);
   });
 }
 

@@ -35,13 +35,13 @@ struct PhaseAArgs {
 // q_i = r_i - alpha_i s_i, y_i = w_i - alpha_i z_i formed in registers.
 // In iteration 0 the previous vectors are zero and beta_0 = 0.  After a
 // residual replacement (SAVED) n_{i-1} is formed from the saved
-// pre-replacement z_{i-1} instead of the replaced one.
-// Each thread handles C = U * (16 bytes / sizeof(T)) consecutive elements per
-// tile; NT selects non-temporal loads and stores.
-template <typename T, int PC, int U, bool NT, bool SAVED>
+// pre-replacement z_{i-1} instead of the replaced one.  NT selects
+// non-temporal loads and stores; AUTO adds the squared norms of k, w, t, m,
+// g, s, l, z, q, y that the automated replacement bound needs.
+template <typename T, int PC, bool NT, bool AUTO, bool SAVED>
 __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T wp,
-                                            double (&acc)[2], int64_t ntiles) {
-  constexpr int C = U * V16<T>::n;
+                                            double (&acc)[12], int64_t ntiles) {
+  constexpr int C = V16<T>::n;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t i = (tile * kBlock + threadIdx.x) * C;
     T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C];
@@ -60,27 +60,48 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T 
       const T sn = w[e] + b * (s[e] - wp * z[e]);
       const T ln = m + b * (l[e] - wp * np);
       const T zn = t[e] + b * (z[e] - wp * v[e]);
-      g[e] = gn; s[e] = sn; l[e] = ln; z[e] = zn;
       const T q = r[e] - a * sn;
       const T y = w[e] - a * zn;
       acc[0] += (double)q * (double)y;
       acc[1] += (double)y * (double)y;
+      if (AUTO) {
+        acc[2] += (double)k[e] * (double)k[e];
+        acc[3] += (double)w[e] * (double)w[e];
+        acc[4] += (double)t[e] * (double)t[e];
+        acc[5] += (double)m * (double)m;
+        acc[6] += (double)gn * (double)gn;
+        acc[7] += (double)sn * (double)sn;
+        acc[8] += (double)ln * (double)ln;
+        acc[9] += (double)zn * (double)zn;
+        acc[10] += (double)q * (double)q;
+        acc[11] += (double)y * (double)y;
+      }
+      g[e] = gn; s[e] = sn; l[e] = ln; z[e] = zn;
     }
     stc<T, C, NT>(A.g + i, g); stc<T, C, NT>(A.s + i, s); stc<T, C, NT>(A.l + i, l);
     stc<T, C, NT>(A.z + i, z);
   }
 }
 
-template <typename T, int PC, int U, bool NT>
+template <typename T, int PC, bool NT, bool AUTO>
 __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, const DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
   if (sc->done) return;
   const T a = (T)sc->alpha, b = (T)sc->beta, wp = (T)sc->omega_prev;
-  double acc[2] = {0.0, 0.0};
-  if (sc->n_saved) phaseA_body<T, PC, U, NT, true>(A, a, b, wp, acc, ntiles);
-  else phaseA_body<T, PC, U, NT, false>(A, a, b, wp, acc, ntiles);
-  const int slots[2] = {SL_QY, SL_YY};
-  block_partials<2>(acc, slots, partials, blockIdx.x);
+  double acc[12];
+#pragma unroll
+  for (int d = 0; d < 12; ++d) acc[d] = 0.0;
+  if (sc->n_saved) phaseA_body<T, PC, NT, AUTO, true>(A, a, b, wp, acc, ntiles);
+  else phaseA_body<T, PC, NT, AUTO, false>(A, a, b, wp, acc, ntiles);
+  if (AUTO) {
+    const int slots[12] = {SL_QY, SL_YY, SL_K2, SL_W2, SL_T2, SL_M2, SL_G2, SL_S2, SL_L2,
+                           SL_Z2, SL_Q2, SL_Y2};
+    block_partials<12>(acc, slots, partials, blockIdx.x);
+  } else {
+    double acc2[2] = {acc[0], acc[1]};
+    const int slots[2] = {SL_QY, SL_YY};
+    block_partials<2>(acc2, slots, partials, blockIdx.x);
+  }
 }
 
 template <typename T>
@@ -107,15 +128,17 @@ struct PhaseBArgs {
 //   k_{i+1} = u_i - omega_i (m_i - alpha_i n_i)           m_i = M^-1 w_i, n_i = M^-1 z_i
 //   w_{i+1} = y_i - omega_i (t_i - alpha_i v_i)
 // in place, and the GLRED 2 partials (r0, r_{i+1}), (r0, w_{i+1}), (r0, s_i),
-// (r0, z_i), (r_{i+1}, r_{i+1}).
-template <typename T, int PC, int U, bool NT>
+// (r0, z_i), (r_{i+1}, r_{i+1}); AUTO adds ||x_i||^2, ||u_i||^2, ||n_i||^2, ||v_i||^2.
+template <typename T, int PC, bool NT, bool AUTO>
 __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
   if (sc->done) return;
-  constexpr int C = U * V16<T>::n;
+  constexpr int C = V16<T>::n;
   const double alpha = sc->alpha, omega = sc->omega;
   const T a = (T)alpha, om = (T)omega;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[9];
+#pragma unroll
+  for (int d = 0; d < 9; ++d) acc[d] = 0.0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t i = (tile * kBlock + threadIdx.x) * C;
     T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C];
@@ -134,6 +157,12 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevSca
       const T q = r[e] - a * s[e];
       const T u = k[e] - a * l[e];
       const T y = w[e] - a * z[e];
+      if (AUTO) {
+        acc[5] += x[e] * x[e];
+        acc[6] += (double)u * (double)u;
+        acc[7] += (double)n * (double)n;
+        acc[8] += (double)v[e] * (double)v[e];
+      }
       x[e] = (x[e] + alpha * (double)g[e]) + omega * (double)u;
       const T rn = q - om * y;
       const T kn = u - om * (m - a * n);
@@ -149,8 +178,14 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevSca
     stc<T, C, NT>(B.r + i, r); stc<T, C, NT>(B.k + i, k); stc<T, C, NT>(B.w + i, w);
     stc<double, C, NT>(B.x + i, x);
   }
-  const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
-  block_partials<5>(acc, slots, partials, blockIdx.x);
+  if (AUTO) {
+    const int slots[9] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_X2, SL_U2, SL_N2, SL_V2};
+    block_partials<9>(acc, slots, partials, blockIdx.x);
+  } else {
+    double acc5[5] = {acc[0], acc[1], acc[2], acc[3], acc[4]};
+    const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+    block_partials<5>(acc5, slots, partials, blockIdx.x);
+  }
 }
 
 // Classic BiCGStab (Algorithm 1) vector update, with alpha_i and omega_i known:
@@ -289,15 +324,15 @@ static void phaseA_t(Solver& S, hipStream_t st) {
   a.g = (T*)S.vec[V_G]; a.s = (T*)S.vec[V_S]; a.l = (T*)S.vec[V_L]; a.z = (T*)S.vec[V_Z];
   a.zsave = (const T*)S.vec[V_TMP];
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
-  const int64_t nt = S.npad / (kBlock * S.vunroll * V16<T>::n);
+  const int64_t nt = S.npad / (kBlock * V16<T>::n);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials, nt);
   };
   const bool ntm = (S.vnt & 1) != 0;
-  if (S.vunroll == 2) {
-    if (ntm) go(k_phaseA<T, PC, 2, true>); else go(k_phaseA<T, PC, 2, false>);
+  if (S.auto_rr) {
+    if (ntm) go(k_phaseA<T, PC, true, true>); else go(k_phaseA<T, PC, false, true>);
   } else {
-    if (ntm) go(k_phaseA<T, PC, 1, true>); else go(k_phaseA<T, PC, 1, false>);
+    if (ntm) go(k_phaseA<T, PC, true, false>); else go(k_phaseA<T, PC, false, false>);
   }
 }
 
@@ -310,15 +345,15 @@ static void phaseB_t(Solver& S, hipStream_t st) {
   a.rhat = (const T*)S.vec[V_RHAT];
   a.r = (T*)S.vec[V_R]; a.k = (T*)S.vec[V_K]; a.w = (T*)S.vec[V_W];
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
-  const int64_t nt = S.npad / (kBlock * S.vunroll * V16<T>::n);
+  const int64_t nt = S.npad / (kBlock * V16<T>::n);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials, nt);
   };
   const bool ntm = (S.vnt & 2) != 0;
-  if (S.vunroll == 2) {
-    if (ntm) go(k_phaseB<T, PC, 2, true>); else go(k_phaseB<T, PC, 2, false>);
+  if (S.auto_rr) {
+    if (ntm) go(k_phaseB<T, PC, true, true>); else go(k_phaseB<T, PC, false, true>);
   } else {
-    if (ntm) go(k_phaseB<T, PC, 1, true>); else go(k_phaseB<T, PC, 1, false>);
+    if (ntm) go(k_phaseB<T, PC, true, false>); else go(k_phaseB<T, PC, false, false>);
   }
 }
 

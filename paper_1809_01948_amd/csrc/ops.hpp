@@ -149,6 +149,62 @@ __device__ __forceinline__ void stop(DevScalars* sc, int status) {
   sc->status = status;
 }
 
+// ----------------------------------------------------------------------------
+// automated residual replacement: the running bound f^r (Section 3.6)
+// ----------------------------------------------------------------------------
+//
+// Local errors of iteration i bounded as in eq:errbounds1-4 (epsilon eps_b,
+// mu = max nonzeros per row, mu~ = 1 for a diagonal M^-1, ||A||, ||M^-1||
+// upper bounds), gap norms by the triangle inequality on eq:Ds, eq:Dw, eq:Dz,
+// accumulated into f^r as in eq:DDr_bound.  All evaluated left to right in
+// FP64 by one thread.
+
+struct IterNorms {
+  double x, g, u, q, y, r, s, k, l, w, z, m, t, n, v;
+};
+
+__device__ inline double gap_bound_step(DevScalars* sc, double a, double b, double w, double wp,
+                                        const IterNorms& nm) {
+  const double e = sc->eps_b, nA = sc->nA;
+  const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
+  const double smut = (sc->rr_est ? 1.0 : sqrt(sc->nN)) * sc->nM;
+  const double d_x = (2 * nm.x + 3 * a * nm.g + 2 * w * nm.u) * e;
+  const double d_r = (nm.q + 2 * w * nm.y) * e;
+  const double d_q = (nm.r + 2 * a * nm.s) * e;
+  const double d_u = (nm.k + 2 * a * nm.l) * e;
+  const double d_y = (nm.w + 2 * a * nm.z) * e;
+  const double d_g = (nm.k + 3 * b * sc->pg + 4 * b * wp * sc->pl) * e;
+  const double d_s = (nm.w + 3 * b * sc->ps + 4 * b * wp * sc->pz) * e;
+  const double d_l = (nm.m + smut * nm.w + 3 * b * sc->pl + 4 * b * wp * sc->pn +
+                      smut * b * wp * sc->pz) * e;
+  const double d_z = (nm.t + smu * nm.m + smut * nA * nm.w + 3 * b * sc->pz + 4 * b * wp * sc->pv +
+                      smu * b * wp * sc->pn + smut * nA * b * wp * sc->pz) * e;
+  const double d_k = (nm.u + 3 * w * nm.m + smut * w * nm.w + 4 * w * a * nm.n +
+                      smut * w * a * nm.z) * e;
+  const double d_w = (nm.y + 3 * w * nm.t + smu * w * nm.m + smut * nA * w * nm.w +
+                      4 * w * a * nm.v + smu * w * a * nm.n + smut * nA * w * a * nm.z) * e;
+  const double dz = b * sc->dz_prev + nA * d_l + d_z;                                  // eq:Dz
+  const double ds = sc->dw + b * sc->ds_prev + b * wp * sc->dz_prev + nA * d_g + d_s;  // eq:Ds
+  const double f = sc->fr + a * ds + w * sc->dw + w * a * dz + nA * d_x + d_r +       // eq:Dr
+                   w * nA * d_u + d_q + w * d_y;
+  const double dw = sc->dw + a * dz + nA * d_k + d_w + nA * d_u + d_y;                 // eq:Dw
+  sc->fr = f; sc->dw = dw; sc->ds_prev = ds; sc->dz_prev = dz;
+  sc->pg = nm.g; sc->ps = nm.s; sc->pl = nm.l; sc->pz = nm.z; sc->pn = nm.n; sc->pv = nm.v;
+  return f;
+}
+
+// bounds right after an explicit recomputation of r, k, w from x and s, l, z
+// from g, in the arithmetic of the recomputation (FP64: eps_r)
+__device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, double ng, double nl) {
+  const double e = sc->eps_r;
+  const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
+  const double smu = cmu * sc->nA;
+  sc->fr = ((cmu + 1.0) * sc->nA * nx + sc->nb) * e;
+  sc->dw = smu * nk * e;
+  sc->ds_prev = smu * ng * e;
+  sc->dz_prev = smu * nl * e;
+}
+
 // Runs one FinalMode over the partials written by the previous kernel(s).
 // Must be executed by all kBlock threads of exactly one block.
 __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
@@ -157,9 +213,9 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
   switch (mode) {
     case FIN_INIT: {
       // Algorithm 2 initialisation: rho_0 = (r0, r0), alpha_0 = rho_0 / (r0, w0)
-      const int sl[4] = {SL_RR0, SL_RW0, SL_RR, SL_BB};
-      double v[4];
-      block_sum_slots<4>(partials, sl, nblk, v);
+      const int sl[6] = {SL_RR0, SL_RW0, SL_RR, SL_BB, SL_X2, SL_K2};
+      double v[6];
+      block_sum_slots<6>(partials, sl, nblk, v);
       const double rho = v[0], rw = v[1], rr = v[2], bb = v[3];
       if (t0) {
         sc->sig[SL_RR0] = rho; sc->sig[SL_RW0] = rw; sc->sig[SL_RR] = rr; sc->sig[SL_BB] = bb;
@@ -171,6 +227,14 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         sc->omega = 0.0;
         sc->omega_prev = 0.0;
         sc->iter = 0;
+        if (sc->rr_auto) {
+          // f^r_0 = ((mu sqrt(N) + 1) ||A|| ||x_0|| + ||b||) eps, ||Delta^w_0|| <= mu sqrt(N) ||A|| ||k_0|| eps
+          gap_bound_reset(sc, sqrt(v[4]), sqrt(v[5]), 0.0, 0.0);
+          sc->pg = sc->ps = sc->pl = sc->pz = sc->pn = sc->pv = 0.0;
+          sc->f_ok_prev = sc->fr <= sc->tau * sc->rn0;
+          sc->rr_next = 0;
+          sc->rr_hit = 0;
+        }
         if (sc->nb == 0.0) stop(sc, ST_CONVERGED);
         else if (sc->rn0 <= sc->tol * sc->nb) stop(sc, ST_CONVERGED);
         else if (!finite(rho) || !finite(rw)) stop(sc, ST_NONFINITE);
@@ -198,9 +262,20 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
     case FIN_REDO: {
       // GLRED 2: beta_{i+1} = (alpha_i/omega_i) (r0,r_{i+1})/(r0,r_i),
       // alpha_{i+1} = (r0,r_{i+1}) / ((r0,w_{i+1}) + beta (r0,s_i) - beta omega (r0,z_i))
-      const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
-      double v[5];
-      block_sum_slots<5>(partials, sl, nblk, v);
+      // In automated mode the norms of the bound are reduced in the same pass.
+      constexpr int NS = 22;
+      const int sl[NS] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_K2, SL_W2, SL_T2,
+                          SL_M2, SL_G2, SL_S2, SL_L2, SL_Z2, SL_Q2, SL_Y2, SL_X2,
+                          SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2};
+      double v[NS];
+      if (sc->rr_auto) {
+        block_sum_slots<NS>(partials, sl, nblk, v);
+      } else {
+        const int sl5[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+        double v5[5];
+        block_sum_slots<5>(partials, sl5, nblk, v5);
+        for (int d = 0; d < 5; ++d) v[d] = v5[d];
+      }
       const double rho1 = v[0], rw = v[1], rs = v[2], rz = v[3], rr = v[4];
       if (t0) {
         sc->sig[SL_RR0] = rho1; sc->sig[SL_RW0] = rw; sc->sig[SL_RS0] = rs;
@@ -210,6 +285,21 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         double* hrow = (sc->history && its >= 1 && its <= sc->hist_len)
                            ? sc->history + 4 * (int64_t)(its - 1) : nullptr;
         if (hrow) { hrow[1] = sc->alpha; hrow[2] = sc->omega; hrow[3] = 0.0; }
+        if (sc->rr_auto) {
+          if (mode == FIN_BETA) {
+            IterNorms nm;
+            nm.k = sqrt(v[5]); nm.w = sqrt(v[6]); nm.t = sqrt(v[7]); nm.m = sqrt(v[8]);
+            nm.g = sqrt(v[9]); nm.s = sqrt(v[10]); nm.l = sqrt(v[11]); nm.z = sqrt(v[12]);
+            nm.q = sqrt(v[13]); nm.y = sqrt(v[14]); nm.x = sqrt(v[15]); nm.u = sqrt(v[16]);
+            nm.n = sqrt(v[17]); nm.v = sqrt(v[18]); nm.r = sc->rn;
+            gap_bound_step(sc, fabs(sc->alpha), fabs(sc->beta), fabs(sc->omega),
+                           fabs(sc->omega_prev), nm);
+          }
+          if (sc->rr_hit) {
+            gap_bound_reset(sc, sqrt(v[19]), sqrt(v[20]), sqrt(v[9]), sqrt(v[21]));
+            sc->rr_hit = 0;
+          }
+        }
         if (!finite(rho1) || !finite(rw) || !finite(rs) || !finite(rz) || !finite(rr)) {
           stop(sc, ST_NONFINITE);
         } else {
@@ -218,22 +308,29 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
           if (hrow) hrow[0] = rn;
           if (rn <= sc->tol * sc->nb) {
             sc->done = RECURSIVE_CONVERGED;          // the host confirms with ||b - A x||
-          } else if (sc->omega == 0.0) {
-            stop(sc, ST_BREAKDOWN_OMEGA);
-          } else if (rho1 == 0.0 || sc->rho == 0.0) {
-            stop(sc, ST_BREAKDOWN_RHO);
           } else {
-            const double beta = ((sc->alpha / sc->omega) * rho1) / sc->rho;
-            const double den = (rw + beta * rs) - (beta * sc->omega) * rz;
-            if (den == 0.0) {
+            if (sc->rr_auto) {                       // eq:criterion for the next step
+              const int f_ok = sc->fr <= sc->tau * rn;
+              sc->rr_next = sc->f_ok_prev && !f_ok;
+              sc->f_ok_prev = f_ok;
+            }
+            if (sc->omega == 0.0) {
+              stop(sc, ST_BREAKDOWN_OMEGA);
+            } else if (rho1 == 0.0 || sc->rho == 0.0) {
               stop(sc, ST_BREAKDOWN_RHO);
             } else {
-              sc->beta = beta;
-              if (hrow) hrow[3] = beta;
-              sc->alpha = rho1 / den;
-              sc->rho = rho1;
-              sc->omega_prev = sc->omega;
-              if (its >= sc->maxit) stop(sc, ST_MAXIT);
+              const double beta = ((sc->alpha / sc->omega) * rho1) / sc->rho;
+              const double den = (rw + beta * rs) - (beta * sc->omega) * rz;
+              if (den == 0.0) {
+                stop(sc, ST_BREAKDOWN_RHO);
+              } else {
+                sc->beta = beta;
+                if (hrow) hrow[3] = beta;
+                sc->alpha = rho1 / den;
+                sc->rho = rho1;
+                sc->omega_prev = sc->omega;
+                if (its >= sc->maxit) stop(sc, ST_MAXIT);
+              }
             }
           }
         }
@@ -325,11 +422,11 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       break;
     }
     case FIN_SUM: {
-      const int sl[kNumSlots] = {0, 1, 2, 3, 4, 5, 6, 7};
-      double v[kNumSlots];
-      block_sum_slots<kNumSlots>(partials, sl, nblk, v);
+      const int sl[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+      double v[8];
+      block_sum_slots<8>(partials, sl, nblk, v);
       if (t0)
-        for (int j = 0; j < aux && j < kNumSlots; ++j) sc->sums[j] = v[j];
+        for (int j = 0; j < aux && j < 8; ++j) sc->sums[j] = v[j];
       break;
     }
     default:

@@ -64,8 +64,11 @@ struct Solver {
   DevScalars* h_sc = nullptr;   // pinned, 2 entries (double-buffered poll)
 
   int nblk = 8;                 // blocks of every streaming kernel (multiple of 8)
-  int vunroll = 1;              // 16-byte chunks per thread and tile in the phase kernels
   int vnt = 0;                  // non-temporal loads/stores: bit 0 phase A, bit 1 phase B
+  bool auto_rr = false;         // the current solve uses the automated replacement
+  double normA = 1.0;           // sqrt(||A||_1 ||A||_inf), an upper bound of ||A||_2
+  double normM = 1.0;           // max |M^-1|
+  int mu_row = 1, mu_col = 1;   // max stored entries per row / per column
   bool spmv_tiled = true;       // several consecutive rows per thread for structured operators
   int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
   int64_t rtiles = 0;           // tiles of 256 rows

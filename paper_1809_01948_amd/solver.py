@@ -105,7 +105,7 @@ class Solver:
 
     # ---- solves ---------------------------------------------------------
     def _opts(self, tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-              gap_history, use_graph):
+              gap_history, use_graph, rr_auto=False, rr_eps=0.0):
         o = L.Opts()
         L.load().pbicgstab_default_opts(ctypes.byref(o))
         o.tol = tol
@@ -123,17 +123,28 @@ class Solver:
             o.gap_len = gap_history.numel()
         o.use_graph = 1 if use_graph else 0
         o.stream = torch.cuda.current_stream().cuda_stream
+        if rr_auto in (False, None, 0):
+            o.rr_auto = 0
+        elif rr_auto == "bound":
+            o.rr_auto = 1
+        elif rr_auto == "estimate":
+            o.rr_auto = 2
+        else:   # True: the worst-case bound in FP64, the estimate with FP32 recurrences
+            o.rr_auto = 1 if self.precision == "fp64" else 2
+        o.rr_eps = rr_eps
         return o
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, *, tol=1e-10,
               maxit=10000, rr_period=0, rr_tau=0.0, check_every=0, transpose=False,
               history: Optional[torch.Tensor] = None, gap_every=0,
               gap_history: Optional[torch.Tensor] = None, use_graph=False,
-              method="pipelined", out: Optional[torch.Tensor] = None):
+              method="pipelined", out: Optional[torch.Tensor] = None, rr_auto=False,
+              rr_eps=0.0):
         """Solve A x = b (A^T x = b with transpose).  Returns (x, stats dict).
 
-        method: 'pipelined' (Algorithm 2 with periodic residual replacement)
-        or 'classic' (Algorithm 1)."""
+        method: 'pipelined' (Algorithm 2 with residual replacement: every
+        ``rr_period`` iterations, or automated with ``rr_auto``) or 'classic'
+        (Algorithm 1)."""
         lib = L.load()
         b = _dev_vec(b, self.n, "b")
         if out is None:
@@ -144,7 +155,7 @@ class Solver:
             if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
                 raise TypeError(f"{nm} must be a contiguous CUDA float64 tensor")
         o = self._opts(tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-                       gap_history, use_graph)
+                       gap_history, use_graph, rr_auto, rr_eps)
         st = L.Stats()
         fn = lib.pbicgstab_solve if method == "pipelined" else lib.classic_bicgstab_solve
         code = fn(self._h, _ptr(b), _ptr(out), ctypes.byref(o), ctypes.byref(st))

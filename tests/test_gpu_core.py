@@ -316,3 +316,50 @@ def test_errors(Solver):
         S.solve(dev(p.b), maxit=0)
     assert e.value.code == -1
     S.close()
+
+
+# -----------------------------------------------------------------------------
+# automated residual replacement (Section 3.6)
+# -----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("form", ["csr", "stencil"])
+def test_automated_replacement_c1(Solver, form):
+    """Same bound and criterion as the oracle: the same early scalar trace,
+    a handful of replacements, convergence to the tolerance."""
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p)
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000, rr_mode="auto")
+    S = Solver.from_problem(p, form=form)
+    hist = history_buffer(2000)
+    x, st = S.solve(dev(p.b), tol=1e-10, maxit=2000, rr_auto=True, history=hist)
+    assert st["status"] == 0 and ref.status == 0
+    rn, al, om, be = split_history(hist, 10)
+    assert np.all(rel(al, ref.alpha[:10]) <= 1e-10)
+    assert 1 <= st["replacements"] <= 10
+    assert abs(st["replacements"] - ref.replacements) <= 2
+    xh = host(x)
+    assert np.linalg.norm(p.b - A @ xh) <= 1e-10 * np.linalg.norm(p.b)
+    S.close()
+
+
+@pytest.mark.parametrize("case", ["c1-64", "poisson-200"])
+def test_automated_replacement_converges(Solver, case):
+    """Automated replacement on a larger unsymmetric problem without
+    preconditioner (oracle: 178 iterations, 7 replacements to 1e-12) and on
+    Poisson 200^2 with Jacobi (oracle: 994 iterations, 13 replacements to
+    1e-10).  Past the first tens of iterations the trajectories depend on
+    the dot-product summation order, so the counts are compared loosely;
+    convergence and the true residual are checked exactly."""
+    from workloads import poisson2d_c2
+    if case == "c1-64":
+        p, tol, form, pc, ref_its, ref_rr = convdiff2d_c1(64), 1e-12, "csr", "none", 178, 7
+    else:
+        p, tol, form, pc, ref_its, ref_rr = poisson2d_c2(200), 1e-10, "stencil", "jacobi", 994, 13
+    A = p.scipy_csr()
+    S = Solver.from_problem(p, form=form, precond=pc)
+    x, st = S.solve(dev(p.b), tol=tol, maxit=6000, rr_auto=True)
+    assert st["status"] == 0, st
+    assert abs(st["replacements"] - ref_rr) <= max(3, ref_rr // 2)
+    assert 0.6 * ref_its <= st["iterations"] <= 1.5 * ref_its
+    assert np.linalg.norm(p.b - A @ host(x)) <= tol * np.linalg.norm(p.b)
+    S.close()

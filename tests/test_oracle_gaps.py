@@ -141,3 +141,21 @@ def test_automated_bound_after_replacements():
     for e, f, sn in zip(errs, res.fr, res.snapshots):
         if not sn["replaced"]:
             assert gaps.exact_norm(e["Dr1"]) <= f
+
+
+def test_automated_estimate_is_below_bound():
+    """The square-root estimate (mu sqrt(N) -> sqrt(mu), mu~ sqrt(N) -> 1) of
+    the same recursion never exceeds the worst-case bound, and without
+    replacements (rr_tau = 0) it leaves the iterates untouched."""
+    p = convdiff2d_c1(8)
+    A = p.scipy_csr()
+    d = 1.0 / A.diagonal()
+    kw = dict(tol=0.0, maxit=25, rr_mode="auto", rr_tau=0.0)
+    wc = pipelined_bicgstab(Float64Ops(A, d), p.b, **kw)
+    es = pipelined_bicgstab(Float64Ops(A, d), p.b, rr_estimate=True, **kw)
+    assert wc.alpha == es.alpha and wc.omega == es.omega
+    ratio = np.array(es.fr) / np.array(wc.fr)
+    mu = int(np.max(np.diff(A.indptr)))
+    assert np.all(ratio <= 1.0)
+    # the start value shrinks by (sqrt(mu) + 1) / (mu sqrt(N) + 1) at most
+    assert ratio.min() >= 1.0 / (mu * math.sqrt(p.n))
