@@ -271,6 +271,18 @@ def main():
                      "status": st["status_name"], "rel_res_true": st["rel_res_true"],
                      "replacements": st["replacements"]}
         log(f"to tol {name}: {sol[name]}")
+    # the true-residual gap ||(b - A x_i) - r_i|| / ||b|| every 50 iterations,
+    # without replacement and with replacement every 50 (logged, not timed)
+    gaps = {}
+    nb = float(np.linalg.norm(prob.b))
+    for P in (0, 50):
+        gh = torch.zeros(ITERS_PER_STEP // 50, dtype=torch.float64, device=dev)
+        _, st = S.solve(b, tol=0.0, maxit=ITERS_PER_STEP, rr_period=P, gap_every=50,
+                        gap_history=gh)
+        gaps[f"rr_{P}"] = {"every": 50, "gap_over_bnorm": [float(v) / nb for v in gh.cpu()],
+                           "rel_res_recursive": st["rel_res_recursive"],
+                           "rel_res_true": st["rel_res_true"]}
+        log(f"gap P={P}: {gaps[f'rr_{P}']['gap_over_bnorm'][-3:]}")
     S.close()
 
     out = {
@@ -300,6 +312,7 @@ def main():
                      "avg_launch_ms": ms_b},
         "kernels": kernels,
         "solve_to_tol": sol,
+        "residual_gap": gaps,
     }
 
     if not args.skip_mixed:

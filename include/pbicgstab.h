@@ -225,11 +225,12 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream);
  * returns the average duration per launch, measured with HIP events recorded
  * on that stream:
  *   0 phase A (g, s, l, z recurrences + GLRED 1 partials)
- *   1 PREC + SPMV  v = A M^-1 z  (with the GLRED 1 final block)
+ *   1 PREC + SPMV  v = A M^-1 z  (with the GLRED 1 final blocks)
  *   2 phase B (x, r, k, w recurrences + GLRED 2 partials)
  *   3 PREC + SPMV  t = A M^-1 w  (with the GLRED 2 reduction, scalars not updated)
  *   4 one full iteration (0-3)
  *   5 a plain copy of N_pad doubles (2 x 8 N bytes), the bandwidth reference
+ *   6 PREC + SPMV  v = A M^-1 z  without any final reduction
  * The solver vectors are overwritten (run it after, not between, the solves
  * whose results are needed); every later solve reinitialises them.
  */

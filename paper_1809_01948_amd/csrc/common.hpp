@@ -100,6 +100,11 @@ struct DevScalars {
   double pg, ps, pl, pz, pn, pv;   // norms of the iteration i-1 vectors
   double* history;                 // optional ||r_{i+1}|| per iteration
   double* gap_history;             // optional gap norms
+  // distributed final reduction: one block per slot stores its sum here, the
+  // last block to arrive runs the scalar logic and resets the counter
+  double red[kNumSlots];
+  int32_t fin_arrive;
+  int32_t pad2_;
 };
 
 // ----------------------------------------------------------------------------

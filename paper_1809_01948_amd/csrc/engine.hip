@@ -1028,7 +1028,7 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream) {
 int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, void* stream) {
   return guarded([&]() -> int {
     Solver& S = H(h);
-    if (kernel < 0 || kernel > 5 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
+    if (kernel < 0 || kernel > 6 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
     hipStream_t cs = (hipStream_t)stream;
     hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
     hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
@@ -1054,6 +1054,7 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
         case 2: launch_phaseB(S, S.s1); break;
         case 3: launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_PROBE, false, S.s1); break;
         case 5: launch_copy(S, S.x, S.b, S.s1); break;
+        case 6: launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_NONE, false, S.s1); break;
       }
     };
     auto launch = [&]() {

@@ -10,6 +10,8 @@
 // "begin global reduction" and "end reduction").  Block 0 is dispatched first,
 // so the reduction overlaps the whole product.
 
+#include <type_traits>
+
 #include "solver.hpp"
 
 namespace pbcg {
@@ -93,14 +95,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
                                                  const T* __restrict__ rhat, int64_t n, int64_t ntiles,
                                                  int nwork, DevScalars* __restrict__ sc,
                                                  double* __restrict__ partials, int fin_mode,
-                                                 int dot_rhat) {
-  if (blockIdx.x == 0) {
-    if (fin_mode != FIN_NONE && (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done))
-      run_final(fin_mode, sc, partials, nwork, 0);
+                                                 int dot_rhat, int nfin) {
+  if ((int)blockIdx.x < nfin) {
+    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done)
+      distributed_final(fin_mode, sc, partials, nwork, nfin);
     return;
   }
   if (sc->done) return;
-  const int blk = blockIdx.x - 1;
+  const int blk = blockIdx.x - nfin;
   double acc[1] = {0.0};
   for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
     const int64_t i = w.t * kBlock + threadIdx.x;
@@ -118,15 +120,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
 }
 
 // ----------------------------------------------------------------------------
-// structured SPMV, R consecutive rows per thread
+// structured SPMV, CH x R consecutive rows per thread
 // ----------------------------------------------------------------------------
 //
-// For the stencil and DIA5 operators with nx a multiple of R = 16 bytes /
-// sizeof(T), the R rows of a thread lie on one grid line, so the centre,
-// S/N (and D/U) neighbours of all R rows are aligned 16-byte chunks and the
-// W/E neighbours are the centre chunk shifted by one plus one scalar at each
-// end.  Each row is still summed in ascending column order, exactly as the
-// row-per-thread kernel does.
+// For the stencil and DIA5 operators with nx a multiple of CH x R (R = 16
+// bytes / sizeof(T), CH = 1 or 2 chunks), the rows of a thread lie on one
+// grid line, so the centre, S/N (and D/U) neighbours of all its rows are
+// aligned 16-byte chunks and the W/E neighbours are the centre chunks
+// shifted by one plus one scalar at each end.  Two chunks per thread double
+// the bytes each load wave has in flight, which the large grids need to
+// approach the HBM bandwidth.  Each row is still summed in ascending column
+// order, exactly as the row-per-thread kernel does.
 
 template <typename T, int PC>
 __device__ __forceinline__ void load_chunk(const T* __restrict__ z, const T* __restrict__ dinv, T ds,
@@ -152,26 +156,27 @@ struct StParams {
   int64_t ld;
 };
 
-template <typename T, int PC, int KIND>
+template <typename T, int PC, int KIND, int CH>
 __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __restrict__ in,
                                                     T* __restrict__ out, const T* __restrict__ dinv,
                                                     T ds, int64_t n, int64_t ntiles, int nwork,
                                                     DevScalars* __restrict__ sc,
                                                     double* __restrict__ partials, int fin_mode,
-                                                    int nblk_partials) {
-  if (blockIdx.x == 0) {
-    if (fin_mode != FIN_NONE && (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done))
-      run_final(fin_mode, sc, partials, nblk_partials, 0);
+                                                    int nblk_partials, int nfin) {
+  if ((int)blockIdx.x < nfin) {
+    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done)
+      distributed_final(fin_mode, sc, partials, nblk_partials, nfin);
     return;
   }
   if (sc->done) return;
   constexpr int R = V16<T>::n;
+  constexpr int RR = R * CH;           // consecutive rows per thread (CH 16-byte chunks)
   constexpr bool THREE = KIND == OP_ST3D7;
-  const int blk = blockIdx.x - 1;
+  const int blk = blockIdx.x - nfin;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int nxy = nx * ny;
   for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
-    const int64_t p0 = (w.t * kBlock + threadIdx.x) * R;
+    const int64_t p0 = (w.t * kBlock + threadIdx.x) * RR;
     if (p0 >= n) continue;
     const int p = (int)p0;
     int ix, iy, iz = 0;
@@ -186,30 +191,62 @@ __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __re
     }
     const bool hS = iy > 0, hN = iy < ny - 1;
     const bool hD = THREE && iz > 0, hU = THREE && iz < nz - 1;
-    const bool hW0 = ix > 0, hEl = ix + R < nx;
-    T xc[R], xs[R], xn[R], xd[R], xu[R];
-    load_chunk<T, PC>(in, dinv, ds, p, xc);
-    load_chunk<T, PC>(in, dinv, ds, hS ? p - nx : p, xs);
-    load_chunk<T, PC>(in, dinv, ds, hN ? p + nx : p, xn);
-    if (THREE) {
-      load_chunk<T, PC>(in, dinv, ds, hD ? p - nxy : p, xd);
-      load_chunk<T, PC>(in, dinv, ds, hU ? p + nxy : p, xu);
+    const bool hW0 = ix > 0, hEl = ix + RR < nx;
+    T xc[RR], xs[RR], xn[RR], xd[RR], xu[RR];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      T t[R];
+      load_chunk<T, PC>(in, dinv, ds, p + c * R, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) xc[c * R + e] = t[e];
+      load_chunk<T, PC>(in, dinv, ds, (hS ? p - nx : p) + c * R, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) xs[c * R + e] = t[e];
+      load_chunk<T, PC>(in, dinv, ds, (hN ? p + nx : p) + c * R, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) xn[c * R + e] = t[e];
+      if (THREE) {
+        load_chunk<T, PC>(in, dinv, ds, (hD ? p - nxy : p) + c * R, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) xd[c * R + e] = t[e];
+        load_chunk<T, PC>(in, dinv, ds, (hU ? p + nxy : p) + c * R, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) xu[c * R + e] = t[e];
+      }
     }
-    const int jw = hW0 ? p - 1 : p, je = hEl ? p + R : p;
+    const int jw = hW0 ? p - 1 : p, je = hEl ? p + RR : p;
     const T xw0 = prec1<T, PC>(in[jw], dinv, ds, jw);
     const T xeR = prec1<T, PC>(in[je], dinv, ds, je);
-    T cS[R], cW[R], cC[R], cE[R], cN[R];
+    T cS[RR], cW[RR], cC[RR], cE[RR], cN[RR];
     if (KIND == OP_DIA5) {
-      ld16(P.dia + p, cS); ld16(P.dia + P.ld + p, cW); ld16(P.dia + 2 * P.ld + p, cC);
-      ld16(P.dia + 3 * P.ld + p, cE); ld16(P.dia + 4 * P.ld + p, cN);
-    }
-    T res[R];
 #pragma unroll
-    for (int e = 0; e < R; ++e) {
+      for (int c = 0; c < CH; ++c) {
+        T t[R];
+        const int64_t q = p + c * R;
+        ld16(P.dia + q, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) cS[c * R + e] = t[e];
+        ld16(P.dia + P.ld + q, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) cW[c * R + e] = t[e];
+        ld16(P.dia + 2 * P.ld + q, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) cC[c * R + e] = t[e];
+        ld16(P.dia + 3 * P.ld + q, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) cE[c * R + e] = t[e];
+        ld16(P.dia + 4 * P.ld + q, t);
+#pragma unroll
+        for (int e = 0; e < R; ++e) cN[c * R + e] = t[e];
+      }
+    }
+    T res[RR];
+#pragma unroll
+    for (int e = 0; e < RR; ++e) {
       const T xw = e == 0 ? xw0 : xc[e - 1];
-      const T xe = e == R - 1 ? xeR : xc[e + 1];
+      const T xe = e == RR - 1 ? xeR : xc[e + 1];
       const bool vw = e == 0 ? hW0 : true;
-      const bool ve = e == R - 1 ? hEl : true;
+      const bool ve = e == RR - 1 ? hEl : true;
       T sum = T(0);
       if (KIND == OP_DIA5) {
         if (hS) sum += cS[e] * xs[e];
@@ -234,7 +271,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __re
       }
       res[e] = sum;
     }
-    st16(out + p, res);
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      T t[R];
+#pragma unroll
+      for (int e = 0; e < R; ++e) t[e] = res[c * R + e];
+      st16(out + p + c * R, t);
+    }
   }
 }
 
@@ -282,6 +325,15 @@ __device__ __forceinline__ bool rr_due(const DevScalars* __restrict__ sc) {
   return sc->rn >= sc->tau * sc->rn0;
 }
 
+// A grid smaller than the partial count that the following final reduces
+// clears the partials of the blocks it does not have.
+template <int NS>
+__device__ __forceinline__ void zero_partials(const int (&slot)[NS], double* __restrict__ partials,
+                                              int npart) {
+  for (int j = blockIdx.x + gridDim.x; j < npart; j += gridDim.x)
+    if (threadIdx.x < NS) partials[slot[threadIdx.x] * kMaxBlocks + j] = 0.0;
+}
+
 // Residual replacement (eq:rr), first half: r = b - A x_{i+1}, k = M^-1 r,
 // s = A g_i, l = M^-1 s.  FP64 products; stored results rounded to T.  Also
 // the partials of ||x_{i+1}||^2, ||k||^2, ||l||^2 that restart the automated
@@ -293,7 +345,8 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
                                                 T* __restrict__ l, const T* __restrict__ dinv, T ds,
                                                 int64_t n, int64_t ntiles, int nwork,
                                                 DevScalars* __restrict__ sc,
-                                                double* __restrict__ partials, int force) {
+                                                double* __restrict__ partials, int force,
+                                                int npart) {
   if (!force && !rr_due(sc)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc->rr_count += 1;
@@ -320,6 +373,7 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
   }
   const int slots[3] = {SL_RX2, SL_RK2, SL_RL2};
   block_partials<3>(acc, slots, partials, blockIdx.x);
+  zero_partials<3>(slots, partials, npart);
 }
 
 // Residual replacement, second half: w = A k, z = A l (FP64 products), and
@@ -335,7 +389,8 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
                                                 const T* __restrict__ rhat, const T* __restrict__ r,
                                                 const T* __restrict__ s, int64_t n, int64_t ntiles,
                                                 int nwork, DevScalars* __restrict__ sc,
-                                                double* __restrict__ partials, int force) {
+                                                double* __restrict__ partials, int force,
+                                                int npart) {
   if (!force && !rr_due(sc)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->n_saved = 1;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -359,6 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
   }
   const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
   block_partials<5>(acc, slots, partials, blockIdx.x);
+  zero_partials<5>(slots, partials, npart);
 }
 
 // partial of ||b - A x||^2 (FP64)
@@ -710,35 +766,60 @@ static void with_op(Solver& S, bool tr, bool use_pc, F&& f) {
 
 #define PBCG_GRID_OP dim3(S.nblk), dim3(kBlock), 0, st
 
+// Grid of the replacement kernels.  With the automated criterion they are
+// launched every iteration and usually exit at once (the decision is made
+// on the device), so a quarter of the usual grid keeps the empty launches
+// cheap; the partials of the missing blocks are cleared by the kernels.
+static int rr_grid(const Solver& S) {
+  const int g = S.auto_rr ? S.nblk / 4 : S.nblk;
+  return g < kXcds ? kXcds : (g / kXcds) * kXcds;
+}
+
+// blocks that run a fused final at the head of an SpMV grid: one per slot
+static int fin_blocks(const Solver& S, int fin_mode) {
+  return fin_mode == FIN_NONE ? 0 : fin_slot_count(fin_mode, S.auto_rr ? 1 : 0);
+}
+
 template <typename T>
 static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* out, int fin_mode,
                             hipStream_t st) {
   constexpr int R = V16<T>::n;
   if (o.kind == OP_SELL || o.dims[0] % R != 0) return false;
+  // two 16-byte chunks per thread (twice the bytes in flight per load wave)
+  // when grid lines allow it and the grid still has two tiles per block
+  const bool two = o.dims[0] % (2 * R) == 0 &&
+                   S.n / ((int64_t)kBlock * 2 * R) >= 2 * (int64_t)S.nblk;
   StParams<T> P;
   P.kind = o.kind;
   P.nx = o.dims[0]; P.ny = o.dims[1]; P.nz = o.dims[2];
   for (int d = 0; d < 7; ++d) P.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
   P.dia = (const T*)o.dia;
   P.ld = S.npad;
-  const int64_t ntiles = (S.n + (int64_t)kBlock * R - 1) / ((int64_t)kBlock * R);
+  const int64_t rows = (int64_t)kBlock * R * (two ? 2 : 1);
+  const int64_t ntiles = (S.n + rows - 1) / rows;
+  const int nfin = fin_blocks(S, fin_mode);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(S.nblk + 1), dim3(kBlock), 0, st, P, (const T*)in, (T*)out,
+    hipLaunchKernelGGL(kern, dim3(S.nblk + nfin), dim3(kBlock), 0, st, P, (const T*)in, (T*)out,
                        (const T*)S.dinv, (T)S.dinv_s, S.n, ntiles, S.nblk, S.sc, S.partials,
-                       fin_mode, S.nblk);
+                       fin_mode, S.nblk, nfin);
   };
   const bool pc = S.pc != PC_NONE;
-  switch (o.kind) {
-    case OP_ST2D5:
-      if (pc) go(k_spmv_st<T, PC_SCALAR, OP_ST2D5>); else go(k_spmv_st<T, PC_NONE, OP_ST2D5>);
-      break;
-    case OP_ST3D7:
-      if (pc) go(k_spmv_st<T, PC_SCALAR, OP_ST3D7>); else go(k_spmv_st<T, PC_NONE, OP_ST3D7>);
-      break;
-    case OP_DIA5:
-      if (pc) go(k_spmv_st<T, PC_VECTOR, OP_DIA5>); else go(k_spmv_st<T, PC_NONE, OP_DIA5>);
-      break;
-  }
+  auto pick = [&](auto ch) {
+    constexpr int CH = decltype(ch)::value;
+    switch (o.kind) {
+      case OP_ST2D5:
+        if (pc) go(k_spmv_st<T, PC_SCALAR, OP_ST2D5, CH>); else go(k_spmv_st<T, PC_NONE, OP_ST2D5, CH>);
+        break;
+      case OP_ST3D7:
+        if (pc) go(k_spmv_st<T, PC_SCALAR, OP_ST3D7, CH>); else go(k_spmv_st<T, PC_NONE, OP_ST3D7, CH>);
+        break;
+      case OP_DIA5:
+        if (pc) go(k_spmv_st<T, PC_VECTOR, OP_DIA5, CH>); else go(k_spmv_st<T, PC_NONE, OP_DIA5, CH>);
+        break;
+    }
+  };
+  if (two) pick(std::integral_constant<int, 2>{});
+  else pick(std::integral_constant<int, 1>{});
   return true;
 }
 
@@ -750,11 +831,12 @@ void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bo
                                        : spmv_structured<float>(S, o, in, out, fin_mode, st);
     if (done) return;
   }
+  const int nfin = fin_blocks(S, fin_mode);
   with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
-    hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(S.nblk + 1), dim3(kBlock), 0, st, op,
+    hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(S.nblk + nfin), dim3(kBlock), 0, st, op,
                        (const T*)in, (T*)out, (const T*)S.dinv, (T)S.dinv_s,
                        (const T*)S.vec[V_RHAT], S.n, S.rtiles, S.nblk, S.sc, S.partials, fin_mode,
-                       dot_rhat ? 1 : 0);
+                       dot_rhat ? 1 : 0, nfin);
   });
 }
 
@@ -770,19 +852,21 @@ void launch_init_res(Solver& S, bool tr, hipStream_t st) {
 
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st) {
   with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
-    hipLaunchKernelGGL((k_rr1<T, PC, Op>), PBCG_GRID_OP, op, (const double*)S.x,
+    const int g = rr_grid(S);
+    hipLaunchKernelGGL((k_rr1<T, PC, Op>), dim3(g), dim3(kBlock), 0, st, op, (const double*)S.x,
                        (const T*)S.vec[V_G], (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_K],
                        (T*)S.vec[V_S], (T*)S.vec[V_L], (const T*)S.dinv, (T)S.dinv_s, S.n,
-                       S.rtiles, S.nblk, S.sc, S.partials, force ? 1 : 0);
+                       S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk);
   });
 }
 
 void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st) {
   with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
-    hipLaunchKernelGGL((k_rr2<T, PC, Op>), PBCG_GRID_OP, op, (const T*)S.vec[V_K],
+    const int g = rr_grid(S);
+    hipLaunchKernelGGL((k_rr2<T, PC, Op>), dim3(g), dim3(kBlock), 0, st, op, (const T*)S.vec[V_K],
                        (const T*)S.vec[V_L], (T*)S.vec[V_W], (T*)S.vec[V_Z], (T*)S.vec[V_TMP],
                        (const T*)S.vec[V_RHAT], (const T*)S.vec[V_R], (const T*)S.vec[V_S], S.n,
-                       S.rtiles, S.nblk, S.sc, S.partials, force ? 1 : 0);
+                       S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk);
   });
 }
 

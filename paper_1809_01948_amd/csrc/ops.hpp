@@ -205,17 +205,61 @@ __device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, dou
   sc->dz_prev = smu * nl * e;
 }
 
+// Slots each fused final reduces (the order is the order run_final reads
+// them in).  GLRED 2 in automated mode adds the norms of the gap bound.
+constexpr int kMaxFinSlots = 22;
+static __constant__ int kFinSlotsInit[6] = {SL_RR0, SL_RW0, SL_RR, SL_BB, SL_X2, SL_K2};
+static __constant__ int kFinSlotsOmega[2] = {SL_QY, SL_YY};
+static __constant__ int kFinSlotsBeta[kMaxFinSlots] = {
+    SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_K2, SL_W2, SL_T2, SL_M2, SL_G2, SL_S2,
+    SL_L2,  SL_Z2,  SL_Q2,  SL_Y2,  SL_X2, SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2};
+
+// number of slots a fused final mode reduces, and their list
+__host__ __device__ inline int fin_slot_count(int mode, int rr_auto) {
+  switch (mode) {
+    case FIN_INIT: return 6;
+    case FIN_OMEGA: return 2;
+    case FIN_BETA:
+    case FIN_REDO: return rr_auto ? kMaxFinSlots : 5;
+    case FIN_PROBE: return 5;
+    default: return 0;
+  }
+}
+__device__ inline const int* fin_slot_list(int mode) {
+  return mode == FIN_INIT ? kFinSlotsInit : mode == FIN_OMEGA ? kFinSlotsOmega : kFinSlotsBeta;
+}
+
+// NS sums, either reduced here from the partials or (PRE) taken from `pre`
+// (indexed by slot) where a distributed final already reduced them.  PRE is
+// a template argument so that kernels with a distributed final do not
+// contain the wide one-block reduction, whose many loads in flight would
+// otherwise set the register budget of the whole kernel.
+template <bool PRE, int NS>
+__device__ __forceinline__ void fin_sums(const double* pre, const double* __restrict__ partials,
+                                         const int (&sl)[NS], int nblk, double (&v)[NS]) {
+  if constexpr (PRE) {
+#pragma unroll
+    for (int d = 0; d < NS; ++d) v[d] = pre[sl[d]];
+  } else {
+    block_sum_slots<NS>(partials, sl, nblk, v);
+  }
+}
+
 // Runs one FinalMode over the partials written by the previous kernel(s).
-// Must be executed by all kBlock threads of exactly one block.
+// Must be executed by all kBlock threads of exactly one block.  With PRE,
+// `pre` holds the already reduced sums of the mode's slots (fused modes
+// only).
+template <bool PRE = false>
 __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
-                                 const double* __restrict__ partials, int nblk, int aux) {
+                                 const double* __restrict__ partials, int nblk, int aux,
+                                 const double* pre = nullptr) {
   const bool t0 = threadIdx.x == 0;
   switch (mode) {
     case FIN_INIT: {
       // Algorithm 2 initialisation: rho_0 = (r0, r0), alpha_0 = rho_0 / (r0, w0)
       const int sl[6] = {SL_RR0, SL_RW0, SL_RR, SL_BB, SL_X2, SL_K2};
       double v[6];
-      block_sum_slots<6>(partials, sl, nblk, v);
+      fin_sums<PRE, 6>(pre, partials, sl, nblk, v);
       const double rho = v[0], rw = v[1], rr = v[2], bb = v[3];
       if (t0) {
         sc->sig[SL_RR0] = rho; sc->sig[SL_RW0] = rw; sc->sig[SL_RR] = rr; sc->sig[SL_BB] = bb;
@@ -248,7 +292,7 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       // omega_i = (q_i, y_i) / (y_i, y_i); (y, y) = 0 gives omega = 0
       const int sl[2] = {SL_QY, SL_YY};
       double v[2];
-      block_sum_slots<2>(partials, sl, nblk, v);
+      fin_sums<PRE, 2>(pre, partials, sl, nblk, v);
       const double s1 = v[0], s2 = v[1];
       if (t0) {
         sc->sig[SL_QY] = s1; sc->sig[SL_YY] = s2;
@@ -269,11 +313,11 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
                           SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2};
       double v[NS];
       if (sc->rr_auto) {
-        block_sum_slots<NS>(partials, sl, nblk, v);
+        fin_sums<PRE, NS>(pre, partials, sl, nblk, v);
       } else {
         const int sl5[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
         double v5[5];
-        block_sum_slots<5>(partials, sl5, nblk, v5);
+        fin_sums<PRE, 5>(pre, partials, sl5, nblk, v5);
         for (int d = 0; d < 5; ++d) v[d] = v5[d];
       }
       const double rho1 = v[0], rw = v[1], rs = v[2], rz = v[3], rr = v[4];
@@ -337,12 +381,14 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       }
       break;
     }
-    case FIN_TRUE: {
+    case FIN_TRUE: if constexpr (!PRE) {
       const double rr = block_sum_slot(partials, SL_RR, nblk);
       if (t0) sc->tr = sqrt(rr);
       break;
+    } else {
+      break;
     }
-    case FIN_GAP: {
+    case FIN_GAP: if constexpr (!PRE) {
       const double rr = block_sum_slot(partials, SL_RR, nblk);
       if (t0) {
         sc->gap = sqrt(rr);
@@ -350,8 +396,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         sc->gap_idx += 1;
       }
       break;
+    } else {
+      break;
     }
-    case FIN_C_INIT: {
+    case FIN_C_INIT: if constexpr (!PRE) {
       // Algorithm 1 initialisation: rho_0 = (r0, r0)
       const int sl[3] = {SL_RR0, SL_RR, SL_BB};
       double v[3];
@@ -369,8 +417,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         else if (!finite(rho)) stop(sc, ST_NONFINITE);
       }
       break;
+    } else {
+      break;
     }
-    case FIN_C_ALPHA: {
+    case FIN_C_ALPHA: if constexpr (!PRE) {
       const double sig = block_sum_slot(partials, SL_RS0, nblk);
       if (t0) {
         sc->sig[SL_RS0] = sig;
@@ -379,8 +429,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         else sc->alpha = sc->rho / sig;
       }
       break;
+    } else {
+      break;
     }
-    case FIN_C_BETA: {
+    case FIN_C_BETA: if constexpr (!PRE) {
       const int sl[2] = {SL_RR0, SL_RR};
       double v[2];
       block_sum_slots<2>(partials, sl, nblk, v);
@@ -412,26 +464,64 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         }
       }
       break;
+    } else {
+      break;
     }
     case FIN_PROBE: {
       const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
       double v[5];
-      block_sum_slots<5>(partials, sl, nblk, v);
+      fin_sums<PRE, 5>(pre, partials, sl, nblk, v);
       if (t0)
         for (int d = 0; d < 5; ++d) sc->sig[sl[d]] = v[d];
       break;
     }
-    case FIN_SUM: {
+    case FIN_SUM: if constexpr (!PRE) {
       const int sl[8] = {0, 1, 2, 3, 4, 5, 6, 7};
       double v[8];
       block_sum_slots<8>(partials, sl, nblk, v);
       if (t0)
         for (int j = 0; j < aux && j < 8; ++j) sc->sums[j] = v[j];
       break;
+    } else {
+      break;
     }
     default:
       break;
   }
+}
+
+// A fused final spread over the first `fb` blocks of a kernel: block b
+// reduces slots b, b + fb, ... of the mode (each with the same fixed-order
+// tree as a one-block final, so the sums are bitwise those of run_final
+// alone), stores them, and arrives at a counter; the last block to arrive
+// reads the sums and runs the scalar logic.  No block waits for another.
+__device__ inline void distributed_final(int mode, DevScalars* __restrict__ sc,
+                                         const double* __restrict__ partials, int nblk, int fb) {
+  const int ns = fin_slot_count(mode, sc->rr_auto);
+  const int* list = fin_slot_list(mode);
+  for (int d = blockIdx.x; d < ns; d += fb) {
+    const int slot = list[d];
+    const double v = block_sum_slot(partials, slot, nblk);
+    if (threadIdx.x == 0)
+      __hip_atomic_store(&sc->red[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __shared__ int last;
+  __shared__ double pre[kNumSlots];
+  if (threadIdx.x == 0) {
+    const int old = __hip_atomic_fetch_add(&sc->fin_arrive, 1, __ATOMIC_ACQ_REL,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    last = old == fb - 1;
+    if (last) {
+      __hip_atomic_store(&sc->fin_arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int d = 0; d < ns; ++d) {
+        const int slot = list[d];
+        pre[slot] = __hip_atomic_load(&sc->red[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+  __syncthreads();
+  if (!last) return;
+  run_final<true>(mode, sc, partials, nblk, 0, pre);
 }
 
 }  // namespace pbcg

@@ -208,7 +208,8 @@ class Solver:
         L.check(L.load().pbicgstab_get_vector(self._h, self.VEC_IDS[which], _ptr(out), _stream()))
         return out
 
-    KERNELS = {"phaseA": 0, "spmv1": 1, "phaseB": 2, "spmv2": 3, "iteration": 4, "copy": 5}
+    KERNELS = {"phaseA": 0, "spmv1": 1, "phaseB": 2, "spmv2": 3, "iteration": 4, "copy": 5,
+               "spmv_bare": 6}
 
     def time_kernel(self, kernel: str, reps: int = 50) -> float:
         """Average duration (ms) of one launch of an iteration kernel, timed

@@ -78,6 +78,28 @@ def c3_full():
     return convdiff3d_c3(200, with_csr=True)
 
 
+@pytest.mark.parametrize("case", ["c3", "c5"])
+def test_full_size_structured_equals_csr(Solver, c3_full, case):
+    """At full size the structured SPMV gives each thread two 16-byte chunks
+    of a grid line; its products are still bitwise those of the row-wise CSR
+    kernel (same ascending column order), so three iterations in the two
+    forms agree bit for bit."""
+    if case == "c3":
+        p, form = c3_full, "stencil"
+    else:
+        p, form = inverse_problem_c5(2048, with_csr=True), "dia5"
+    out = {}
+    for f in (form, "csr"):
+        S = Solver.from_problem(p, form=f)
+        x, st = S.solve(dev(p.b), tol=0.0, maxit=3)
+        out[f] = (host(x), host(S.get_vector("v")), host(S.get_vector("w")), st["iterations"])
+        S.close()
+    a, b = out[form], out["csr"]
+    assert a[3] == b[3] == 3
+    for u, v in zip(a[:3], b[:3]):
+        assert np.array_equal(u, v)
+
+
 @pytest.mark.parametrize("precision,rr", [("fp64", 100), ("mixed", 50)])
 def test_c3_full_size_to_1e10(Solver, c3_full, precision, rr):
     """200^3 (N = 8e6): FP64 and FP32-storage solves both reach a 1e-10
