@@ -67,18 +67,21 @@ def log(msg):
 
 
 TRAFFIC_FILE = os.path.join(HERE, "profiles", "phaseB_poisson1000_fp64_traffic.txt")
-KERNEL_SOURCES = ("paper_1809_01948_amd/csrc/kernels_vec.hip", "paper_1809_01948_amd/csrc/common.hpp")
 KERNELS_ONLY_REPS = 20
 
 
 def kernel_source_hash():
-    """Hash of the sources phase B and the copy kernel are built from: a
-    stored counter reading is used only while they are unchanged."""
+    """Hash of the device code phase B and the copy kernel are built from
+    (their definitions and the shared device header): a stored counter
+    reading is used only while that code is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+    vec = open(os.path.join(HERE, "paper_1809_01948_amd/csrc/kernels_vec.hip")).read()
+    for start in ("struct PhaseBArgs", "void k_phaseB(", "void k_copy("):
+        i = vec.index(start)
+        h.update(vec[i:vec.index("\n}\n", i)].encode())
+    with open(os.path.join(HERE, "paper_1809_01948_amd/csrc/common.hpp"), "rb") as f:
+        h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -499,6 +499,15 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
   }
   while (status < 0) {
     d = run_iterations(S, tr, start, o);
+    // the gap of a stopping iteration: the device skipped it once `done` was
+    // raised in that iteration's GLRED 2 final
+    if (o.gap_every > 0 && d.iter > 0 && d.iter % o.gap_every == 0 &&
+        d.gap_idx < d.iter / o.gap_every) {
+      launch_gap(S, tr, S.s1, true);
+      launch_final(S, FIN_GAP, 0, S.s1, true);
+      hipck(hipGetLastError(), "gap launch");
+      d = read_scalars(S);
+    }
     if (d.done == STOPPED) {
       status = d.status;
       break;

@@ -443,8 +443,8 @@ __global__ __launch_bounds__(kBlock) void k_gap(Op op, const double* __restrict_
                                                 const double* __restrict__ b, const T* __restrict__ r,
                                                 int64_t n, int64_t ntiles, int nwork,
                                                 DevScalars* __restrict__ sc,
-                                                double* __restrict__ partials) {
-  if (sc->done) return;
+                                                double* __restrict__ partials, int force) {
+  if (sc->done && !force) return;
   double acc[1] = {0.0};
   for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
     const int64_t i = w.t * kBlock + threadIdx.x;
@@ -877,10 +877,11 @@ void launch_true_res(Solver& S, bool tr, hipStream_t st) {
   });
 }
 
-void launch_gap(Solver& S, bool tr, hipStream_t st) {
+void launch_gap(Solver& S, bool tr, hipStream_t st, bool force) {
   with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
     hipLaunchKernelGGL((k_gap<T, Op>), PBCG_GRID_OP, op, (const double*)S.x, (const double*)S.b,
-                       (const T*)S.vec[V_R], S.n, S.rtiles, S.nblk, S.sc, S.partials);
+                       (const T*)S.vec[V_R], S.n, S.rtiles, S.nblk, S.sc, S.partials,
+                       force ? 1 : 0);
   });
 }
 

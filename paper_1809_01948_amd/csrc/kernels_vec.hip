@@ -396,8 +396,8 @@ void launch_cl_p(Solver& S, hipStream_t st) {
                        S.sc, S.vtiles);
 }
 
-void launch_final(Solver& S, int mode, int aux, hipStream_t st) {
-  const int respect = (mode == FIN_TRUE || mode == FIN_SUM || mode == FIN_INIT ||
+void launch_final(Solver& S, int mode, int aux, hipStream_t st, bool force) {
+  const int respect = (force || mode == FIN_TRUE || mode == FIN_SUM || mode == FIN_INIT ||
                        mode == FIN_C_INIT || mode == FIN_REDO) ? 0 : 1;
   hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, st, mode, S.sc, S.partials, S.nblk, aux,
                      respect);

@@ -88,7 +88,7 @@ enum VecId : int {
 // ---- launchers (kernels_vec.hip) ----
 void launch_phaseA(Solver& S, hipStream_t st);
 void launch_phaseB(Solver& S, hipStream_t st);
-void launch_final(Solver& S, int mode, int aux, hipStream_t st);
+void launch_final(Solver& S, int mode, int aux, hipStream_t st, bool force = false);
 void launch_cl_update(Solver& S, hipStream_t st);
 void launch_cl_p(Solver& S, hipStream_t st);
 void launch_fill_zero(Solver& S, void* ptr, int64_t count, size_t elem, hipStream_t st);
@@ -104,7 +104,7 @@ void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bo
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_true_res(Solver& S, bool tr, hipStream_t st);
-void launch_gap(Solver& S, bool tr, hipStream_t st);
+void launch_gap(Solver& S, bool tr, hipStream_t st, bool force = false);
 void launch_cl_init(Solver& S, bool tr, hipStream_t st);
 void launch_cl_spmv_s(Solver& S, bool tr, hipStream_t st);
 void launch_cl_spmv_y(Solver& S, bool tr, hipStream_t st);

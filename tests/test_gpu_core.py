@@ -283,8 +283,11 @@ def test_gap_history(Solver, P):
     xh, rh = host(x), host(S.get_vector("r"))
     assert rel(gap[-1], np.linalg.norm((p.b - A @ xh) - rh)) <= 1e-12
     if P:
-        for i in range(P - 1, its, P):
-            assert gap[i] == 0.0 and ref_gap[i] == 0.0
+        # the first replacement (iteration P - 1) happens on both sides; later
+        # ones stop once ||r|| < sqrt(eps) ||r_0|| (Section 3.6)
+        assert ref.rr_iters[0] == P - 1
+        assert gap[P - 1] == 0.0 and ref_gap[P - 1] == 0.0
+        assert st["replacements"] >= 1
     ok = (ref_gap > 0) & (gap > 0)
     run_g = np.maximum.accumulate(np.where(ok, gap, 0.0))[5:]
     run_r = np.maximum.accumulate(np.where(ok, ref_gap, 0.0))[5:]
