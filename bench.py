@@ -76,12 +76,14 @@ def kernel_source_hash():
     reading is used only while that code is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    vec = open(os.path.join(HERE, "paper_1809_01948_amd/csrc/kernels_vec.hip")).read()
-    for start in ("struct PhaseBArgs", "void k_phaseB(", "void k_copy("):
-        i = vec.index(start)
-        h.update(vec[i:vec.index("\n}\n", i)].encode())
-    with open(os.path.join(HERE, "paper_1809_01948_amd/csrc/common.hpp"), "rb") as f:
-        h.update(f.read())
+    parts = (("kernels_vec.hip", ("struct PhaseBArgs", "void k_phaseB(", "void k_copy(")),
+             ("common.hpp", ("double wave_sum(", "void block_partials(", "void ld16(",
+                             "void st16(", "void ldc(", "void stc(")))
+    for fname, starts in parts:
+        src = open(os.path.join(HERE, "paper_1809_01948_amd/csrc", fname)).read()
+        for start in starts:
+            i = src.index(start)
+            h.update(src[i:src.index("\n}\n", i)].encode())
     return h.hexdigest()[:16]
 
 

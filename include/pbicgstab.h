@@ -109,6 +109,10 @@ typedef struct {
                             -> sqrt(mu), mu~ sqrt(N) -> 1); 0: periodic replacement */
   double rr_eps;         /* epsilon of the bound; 0 selects the unit roundoff of the storage
                             precision (2^-53 FP64, 2^-24 mixed) */
+  double* bound_history; /* optional device buffer of bound_len doubles: with rr_auto, entry i
+                            (0-based) receives f^r_{i+1}, the bound after iteration i (after a
+                            replacement in that iteration: its restart value) */
+  int32_t bound_len;
 } pbcg_opts;
 
 typedef struct {
@@ -125,7 +129,7 @@ typedef struct {
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
  * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
- * rr_eps 0. */
+ * rr_eps 0, no bound history. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

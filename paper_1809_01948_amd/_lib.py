@@ -60,6 +60,8 @@ class Opts(ctypes.Structure):
         ("stream", _P),
         ("rr_auto", _c.c_int32),
         ("rr_eps", _c.c_double),
+        ("bound_history", _P),
+        ("bound_len", _c.c_int32),
     ]
 
 

@@ -104,7 +104,8 @@ struct DevScalars {
   // last block to arrive runs the scalar logic and resets the counter
   double red[kNumSlots];
   int32_t fin_arrive;
-  int32_t pad2_;
+  int32_t bound_len;               // entries of bound_history
+  double* bound_history;           // optional f^r per iteration (automated mode)
 };
 
 // ----------------------------------------------------------------------------

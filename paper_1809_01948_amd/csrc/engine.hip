@@ -317,6 +317,8 @@ DevScalars initial_scalars(const Solver& S, const pbcg_opts& o, bool tr) {
   std::memset(&d, 0, sizeof(d));
   d.tol = o.tol;
   d.tau = o.rr_tau > 0 ? o.rr_tau : std::sqrt(std::ldexp(1.0, -53));
+  d.bound_history = o.bound_history;
+  d.bound_len = o.bound_history ? o.bound_len : 0;
   d.rr_auto = o.rr_auto ? 1 : 0;
   d.rr_est = o.rr_auto == 2 ? 1 : 0;
   d.eps_b = o.rr_eps > 0 ? o.rr_eps : std::ldexp(1.0, S.precision == PBCG_FP64 ? -53 : -24);
@@ -341,7 +343,7 @@ void validate_opts(const pbcg_opts& o) {
   if (o.rr_period < 0) fail(PBCG_ERR_INVALID_ARG, "rr_period must be >= 0");
   if (o.rr_tau < 0) fail(PBCG_ERR_INVALID_ARG, "rr_tau must be >= 0");
   if (o.check_every < 0) fail(PBCG_ERR_INVALID_ARG, "check_every must be >= 0");
-  if (o.history_len < 0 || o.gap_len < 0 || o.gap_every < 0)
+  if (o.history_len < 0 || o.gap_len < 0 || o.gap_every < 0 || o.bound_len < 0)
     fail(PBCG_ERR_INVALID_ARG, "negative history length");
 }
 

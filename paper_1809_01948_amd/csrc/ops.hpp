@@ -343,6 +343,8 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
             gap_bound_reset(sc, sqrt(v[19]), sqrt(v[20]), sqrt(v[9]), sqrt(v[21]));
             sc->rr_hit = 0;
           }
+          if (sc->bound_history && its >= 1 && its <= sc->bound_len)
+            sc->bound_history[its - 1] = sc->fr;
         }
         if (!finite(rho1) || !finite(rw) || !finite(rs) || !finite(rz) || !finite(rr)) {
           stop(sc, ST_NONFINITE);

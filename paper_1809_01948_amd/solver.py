@@ -105,7 +105,7 @@ class Solver:
 
     # ---- solves ---------------------------------------------------------
     def _opts(self, tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-              gap_history, use_graph, rr_auto=False, rr_eps=0.0):
+              gap_history, use_graph, rr_auto=False, rr_eps=0.0, bound_history=None):
         o = L.Opts()
         L.load().pbicgstab_default_opts(ctypes.byref(o))
         o.tol = tol
@@ -132,6 +132,9 @@ class Solver:
         else:   # True: the worst-case bound in FP64, the estimate with FP32 recurrences
             o.rr_auto = 1 if self.precision == "fp64" else 2
         o.rr_eps = rr_eps
+        if bound_history is not None:
+            o.bound_history = bound_history.data_ptr()
+            o.bound_len = bound_history.numel()
         return o
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, *, tol=1e-10,
@@ -139,7 +142,7 @@ class Solver:
               history: Optional[torch.Tensor] = None, gap_every=0,
               gap_history: Optional[torch.Tensor] = None, use_graph=False,
               method="pipelined", out: Optional[torch.Tensor] = None, rr_auto=False,
-              rr_eps=0.0):
+              rr_eps=0.0, bound_history: Optional[torch.Tensor] = None):
         """Solve A x = b (A^T x = b with transpose).  Returns (x, stats dict).
 
         method: 'pipelined' (Algorithm 2 with residual replacement: every
@@ -151,11 +154,12 @@ class Solver:
             out = torch.zeros_like(b) if x0 is None else _dev_vec(x0, self.n, "x0").clone()
         elif x0 is not None:
             out.copy_(x0)
-        for t, nm in ((history, "history"), (gap_history, "gap_history")):
+        for t, nm in ((history, "history"), (gap_history, "gap_history"),
+                      (bound_history, "bound_history")):
             if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
                 raise TypeError(f"{nm} must be a contiguous CUDA float64 tensor")
         o = self._opts(tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-                       gap_history, use_graph, rr_auto, rr_eps)
+                       gap_history, use_graph, rr_auto, rr_eps, bound_history)
         st = L.Stats()
         fn = lib.pbicgstab_solve if method == "pipelined" else lib.classic_bicgstab_solve
         code = fn(self._h, _ptr(b), _ptr(out), ctypes.byref(o), ctypes.byref(st))

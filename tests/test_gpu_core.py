@@ -400,6 +400,28 @@ def test_automated_replacement_c1(Solver, form):
     S.close()
 
 
+@pytest.mark.parametrize("case,variant", [("c1", "bound"), ("c1", "estimate"),
+                                          ("poisson-200", "bound"), ("poisson-200", "estimate")])
+def test_automated_bound_trace(Solver, case, variant):
+    """The running bound f^r of eq:DDr_bound, logged per iteration, equals the
+    oracle's over the first iterations (it is a function of the iteration's
+    scalars and vector norms, which agree to ~1e-13 there)."""
+    from workloads import poisson2d_c2
+    p = convdiff2d_c1(32) if case == "c1" else poisson2d_c2(200)
+    A, ops = oracle_ops(p)
+    k = 12
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, rr_mode="auto",
+                             rr_estimate=variant == "estimate")
+    S = Solver.from_problem(p, form="csr" if case == "c1" else "stencil")
+    bh = torch.zeros(k, dtype=torch.float64, device="cuda")
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto=variant, bound_history=bh)
+    fr = host(bh)
+    assert st["iterations"] == k and len(ref.fr) == k
+    assert np.all(rel(fr, np.array(ref.fr)) <= 1e-9), (fr, ref.fr)
+    assert st["replacements"] == ref.replacements
+    S.close()
+
+
 @pytest.mark.parametrize("case", ["c1-64", "poisson-200"])
 def test_automated_replacement_converges(Solver, case):
     """Automated replacement on a larger unsymmetric problem without

@@ -1,0 +1,89 @@
+"""Pins of the low-precision-storage oracle (oracle.mixed).
+
+* With FP64 storage it is the FP64 oracle of Algorithm 2, bit for bit (the
+  same lines in the same order), with periodic and automated replacement.
+* With FP32 storage, the local rounding errors are those of single
+  precision: the true-minus-recursive residual gap stays below the paper's
+  bound eq:DDr_bound evaluated with the FP32 unit roundoff (no replacement),
+  and is far above what FP64 arithmetic would leave (the storage really is
+  FP32).
+* With FP32 storage and replacement in FP64 the method still reaches a
+  1e-10 true residual on a well-conditioned problem.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import Float64Ops, pipelined_bicgstab
+from oracle.mixed import pipelined_bicgstab_lowprec
+from workloads import convdiff2d_c1, random_dense_system
+
+
+def _cases():
+    return [("c1-m", convdiff2d_c1(12), False), ("c1-j", convdiff2d_c1(12), True),
+            ("dense", random_dense_system(30, 5, shift=8.0), False)]
+
+
+@pytest.mark.parametrize("name,p,jacobi", _cases(), ids=[c[0] for c in _cases()])
+@pytest.mark.parametrize("mode", ["periodic", "auto"])
+def test_float64_storage_is_the_fp64_oracle(name, p, jacobi, mode):
+    A = p.scipy_csr()
+    ops = Float64Ops(A, 1.0 / A.diagonal() if jacobi else None)
+    kw = dict(tol=1e-12, maxit=300)
+    if mode == "periodic":
+        kw["rr_period"] = 7
+    else:
+        kw["rr_mode"] = "auto"
+    ref = pipelined_bicgstab(ops, p.b, **kw)
+    got = pipelined_bicgstab_lowprec(A, p.b, jacobi=jacobi, store=np.float64, **kw)
+    assert got.status == ref.status and got.iterations == ref.iterations
+    assert got.replacements == ref.replacements and got.rr_iters == ref.rr_iters
+    assert got.alpha == ref.alpha and got.omega == ref.omega and got.beta == ref.beta
+    assert got.rnorm == ref.rnorm and got.fr == ref.fr
+    assert np.array_equal(got.x, ref.x)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_fp32_gap_within_the_bound_with_fp32_roundoff(jacobi):
+    p = convdiff2d_c1(16)
+    A = p.scipy_csr()
+    res = pipelined_bicgstab_lowprec(A, p.b, jacobi=jacobi, tol=0.0, maxit=60, rr_mode="auto",
+                                     rr_tau=0.0, rr_estimate=False, record=True)
+    assert res.replacements == 0 and len(res.fr) == 60
+    A_w = A.astype(np.float32).astype(np.float64)
+    gaps = np.array([np.linalg.norm((p.b - A_w @ sn["x1"]) - sn["r1"].astype(np.float64))
+                     for sn in res.snapshots])
+    assert np.all(gaps <= np.array(res.fr))
+    nb = np.linalg.norm(p.b)
+    # FP32 rounding is present: FP64 recurrences leave gaps near 1e-16 ||b||
+    assert gaps.max() > 1e-9 * nb
+    sn = res.snapshots[-1]
+    assert sn["r1"].dtype == np.float32 and sn["g"].dtype == np.float32
+    assert sn["x1"].dtype == np.float64
+
+
+@pytest.mark.parametrize("kw", [dict(rr_period=25), dict(rr_period=10, rr_tau=0.0)],
+                         ids=["P25", "P10-no-cutoff"])
+def test_fp32_storage_with_fp64_replacement_converges(kw):
+    """Replacement every 25 iterations, or every 10 without the sqrt(eps)
+    cutoff, reaches 1e-10 (with every 10 and the FP64 cutoff the last
+    replacement comes at ||r|| ~ 1e-8 ||r_0|| and the FP32 gap then stalls the
+    true residual near 4e-10; every 50 is too rare)."""
+    p = convdiff2d_c1(32)
+    A = p.scipy_csr()
+    res = pipelined_bicgstab_lowprec(A, p.b, tol=1e-10, maxit=3000, **kw)
+    assert res.status == 0, res.status_name
+    assert res.true_rel_res <= 1e-10
+    assert res.replacements >= 1
+    # the solution of the FP32-rounded system is that of A up to kappa * u32
+    assert np.linalg.norm(res.x - p.x_exact) <= 1e-4 * np.linalg.norm(p.x_exact)
+
+
+def test_fp32_storage_without_replacement_stalls():
+    """FP32 recurrences alone cannot reach 1e-10: the recursive residual
+    meets the tolerance long before the true one does."""
+    p = convdiff2d_c1(32)
+    A = p.scipy_csr()
+    res = pipelined_bicgstab_lowprec(A, p.b, tol=1e-10, maxit=3000)
+    assert res.status != 0
+    assert res.true_rel_res > 1e-8
