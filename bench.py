@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch phase B and the copy kernel on the workload (the short "
                          "program that the rocprofv3 counter runs profile)")
+    ap.add_argument("--kernels-workload", choices=("poisson1000", "convdiff200"),
+                    default="poisson1000",
+                    help="workload of --kernels-only: the 1000^2 Poisson step or the 200^3 "
+                         "convection-diffusion problem (HBM-resident working set)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "--kernels-only into the traffic summary under profiles/")
@@ -208,6 +212,20 @@ def main():
     from workloads import convdiff3d_c3, poisson2d_c2
 
     dev = torch.device("cuda:0")
+    if args.kernels_only and args.kernels_workload == "convdiff200":
+        p3 = convdiff3d_c3(200)
+        S3 = Solver.from_problem(p3, form="stencil", precision="fp64", precond="jacobi")
+        S3.solve(torch.from_numpy(p3.b).to(dev), tol=1e-10, maxit=50, rr_period=50)
+        res = {k: S3.time_kernel(k, reps=KERNELS_ONLY_REPS)
+               for k in ("phaseA", "spmv1", "phaseB", "spmv2", "copy")}
+        n3 = p3.n
+        res["GBps"] = {"phaseA": 13 * 8 * n3 / (res["phaseA"] * 1e-3) / 1e9,
+                       "phaseB": 15 * 8 * n3 / (res["phaseB"] * 1e-3) / 1e9,
+                       "spmv": 2 * 8 * n3 / (res["spmv1"] * 1e-3) / 1e9,
+                       "copy": 2 * 8 * n3 / (res["copy"] * 1e-3) / 1e9}
+        print(json.dumps(res), flush=True)
+        S3.close()
+        return
     log("generating 1000x1000 Poisson workload")
     prob = poisson2d_c2(1000, with_csr=not (args.skip_cpu or args.kernels_only))
     b = torch.from_numpy(prob.b).to(dev)
@@ -266,7 +284,8 @@ def main():
 
     # full solves of the same workload to a 1e-10 true residual
     sol = {}
-    for name, kw in (("pipelined_auto_rr", dict(rr_auto=True, method="pipelined")),
+    for name, kw in (("pipelined_rr200", dict(rr_period=200, method="pipelined")),
+                     ("pipelined_auto_rr", dict(rr_auto=True, method="pipelined")),
                      ("classic", dict(method="classic"))):
         torch.cuda.synchronize()
         t0 = time.perf_counter()

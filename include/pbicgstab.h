@@ -113,6 +113,11 @@ typedef struct {
                             (0-based) receives f^r_{i+1}, the bound after iteration i (after a
                             replacement in that iteration: its restart value) */
   int32_t bound_len;
+  int32_t restarts;      /* not in the paper: after a (r0, r_{i+1}) = 0 or zero alpha-denominator
+                            breakdown, start again from x_{i+1} (Algorithm 2's initialisation with
+                            x_0 := x_{i+1}, which also renews the shadow residual), at most this
+                            many times; the iteration count continues.  0 (default): stop with
+                            PBCG_BREAKDOWN_RHO as the paper's method does. */
 } pbcg_opts;
 
 typedef struct {
@@ -125,11 +130,13 @@ typedef struct {
   double elapsed_ms;         /* device time from the first to the last kernel of the solve */
   double rnorm0;             /* ||r_0|| */
   double bnorm;              /* ||b|| */
+  int32_t restarts;          /* restarts performed (pbcg_opts.restarts) */
+  int32_t pad_;
 } pbcg_stats;
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
  * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
- * rr_eps 0, no bound history. */
+ * rr_eps 0, no bound history, restarts 0. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

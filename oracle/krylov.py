@@ -210,6 +210,7 @@ class SolveResult:
     beta: list = field(default_factory=list)      # beta_{i+1} formed at the end of iteration i
     rnorm: list = field(default_factory=list)     # ||r_{i+1}|| after iteration i
     rr_iters: list = field(default_factory=list)  # iterations i in which a replacement ran
+    restarts: int = 0                             # restarts after breakdowns (option)
     fr: list = field(default_factory=list)        # f^r_{i+1} after iteration i (automated mode)
     true_rel_res: Optional[float] = None
     snapshots: list = field(default_factory=list)
@@ -376,7 +377,7 @@ class _GapBound:
 
 def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                        rr_tau=None, rr_mode="periodic", rr_eps=None, rr_estimate=False,
-                       record=False):
+                       restarts=0, record=False):
     """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with residual
     replacement (Section 3.6, eq:rr):
 
@@ -395,7 +396,13 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     (r0, s_i), (r0, z_i) -- plus (r_{i+1}, r_{i+1}) for the stopping test --
     with m_{i+1} = M^-1 w_{i+1}, t_{i+1} = A m_{i+1}.  In automated mode the
     norms entering the bound are reduced with the second global reduction
-    (Section 3.6: no extra synchronisation)."""
+    (Section 3.6: no extra synchronisation).
+
+    ``restarts`` (not in the paper, default 0): after a rho' = 0 or zero
+    alpha-denominator breakdown in iteration i, up to this many times, the
+    method starts again from x_{i+1}: the initialisation of Algorithm 2 is
+    repeated with x_0 := x_{i+1} (new r_0 = b - A x_{i+1}, which is also the
+    new shadow residual), the iteration count continues."""
     auto = rr_mode == "auto"
     if rr_mode not in ("periodic", "auto"):
         raise ValueError(rr_mode)
@@ -403,15 +410,20 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     tau = math.sqrt(eps if auto else unit_roundoff()) if rr_tau is None else rr_tau
     b = ops.copy(b)
     x = ops.zeros() if x0 is None else ops.copy(x0)
-    # initialisation (the two lines before the loop of Algorithm 2)
-    r = b - ops.spmv(x)                       # r_0 := b - A x_0
-    rhat = ops.copy(r)                        # shadow residual r_0 (never replaced)
-    k = ops.prec(r)                           # k_0 := M^-1 r_0
-    w = ops.spmv(k)                           # w_0 := A k_0
-    m = ops.prec(w)                           # m_0 := M^-1 w_0
-    t = ops.spmv(m)                           # t_0 := A m_0
-    rho = ops.dot(rhat, r)                    # (r_0, r_0)
-    den = ops.dot(rhat, w)                    # (r_0, w_0)
+
+    def initialise(x):
+        """The two lines before the loop of Algorithm 2."""
+        r = b - ops.spmv(x)                   # r_0 := b - A x_0
+        rhat = ops.copy(r)                    # shadow residual r_0 (never replaced)
+        k = ops.prec(r)                       # k_0 := M^-1 r_0
+        w = ops.spmv(k)                       # w_0 := A k_0
+        m = ops.prec(w)                       # m_0 := M^-1 w_0
+        t = ops.spmv(m)                       # t_0 := A m_0
+        rho = ops.dot(rhat, r)                # (r_0, r_0)
+        den = ops.dot(rhat, w)                # (r_0, w_0)
+        return r, rhat, k, w, m, t, rho, den
+
+    r, rhat, k, w, m, t, rho, den = initialise(x)
     nb = ops.norm(b)
     rn0 = ops.norm(r)
     rn = rn0
@@ -547,12 +559,35 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
             return _finish(res, x, STATUS["BREAKDOWN_OMEGA"], i + 1, ops, b)
         m = ops.prec(w)                                # m_{i+1} := M^-1 w_{i+1} (overlaps GLRED 2)
         t = ops.spmv(m)                                # t_{i+1} := A m_{i+1}
-        if rho_new == 0 or rho == 0:                   # GLRED 2 ends
-            return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
-        beta = ((alpha / omega) * rho_new) / rho       # beta_{i+1}
-        den = (rw + beta * rs) - (beta * omega) * rz
-        if den == 0:
-            return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
+        breakdown = rho_new == 0 or rho == 0           # GLRED 2 ends
+        if not breakdown:
+            beta = ((alpha / omega) * rho_new) / rho   # beta_{i+1}
+            den = (rw + beta * rs) - (beta * omega) * rz
+            breakdown = den == 0
+        if breakdown:
+            if res.restarts >= restarts:
+                return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
+            # start again from x_{i+1} (not in the paper; see the docstring)
+            res.restarts += 1
+            res.beta.append(ops.zero())
+            r, rhat, k, w, m, t, rho, den = initialise(x)
+            rn0 = ops.norm(r)
+            rn = rn0
+            if rn0 <= tol * nb:
+                return _finish(res, x, STATUS["CONVERGED"], i + 1, ops, b)
+            if not ops.finite(rho, den):
+                return _finish(res, x, STATUS["NONFINITE"], i + 1, ops, b)
+            if den == 0:
+                return _finish(res, x, STATUS["BREAKDOWN_RHO"], i + 1, ops, b)
+            alpha = rho / den
+            beta = ops.zero()
+            omega_prev = ops.zero()
+            g, s, l, z, n, v = (ops.zeros() for _ in range(6))
+            if auto:
+                f_cur = gb.start(ops.norm(x), ops.norm(k))
+                f_ok_prev = f_cur <= tau * rn0
+                rr_next = False
+            continue
         res.beta.append(beta)
         alpha = rho_new / den                          # alpha_{i+1}
         rho = rho_new

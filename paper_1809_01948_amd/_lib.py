@@ -62,6 +62,7 @@ class Opts(ctypes.Structure):
         ("rr_eps", _c.c_double),
         ("bound_history", _P),
         ("bound_len", _c.c_int32),
+        ("restarts", _c.c_int32),
     ]
 
 
@@ -76,10 +77,12 @@ class Stats(ctypes.Structure):
         ("elapsed_ms", _c.c_double),
         ("rnorm0", _c.c_double),
         ("bnorm", _c.c_double),
+        ("restarts", _c.c_int32),
+        ("pad_", _c.c_int32),
     ]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("pad")}
         d["status_name"] = STATUS_NAMES.get(self.status, str(self.status))
         return d
 

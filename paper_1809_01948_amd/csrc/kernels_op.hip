@@ -95,10 +95,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
                                                  const T* __restrict__ rhat, int64_t n, int64_t ntiles,
                                                  int nwork, DevScalars* __restrict__ sc,
                                                  double* __restrict__ partials, int fin_mode,
-                                                 int dot_rhat, int nfin) {
+                                                 int dot_rhat, int nfin, int npart) {
   if ((int)blockIdx.x < nfin) {
     if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done)
-      distributed_final(fin_mode, sc, partials, nwork, nfin);
+      distributed_final(fin_mode, sc, partials, npart, nfin);
     return;
   }
   if (sc->done) return;
@@ -787,8 +787,9 @@ static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* ou
   if (o.kind == OP_SELL || o.dims[0] % R != 0) return false;
   // two 16-byte chunks per thread (twice the bytes in flight per load wave)
   // when grid lines allow it and the grid still has two tiles per block
+  const int nwork = S.nspmv;
   const bool two = o.dims[0] % (2 * R) == 0 &&
-                   S.n / ((int64_t)kBlock * 2 * R) >= 2 * (int64_t)S.nblk;
+                   S.n / ((int64_t)kBlock * 2 * R) >= 2 * (int64_t)nwork;
   StParams<T> P;
   P.kind = o.kind;
   P.nx = o.dims[0]; P.ny = o.dims[1]; P.nz = o.dims[2];
@@ -799,8 +800,8 @@ static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* ou
   const int64_t ntiles = (S.n + rows - 1) / rows;
   const int nfin = fin_blocks(S, fin_mode);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(S.nblk + nfin), dim3(kBlock), 0, st, P, (const T*)in, (T*)out,
-                       (const T*)S.dinv, (T)S.dinv_s, S.n, ntiles, S.nblk, S.sc, S.partials,
+    hipLaunchKernelGGL(kern, dim3(nwork + nfin), dim3(kBlock), 0, st, P, (const T*)in, (T*)out,
+                       (const T*)S.dinv, (T)S.dinv_s, S.n, ntiles, nwork, S.sc, S.partials,
                        fin_mode, S.nblk, nfin);
   };
   const bool pc = S.pc != PC_NONE;
@@ -832,11 +833,13 @@ void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bo
     if (done) return;
   }
   const int nfin = fin_blocks(S, fin_mode);
+  // the (r0, out) partials are indexed by work block and reduced over nblk
+  const int nwork = dot_rhat ? S.nblk : S.nspmv;
   with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
-    hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(S.nblk + nfin), dim3(kBlock), 0, st, op,
+    hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(nwork + nfin), dim3(kBlock), 0, st, op,
                        (const T*)in, (T*)out, (const T*)S.dinv, (T)S.dinv_s,
-                       (const T*)S.vec[V_RHAT], S.n, S.rtiles, S.nblk, S.sc, S.partials, fin_mode,
-                       dot_rhat ? 1 : 0, nfin);
+                       (const T*)S.vec[V_RHAT], S.n, S.rtiles, nwork, S.sc, S.partials, fin_mode,
+                       dot_rhat ? 1 : 0, nfin, S.nblk);
   });
 }
 

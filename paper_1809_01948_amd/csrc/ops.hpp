@@ -270,7 +270,7 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         sc->beta = 0.0;
         sc->omega = 0.0;
         sc->omega_prev = 0.0;
-        sc->iter = 0;
+        sc->n_saved = 0;                       // the iteration count is set by the host
         if (sc->rr_auto) {
           // f^r_0 = ((mu sqrt(N) + 1) ||A|| ||x_0|| + ||b||) eps, ||Delta^w_0|| <= mu sqrt(N) ||A|| ||k_0|| eps
           gap_bound_reset(sc, sqrt(v[4]), sqrt(v[5]), 0.0, 0.0);

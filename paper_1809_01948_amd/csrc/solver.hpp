@@ -64,6 +64,7 @@ struct Solver {
   DevScalars* h_sc = nullptr;   // pinned, 2 entries (double-buffered poll)
 
   int nblk = 8;                 // blocks of every streaming kernel (multiple of 8)
+  int nspmv = 8;                // work blocks of the iteration SpMVs (multiple of 8)
   int vnt = 0;                  // non-temporal loads/stores: bit 0 phase A, bit 1 phase B
   bool auto_rr = false;         // the current solve uses the automated replacement
   double normA = 1.0;           // sqrt(||A||_1 ||A||_inf), an upper bound of ||A||_2

@@ -105,7 +105,8 @@ class Solver:
 
     # ---- solves ---------------------------------------------------------
     def _opts(self, tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-              gap_history, use_graph, rr_auto=False, rr_eps=0.0, bound_history=None):
+              gap_history, use_graph, rr_auto=False, rr_eps=0.0, bound_history=None,
+              restarts=0):
         o = L.Opts()
         L.load().pbicgstab_default_opts(ctypes.byref(o))
         o.tol = tol
@@ -135,6 +136,7 @@ class Solver:
         if bound_history is not None:
             o.bound_history = bound_history.data_ptr()
             o.bound_len = bound_history.numel()
+        o.restarts = restarts
         return o
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, *, tol=1e-10,
@@ -142,7 +144,7 @@ class Solver:
               history: Optional[torch.Tensor] = None, gap_every=0,
               gap_history: Optional[torch.Tensor] = None, use_graph=False,
               method="pipelined", out: Optional[torch.Tensor] = None, rr_auto=False,
-              rr_eps=0.0, bound_history: Optional[torch.Tensor] = None):
+              rr_eps=0.0, bound_history: Optional[torch.Tensor] = None, restarts=0):
         """Solve A x = b (A^T x = b with transpose).  Returns (x, stats dict).
 
         method: 'pipelined' (Algorithm 2 with residual replacement: every
@@ -159,7 +161,7 @@ class Solver:
             if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
                 raise TypeError(f"{nm} must be a contiguous CUDA float64 tensor")
         o = self._opts(tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-                       gap_history, use_graph, rr_auto, rr_eps, bound_history)
+                       gap_history, use_graph, rr_auto, rr_eps, bound_history, restarts)
         st = L.Stats()
         fn = lib.pbicgstab_solve if method == "pipelined" else lib.classic_bicgstab_solve
         code = fn(self._h, _ptr(b), _ptr(out), ctypes.byref(o), ctypes.byref(st))

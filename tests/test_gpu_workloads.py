@@ -100,15 +100,18 @@ def test_full_size_structured_equals_csr(Solver, c3_full, case):
         assert np.array_equal(u, v)
 
 
-@pytest.mark.parametrize("precision,rr", [("fp64", 100), ("mixed", 50)])
+@pytest.mark.parametrize("precision,rr", [("fp64", 100), ("mixed", 10)])
 def test_c3_full_size_to_1e10(Solver, c3_full, precision, rr):
     """200^3 (N = 8e6): FP64 and FP32-storage solves both reach a 1e-10
     relative true residual, recomputed by the oracle's FP64 SPMV, and the
-    exact solution ones/sqrt(N) to the accuracy that residual allows."""
+    exact solution ones/sqrt(N) to the accuracy that residual allows.  (With
+    FP32 storage, replacement every 50 converged on one build and diverged
+    on another: the outcome hangs on the last bits of the reductions; every
+    10 converged on all builds measured.)"""
     p = c3_full
     A = p.scipy_csr()
     S = Solver.from_problem(p, form="stencil", precision=precision)
-    x, st = S.solve(dev(p.b), tol=1e-10, maxit=20000, rr_period=rr)
+    x, st = S.solve(dev(p.b), tol=1e-10, maxit=20000, rr_period=rr, restarts=3)
     assert st["status"] == 0, st
     xh = host(x)
     res = np.linalg.norm(p.b - A @ xh) / np.linalg.norm(p.b)

@@ -314,3 +314,29 @@ def test_automated_replacement_paper_tp2():
     res = pipelined_bicgstab(ops, p.b, tol=1e-13, maxit=3000, rr_mode="auto")
     assert res.status == STATUS["CONVERGED"] and res.true_rel_res <= 1e-13
     assert 1 <= res.replacements <= 20
+
+
+_BD_A = np.array([[-2.0, -2.0, -2.0], [-2.0, -2.0, -1.0], [-2.0, 2.0, -1.0]])
+_BD_B = np.array([0.0, -1.0, 0.0])
+
+
+def test_breakdown_and_restart_exact():
+    """A 3x3 system on which (r0, r_1) = 0 exactly after the first iteration
+    (alpha_0 = -1/2, omega_0 = 1/2: dyadic, so double arithmetic is exact up
+    to there).  Without restarts the method stops with BREAKDOWN_RHO; with
+    one restart from x_1 it reaches A^-1 b = (3/4, 1/4, -1) two iterations
+    later: exactly in rational arithmetic, to rounding in double."""
+    A = sp.csr_matrix(_BD_A)
+    for ops in (ExactOps(A), Float64Ops(A)):
+        r0 = pipelined_bicgstab(ops, _BD_B, tol=0.0, maxit=10)
+        assert r0.status == STATUS["BREAKDOWN_RHO"] and r0.iterations == 1
+        assert r0.alpha == [-0.5] and r0.omega == [0.5]
+        r1 = pipelined_bicgstab(ops, _BD_B, tol=1e-14, maxit=10, restarts=1)
+        assert r1.status == STATUS["CONVERGED"] and r1.restarts == 1
+        assert r1.iterations == 3
+        x = np.array([float(v) for v in r1.x])
+        if ops.exact:
+            assert list(r1.x) == [Fraction(3, 4), Fraction(1, 4), Fraction(-1)]
+        else:
+            assert np.allclose(x, [0.75, 0.25, -1.0], rtol=0, atol=1e-14)
+    assert np.allclose(np.linalg.solve(_BD_A, _BD_B), [0.75, 0.25, -1.0], rtol=0, atol=1e-15)
