@@ -80,13 +80,15 @@ KERNELS_ONLY_REPS = 20
 
 def kernel_source_hash():
     """Hash of the device code phase B and the copy kernel are built from
-    (their definitions and the shared device header): a stored counter
-    reading is used only while that code is unchanged."""
+    (their definitions, the shared device helpers and the stencil product
+    phase B computes): a stored counter reading is used only while that code
+    is unchanged."""
     import hashlib
     h = hashlib.sha256()
     parts = (("kernels_vec.hip", ("struct PhaseBArgs", "void k_phaseB(", "void k_copy(")),
              ("common.hpp", ("double wave_sum(", "void block_partials(", "void ld16(",
-                             "void st16(", "void ldc(", "void stc(")))
+                             "void st16(", "void ldc(", "void stc(")),
+             ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "void st_apply(")))
     for fname, starts in parts:
         src = open(os.path.join(HERE, "paper_1809_01948_amd/csrc", fname)).read()
         for start in starts:

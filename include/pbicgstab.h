@@ -242,6 +242,11 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream);
  *   4 one full iteration (0-3)
  *   5 a plain copy of N_pad doubles (2 x 8 N bytes), the bandwidth reference
  *   6 PREC + SPMV  v = A M^-1 z  without any final reduction
+ *   7 the GLRED 2 final reduction alone (scalars not updated)
+ * For structured operators (constant stencils, DIA5) the iteration computes
+ * t = A M^-1 w inside phase A and v = A M^-1 z inside phase B; then 0 and 2
+ * time those fused kernels, 1 and 3 the GLRED finals that run on their own
+ * between them, and 6 the stand-alone product for reference.
  * The solver vectors are overwritten (run it after, not between, the solves
  * whose results are needed); every later solve reinitialises them.
  */

@@ -17,6 +17,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace pbcg {
@@ -73,24 +74,31 @@ enum Status : int {
   ST_NONFINITE = 4, ST_TRUE_RES_NOT_MET = 5,
 };
 
-struct DevScalars {
-  double alpha, beta, omega, omega_prev, rho;
-  double rn, rn0, nb, tol, tau;
+// The fields that kernels read in their prologue (the done flag, the flags
+// of the replacement decision and the scalars of the vector updates) come
+// first, in one 64-byte line: a kernel that tests `done` and then reads the
+// scalars finds them in the line the test has already brought in.
+struct alignas(64) DevScalars {
+  int32_t done;                    // Done
+  int32_t n_saved;                 // 1: the iteration's pre-replacement z is in the spare vector
+  int32_t rr_auto;                 // 1: automated replacement strategy instead of the period
+  int32_t rr_next;                 // replacement due in the current iteration (automated)
+  int32_t iter;                    // completed iterations
+  int32_t rr_period;
+  double alpha, beta, omega, omega_prev;
+  double rn;
+  // (end of the first 64 bytes)
+  double tau, rn0, rho, nb, tol;
   double tr, gap;                  // last true residual norm / last gap norm
   double sig[8];                   // last reduced sums (diagnostics)
   double sums[8];                  // FIN_SUM output
-  int32_t iter;                    // completed iterations
-  int32_t done;                    // Done
   int32_t status;                  // Status (valid when done == STOPPED)
   int32_t rr_count;                // replacements performed
-  int32_t rr_period, maxit;
+  int32_t maxit;
   int32_t hist_len, gap_len;
   int32_t gap_idx;                 // next free gap-history slot
   int32_t bad_diag;                // set by value-update kernels on a zero diagonal
-  int32_t n_saved;                 // 1: the iteration's pre-replacement z is in the spare vector
   // automated residual replacement (running gap bound f^r and eq:criterion)
-  int32_t rr_auto;                 // 1: automated strategy instead of the period
-  int32_t rr_next;                 // replacement due in the current iteration
   int32_t rr_hit;                  // a replacement ran in the current iteration
   int32_t f_ok_prev;               // f^r_i <= tau ||r_i|| at the previous reduction
   int32_t rr_est;                  // 1: square-root estimate instead of the worst-case bound
@@ -142,23 +150,40 @@ __device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&sl
 
 // Sums of the first nblk partials of NS slots, computed by one whole block in
 // a fixed order (per thread: ascending j; then the wave tree; then the 4 wave
-// sums left to right); every thread returns the results.  All loads of all
-// slots are issued before any reduction, so the cost is one memory round
-// trip however many slots are reduced.
+// sums left to right); every thread returns the results.  The loads of up to
+// eight slots are issued together before any of them is added: every slot
+// holds kMaxBlocks entries, so all kMaxBlocks / kBlock strides are loaded
+// unconditionally (in bounds) and the entries at j >= nblk are not added.
+// Guarding each load instead would make each stride wait for the previous
+// one, one memory round trip per stride.
 template <int NS>
 __device__ __forceinline__ void block_sum_slots(const double* __restrict__ partials,
                                                 const int (&slot)[NS], int nblk,
                                                 double (&out)[NS]) {
   __shared__ double red[NS][kWaves];
+  constexpr int U = kMaxBlocks / kBlock;
+  constexpr int G = NS < 8 ? NS : 8;
   double s[NS];
 #pragma unroll
   for (int d = 0; d < NS; ++d) s[d] = 0.0;
 #pragma unroll
-  for (int u = 0; u < kMaxBlocks / kBlock; ++u) {
-    const int j = u * kBlock + threadIdx.x;
-    if (j < nblk) {
+  for (int d0 = 0; d0 < NS; d0 += G) {
+    double p[G][U];
 #pragma unroll
-      for (int d = 0; d < NS; ++d) s[d] += partials[slot[d] * kMaxBlocks + j];
+    for (int g = 0; g < G; ++g) {
+      if (d0 + g < NS) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          p[g][u] = partials[slot[d0 + g] * kMaxBlocks + u * kBlock + threadIdx.x];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (d0 + g < NS) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (u * kBlock + (int)threadIdx.x < nblk) s[d0 + g] += p[g][u];
+      }
     }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -188,6 +213,35 @@ __device__ __forceinline__ double block_sum_slot(const double* __restrict__ part
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// The scalar logic of a final reads and writes a few dozen fields of the
+// scalar struct, most of them behind branches, so on global memory every
+// access is a dependent round trip.  The block running a final therefore
+// copies the struct into LDS with one load per thread, one thread runs the
+// logic on the copy, and the block writes the copy back.  While a final
+// runs, no other block writes the struct (the other blocks of the kernel
+// only read `done`), so writing back every word is safe.
+constexpr int kScWords = (int)(sizeof(DevScalars) / 4);
+static_assert(sizeof(DevScalars) % 4 == 0, "scalar struct is copied in 32-bit words");
+static_assert(kScWords <= 4 * kBlock, "scalar struct copy: at most four words per thread");
+static_assert(offsetof(DevScalars, tau) == 64, "prologue fields fill the first 64 bytes");
+
+__device__ __forceinline__ void scalars_to_lds(const DevScalars* __restrict__ sc,
+                                               DevScalars* lsc) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(lsc);
+  for (int i = threadIdx.x; i < kScWords; i += kBlock)
+    dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+}
+
+__device__ __forceinline__ void scalars_from_lds(DevScalars* __restrict__ sc,
+                                                 const DevScalars* lsc) {
+  __syncthreads();
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(lsc);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(sc);
+  for (int i = threadIdx.x; i < kScWords; i += kBlock) dst[i] = src[i];
+}
 
 // ----------------------------------------------------------------------------
 // tile scheduling

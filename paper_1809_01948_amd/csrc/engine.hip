@@ -119,6 +119,7 @@ void common_setup(Solver& S, int precision, int precond) {
   if (footprint > ((int64_t)192 << 20)) S.vnt = precision == PBCG_FP64 ? 3 : 2;
   if (const char* env = std::getenv("PBCG_VEC_NT")) S.vnt = std::atoi(env) & 3;
   if (const char* env = std::getenv("PBCG_SPMV_TILED")) S.spmv_tiled = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_FUSE")) S.fuse = std::atoi(env) != 0;
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
   hipck(hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming), "hipEventCreate");
   hipck(hipEventCreateWithFlags(&S.ev_out, hipEventDisableTiming), "hipEventCreate");
@@ -126,9 +127,23 @@ void common_setup(Solver& S, int precision, int precond) {
   hipck(hipEventCreateWithFlags(&S.ev_poll[1], hipEventDisableTiming), "hipEventCreate");
   hipck(hipEventCreate(&S.ev_t0), "hipEventCreate");
   hipck(hipEventCreate(&S.ev_t1), "hipEventCreate");
-  for (int v = 0; v < V_COUNT; ++v) S.vec[v] = dalloc(S, S.npad * S.tsize);
-  S.x = (double*)dalloc(S, S.npad * 8);
-  S.b = (double*)dalloc(S, S.npad * 8);
+  long stagger = -1;
+  if (const char* env = std::getenv("PBCG_VEC_STAGGER")) stagger = std::strtol(env, nullptr, 10);
+  if (stagger < 0) {
+    for (int v = 0; v < V_COUNT; ++v) S.vec[v] = dalloc(S, S.npad * S.tsize);
+    S.x = (double*)dalloc(S, S.npad * 8);
+    S.b = (double*)dalloc(S, S.npad * 8);
+  } else {
+    // one slab; consecutive arrays start `stagger` bytes (a multiple of 256)
+    // past the end of the previous one
+    const int64_t st = round_up(stagger, 256);
+    const int64_t vb = round_up(S.npad * S.tsize, 256) + st;
+    const int64_t xb = round_up(S.npad * 8, 256) + st;
+    char* slab = (char*)dalloc(S, V_COUNT * vb + 2 * xb);
+    for (int v = 0; v < V_COUNT; ++v) S.vec[v] = slab + v * vb;
+    S.x = (double*)(slab + V_COUNT * vb);
+    S.b = (double*)(slab + V_COUNT * vb + xb);
+  }
   S.partials = (double*)dalloc(S, sizeof(double) * kNumSlots * kMaxBlocks);
   S.sc = (DevScalars*)dalloc(S, sizeof(DevScalars));
   hipck(hipHostMalloc((void**)&S.h_sc, 3 * sizeof(DevScalars), hipHostMallocDefault),
@@ -394,15 +409,24 @@ double true_residual(Solver& S, bool tr) {
 }
 
 // one iteration of Algorithm 2 (index i) on stream st
+//
+// Structured operators (fused_kind != 0): phase A computes t_i = A M^-1 w_i
+// and phase B v_i = A M^-1 z_i themselves, so each GLRED final runs as a
+// small kernel of its own between the phases.  Other operators: the two
+// SPMVs are kernels of their own and carry the finals in their first blocks,
+// overlapped with the product.
 void enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_t st) {
-  launch_phaseA(S, st);
-  launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
-  launch_phaseB(S, st);
+  const bool fused = fused_kind(S, tr) != 0;
+  launch_phaseA(S, tr, st);
+  if (fused) launch_fin(S, FIN_OMEGA, st);
+  else launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
+  launch_phaseB(S, tr, st);
   if (o.rr_auto || (o.rr_period > 0 && (i + 1) % o.rr_period == 0)) {
     launch_rr1(S, tr, false, st);      // predicated on the device (eq:criterion or the period)
     launch_rr2(S, tr, false, st);
   }
-  launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
+  if (fused) launch_fin(S, FIN_BETA, st);
+  else launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
   if (o.gap_every > 0 && (i + 1) % o.gap_every == 0) {
     launch_gap(S, tr, st);
     launch_final(S, FIN_GAP, 0, st);
@@ -1070,7 +1094,7 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream) {
 int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, void* stream) {
   return guarded([&]() -> int {
     Solver& S = H(h);
-    if (kernel < 0 || kernel > 6 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
+    if (kernel < 0 || kernel > 7 || reps < 1 || !avg_ms) fail(PBCG_ERR_INVALID_ARG, "bad arguments");
     hipStream_t cs = (hipStream_t)stream;
     hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
     hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
@@ -1089,14 +1113,22 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
     S.h_sc[2].nb = 1.0;
     hipck(hipMemcpyAsync(S.sc, &S.h_sc[2], sizeof(DevScalars), hipMemcpyHostToDevice, S.s1),
           "hipMemcpyAsync");
+    const bool fused = fused_kind(S, false) != 0;
     auto one = [&](int kk) {
       switch (kk) {
-        case 0: launch_phaseA(S, S.s1); break;
-        case 1: launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, S.s1); break;
-        case 2: launch_phaseB(S, S.s1); break;
-        case 3: launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_PROBE, false, S.s1); break;
+        case 0: launch_phaseA(S, false, S.s1); break;
+        case 1:
+          if (fused) launch_fin(S, FIN_OMEGA, S.s1);
+          else launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, S.s1);
+          break;
+        case 2: launch_phaseB(S, false, S.s1); break;
+        case 3:
+          if (fused) launch_fin(S, FIN_PROBE, S.s1);
+          else launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_PROBE, false, S.s1);
+          break;
         case 5: launch_copy(S, S.x, S.b, S.s1); break;
         case 6: launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_NONE, false, S.s1); break;
+        case 7: launch_fin(S, FIN_PROBE, S.s1); break;
       }
     };
     auto launch = [&]() {

@@ -20,13 +20,6 @@ namespace pbcg {
 // visitors
 // ----------------------------------------------------------------------------
 
-template <typename T, int PC>
-__device__ __forceinline__ T prec1(T zj, const T* __restrict__ dinv, T ds, int64_t j) {
-  if (PC == PC_NONE) return zj;
-  if (PC == PC_SCALAR) return ds * zj;
-  return dinv[j] * zj;
-}
-
 // sum_j a_ij (M^-1 z)_j in the storage precision
 template <typename T, int PC>
 struct SpmvVis {
@@ -97,8 +90,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
                                                  double* __restrict__ partials, int fin_mode,
                                                  int dot_rhat, int nfin, int npart) {
   if ((int)blockIdx.x < nfin) {
-    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done)
-      distributed_final(fin_mode, sc, partials, npart, nfin);
+    const int done = sc->done, rr_auto = sc->rr_auto;
+    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)
+      distributed_final(fin_mode, sc, partials, npart, nfin, rr_auto);
     return;
   }
   if (sc->done) return;
@@ -132,30 +126,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
 // approach the HBM bandwidth.  Each row is still summed in ascending column
 // order, exactly as the row-per-thread kernel does.
 
-template <typename T, int PC>
-__device__ __forceinline__ void load_chunk(const T* __restrict__ z, const T* __restrict__ dinv, T ds,
-                                           int64_t j, T (&v)[V16<T>::n]) {
-  ld16(z + j, v);
-  if (PC == PC_SCALAR) {
-#pragma unroll
-    for (int e = 0; e < V16<T>::n; ++e) v[e] = ds * v[e];
-  } else if (PC == PC_VECTOR) {
-    T d[V16<T>::n];
-    ld16(dinv + j, d);
-#pragma unroll
-    for (int e = 0; e < V16<T>::n; ++e) v[e] = d[e] * v[e];
-  }
-}
-
-template <typename T>
-struct StParams {
-  int kind;          // OP_ST2D5, OP_ST3D7 or OP_DIA5
-  int nx, ny, nz;
-  T c[7];            // constant coefficients (ascending column order)
-  const T* __restrict__ dia;
-  int64_t ld;
-};
-
 template <typename T, int PC, int KIND, int CH>
 __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __restrict__ in,
                                                     T* __restrict__ out, const T* __restrict__ dinv,
@@ -164,113 +134,28 @@ __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __re
                                                     double* __restrict__ partials, int fin_mode,
                                                     int nblk_partials, int nfin) {
   if ((int)blockIdx.x < nfin) {
-    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !sc->done)
-      distributed_final(fin_mode, sc, partials, nblk_partials, nfin);
+    const int done = sc->done, rr_auto = sc->rr_auto;
+    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)
+      distributed_final(fin_mode, sc, partials, nblk_partials, nfin, rr_auto);
     return;
   }
   if (sc->done) return;
   constexpr int R = V16<T>::n;
   constexpr int RR = R * CH;           // consecutive rows per thread (CH 16-byte chunks)
-  constexpr bool THREE = KIND == OP_ST3D7;
   const int blk = blockIdx.x - nfin;
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int nxy = nx * ny;
   for (XcdWalk w(ntiles, blk, nwork); w.t < w.end; w.t += w.step) {
     const int64_t p0 = (w.t * kBlock + threadIdx.x) * RR;
     if (p0 >= n) continue;
     const int p = (int)p0;
-    int ix, iy, iz = 0;
-    if (THREE) {
-      iz = p / nxy;
-      const int rem = p - iz * nxy;
-      iy = rem / nx;
-      ix = rem - iy * nx;
-    } else {
-      iy = p / nx;
-      ix = p - iy * nx;
-    }
-    const bool hS = iy > 0, hN = iy < ny - 1;
-    const bool hD = THREE && iz > 0, hU = THREE && iz < nz - 1;
-    const bool hW0 = ix > 0, hEl = ix + RR < nx;
-    T xc[RR], xs[RR], xn[RR], xd[RR], xu[RR];
+    T xc[RR], res[RR];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       T t[R];
       load_chunk<T, PC>(in, dinv, ds, p + c * R, t);
 #pragma unroll
       for (int e = 0; e < R; ++e) xc[c * R + e] = t[e];
-      load_chunk<T, PC>(in, dinv, ds, (hS ? p - nx : p) + c * R, t);
-#pragma unroll
-      for (int e = 0; e < R; ++e) xs[c * R + e] = t[e];
-      load_chunk<T, PC>(in, dinv, ds, (hN ? p + nx : p) + c * R, t);
-#pragma unroll
-      for (int e = 0; e < R; ++e) xn[c * R + e] = t[e];
-      if (THREE) {
-        load_chunk<T, PC>(in, dinv, ds, (hD ? p - nxy : p) + c * R, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) xd[c * R + e] = t[e];
-        load_chunk<T, PC>(in, dinv, ds, (hU ? p + nxy : p) + c * R, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) xu[c * R + e] = t[e];
-      }
     }
-    const int jw = hW0 ? p - 1 : p, je = hEl ? p + RR : p;
-    const T xw0 = prec1<T, PC>(in[jw], dinv, ds, jw);
-    const T xeR = prec1<T, PC>(in[je], dinv, ds, je);
-    T cS[RR], cW[RR], cC[RR], cE[RR], cN[RR];
-    if (KIND == OP_DIA5) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        T t[R];
-        const int64_t q = p + c * R;
-        ld16(P.dia + q, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) cS[c * R + e] = t[e];
-        ld16(P.dia + P.ld + q, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) cW[c * R + e] = t[e];
-        ld16(P.dia + 2 * P.ld + q, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) cC[c * R + e] = t[e];
-        ld16(P.dia + 3 * P.ld + q, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) cE[c * R + e] = t[e];
-        ld16(P.dia + 4 * P.ld + q, t);
-#pragma unroll
-        for (int e = 0; e < R; ++e) cN[c * R + e] = t[e];
-      }
-    }
-    T res[RR];
-#pragma unroll
-    for (int e = 0; e < RR; ++e) {
-      const T xw = e == 0 ? xw0 : xc[e - 1];
-      const T xe = e == RR - 1 ? xeR : xc[e + 1];
-      const bool vw = e == 0 ? hW0 : true;
-      const bool ve = e == RR - 1 ? hEl : true;
-      T sum = T(0);
-      if (KIND == OP_DIA5) {
-        if (hS) sum += cS[e] * xs[e];
-        if (vw) sum += cW[e] * xw;
-        sum += cC[e] * xc[e];
-        if (ve) sum += cE[e] * xe;
-        if (hN) sum += cN[e] * xn[e];
-      } else if (THREE) {
-        if (hD) sum += P.c[0] * xd[e];
-        if (hS) sum += P.c[1] * xs[e];
-        if (vw) sum += P.c[2] * xw;
-        sum += P.c[3] * xc[e];
-        if (ve) sum += P.c[4] * xe;
-        if (hN) sum += P.c[5] * xn[e];
-        if (hU) sum += P.c[6] * xu[e];
-      } else {
-        if (hS) sum += P.c[0] * xs[e];
-        if (vw) sum += P.c[1] * xw;
-        sum += P.c[2] * xc[e];
-        if (ve) sum += P.c[3] * xe;
-        if (hN) sum += P.c[4] * xn[e];
-      }
-      res[e] = sum;
-    }
+    st_apply<T, PC, KIND, CH>(P, in, dinv, ds, p, xc, res);
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       T t[R];
@@ -317,12 +202,16 @@ __global__ __launch_bounds__(kBlock) void k_init_res(Op op, const double* __rest
   block_partials<5>(acc, slots, partials, blk);
 }
 
+// Every field is loaded before the first test, so that the loads go out
+// together (tested one after another they would be dependent round trips).
 __device__ __forceinline__ bool rr_due(const DevScalars* __restrict__ sc) {
-  if (sc->done) return false;
-  if (sc->rr_auto) return sc->rr_next != 0;       // eq:criterion, decided at the last GLRED 2
-  const int P = sc->rr_period;
-  if (P <= 0 || ((sc->iter + 1) % P) != 0) return false;
-  return sc->rn >= sc->tau * sc->rn0;
+  const int done = sc->done, rr_auto = sc->rr_auto, rr_next = sc->rr_next;
+  const int P = sc->rr_period, iter = sc->iter;
+  const double rn = sc->rn, tau = sc->tau, rn0 = sc->rn0;
+  if (done) return false;
+  if (rr_auto) return rr_next != 0;               // eq:criterion, decided at the last GLRED 2
+  if (P <= 0 || ((iter + 1) % P) != 0) return false;
+  return rn >= tau * rn0;
 }
 
 // A grid smaller than the partial count that the following final reduces
@@ -515,8 +404,10 @@ __global__ __launch_bounds__(kBlock) void k_cl_spmv_y(Op op, const T* __restrict
                                                       int64_t ntiles, int nwork,
                                                       const DevScalars* __restrict__ sc,
                                                       double* __restrict__ partials) {
-  if (sc->done) return;
-  const T a = (T)sc->alpha;
+  const int done = sc->done;
+  const double alpha = sc->alpha;
+  if (done) return;
+  const T a = (T)alpha;
   double acc[2] = {0.0, 0.0};
   for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
     const int64_t i = w.t * kBlock + threadIdx.x;
@@ -790,12 +681,7 @@ static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* ou
   const int nwork = S.nspmv;
   const bool two = o.dims[0] % (2 * R) == 0 &&
                    S.n / ((int64_t)kBlock * 2 * R) >= 2 * (int64_t)nwork;
-  StParams<T> P;
-  P.kind = o.kind;
-  P.nx = o.dims[0]; P.ny = o.dims[1]; P.nz = o.dims[2];
-  for (int d = 0; d < 7; ++d) P.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
-  P.dia = (const T*)o.dia;
-  P.ld = S.npad;
+  const StParams<T> P = st_params<T>(S, o);
   const int64_t rows = (int64_t)kBlock * R * (two ? 2 : 1);
   const int64_t ntiles = (S.n + rows - 1) / rows;
   const int nfin = fin_blocks(S, fin_mode);
@@ -823,6 +709,25 @@ static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* ou
   else pick(std::integral_constant<int, 1>{});
   return true;
 }
+
+// Measured on MI355X: computing the products inside the phase kernels pays
+// for 2D grids (constant stencils, DIA5) in both precisions and for 3D grids
+// with FP32 storage (200^3: 182 against 197 us per iteration); with FP64
+// storage on 3D grids the fused phase kernels re-read the stencil input from
+// HBM (plane neighbours 320 KB apart fall out of the L2 under the other
+// streams) and the separate SPMVs are faster (356 against 366 us).
+int fused_kind(Solver& S, bool tr) {
+  if (!S.fuse || !S.spmv_tiled) return 0;
+  const OpData& o = op_of(S, tr);
+  const int R = (int)(16 / S.tsize);
+  if (o.kind == OP_SELL || o.dims[0] % R != 0) return 0;
+  if (o.kind == OP_ST3D7 && S.precision == 0) return 0;
+  if ((o.kind == OP_ST2D5 || o.kind == OP_ST3D7) && S.pc == PC_VECTOR) return 0;
+  if (o.kind == OP_DIA5 && S.pc == PC_SCALAR) return 0;
+  return o.kind;
+}
+
+void launch_fin(Solver& S, int fin_mode, hipStream_t st) { launch_final(S, fin_mode, 0, st); }
 
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
                  hipStream_t st) {

@@ -6,6 +6,9 @@
 // wave moves 1 KiB per vector per tile with fully coalesced dwordx4 accesses.
 // Vectors are zero-padded to whole tiles: no bounds checks.
 
+#include <stdexcept>
+#include <type_traits>
+
 #include "solver.hpp"
 
 namespace pbcg {
@@ -14,7 +17,7 @@ template <typename T>
 struct PhaseAArgs {
   const T* __restrict__ k;
   const T* __restrict__ w;
-  const T* __restrict__ t;
+  T* __restrict__ t;                // read, or written when the product is fused
   const T* __restrict__ r;
   const T* __restrict__ v;
   T* __restrict__ g;
@@ -38,14 +41,23 @@ struct PhaseAArgs {
 // pre-replacement z_{i-1} instead of the replaced one.  NT selects
 // non-temporal loads and stores; AUTO adds the squared norms of k, w, t, m,
 // g, s, l, z, q, y that the automated replacement bound needs.
-template <typename T, int PC, bool NT, bool AUTO, bool SAVED>
-__device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T wp,
-                                            double (&acc)[12], int64_t ntiles) {
+//
+// KIND != 0 (a structured operator): t_i = A m_i = A M^-1 w_i is computed
+// here from w_i, which is final when this kernel starts, instead of being
+// read (the SPMV that the unfused iteration runs after GLRED 2), and
+// stored.  w is then read with cached loads so that the stencil neighbours
+// of other tiles are served by the L2 of the XCD that walks them.
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool SAVED>
+__device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StParams<T>& P,
+                                            int64_t n, T a, T b, T wp, double (&acc)[12],
+                                            int64_t ntiles) {
   constexpr int C = V16<T>::n;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t i = (tile * kBlock + threadIdx.x) * C;
-    T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C];
-    ldc<T, C, NT>(A.k + i, k); ldc<T, C, NT>(A.w + i, w); ldc<T, C, NT>(A.t + i, t);
+  constexpr bool FUSE = KIND != 0;
+  for (XcdWalk it(ntiles, blockIdx.x, gridDim.x); it.t < it.end; it.t += it.step) {
+    const int64_t i = (it.t * kBlock + threadIdx.x) * C;
+    T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C], m[C];
+    ldc<T, C, NT>(A.k + i, k); ldc<T, C, NT && !FUSE>(A.w + i, w);
+    if (!FUSE) ldc<T, C, NT>(A.t + i, t);
     ldc<T, C, NT>(A.r + i, r); ldc<T, C, NT>(A.v + i, v); ldc<T, C, NT>(A.g + i, g);
     ldc<T, C, NT>(A.s + i, s); ldc<T, C, NT>(A.l + i, l); ldc<T, C, NT>(A.z + i, z);
     if (SAVED) ldc<T, C, NT>(A.zsave + i, zp);
@@ -53,12 +65,24 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T 
 #pragma unroll
     for (int e = 0; e < C; ++e) {
       const T de = (PC == PC_VECTOR) ? d[e] : A.dinv_s;
+      m[e] = (PC == PC_NONE) ? w[e] : de * w[e];
+    }
+    if constexpr (FUSE) {
+      if (i < n) {
+        st_apply<T, PC, KIND, 1>(P, A.w, A.dinv, A.dinv_s, (int)i, m, t);
+      } else {
+#pragma unroll
+        for (int e = 0; e < C; ++e) t[e] = T(0);          // padding rows stay zero
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const T de = (PC == PC_VECTOR) ? d[e] : A.dinv_s;
       const T zprev = SAVED ? zp[e] : z[e];
-      const T m = (PC == PC_NONE) ? w[e] : de * w[e];
       const T np = (PC == PC_NONE) ? zprev : de * zprev;
       const T gn = k[e] + b * (g[e] - wp * l[e]);
       const T sn = w[e] + b * (s[e] - wp * z[e]);
-      const T ln = m + b * (l[e] - wp * np);
+      const T ln = m[e] + b * (l[e] - wp * np);
       const T zn = t[e] + b * (z[e] - wp * v[e]);
       const T q = r[e] - a * sn;
       const T y = w[e] - a * zn;
@@ -68,7 +92,7 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T 
         acc[2] += (double)k[e] * (double)k[e];
         acc[3] += (double)w[e] * (double)w[e];
         acc[4] += (double)t[e] * (double)t[e];
-        acc[5] += (double)m * (double)m;
+        acc[5] += (double)m[e] * (double)m[e];
         acc[6] += (double)gn * (double)gn;
         acc[7] += (double)sn * (double)sn;
         acc[8] += (double)ln * (double)ln;
@@ -80,19 +104,24 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, T a, T b, T 
     }
     stc<T, C, NT>(A.g + i, g); stc<T, C, NT>(A.s + i, s); stc<T, C, NT>(A.l + i, l);
     stc<T, C, NT>(A.z + i, z);
+    if (FUSE) stc<T, C, NT>(A.t + i, t);
   }
 }
 
-template <typename T, int PC, bool NT, bool AUTO>
-__global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, const DevScalars* __restrict__ sc,
+template <typename T, int PC, bool NT, bool AUTO, int KIND>
+__global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> P, int64_t n,
+                                                   const DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
-  if (sc->done) return;
-  const T a = (T)sc->alpha, b = (T)sc->beta, wp = (T)sc->omega_prev;
+  // the scalars are loaded with the done flag (one round trip, not two)
+  const int done = sc->done, n_saved = sc->n_saved;
+  const double alpha = sc->alpha, beta = sc->beta, omega_prev = sc->omega_prev;
+  if (done) return;
+  const T a = (T)alpha, b = (T)beta, wp = (T)omega_prev;
   double acc[12];
 #pragma unroll
   for (int d = 0; d < 12; ++d) acc[d] = 0.0;
-  if (sc->n_saved) phaseA_body<T, PC, NT, AUTO, true>(A, a, b, wp, acc, ntiles);
-  else phaseA_body<T, PC, NT, AUTO, false>(A, a, b, wp, acc, ntiles);
+  if (n_saved) phaseA_body<T, PC, NT, AUTO, KIND, true>(A, P, n, a, b, wp, acc, ntiles);
+  else phaseA_body<T, PC, NT, AUTO, KIND, false>(A, P, n, a, b, wp, acc, ntiles);
   if (AUTO) {
     const int slots[12] = {SL_QY, SL_YY, SL_K2, SL_W2, SL_T2, SL_M2, SL_G2, SL_S2, SL_L2,
                            SL_Z2, SL_Q2, SL_Y2};
@@ -112,7 +141,7 @@ struct PhaseBArgs {
   const T* __restrict__ s;
   const T* __restrict__ z;
   const T* __restrict__ t;
-  const T* __restrict__ v;
+  T* __restrict__ v;                // read, or written when the product is fused
   const T* __restrict__ rhat;
   T* __restrict__ r;
   T* __restrict__ k;
@@ -129,22 +158,31 @@ struct PhaseBArgs {
 //   w_{i+1} = y_i - omega_i (t_i - alpha_i v_i)
 // in place, and the GLRED 2 partials (r0, r_{i+1}), (r0, w_{i+1}), (r0, s_i),
 // (r0, z_i), (r_{i+1}, r_{i+1}); AUTO adds ||x_i||^2, ||u_i||^2, ||n_i||^2, ||v_i||^2.
-template <typename T, int PC, bool NT, bool AUTO>
-__global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevScalars* __restrict__ sc,
+//
+// KIND != 0 (a structured operator): v_i = A n_i = A M^-1 z_i is computed
+// here from z_i, final since phase A, instead of being read (the SPMV that
+// the unfused iteration runs between the phases), and stored for the next
+// phase A; z is read with cached loads for the neighbours' sake.
+template <typename T, int PC, bool NT, bool AUTO, int KIND>
+__global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> P, int64_t nrows,
+                                                   const DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
-  if (sc->done) return;
-  constexpr int C = V16<T>::n;
+  const int done = sc->done;
   const double alpha = sc->alpha, omega = sc->omega;
+  if (done) return;
+  constexpr int C = V16<T>::n;
+  constexpr bool FUSE = KIND != 0;
   const T a = (T)alpha, om = (T)omega;
   double acc[9];
 #pragma unroll
   for (int d = 0; d < 9; ++d) acc[d] = 0.0;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t i = (tile * kBlock + threadIdx.x) * C;
-    T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C];
+  for (XcdWalk it(ntiles, blockIdx.x, gridDim.x); it.t < it.end; it.t += it.step) {
+    const int64_t i = (it.t * kBlock + threadIdx.x) * C;
+    T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C], n[C];
     double x[C];
     ldc<T, C, NT>(B.g + i, g); ldc<T, C, NT>(B.l + i, l); ldc<T, C, NT>(B.s + i, s);
-    ldc<T, C, NT>(B.z + i, z); ldc<T, C, NT>(B.t + i, t); ldc<T, C, NT>(B.v + i, v);
+    ldc<T, C, NT && !FUSE>(B.z + i, z); ldc<T, C, NT>(B.t + i, t);
+    if (!FUSE) ldc<T, C, NT>(B.v + i, v);
     ldc<T, C, NT>(B.rhat + i, rh); ldc<T, C, NT>(B.r + i, r); ldc<T, C, NT>(B.k + i, k);
     ldc<T, C, NT>(B.w + i, w);
     ldc<double, C, NT>(B.x + i, x);
@@ -152,20 +190,32 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevSca
 #pragma unroll
     for (int e = 0; e < C; ++e) {
       const T de = (PC == PC_VECTOR) ? d[e] : B.dinv_s;
+      n[e] = (PC == PC_NONE) ? z[e] : de * z[e];
+    }
+    if constexpr (FUSE) {
+      if (i < nrows) {
+        st_apply<T, PC, KIND, 1>(P, B.z, B.dinv, B.dinv_s, (int)i, n, v);
+      } else {
+#pragma unroll
+        for (int e = 0; e < C; ++e) v[e] = T(0);          // padding rows stay zero
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < C; ++e) {
+      const T de = (PC == PC_VECTOR) ? d[e] : B.dinv_s;
       const T m = (PC == PC_NONE) ? w[e] : de * w[e];
-      const T n = (PC == PC_NONE) ? z[e] : de * z[e];
       const T q = r[e] - a * s[e];
       const T u = k[e] - a * l[e];
       const T y = w[e] - a * z[e];
       if (AUTO) {
         acc[5] += x[e] * x[e];
         acc[6] += (double)u * (double)u;
-        acc[7] += (double)n * (double)n;
+        acc[7] += (double)n[e] * (double)n[e];
         acc[8] += (double)v[e] * (double)v[e];
       }
       x[e] = (x[e] + alpha * (double)g[e]) + omega * (double)u;
       const T rn = q - om * y;
-      const T kn = u - om * (m - a * n);
+      const T kn = u - om * (m - a * n[e]);
       const T wn = y - om * (t[e] - a * v[e]);
       r[e] = rn; k[e] = kn; w[e] = wn;
       const double rhd = (double)rh[e];
@@ -177,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, const DevSca
     }
     stc<T, C, NT>(B.r + i, r); stc<T, C, NT>(B.k + i, k); stc<T, C, NT>(B.w + i, w);
     stc<double, C, NT>(B.x + i, x);
+    if (FUSE) stc<T, C, NT>(B.v + i, v);
   }
   if (AUTO) {
     const int slots[9] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_X2, SL_U2, SL_N2, SL_V2};
@@ -207,9 +258,10 @@ struct ClUpdArgs {
 template <typename T, int PC>
 __global__ __launch_bounds__(kBlock) void k_cl_update(ClUpdArgs<T> U, const DevScalars* __restrict__ sc,
                                                       double* __restrict__ partials, int64_t ntiles) {
-  if (sc->done) return;
-  constexpr int W = V16<T>::n;
+  const int done = sc->done;
   const double alpha = sc->alpha, omega = sc->omega;
+  if (done) return;
+  constexpr int W = V16<T>::n;
   const T a = (T)alpha, om = (T)omega;
   double acc[2] = {0.0, 0.0};
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -252,9 +304,11 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cl_p(const T* __restrict__ r, T* __restrict__ p,
                                                  const T* __restrict__ s,
                                                  const DevScalars* __restrict__ sc, int64_t ntiles) {
-  if (sc->done) return;
+  const int done = sc->done;
+  const double beta = sc->beta, omega = sc->omega;
+  if (done) return;
   constexpr int W = V16<T>::n;
-  const T b = (T)sc->beta, om = (T)sc->omega;
+  const T b = (T)beta, om = (T)omega;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t i = (tile * kBlock + threadIdx.x) * W;
     T rr[W], pp[W], ss[W];
@@ -265,11 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_cl_p(const T* __restrict__ r, T* __r
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_final(int mode, DevScalars* __restrict__ sc,
+template <int NS>
+__global__ __launch_bounds__(kBlock) void k_final(int mode, FinSlots fs, DevScalars* __restrict__ sc,
                                                   const double* __restrict__ partials, int nblk,
                                                   int aux, int respect_done) {
-  if (respect_done && sc->done) return;
-  run_final(mode, sc, partials, nblk, aux);
+  one_block_final<NS>(mode, fs, sc, partials, nblk, aux, respect_done != 0);
 }
 
 template <typename T>
@@ -316,45 +370,74 @@ static inline int fill_blocks(int64_t count) {
   return (int)b;
 }
 
+// Launches kern<KIND> for the fused operator kind (0: none).  Only the
+// kinds that fused_kind() can return for this preconditioner are
+// instantiated: constant stencils with a scalar Jacobi scale, DIA5 with a
+// Jacobi vector, either without a preconditioner.
+template <int PC, class F>
+static void with_fused_kind(int kind, F&& f) {
+  if (kind == OP_ST2D5) {
+    if constexpr (PC != PC_VECTOR) { f(std::integral_constant<int, OP_ST2D5>{}); return; }
+  } else if (kind == OP_ST3D7) {
+    if constexpr (PC != PC_VECTOR) { f(std::integral_constant<int, OP_ST3D7>{}); return; }
+  } else if (kind == OP_DIA5) {
+    if constexpr (PC != PC_SCALAR) { f(std::integral_constant<int, OP_DIA5>{}); return; }
+  } else {
+    f(std::integral_constant<int, 0>{});
+    return;
+  }
+  throw std::logic_error("fused operator kind without a phase kernel");
+}
+
 template <typename T, int PC>
-static void phaseA_t(Solver& S, hipStream_t st) {
+static void phaseA_t(Solver& S, bool tr, hipStream_t st) {
   PhaseAArgs<T> a;
-  a.k = (const T*)S.vec[V_K]; a.w = (const T*)S.vec[V_W]; a.t = (const T*)S.vec[V_T];
+  a.k = (const T*)S.vec[V_K]; a.w = (const T*)S.vec[V_W]; a.t = (T*)S.vec[V_T];
   a.r = (const T*)S.vec[V_R]; a.v = (const T*)S.vec[V_V];
   a.g = (T*)S.vec[V_G]; a.s = (T*)S.vec[V_S]; a.l = (T*)S.vec[V_L]; a.z = (T*)S.vec[V_Z];
   a.zsave = (const T*)S.vec[V_TMP];
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
+  const int kind = fused_kind(S, tr);
+  const StParams<T> P = st_params<T>(S, op_of(S, tr));
   const int64_t nt = S.npad / (kBlock * V16<T>::n);
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials, nt);
-  };
   const bool ntm = (S.vnt & 1) != 0;
-  if (S.auto_rr) {
-    if (ntm) go(k_phaseA<T, PC, true, true>); else go(k_phaseA<T, PC, false, true>);
-  } else {
-    if (ntm) go(k_phaseA<T, PC, true, false>); else go(k_phaseA<T, PC, false, false>);
-  }
+  with_fused_kind<PC>(kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, P, S.n, S.sc, S.partials, nt);
+    };
+    if (S.auto_rr) {
+      if (ntm) go(k_phaseA<T, PC, true, true, K>); else go(k_phaseA<T, PC, false, true, K>);
+    } else {
+      if (ntm) go(k_phaseA<T, PC, true, false, K>); else go(k_phaseA<T, PC, false, false, K>);
+    }
+  });
 }
 
 template <typename T, int PC>
-static void phaseB_t(Solver& S, hipStream_t st) {
+static void phaseB_t(Solver& S, bool tr, hipStream_t st) {
   PhaseBArgs<T> a;
   a.x = S.x;
   a.g = (const T*)S.vec[V_G]; a.l = (const T*)S.vec[V_L]; a.s = (const T*)S.vec[V_S];
-  a.z = (const T*)S.vec[V_Z]; a.t = (const T*)S.vec[V_T]; a.v = (const T*)S.vec[V_V];
+  a.z = (const T*)S.vec[V_Z]; a.t = (const T*)S.vec[V_T]; a.v = (T*)S.vec[V_V];
   a.rhat = (const T*)S.vec[V_RHAT];
   a.r = (T*)S.vec[V_R]; a.k = (T*)S.vec[V_K]; a.w = (T*)S.vec[V_W];
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
+  const int kind = fused_kind(S, tr);
+  const StParams<T> P = st_params<T>(S, op_of(S, tr));
   const int64_t nt = S.npad / (kBlock * V16<T>::n);
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, S.sc, S.partials, nt);
-  };
   const bool ntm = (S.vnt & 2) != 0;
-  if (S.auto_rr) {
-    if (ntm) go(k_phaseB<T, PC, true, true>); else go(k_phaseB<T, PC, false, true>);
-  } else {
-    if (ntm) go(k_phaseB<T, PC, true, false>); else go(k_phaseB<T, PC, false, false>);
-  }
+  with_fused_kind<PC>(kind, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, P, S.n, S.sc, S.partials, nt);
+    };
+    if (S.auto_rr) {
+      if (ntm) go(k_phaseB<T, PC, true, true, K>); else go(k_phaseB<T, PC, false, true, K>);
+    } else {
+      if (ntm) go(k_phaseB<T, PC, true, false, K>); else go(k_phaseB<T, PC, false, false, K>);
+    }
+  });
 }
 
 template <typename T, int PC>
@@ -381,8 +464,8 @@ static void clupd_t(Solver& S, hipStream_t st) {
     }                                                                       \
   } while (0)
 
-void launch_phaseA(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseA_t, S, st); }
-void launch_phaseB(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseB_t, S, st); }
+void launch_phaseA(Solver& S, bool tr, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseA_t, S, tr, st); }
+void launch_phaseB(Solver& S, bool tr, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseB_t, S, tr, st); }
 void launch_cl_update(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, clupd_t, S, st); }
 
 void launch_cl_p(Solver& S, hipStream_t st) {
@@ -399,8 +482,17 @@ void launch_cl_p(Solver& S, hipStream_t st) {
 void launch_final(Solver& S, int mode, int aux, hipStream_t st, bool force) {
   const int respect = (force || mode == FIN_TRUE || mode == FIN_SUM || mode == FIN_INIT ||
                        mode == FIN_C_INIT || mode == FIN_REDO) ? 0 : 1;
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(kBlock), 0, st, mode, S.sc, S.partials, S.nblk, aux,
-                     respect);
+  const FinSlots fs = fin_slots(mode, S.auto_rr ? 1 : 0, aux);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kBlock), 0, st, mode, fs, S.sc, S.partials, S.nblk,
+                       aux, respect);
+  };
+  // the smallest instantiated slot count that holds the mode's slots
+  if (fs.n <= 1) go(k_final<1>);
+  else if (fs.n <= 2) go(k_final<2>);
+  else if (fs.n <= 5) go(k_final<5>);
+  else if (fs.n <= 8) go(k_final<8>);
+  else go(k_final<kMaxFinSlots>);
 }
 
 void launch_fill_zero(Solver& S, void* ptr, int64_t count, size_t elem, hipStream_t st) {

@@ -141,6 +141,153 @@ struct Dia5Op {
 };
 
 // ----------------------------------------------------------------------------
+// structured operators, several consecutive rows per thread
+// ----------------------------------------------------------------------------
+
+// (M^-1 z)_j for the compile-time preconditioner kind
+template <typename T, int PC>
+__device__ __forceinline__ T prec1(T zj, const T* __restrict__ dinv, T ds, int64_t j) {
+  if (PC == PC_NONE) return zj;
+  if (PC == PC_SCALAR) return ds * zj;
+  return dinv[j] * zj;
+}
+
+// one 16-byte chunk of M^-1 z starting at element j
+template <typename T, int PC>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ z, const T* __restrict__ dinv, T ds,
+                                           int64_t j, T (&v)[V16<T>::n]) {
+  ld16(z + j, v);
+  if (PC == PC_SCALAR) {
+#pragma unroll
+    for (int e = 0; e < V16<T>::n; ++e) v[e] = ds * v[e];
+  } else if (PC == PC_VECTOR) {
+    T d[V16<T>::n];
+    ld16(dinv + j, d);
+#pragma unroll
+    for (int e = 0; e < V16<T>::n; ++e) v[e] = d[e] * v[e];
+  }
+}
+
+template <typename T>
+struct StParams {
+  int kind;          // OP_ST2D5, OP_ST3D7 or OP_DIA5
+  int nx, ny, nz;
+  T c[7];            // constant coefficients (ascending column order)
+  const T* __restrict__ dia;
+  int64_t ld;
+};
+
+// Rows p .. p + R*CH - 1 of A M^-1 z for a structured operator (constant 2D
+// 5-point or 3D 7-point stencil, or DIA5), R = elements per 16-byte chunk.
+// The caller passes the centre values xc = (M^-1 z)[p ..] it already holds;
+// the neighbours are loaded here.  Requires p < n and nx a multiple of R, so
+// that a chunk never crosses a grid line.  Each row is summed in ascending
+// column order with one rounding per operation, which is the CSR product of
+// the same matrix bit for bit; the result does not depend on CH or on which
+// kernel calls this.
+template <typename T, int PC, int KIND, int CH>
+__device__ __forceinline__ void st_apply(const StParams<T>& P, const T* __restrict__ z,
+                                         const T* __restrict__ dinv, T ds, int p,
+                                         const T (&xc)[V16<T>::n * CH],
+                                         T (&res)[V16<T>::n * CH]) {
+  constexpr int R = V16<T>::n;
+  constexpr int RR = R * CH;
+  constexpr bool THREE = KIND == OP_ST3D7;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int nxy = nx * ny;
+  int ix, iy, iz = 0;
+  if (THREE) {
+    iz = p / nxy;
+    const int rem = p - iz * nxy;
+    iy = rem / nx;
+    ix = rem - iy * nx;
+  } else {
+    iy = p / nx;
+    ix = p - iy * nx;
+  }
+  // neighbours outside the grid are redirected to row p itself (in bounds)
+  // and their terms skipped
+  const bool hS = iy > 0, hN = iy < ny - 1;
+  const bool hD = THREE && iz > 0, hU = THREE && iz < nz - 1;
+  const bool hW0 = ix > 0, hEl = ix + RR < nx;
+  T xs[RR], xn[RR], xd[RR], xu[RR];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    T t[R];
+    load_chunk<T, PC>(z, dinv, ds, (hS ? p - nx : p) + c * R, t);
+#pragma unroll
+    for (int e = 0; e < R; ++e) xs[c * R + e] = t[e];
+    load_chunk<T, PC>(z, dinv, ds, (hN ? p + nx : p) + c * R, t);
+#pragma unroll
+    for (int e = 0; e < R; ++e) xn[c * R + e] = t[e];
+    if (THREE) {
+      load_chunk<T, PC>(z, dinv, ds, (hD ? p - nxy : p) + c * R, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) xd[c * R + e] = t[e];
+      load_chunk<T, PC>(z, dinv, ds, (hU ? p + nxy : p) + c * R, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) xu[c * R + e] = t[e];
+    }
+  }
+  const int jw = hW0 ? p - 1 : p, je = hEl ? p + RR : p;
+  const T xw0 = prec1<T, PC>(z[jw], dinv, ds, jw);
+  const T xeR = prec1<T, PC>(z[je], dinv, ds, je);
+  T cS[RR], cW[RR], cC[RR], cE[RR], cN[RR];
+  if (KIND == OP_DIA5) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      T t[R];
+      const int64_t q = p + c * R;
+      ld16(P.dia + q, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) cS[c * R + e] = t[e];
+      ld16(P.dia + P.ld + q, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) cW[c * R + e] = t[e];
+      ld16(P.dia + 2 * P.ld + q, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) cC[c * R + e] = t[e];
+      ld16(P.dia + 3 * P.ld + q, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) cE[c * R + e] = t[e];
+      ld16(P.dia + 4 * P.ld + q, t);
+#pragma unroll
+      for (int e = 0; e < R; ++e) cN[c * R + e] = t[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < RR; ++e) {
+    const T xw = e == 0 ? xw0 : xc[e - 1];
+    const T xe = e == RR - 1 ? xeR : xc[e + 1];
+    const bool vw = e == 0 ? hW0 : true;
+    const bool ve = e == RR - 1 ? hEl : true;
+    T sum = T(0);
+    if (KIND == OP_DIA5) {
+      if (hS) sum += cS[e] * xs[e];
+      if (vw) sum += cW[e] * xw;
+      sum += cC[e] * xc[e];
+      if (ve) sum += cE[e] * xe;
+      if (hN) sum += cN[e] * xn[e];
+    } else if (THREE) {
+      if (hD) sum += P.c[0] * xd[e];
+      if (hS) sum += P.c[1] * xs[e];
+      if (vw) sum += P.c[2] * xw;
+      sum += P.c[3] * xc[e];
+      if (ve) sum += P.c[4] * xe;
+      if (hN) sum += P.c[5] * xn[e];
+      if (hU) sum += P.c[6] * xu[e];
+    } else {
+      if (hS) sum += P.c[0] * xs[e];
+      if (vw) sum += P.c[1] * xw;
+      sum += P.c[2] * xc[e];
+      if (ve) sum += P.c[3] * xe;
+      if (hN) sum += P.c[4] * xn[e];
+    }
+    res[e] = sum;
+  }
+}
+
+// ----------------------------------------------------------------------------
 // final reductions (one block)
 // ----------------------------------------------------------------------------
 
@@ -205,63 +352,81 @@ __device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, dou
   sc->dz_prev = smu * nl * e;
 }
 
-// Slots each fused final reduces (the order is the order run_final reads
-// them in).  GLRED 2 in automated mode adds the norms of the gap bound.
+// Slots each final mode reduces.  GLRED 2 in automated mode adds the norms
+// of the gap bound; FIN_SUM reduces slots 0 .. aux-1.
 constexpr int kMaxFinSlots = 22;
-static __constant__ int kFinSlotsInit[6] = {SL_RR0, SL_RW0, SL_RR, SL_BB, SL_X2, SL_K2};
-static __constant__ int kFinSlotsOmega[2] = {SL_QY, SL_YY};
-static __constant__ int kFinSlotsBeta[kMaxFinSlots] = {
-    SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_K2, SL_W2, SL_T2, SL_M2, SL_G2, SL_S2,
-    SL_L2,  SL_Z2,  SL_Q2,  SL_Y2,  SL_X2, SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2};
 
-// number of slots a fused final mode reduces, and their list
-__host__ __device__ inline int fin_slot_count(int mode, int rr_auto) {
+struct FinSlots {
+  int n;
+  int s[kMaxFinSlots];
+};
+
+__host__ __device__ inline FinSlots fin_slots(int mode, int rr_auto, int aux) {
+  FinSlots f{};
+  auto put = [&f](int slot) { f.s[f.n++] = slot; };
   switch (mode) {
-    case FIN_INIT: return 6;
-    case FIN_OMEGA: return 2;
+    case FIN_INIT:
+      put(SL_RR0); put(SL_RW0); put(SL_RR); put(SL_BB); put(SL_X2); put(SL_K2);
+      break;
+    case FIN_OMEGA:
+    case FIN_C_OMEGA:
+      put(SL_QY); put(SL_YY);
+      break;
     case FIN_BETA:
-    case FIN_REDO: return rr_auto ? kMaxFinSlots : 5;
-    case FIN_PROBE: return 5;
-    default: return 0;
+    case FIN_REDO:
+    case FIN_PROBE:
+      put(SL_RR0); put(SL_RW0); put(SL_RS0); put(SL_RZ0); put(SL_RR);
+      if (rr_auto && mode != FIN_PROBE) {
+        put(SL_K2); put(SL_W2); put(SL_T2); put(SL_M2); put(SL_G2); put(SL_S2); put(SL_L2);
+        put(SL_Z2); put(SL_Q2); put(SL_Y2); put(SL_X2); put(SL_U2); put(SL_N2); put(SL_V2);
+        put(SL_RX2); put(SL_RK2); put(SL_RL2);
+      }
+      break;
+    case FIN_TRUE:
+    case FIN_GAP:
+      put(SL_RR);
+      break;
+    case FIN_C_INIT:
+      put(SL_RR0); put(SL_RR); put(SL_BB);
+      break;
+    case FIN_C_ALPHA:
+      put(SL_RS0);
+      break;
+    case FIN_C_BETA:
+      put(SL_RR0); put(SL_RR);
+      break;
+    case FIN_SUM:
+      for (int j = 0; j < aux && j < 8; ++j) put(j);
+      break;
+    default:
+      break;
   }
-}
-__device__ inline const int* fin_slot_list(int mode) {
-  return mode == FIN_INIT ? kFinSlotsInit : mode == FIN_OMEGA ? kFinSlotsOmega : kFinSlotsBeta;
+  return f;
 }
 
-// NS sums, either reduced here from the partials or (PRE) taken from `pre`
-// (indexed by slot) where a distributed final already reduced them.  PRE is
-// a template argument so that kernels with a distributed final do not
-// contain the wide one-block reduction, whose many loads in flight would
-// otherwise set the register budget of the whole kernel.
-template <bool PRE, int NS>
-__device__ __forceinline__ void fin_sums(const double* pre, const double* __restrict__ partials,
-                                         const int (&sl)[NS], int nblk, double (&v)[NS]) {
-  if constexpr (PRE) {
+// number of slots a final mode reduces
+__host__ __device__ inline int fin_slot_count(int mode, int rr_auto) {
+  return fin_slots(mode, rr_auto, 8).n;
+}
+
+// NS sums of a final, already reduced and stored in pre[] by slot
+template <int NS>
+__device__ __forceinline__ void take_sums(const double* pre, const int (&sl)[NS], double (&v)[NS]) {
 #pragma unroll
-    for (int d = 0; d < NS; ++d) v[d] = pre[sl[d]];
-  } else {
-    block_sum_slots<NS>(partials, sl, nblk, v);
-  }
+  for (int d = 0; d < NS; ++d) v[d] = pre[sl[d]];
 }
 
-// Runs one FinalMode over the partials written by the previous kernel(s).
-// Must be executed by all kBlock threads of exactly one block.  With PRE,
-// `pre` holds the already reduced sums of the mode's slots (fused modes
-// only).
-template <bool PRE = false>
-__device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
-                                 const double* __restrict__ partials, int nblk, int aux,
-                                 const double* pre = nullptr) {
-  const bool t0 = threadIdx.x == 0;
+// Runs the scalar logic of one final mode on the sums in pre[] (indexed by
+// slot).  Executed by one thread.
+__device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const double* pre, int aux) {
   switch (mode) {
     case FIN_INIT: {
       // Algorithm 2 initialisation: rho_0 = (r0, r0), alpha_0 = rho_0 / (r0, w0)
       const int sl[6] = {SL_RR0, SL_RW0, SL_RR, SL_BB, SL_X2, SL_K2};
       double v[6];
-      fin_sums<PRE, 6>(pre, partials, sl, nblk, v);
+      take_sums<6>(pre, sl, v);
       const double rho = v[0], rw = v[1], rr = v[2], bb = v[3];
-      if (t0) {
+      {
         sc->sig[SL_RR0] = rho; sc->sig[SL_RW0] = rw; sc->sig[SL_RR] = rr; sc->sig[SL_BB] = bb;
         sc->rho = rho;
         sc->rn0 = sqrt(rr);
@@ -292,9 +457,9 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       // omega_i = (q_i, y_i) / (y_i, y_i); (y, y) = 0 gives omega = 0
       const int sl[2] = {SL_QY, SL_YY};
       double v[2];
-      fin_sums<PRE, 2>(pre, partials, sl, nblk, v);
+      take_sums<2>(pre, sl, v);
       const double s1 = v[0], s2 = v[1];
-      if (t0) {
+      {
         sc->sig[SL_QY] = s1; sc->sig[SL_YY] = s2;
         sc->n_saved = 0;                       // phase A of this iteration has consumed it
         if (!finite(s1) || !finite(s2)) stop(sc, ST_NONFINITE);
@@ -313,15 +478,15 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
                           SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2};
       double v[NS];
       if (sc->rr_auto) {
-        fin_sums<PRE, NS>(pre, partials, sl, nblk, v);
+        take_sums<NS>(pre, sl, v);
       } else {
         const int sl5[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
         double v5[5];
-        fin_sums<PRE, 5>(pre, partials, sl5, nblk, v5);
+        take_sums<5>(pre, sl5, v5);
         for (int d = 0; d < 5; ++d) v[d] = v5[d];
       }
       const double rho1 = v[0], rw = v[1], rs = v[2], rz = v[3], rr = v[4];
-      if (t0) {
+      {
         sc->sig[SL_RR0] = rho1; sc->sig[SL_RW0] = rw; sc->sig[SL_RS0] = rs;
         sc->sig[SL_RZ0] = rz; sc->sig[SL_RR] = rr;
         int its = sc->iter;
@@ -383,31 +548,27 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
       }
       break;
     }
-    case FIN_TRUE: if constexpr (!PRE) {
-      const double rr = block_sum_slot(partials, SL_RR, nblk);
-      if (t0) sc->tr = sqrt(rr);
-      break;
-    } else {
+    case FIN_TRUE: {
+      const double rr = pre[SL_RR];
+      sc->tr = sqrt(rr);
       break;
     }
-    case FIN_GAP: if constexpr (!PRE) {
-      const double rr = block_sum_slot(partials, SL_RR, nblk);
-      if (t0) {
+    case FIN_GAP: {
+      const double rr = pre[SL_RR];
+      {
         sc->gap = sqrt(rr);
         if (sc->gap_history && sc->gap_idx < sc->gap_len) sc->gap_history[sc->gap_idx] = sc->gap;
         sc->gap_idx += 1;
       }
       break;
-    } else {
-      break;
     }
-    case FIN_C_INIT: if constexpr (!PRE) {
+    case FIN_C_INIT: {
       // Algorithm 1 initialisation: rho_0 = (r0, r0)
       const int sl[3] = {SL_RR0, SL_RR, SL_BB};
       double v[3];
-      block_sum_slots<3>(partials, sl, nblk, v);
+      take_sums<3>(pre, sl, v);
       const double rho = v[0], rr = v[1], bb = v[2];
-      if (t0) {
+      {
         sc->rho = rho;
         sc->rn0 = sqrt(rr);
         sc->rn = sc->rn0;
@@ -419,27 +580,23 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         else if (!finite(rho)) stop(sc, ST_NONFINITE);
       }
       break;
-    } else {
-      break;
     }
-    case FIN_C_ALPHA: if constexpr (!PRE) {
-      const double sig = block_sum_slot(partials, SL_RS0, nblk);
-      if (t0) {
+    case FIN_C_ALPHA: {
+      const double sig = pre[SL_RS0];
+      {
         sc->sig[SL_RS0] = sig;
         if (!finite(sig)) stop(sc, ST_NONFINITE);
         else if (sig == 0.0) stop(sc, ST_BREAKDOWN_RHO);
         else sc->alpha = sc->rho / sig;
       }
       break;
-    } else {
-      break;
     }
-    case FIN_C_BETA: if constexpr (!PRE) {
+    case FIN_C_BETA: {
       const int sl[2] = {SL_RR0, SL_RR};
       double v[2];
-      block_sum_slots<2>(partials, sl, nblk, v);
+      take_sums<2>(pre, sl, v);
       const double rho1 = v[0], rr = v[1];
-      if (t0) {
+      {
         sc->sig[SL_RR0] = rho1; sc->sig[SL_RR] = rr;
         const int its = ++sc->iter;
         double* hrow = (sc->history && its <= sc->hist_len)
@@ -466,25 +623,19 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
         }
       }
       break;
-    } else {
-      break;
     }
     case FIN_PROBE: {
       const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
       double v[5];
-      fin_sums<PRE, 5>(pre, partials, sl, nblk, v);
-      if (t0)
-        for (int d = 0; d < 5; ++d) sc->sig[sl[d]] = v[d];
+      take_sums<5>(pre, sl, v);
+      for (int d = 0; d < 5; ++d) sc->sig[sl[d]] = v[d];
       break;
     }
-    case FIN_SUM: if constexpr (!PRE) {
+    case FIN_SUM: {
       const int sl[8] = {0, 1, 2, 3, 4, 5, 6, 7};
       double v[8];
-      block_sum_slots<8>(partials, sl, nblk, v);
-      if (t0)
-        for (int j = 0; j < aux && j < 8; ++j) sc->sums[j] = v[j];
-      break;
-    } else {
+      take_sums<8>(pre, sl, v);
+      for (int j = 0; j < aux && j < 8; ++j) sc->sums[j] = v[j];
       break;
     }
     default:
@@ -492,38 +643,74 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc,
   }
 }
 
-// A fused final spread over the first `fb` blocks of a kernel: block b
-// reduces slots b, b + fb, ... of the mode (each with the same fixed-order
-// tree as a one-block final, so the sums are bitwise those of run_final
-// alone), stores them, and arrives at a counter; the last block to arrive
-// reads the sums and runs the scalar logic.  No block waits for another.
+// A final spread over the first `fb` blocks of a kernel: block b reduces
+// slots b, b + fb, ... of the mode (each with the fixed-order tree of
+// block_sum_slots, so the sums are bitwise those of a one-block final),
+// stores them, and arrives at a counter; the last block to arrive runs the
+// scalar logic on the stored sums.  No block waits for another.
 __device__ inline void distributed_final(int mode, DevScalars* __restrict__ sc,
-                                         const double* __restrict__ partials, int nblk, int fb) {
-  const int ns = fin_slot_count(mode, sc->rr_auto);
-  const int* list = fin_slot_list(mode);
-  for (int d = blockIdx.x; d < ns; d += fb) {
-    const int slot = list[d];
+                                         const double* __restrict__ partials, int nblk, int fb,
+                                         int rr_auto) {
+  const FinSlots fs = fin_slots(mode, rr_auto, 0);
+  for (int d = blockIdx.x; d < fs.n; d += fb) {
+    const int slot = fs.s[d];
     const double v = block_sum_slot(partials, slot, nblk);
     if (threadIdx.x == 0)
       __hip_atomic_store(&sc->red[slot], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __shared__ int last;
-  __shared__ double pre[kNumSlots];
   if (threadIdx.x == 0) {
     const int old = __hip_atomic_fetch_add(&sc->fin_arrive, 1, __ATOMIC_ACQ_REL,
                                            __HIP_MEMORY_SCOPE_AGENT);
     last = old == fb - 1;
-    if (last) {
-      __hip_atomic_store(&sc->fin_arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (int d = 0; d < ns; ++d) {
-        const int slot = list[d];
-        pre[slot] = __hip_atomic_load(&sc->red[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
   }
   __syncthreads();
   if (!last) return;
-  run_final<true>(mode, sc, partials, nblk, 0, pre);
+  // every slot block has arrived: the struct (red[] included) is complete
+  __shared__ DevScalars lsc;
+  scalars_to_lds(sc, &lsc);
+  if (threadIdx.x == 0) {
+    lsc.fin_arrive = 0;
+    run_final(mode, &lsc, lsc.red, 0);
+  }
+  scalars_from_lds(sc, &lsc);
+}
+
+// A final in one block: the scalar struct and the partials of all the
+// mode's slots are loaded together (one memory round trip), reduced with the
+// fixed-order tree of block_sum_slots, and one thread runs the scalar logic
+// on an LDS copy of the struct.  NS >= fs.n; the slots past fs.n repeat the
+// first one and are not used.
+template <int NS>
+__device__ inline void one_block_final(int mode, const FinSlots& fs, DevScalars* __restrict__ sc,
+                                       const double* __restrict__ partials, int nblk, int aux,
+                                       bool respect_done) {
+  static_assert(kScWords <= 2 * kBlock, "two struct words per thread at most");
+  __shared__ DevScalars lsc;
+  __shared__ double pre[kNumSlots];
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
+  const int tid = threadIdx.x;
+  uint32_t w0 = 0, w1 = 0;
+  if (tid < kScWords) w0 = __hip_atomic_load(src + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid + kBlock < kScWords)
+    w1 = __hip_atomic_load(src + tid + kBlock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int sl[NS];
+#pragma unroll
+  for (int d = 0; d < NS; ++d) sl[d] = d < fs.n ? fs.s[d] : fs.s[0];
+  double v[NS];
+  block_sum_slots<NS>(partials, sl, nblk, v);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&lsc);
+  if (tid < kScWords) dst[tid] = w0;
+  if (tid + kBlock < kScWords) dst[tid + kBlock] = w1;
+  if (tid == 0) {
+#pragma unroll
+    for (int d = 0; d < NS; ++d)            // compile-time indices keep v[] in registers
+      if (d < fs.n) pre[sl[d]] = v[d];
+  }
+  __syncthreads();
+  if (respect_done && lsc.done) return;
+  if (tid == 0) run_final(mode, &lsc, pre, aux);
+  scalars_from_lds(sc, &lsc);
 }
 
 }  // namespace pbcg

@@ -71,6 +71,7 @@ struct Solver {
   double normM = 1.0;           // max |M^-1|
   int mu_row = 1, mu_col = 1;   // max stored entries per row / per column
   bool spmv_tiled = true;       // several consecutive rows per thread for structured operators
+  bool fuse = true;             // phase kernels compute the SPMVs of structured operators
   int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
   int64_t rtiles = 0;           // tiles of 256 rows
 
@@ -86,9 +87,23 @@ enum VecId : int {
   V_RHAT = 0, V_R, V_G, V_S, V_L, V_Z, V_K, V_W, V_T, V_V, V_TMP, V_COUNT
 };
 
+// Parameters of a structured operator (stencil or DIA5) for the kernels.
+template <typename T>
+inline StParams<T> st_params(const Solver& S, const OpData& o) {
+  StParams<T> P;
+  P.kind = o.kind;
+  P.nx = o.dims[0]; P.ny = o.dims[1]; P.nz = o.dims[2];
+  for (int d = 0; d < 7; ++d) P.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
+  P.dia = (const T*)o.dia;
+  P.ld = S.npad;
+  return P;
+}
+
 // ---- launchers (kernels_vec.hip) ----
-void launch_phaseA(Solver& S, hipStream_t st);
-void launch_phaseB(Solver& S, hipStream_t st);
+// phase A / phase B of Algorithm 2; with a fused operator (fused_kind != 0)
+// they also compute t = A M^-1 w and v = A M^-1 z respectively
+void launch_phaseA(Solver& S, bool tr, hipStream_t st);
+void launch_phaseB(Solver& S, bool tr, hipStream_t st);
 void launch_final(Solver& S, int mode, int aux, hipStream_t st, bool force = false);
 void launch_cl_update(Solver& S, hipStream_t st);
 void launch_cl_p(Solver& S, hipStream_t st);
@@ -99,6 +114,11 @@ void launch_copy(Solver& S, const double* src, double* dst, hipStream_t st);
 
 // ---- launchers (kernels_op.hip) ----
 const OpData& op_of(Solver& S, bool transpose);
+// The operator kind whose products the phase kernels compute themselves
+// (OP_ST2D5, OP_ST3D7, OP_DIA5), or 0 when the iteration runs separate SPMVs.
+int fused_kind(Solver& S, bool transpose);
+// a GLRED final on its own (one block)
+void launch_fin(Solver& S, int fin_mode, hipStream_t st);
 void launch_init_res(Solver& S, bool tr, hipStream_t st);
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
                  hipStream_t st);

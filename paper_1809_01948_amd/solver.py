@@ -215,7 +215,7 @@ class Solver:
         return out
 
     KERNELS = {"phaseA": 0, "spmv1": 1, "phaseB": 2, "spmv2": 3, "iteration": 4, "copy": 5,
-               "spmv_bare": 6}
+               "spmv_bare": 6, "final": 7}
 
     def time_kernel(self, kernel: str, reps: int = 50) -> float:
         """Average duration (ms) of one launch of an iteration kernel, timed

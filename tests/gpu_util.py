@@ -1,5 +1,8 @@
 """Helpers shared by the GPU tests (host<->device copies, oracle set-up)."""
 
+import contextlib
+import os
+
 import numpy as np
 import scipy.sparse as sp
 import torch
@@ -40,3 +43,19 @@ def rel(a, b):
 
 def csr_T(A):
     return sp.csr_matrix(A.T)
+
+
+@contextlib.contextmanager
+def solver_env(**values):
+    """Tuning switches that a solver reads when it is created (PBCG_FUSE,
+    PBCG_NBLK, ...), set for the duration of the block."""
+    old = {k: os.environ.get(k) for k in values}
+    os.environ.update({k: str(v) for k, v in values.items()})
+    try:
+        yield
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v

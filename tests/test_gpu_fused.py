@@ -1,0 +1,85 @@
+"""The phase kernels that compute the structured operators' products
+themselves (t = A M^-1 w in phase A, v = A M^-1 z in phase B) against the
+iteration with separate SPMV kernels.
+
+Both iterations evaluate every element with the same expressions and reduce
+the dot products over the same tiles in the same order, so whole solves,
+replacements included, agree bit for bit.  The separate-SPMV iteration is
+selected with PBCG_FUSE=0 when the solver is created.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import dev, history_buffer, host, solver_env
+from workloads import convdiff2d_c1, convdiff3d_c3, inverse_problem_c5, poisson2d_c2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    from paper_1809_01948_amd.solver import Solver as S
+    return S
+
+
+def _make(Solver, p, fuse, **kw):
+    with solver_env(PBCG_FUSE=1 if fuse else 0):
+        return Solver.from_problem(p, **kw)
+
+
+_CASES = [
+    # name, problem, create kwargs, solve kwargs
+    ("2d5-fp64-jacobi-P7", lambda: poisson2d_c2(64),
+     dict(form="stencil", precision="fp64", precond="jacobi"), dict(tol=0.0, maxit=60, rr_period=7)),
+    ("2d5-fp64-none-auto", lambda: convdiff2d_c1(32),
+     dict(form="stencil", precision="fp64", precond="none"), dict(tol=1e-12, maxit=500, rr_auto=True)),
+    ("2d5-fp64-transpose", lambda: convdiff2d_c1(32),
+     dict(form="stencil", precision="fp64", precond="jacobi"), dict(tol=1e-12, maxit=500, transpose=True)),
+    ("3d7-fp64-jacobi-auto-separate", lambda: convdiff3d_c3(24),
+     dict(form="stencil", precision="fp64", precond="jacobi"), dict(tol=0.0, maxit=40, rr_auto=True)),
+    ("3d7-mixed-jacobi-P10", lambda: convdiff3d_c3(24),
+     dict(form="stencil", precision="mixed", precond="jacobi"), dict(tol=0.0, maxit=40, rr_period=10)),
+    ("dia5-fp64-jacobi-P10", lambda: inverse_problem_c5(48, sigma=1.0),
+     dict(form="dia5", precision="fp64", precond="jacobi"), dict(tol=0.0, maxit=50, rr_period=10)),
+    ("dia5-mixed-none", lambda: inverse_problem_c5(48, sigma=1.0),
+     dict(form="dia5", precision="mixed", precond="none"), dict(tol=0.0, maxit=30)),
+    ("2d5-ragged-fp64", lambda: poisson2d_c2(30),
+     dict(form="stencil", precision="fp64", precond="jacobi"), dict(tol=0.0, maxit=25, rr_period=5)),
+    ("2d5-ragged-mixed", lambda: poisson2d_c2(36),
+     dict(form="stencil", precision="mixed", precond="jacobi"), dict(tol=0.0, maxit=25, rr_period=5)),
+]
+
+
+@pytest.mark.parametrize("name,make,ck,sk", _CASES, ids=[c[0] for c in _CASES])
+def test_fused_equals_separate_spmvs(Solver, name, make, ck, sk):
+    p = make()
+    out = {}
+    for fuse in (True, False):
+        S = _make(Solver, p, fuse, **ck)
+        its = sk["maxit"]
+        hist = history_buffer(its)
+        x, st = S.solve(dev(p.b), history=hist, **sk)
+        vecs = {v: host(S.get_vector(v)) for v in ("r", "w", "z", "v", "g", "s", "l", "k")}
+        out[fuse] = (host(x), st, host(hist), vecs)
+        S.close()
+    (xa, sa, ha, va), (xb, sb, hb, vb) = out[True], out[False]
+    print(name, sa["status_name"], sa["iterations"], sa["replacements"])
+    assert sa["iterations"] == sb["iterations"] and sa["status"] == sb["status"]
+    assert sa["replacements"] == sb["replacements"]
+    assert np.array_equal(xa, xb)
+    assert np.array_equal(ha, hb)
+    for v in va:
+        assert np.array_equal(va[v], vb[v]), v
+
+
+def test_fused_kernel_timing(Solver):
+    """The timing entry points run the fused kernels and the stand-alone final."""
+    p = poisson2d_c2(256)
+    S = Solver.from_problem(p, form="stencil", precision="fp64", precond="jacobi")
+    S.solve(dev(p.b), tol=0.0, maxit=5)
+    for k in ("phaseA", "spmv1", "phaseB", "spmv2", "iteration", "spmv_bare", "final"):
+        ms = S.time_kernel(k, reps=3)
+        assert 0.0 < ms < 50.0, k
+    S.close()
