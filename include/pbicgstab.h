@@ -243,10 +243,11 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream);
  *   5 a plain copy of N_pad doubles (2 x 8 N bytes), the bandwidth reference
  *   6 PREC + SPMV  v = A M^-1 z  without any final reduction
  *   7 the GLRED 2 final reduction alone (scalars not updated)
- * For structured operators (constant stencils, DIA5) the iteration computes
- * t = A M^-1 w inside phase A and v = A M^-1 z inside phase B; then 0 and 2
- * time those fused kernels, 1 and 3 the GLRED finals that run on their own
- * between them, and 6 the stand-alone product for reference.
+ * When the iteration computes the products inside the phase kernels
+ * (constant 2D stencils and DIA5; 3D stencils with FP32 storage), 0 and 2
+ * time those kernels (phase B then includes the GLRED 1 final), 1 a
+ * stand-alone GLRED 1 final for reference, 3 the GLRED 2 final kernel, 4
+ * phase A + phase B + GLRED 2 final, and 6 the stand-alone product.
  * The solver vectors are overwritten (run it after, not between, the solves
  * whose results are needed); every later solve reinitialises them.
  */

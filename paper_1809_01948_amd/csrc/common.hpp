@@ -8,7 +8,7 @@
 //     bounds checks and can use 16-byte vector loads throughout.
 //   * Global reductions (the GLRED phases) are two-level: each block of a
 //     streaming kernel writes one FP64 partial per dot product into
-//     partials[slot * kMaxBlocks + block]; a single "final" block then sums
+//     partials[slot * kMaxPartials + block]; a single "final" block then sums
 //     the partials of each slot in a fixed order and updates the device
 //     scalar block.  The summation tree is fixed, so results are bitwise
 //     reproducible run to run.
@@ -24,7 +24,8 @@ namespace pbcg {
 
 constexpr int kBlock = 256;          // threads per block (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxBlocks = 2048;     // max blocks of a streaming kernel = partials per slot
+constexpr int kMaxBlocks = 2048;     // max blocks of an SPMV kernel
+constexpr int kMaxPartials = 1024;   // partials per slot = max blocks of a kernel writing partials
 constexpr int kNumSlots = 32;        // partial slots
 constexpr int64_t kPadElems = 2048;  // vector padding granularity (elements)
 constexpr int kXcds = 8;             // MI355X: workgroups are dispatched round-robin over 8 XCDs
@@ -127,7 +128,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Block-level sum of ND per-thread accumulators; thread d < ND writes the
-// block's partial of dot d into partials[slot[d] * kMaxBlocks + blk].
+// block's partial of dot d into partials[slot[d] * kMaxPartials + blk].
 template <int ND>
 __device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&slot)[ND],
                                                double* __restrict__ partials, int blk) {
@@ -144,7 +145,7 @@ __device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&sl
     double s = red[d][0];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) s += red[d][w];
-    partials[slot[d] * kMaxBlocks + blk] = s;
+    partials[slot[d] * kMaxPartials + blk] = s;
   }
 }
 
@@ -152,40 +153,41 @@ __device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&sl
 // a fixed order (per thread: ascending j; then the wave tree; then the 4 wave
 // sums left to right); every thread returns the results.  The loads of up to
 // eight slots are issued together before any of them is added: every slot
-// holds kMaxBlocks entries, so all kMaxBlocks / kBlock strides are loaded
+// holds kMaxPartials entries, so all kMaxPartials / kBlock strides are loaded
 // unconditionally (in bounds) and the entries at j >= nblk are not added.
 // Guarding each load instead would make each stride wait for the previous
-// one, one memory round trip per stride.
+// one, one memory round trip per stride.  The three steps are also available
+// separately (slot_loads, slot_thread_sums, block_tree) for kernels that
+// issue the loads early and reduce later.
+constexpr int kSlotStrides = kMaxPartials / kBlock;
+
 template <int NS>
-__device__ __forceinline__ void block_sum_slots(const double* __restrict__ partials,
-                                                const int (&slot)[NS], int nblk,
-                                                double (&out)[NS]) {
-  __shared__ double red[NS][kWaves];
-  constexpr int U = kMaxBlocks / kBlock;
-  constexpr int G = NS < 8 ? NS : 8;
-  double s[NS];
+__device__ __forceinline__ void slot_loads(const double* __restrict__ partials,
+                                           const int (&slot)[NS],
+                                           double (&p)[NS][kSlotStrides]) {
 #pragma unroll
-  for (int d = 0; d < NS; ++d) s[d] = 0.0;
+  for (int d = 0; d < NS; ++d) {
 #pragma unroll
-  for (int d0 = 0; d0 < NS; d0 += G) {
-    double p[G][U];
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (d0 + g < NS) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          p[g][u] = partials[slot[d0 + g] * kMaxBlocks + u * kBlock + threadIdx.x];
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      if (d0 + g < NS) {
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (u * kBlock + (int)threadIdx.x < nblk) s[d0 + g] += p[g][u];
-      }
-    }
+    for (int u = 0; u < kSlotStrides; ++u)
+      p[d][u] = partials[slot[d] * kMaxPartials + u * kBlock + threadIdx.x];
   }
+}
+
+template <int NS>
+__device__ __forceinline__ void slot_thread_sums(const double (&p)[NS][kSlotStrides], int nblk,
+                                                 double (&s)[NS]) {
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    s[d] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSlotStrides; ++u)
+      if (u * kBlock + (int)threadIdx.x < nblk) s[d] += p[d][u];
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void block_tree(const double (&s)[NS], double (&out)[NS]) {
+  __shared__ double red[NS][kWaves];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
@@ -201,6 +203,27 @@ __device__ __forceinline__ void block_sum_slots(const double* __restrict__ parti
     out[d] = t;
   }
   __syncthreads();
+}
+
+template <int NS>
+__device__ __forceinline__ void block_sum_slots(const double* __restrict__ partials,
+                                                const int (&slot)[NS], int nblk,
+                                                double (&out)[NS]) {
+  constexpr int G = NS < 8 ? NS : 8;
+  double s[NS];
+#pragma unroll
+  for (int d0 = 0; d0 < NS; d0 += G) {
+    int sl[G];
+    double p[G][kSlotStrides], t[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) sl[g] = slot[d0 + g < NS ? d0 + g : d0];
+    slot_loads<G>(partials, sl, p);
+    slot_thread_sums<G>(p, nblk, t);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (d0 + g < NS) s[d0 + g] = t[g];
+  }
+  block_tree<NS>(s, out);
 }
 
 // Sum of the first nblk partials of one slot (see block_sum_slots).

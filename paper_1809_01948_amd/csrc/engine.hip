@@ -98,13 +98,13 @@ void common_setup(Solver& S, int precision, int precond) {
   // (measured: 1000^2 Poisson iteration 52.1 -> 49.3 us, unchanged at 200^3).
   // The SpMVs keep up to 2048 work blocks.
   const int64_t tiles = std::max<int64_t>(S.vtiles, S.rtiles);
-  int64_t nb = std::min<int64_t>(kMaxBlocks / 2, tiles);
+  int64_t nb = std::min<int64_t>(kMaxPartials, tiles);
   if (const char* env = std::getenv("PBCG_NBLK")) {   // tuning override
     const long v = std::strtol(env, nullptr, 10);
     if (v > 0) nb = v;
   }
   nb = round_up(std::max<int64_t>(nb, kXcds), kXcds);
-  if (nb > kMaxBlocks) nb = kMaxBlocks;
+  if (nb > kMaxPartials) nb = kMaxPartials;
   S.nblk = (int)nb;
   S.nspmv = (int)std::min<int64_t>(kMaxBlocks, round_up(std::max<int64_t>(tiles, kXcds), kXcds));
   if (const char* env = std::getenv("PBCG_SPMV_BLOCKS")) {   // tuning override
@@ -144,8 +144,8 @@ void common_setup(Solver& S, int precision, int precond) {
     S.x = (double*)(slab + V_COUNT * vb);
     S.b = (double*)(slab + V_COUNT * vb + xb);
   }
-  S.partials = (double*)dalloc(S, sizeof(double) * kNumSlots * kMaxBlocks);
-  S.sc = (DevScalars*)dalloc(S, sizeof(DevScalars));
+  S.partials = (double*)dalloc(S, sizeof(double) * kNumSlots * kMaxPartials);
+  S.sc = (DevScalars*)dalloc(S, 2 * sizeof(DevScalars));
   hipck(hipHostMalloc((void**)&S.h_sc, 3 * sizeof(DevScalars), hipHostMallocDefault),
         "hipHostMalloc");
   std::memset(S.h_sc, 0, 3 * sizeof(DevScalars));
@@ -408,29 +408,43 @@ double true_residual(Solver& S, bool tr) {
   return read_scalars(S).tr;
 }
 
-// one iteration of Algorithm 2 (index i) on stream st
+// One iteration of Algorithm 2 (index i) on stream st.
 //
 // Structured operators (fused_kind != 0): phase A computes t_i = A M^-1 w_i
-// and phase B v_i = A M^-1 z_i themselves, so each GLRED final runs as a
-// small kernel of its own between the phases.  Other operators: the two
-// SPMVs are kernels of their own and carry the finals in their first blocks,
-// overlapped with the product.
-void enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_t st) {
+// and phase B v_i = A M^-1 z_i themselves, and phase B runs the GLRED 1
+// final in its prologue.  Without the automated criterion the GLRED 2 final
+// of an iteration is left to the next phase A's prologue (the return value
+// says so; `pending` passes it on), except in the last iteration of a chunk
+// and before a gap measurement, which end with the GLRED 2 final as a kernel
+// of its own: the scalars the host polls between chunks are then complete.
+// Other operators: the two SPMVs are kernels of their own and carry the
+// finals in their first blocks, overlapped with the product.
+bool enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_t st,
+                       bool pending, bool last_of_chunk) {
   const bool fused = fused_kind(S, tr) != 0;
-  launch_phaseA(S, tr, st);
-  if (fused) launch_fin(S, FIN_OMEGA, st);
-  else launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
-  launch_phaseB(S, tr, st);
+  const bool gap = o.gap_every > 0 && (i + 1) % o.gap_every == 0;
+  const bool defer = fused && !o.rr_auto && !last_of_chunk && !gap;
+  launch_phaseA(S, tr, pending, st);
+  if (!fused) launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
+  launch_phaseB(S, tr, pending, st);
   if (o.rr_auto || (o.rr_period > 0 && (i + 1) % o.rr_period == 0)) {
     launch_rr1(S, tr, false, st);      // predicated on the device (eq:criterion or the period)
     launch_rr2(S, tr, false, st);
   }
-  if (fused) launch_fin(S, FIN_BETA, st);
-  else launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
-  if (o.gap_every > 0 && (i + 1) % o.gap_every == 0) {
+  if (!fused) launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
+  else if (!defer) launch_fin(S, FIN_BETA, st);
+  if (gap) {
     launch_gap(S, tr, st);
     launch_final(S, FIN_GAP, 0, st);
   }
+  return defer;
+}
+
+// iterations start .. start + len - 1 as one chunk
+void enqueue_chunk(Solver& S, bool tr, int start, int len, const pbcg_opts& o, hipStream_t st) {
+  bool pending = false;
+  for (int j = 0; j < len; ++j)
+    pending = enqueue_iteration(S, tr, start + j, o, st, pending, j == len - 1);
 }
 
 hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_opts& o) {
@@ -444,7 +458,7 @@ hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_op
   if (it != S.graphs.end()) return it->second;
   hipGraph_t g = nullptr;
   hipck(hipStreamBeginCapture(S.s1, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  for (int j = 0; j < len; ++j) enqueue_iteration(S, tr, start + j, o, S.s1);
+  enqueue_chunk(S, tr, start, len, o, S.s1);
   hipck(hipStreamEndCapture(S.s1, &g), "hipStreamEndCapture");
   hipGraphExec_t ge = nullptr;
   hipck(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
@@ -456,7 +470,10 @@ hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_op
 // Runs iterations until the device reports done or `maxit` iterations have
 // been completed.  Returns the device scalars after draining the stream.
 DevScalars run_iterations(Solver& S, bool tr, int start, const pbcg_opts& o) {
-  int K = o.check_every > 0 ? o.check_every : (o.use_graph ? 16 : 8);
+  // a chunk ends with a host poll (a copy of the scalars and an event) and,
+  // with graphs, a graph launch: about 15 us per chunk, so graph chunks are
+  // long (the early-exit launches after convergence cost ~1 us each)
+  int K = o.check_every > 0 ? o.check_every : (o.use_graph ? 32 : 8);
   if (o.use_graph && o.rr_period > 0 && !o.rr_auto) {
     // chunk length dividing the replacement period keeps the captured variants few
     int best = 1;
@@ -473,7 +490,7 @@ DevScalars run_iterations(Solver& S, bool tr, int start, const pbcg_opts& o) {
       hipGraphExec_t ge = chunk_graph(S, tr, it, len, o);
       hipck(hipGraphLaunch(ge, S.s1), "hipGraphLaunch");
     } else {
-      for (int j = 0; j < len; ++j) enqueue_iteration(S, tr, it + j, o, S.s1);
+      enqueue_chunk(S, tr, it, len, o, S.s1);
     }
     hipck(hipGetLastError(), "iteration launch");
     it += len;
@@ -1116,12 +1133,12 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
     const bool fused = fused_kind(S, false) != 0;
     auto one = [&](int kk) {
       switch (kk) {
-        case 0: launch_phaseA(S, false, S.s1); break;
+        case 0: launch_phaseA(S, false, false, S.s1); break;
         case 1:
           if (fused) launch_fin(S, FIN_OMEGA, S.s1);
           else launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, S.s1);
           break;
-        case 2: launch_phaseB(S, false, S.s1); break;
+        case 2: launch_phaseB(S, false, false, S.s1); break;
         case 3:
           if (fused) launch_fin(S, FIN_PROBE, S.s1);
           else launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_PROBE, false, S.s1);
@@ -1132,8 +1149,12 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
       }
     };
     auto launch = [&]() {
-      if (kernel == 4) for (int kk = 0; kk < 4; ++kk) one(kk);
-      else one(kernel);
+      if (kernel == 4) {
+        for (int kk = 0; kk < 4; ++kk)
+          if (!(fused && kk == 1)) one(kk);      // phase B carries the GLRED 1 final
+      } else {
+        one(kernel);
+      }
     };
     launch();  // warm-up
     hipck(hipEventRecord(S.ev_t0, S.s1), "hipEventRecord");

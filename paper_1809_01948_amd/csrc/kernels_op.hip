@@ -220,7 +220,7 @@ template <int NS>
 __device__ __forceinline__ void zero_partials(const int (&slot)[NS], double* __restrict__ partials,
                                               int npart) {
   for (int j = blockIdx.x + gridDim.x; j < npart; j += gridDim.x)
-    if (threadIdx.x < NS) partials[slot[threadIdx.x] * kMaxBlocks + j] = 0.0;
+    if (threadIdx.x < NS) partials[slot[threadIdx.x] * kMaxPartials + j] = 0.0;
 }
 
 // Residual replacement (eq:rr), first half: r = b - A x_{i+1}, k = M^-1 r,

@@ -47,81 +47,161 @@ struct PhaseAArgs {
 // read (the SPMV that the unfused iteration runs after GLRED 2), and
 // stored.  w is then read with cached loads so that the stencil neighbours
 // of other tiles are served by the L2 of the XCD that walks them.
-template <typename T, int PC, bool NT, bool AUTO, int KIND, bool SAVED>
-__device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StParams<T>& P,
-                                            int64_t n, T a, T b, T wp, double (&acc)[12],
-                                            int64_t ntiles) {
+// Registers of one phase A chunk
+template <typename T>
+struct ATile {
+  static constexpr int C = V16<T>::n;
+  T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C], m[C];
+};
+
+// the loads of one chunk
+template <typename T, int PC, bool NT, int KIND, bool SAVED>
+__device__ __forceinline__ void phaseA_issue(const PhaseAArgs<T>& A, int64_t i, ATile<T>& R) {
   constexpr int C = V16<T>::n;
   constexpr bool FUSE = KIND != 0;
-  for (XcdWalk it(ntiles, blockIdx.x, gridDim.x); it.t < it.end; it.t += it.step) {
-    const int64_t i = (it.t * kBlock + threadIdx.x) * C;
-    T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C], m[C];
-    ldc<T, C, NT>(A.k + i, k); ldc<T, C, NT && !FUSE>(A.w + i, w);
-    if (!FUSE) ldc<T, C, NT>(A.t + i, t);
-    ldc<T, C, NT>(A.r + i, r); ldc<T, C, NT>(A.v + i, v); ldc<T, C, NT>(A.g + i, g);
-    ldc<T, C, NT>(A.s + i, s); ldc<T, C, NT>(A.l + i, l); ldc<T, C, NT>(A.z + i, z);
-    if (SAVED) ldc<T, C, NT>(A.zsave + i, zp);
-    if (PC == PC_VECTOR) ldc<T, C, NT>(A.dinv + i, d);
+  ldc<T, C, NT>(A.k + i, R.k); ldc<T, C, NT && !FUSE>(A.w + i, R.w);
+  if (!FUSE) ldc<T, C, NT>(A.t + i, R.t);
+  ldc<T, C, NT>(A.r + i, R.r); ldc<T, C, NT>(A.v + i, R.v); ldc<T, C, NT>(A.g + i, R.g);
+  ldc<T, C, NT>(A.s + i, R.s); ldc<T, C, NT>(A.l + i, R.l); ldc<T, C, NT>(A.z + i, R.z);
+  if (SAVED) ldc<T, C, NT>(A.zsave + i, R.zp);
+  if (PC == PC_VECTOR) ldc<T, C, NT>(A.dinv + i, R.d);
+}
+
+// m = M^-1 w of one chunk and, fused, t = A m from the neighbours of w
+template <typename T, int PC, int KIND>
+__device__ __forceinline__ void phaseA_stencil(const PhaseAArgs<T>& A, const StParams<T>& P,
+                                               int64_t n, int64_t i, ATile<T>& R) {
+  constexpr int C = V16<T>::n;
 #pragma unroll
-    for (int e = 0; e < C; ++e) {
-      const T de = (PC == PC_VECTOR) ? d[e] : A.dinv_s;
-      m[e] = (PC == PC_NONE) ? w[e] : de * w[e];
-    }
-    if constexpr (FUSE) {
-      if (i < n) {
-        st_apply<T, PC, KIND, 1>(P, A.w, A.dinv, A.dinv_s, (int)i, m, t);
-      } else {
+  for (int e = 0; e < C; ++e) {
+    const T de = (PC == PC_VECTOR) ? R.d[e] : A.dinv_s;
+    R.m[e] = (PC == PC_NONE) ? R.w[e] : de * R.w[e];
+  }
+  if constexpr (KIND != 0) {
+    if (i < n) {
+      st_apply<T, PC, KIND, 1>(P, A.w, A.dinv, A.dinv_s, (int)i, R.m, R.t);
+    } else {
 #pragma unroll
-        for (int e = 0; e < C; ++e) t[e] = T(0);          // padding rows stay zero
-      }
+      for (int e = 0; e < C; ++e) R.t[e] = T(0);          // padding rows stay zero
     }
-#pragma unroll
-    for (int e = 0; e < C; ++e) {
-      const T de = (PC == PC_VECTOR) ? d[e] : A.dinv_s;
-      const T zprev = SAVED ? zp[e] : z[e];
-      const T np = (PC == PC_NONE) ? zprev : de * zprev;
-      const T gn = k[e] + b * (g[e] - wp * l[e]);
-      const T sn = w[e] + b * (s[e] - wp * z[e]);
-      const T ln = m[e] + b * (l[e] - wp * np);
-      const T zn = t[e] + b * (z[e] - wp * v[e]);
-      const T q = r[e] - a * sn;
-      const T y = w[e] - a * zn;
-      acc[0] += (double)q * (double)y;
-      acc[1] += (double)y * (double)y;
-      if (AUTO) {
-        acc[2] += (double)k[e] * (double)k[e];
-        acc[3] += (double)w[e] * (double)w[e];
-        acc[4] += (double)t[e] * (double)t[e];
-        acc[5] += (double)m[e] * (double)m[e];
-        acc[6] += (double)gn * (double)gn;
-        acc[7] += (double)sn * (double)sn;
-        acc[8] += (double)ln * (double)ln;
-        acc[9] += (double)zn * (double)zn;
-        acc[10] += (double)q * (double)q;
-        acc[11] += (double)y * (double)y;
-      }
-      g[e] = gn; s[e] = sn; l[e] = ln; z[e] = zn;
-    }
-    stc<T, C, NT>(A.g + i, g); stc<T, C, NT>(A.s + i, s); stc<T, C, NT>(A.l + i, l);
-    stc<T, C, NT>(A.z + i, z);
-    if (FUSE) stc<T, C, NT>(A.t + i, t);
   }
 }
 
-template <typename T, int PC, bool NT, bool AUTO, int KIND>
-__global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> P, int64_t n,
-                                                   const DevScalars* __restrict__ sc,
-                                                   double* __restrict__ partials, int64_t ntiles) {
-  // the scalars are loaded with the done flag (one round trip, not two)
-  const int done = sc->done, n_saved = sc->n_saved;
-  const double alpha = sc->alpha, beta = sc->beta, omega_prev = sc->omega_prev;
-  if (done) return;
+// the recurrences of one chunk and their partials
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool SAVED>
+__device__ __forceinline__ void phaseA_update(const PhaseAArgs<T>& A, int64_t i, ATile<T>& R,
+                                              T a, T b, T wp, double (&acc)[12]) {
+  constexpr int C = V16<T>::n;
+  constexpr bool FUSE = KIND != 0;
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    const T de = (PC == PC_VECTOR) ? R.d[e] : A.dinv_s;
+    const T zprev = SAVED ? R.zp[e] : R.z[e];
+    const T np = (PC == PC_NONE) ? zprev : de * zprev;
+    const T gn = R.k[e] + b * (R.g[e] - wp * R.l[e]);
+    const T sn = R.w[e] + b * (R.s[e] - wp * R.z[e]);
+    const T ln = R.m[e] + b * (R.l[e] - wp * np);
+    const T zn = R.t[e] + b * (R.z[e] - wp * R.v[e]);
+    const T q = R.r[e] - a * sn;
+    const T y = R.w[e] - a * zn;
+    acc[0] += (double)q * (double)y;
+    acc[1] += (double)y * (double)y;
+    if (AUTO) {
+      acc[2] += (double)R.k[e] * (double)R.k[e];
+      acc[3] += (double)R.w[e] * (double)R.w[e];
+      acc[4] += (double)R.t[e] * (double)R.t[e];
+      acc[5] += (double)R.m[e] * (double)R.m[e];
+      acc[6] += (double)gn * (double)gn;
+      acc[7] += (double)sn * (double)sn;
+      acc[8] += (double)ln * (double)ln;
+      acc[9] += (double)zn * (double)zn;
+      acc[10] += (double)q * (double)q;
+      acc[11] += (double)y * (double)y;
+    }
+    R.g[e] = gn; R.s[e] = sn; R.l[e] = ln; R.z[e] = zn;
+  }
+  stc<T, C, NT>(A.g + i, R.g); stc<T, C, NT>(A.s + i, R.s); stc<T, C, NT>(A.l + i, R.l);
+  stc<T, C, NT>(A.z + i, R.z);
+  if (FUSE) stc<T, C, NT>(A.t + i, R.t);
+}
+
+// Phase A over the block's chunks.  PRO: the GLRED 2 final of the previous
+// iteration runs first (see k_phaseA).  (Issuing the first chunk's loads
+// before the final, as phase B does, costs registers: 149 instead of 101,
+// three waves per SIMD instead of four, and measured 44.2 against 41.9 us per
+// iteration on the 1000 x 1000 Poisson problem.)
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool PRO, bool SAVED>
+__device__ __forceinline__ void phaseA_run(const PhaseAArgs<T>& A, const StParams<T>& P, int64_t n,
+                                           DevScalars* __restrict__ sc,
+                                           double* __restrict__ partials, int64_t ntiles,
+                                           double alpha, double beta, double omega_prev) {
+  constexpr int C = V16<T>::n;
+  XcdWalk it(ntiles, blockIdx.x, gridDim.x);
+  auto row = [&](int64_t t) { return (t * kBlock + threadIdx.x) * C; };
+  const bool any = it.t < it.end;
+  ATile<T> R;
+  if constexpr (PRO) {
+    // every thread evaluates the GLRED 2 step from the reduced sums (the
+    // same expressions as run_final, so the same values everywhere); block 0
+    // also runs run_final on an LDS copy of the struct, with the history
+    // log, and stages the copy in sc[1]
+    __shared__ DevScalars lsc;
+    __shared__ double pre[kNumSlots];
+    const int tid = threadIdx.x;
+    const double omega = sc->omega, rho = sc->rho, tol = sc->tol, nb = sc->nb;
+    const int its = sc->iter + 1, maxit = sc->maxit;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
+    uint32_t w0 = 0, w1 = 0;
+    if (blockIdx.x == 0) {
+      if (tid < kScWords) w0 = src[tid];
+      if (tid + kBlock < kScWords) w1 = src[tid + kBlock];
+    }
+    const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+    double pp[5][kSlotStrides], ts[5], v[5];
+    slot_loads<5>(partials, sl, pp);
+    slot_thread_sums<5>(pp, gridDim.x, ts);
+    if (blockIdx.x == 0) {
+      uint32_t* dl = reinterpret_cast<uint32_t*>(&lsc);
+      if (tid < kScWords) dl[tid] = w0;
+      if (tid + kBlock < kScWords) dl[tid + kBlock] = w1;
+    }
+    block_tree<5>(ts, v);                 // (its barriers also publish lsc)
+    const G2Step g = glred2_step(v, alpha, omega, rho, tol, nb);
+    const bool go = g.outcome == G2_CONTINUE && its < maxit;
+    if (blockIdx.x == 0) {
+      if (tid == 0) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d) pre[sl[d]] = v[d];
+        run_final(FIN_BETA, &lsc, pre, 0);
+      }
+      scalars_from_lds(sc + 1, &lsc);
+    }
+    // (with its == maxit the step still runs and the solve then stops, as
+    // in run_final, but there is no iteration left to update)
+    if (!go) return;
+    beta = g.beta;
+    alpha = g.alpha;
+    omega_prev = omega;
+  } else {
+    if (any) phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
+    if (any) phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
+  }
+  if (PRO && any) {
+    phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
+    phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
+  }
   const T a = (T)alpha, b = (T)beta, wp = (T)omega_prev;
   double acc[12];
 #pragma unroll
   for (int d = 0; d < 12; ++d) acc[d] = 0.0;
-  if (n_saved) phaseA_body<T, PC, NT, AUTO, KIND, true>(A, P, n, a, b, wp, acc, ntiles);
-  else phaseA_body<T, PC, NT, AUTO, KIND, false>(A, P, n, a, b, wp, acc, ntiles);
+  while (it.t < it.end) {
+    phaseA_update<T, PC, NT, AUTO, KIND, SAVED>(A, row(it.t), R, a, b, wp, acc);
+    it.t += it.step;
+    if (it.t < it.end) {
+      phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
+      phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
+    }
+  }
   if (AUTO) {
     const int slots[12] = {SL_QY, SL_YY, SL_K2, SL_W2, SL_T2, SL_M2, SL_G2, SL_S2, SL_L2,
                            SL_Z2, SL_Q2, SL_Y2};
@@ -131,6 +211,41 @@ __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> 
     const int slots[2] = {SL_QY, SL_YY};
     block_partials<2>(acc2, slots, partials, blockIdx.x);
   }
+}
+
+// PRO: the GLRED 2 final of the previous iteration (beta_i, alpha_i, the
+// stopping test, the iteration count) runs in this kernel's prologue instead
+// of a kernel of its own.  Every block loads the scalar struct and the GLRED 2
+// partials (one memory round trip), reduces them with the fixed-order tree
+// of block_sum_slots and runs the scalar logic on an LDS copy of the struct,
+// so all blocks hold the same alpha_i, beta_i, omega_{i-1} and stopping
+// decision.  The struct itself must not change while blocks may still read
+// it, so block 0 writes the updated copy to the staging struct sc[1] (and
+// the history row); phase B, which follows, reads its scalars from there and
+// its block 0 commits sc[1] to sc[0].  Used without the automated criterion
+// only (its 22 reduced slots are too many to load in every block).
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool PRO>
+__global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> P, int64_t n,
+                                                   DevScalars* __restrict__ sc,
+                                                   double* __restrict__ partials, int64_t ntiles) {
+  static_assert(!(PRO && AUTO), "the prologue final serves the periodic strategy only");
+  // the scalars are loaded with the done flag (one round trip, not two)
+  const int done = sc->done, n_saved = sc->n_saved;
+  const double alpha = sc->alpha, beta = sc->beta, omega_prev = sc->omega_prev;
+  if (done) {
+    if (PRO && blockIdx.x == 0) {        // stopped earlier: the staged copy is sc[0] itself
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(sc + 1);
+      for (int i = threadIdx.x; i < kScWords; i += kBlock) dst[i] = src[i];
+    }
+    return;
+  }
+  if (n_saved)
+    phaseA_run<T, PC, NT, AUTO, KIND, PRO, true>(A, P, n, sc, partials, ntiles, alpha, beta,
+                                                 omega_prev);
+  else
+    phaseA_run<T, PC, NT, AUTO, KIND, PRO, false>(A, P, n, sc, partials, ntiles, alpha, beta,
+                                                  omega_prev);
 }
 
 template <typename T>
@@ -162,72 +277,149 @@ struct PhaseBArgs {
 // KIND != 0 (a structured operator): v_i = A n_i = A M^-1 z_i is computed
 // here from z_i, final since phase A, instead of being read (the SPMV that
 // the unfused iteration runs between the phases), and stored for the next
-// phase A; z is read with cached loads for the neighbours' sake.
+// phase A; z is read with cached loads for the neighbours' sake.  With no
+// SPMV kernel between the phases to carry it, the GLRED 1 final runs in
+// this kernel's prologue.
+// Registers of one phase B chunk
+template <typename T>
+struct BTile {
+  static constexpr int C = V16<T>::n;
+  T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C], n[C];
+  double x[C];
+};
+
+// the loads of one chunk
+template <typename T, int PC, bool NT, int KIND>
+__device__ __forceinline__ void phaseB_issue(const PhaseBArgs<T>& B, int64_t i, BTile<T>& R) {
+  constexpr int C = V16<T>::n;
+  constexpr bool FUSE = KIND != 0;
+  ldc<T, C, NT>(B.g + i, R.g); ldc<T, C, NT>(B.l + i, R.l); ldc<T, C, NT>(B.s + i, R.s);
+  ldc<T, C, NT && !FUSE>(B.z + i, R.z); ldc<T, C, NT>(B.t + i, R.t);
+  if (!FUSE) ldc<T, C, NT>(B.v + i, R.v);
+  ldc<T, C, NT>(B.rhat + i, R.rh); ldc<T, C, NT>(B.r + i, R.r); ldc<T, C, NT>(B.k + i, R.k);
+  ldc<T, C, NT>(B.w + i, R.w);
+  ldc<double, C, NT>(B.x + i, R.x);
+  if (PC == PC_VECTOR) ldc<T, C, NT>(B.dinv + i, R.d);
+}
+
+// n = M^-1 z of one chunk and, fused, v = A n from the neighbours of z
+template <typename T, int PC, int KIND>
+__device__ __forceinline__ void phaseB_stencil(const PhaseBArgs<T>& B, const StParams<T>& P,
+                                               int64_t nrows, int64_t i, BTile<T>& R) {
+  constexpr int C = V16<T>::n;
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    const T de = (PC == PC_VECTOR) ? R.d[e] : B.dinv_s;
+    R.n[e] = (PC == PC_NONE) ? R.z[e] : de * R.z[e];
+  }
+  if constexpr (KIND != 0) {
+    if (i < nrows) {
+      st_apply<T, PC, KIND, 1>(P, B.z, B.dinv, B.dinv_s, (int)i, R.n, R.v);
+    } else {
+#pragma unroll
+      for (int e = 0; e < C; ++e) R.v[e] = T(0);          // padding rows stay zero
+    }
+  }
+}
+
+// the updates of one chunk and their partials
 template <typename T, int PC, bool NT, bool AUTO, int KIND>
-__global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> P, int64_t nrows,
-                                                   const DevScalars* __restrict__ sc,
-                                                   double* __restrict__ partials, int64_t ntiles) {
-  const int done = sc->done;
-  const double alpha = sc->alpha, omega = sc->omega;
-  if (done) return;
+__device__ __forceinline__ void phaseB_update(const PhaseBArgs<T>& B, int64_t i, BTile<T>& R,
+                                              double alpha, double omega, double (&acc)[9]) {
   constexpr int C = V16<T>::n;
   constexpr bool FUSE = KIND != 0;
   const T a = (T)alpha, om = (T)omega;
+#pragma unroll
+  for (int e = 0; e < C; ++e) {
+    const T de = (PC == PC_VECTOR) ? R.d[e] : B.dinv_s;
+    const T m = (PC == PC_NONE) ? R.w[e] : de * R.w[e];
+    const T q = R.r[e] - a * R.s[e];
+    const T u = R.k[e] - a * R.l[e];
+    const T y = R.w[e] - a * R.z[e];
+    if (AUTO) {
+      acc[5] += R.x[e] * R.x[e];
+      acc[6] += (double)u * (double)u;
+      acc[7] += (double)R.n[e] * (double)R.n[e];
+      acc[8] += (double)R.v[e] * (double)R.v[e];
+    }
+    R.x[e] = (R.x[e] + alpha * (double)R.g[e]) + omega * (double)u;
+    const T rn = q - om * y;
+    const T kn = u - om * (m - a * R.n[e]);
+    const T wn = y - om * (R.t[e] - a * R.v[e]);
+    R.r[e] = rn; R.k[e] = kn; R.w[e] = wn;
+    const double rhd = (double)R.rh[e];
+    acc[0] += rhd * (double)rn;
+    acc[1] += rhd * (double)wn;
+    acc[2] += rhd * (double)R.s[e];
+    acc[3] += rhd * (double)R.z[e];
+    acc[4] += (double)rn * (double)rn;
+  }
+  stc<T, C, NT>(B.r + i, R.r); stc<T, C, NT>(B.k + i, R.k); stc<T, C, NT>(B.w + i, R.w);
+  stc<double, C, NT>(B.x + i, R.x);
+  if (FUSE) stc<T, C, NT>(B.v + i, R.v);
+}
+
+// STAGED: phase A ran the previous GLRED 2 final in its prologue and left
+// the updated scalars in sc[1]; they are read from there, and block 0
+// commits them to sc[0] before it records omega.
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool STAGED>
+__global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> P, int64_t nrows,
+                                                   DevScalars* __restrict__ sc,
+                                                   double* __restrict__ partials, int64_t ntiles) {
+  constexpr int C = V16<T>::n;
+  const DevScalars* in = STAGED ? sc + 1 : sc;
+  const int done = in->done;
+  const double alpha = in->alpha;
+  double omega = in->omega;
+  if (STAGED && blockIdx.x == 0) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(sc + 1);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(sc);
+    for (int i = threadIdx.x; i < kScWords; i += kBlock) dst[i] = src[i];
+    __syncthreads();
+  }
+  if (done) return;
+  XcdWalk it(ntiles, blockIdx.x, gridDim.x);
+  BTile<T> R;
+  auto row = [&](int64_t t) { return (t * kBlock + threadIdx.x) * C; };
+  const bool any = it.t < it.end;
+  // The first chunk's loads do not depend on omega: they go out together
+  // with the loads of the GLRED 1 partials (one memory round trip for both).
+  if (any) phaseB_issue<T, PC, NT, KIND>(B, row(it.t), R);
+  if constexpr (KIND != 0) {
+    // GLRED 1 final (omega_i = (q_i, y_i) / (y_i, y_i)), reduced by every
+    // block from phase A's partials with the fixed-order tree of
+    // block_sum_slots, so all blocks hold the same omega; block 0 records
+    // it.  This kernel writes only GLRED 2 slots, so the GLRED 1 partials
+    // stay intact while it runs.
+    const int sl[2] = {SL_QY, SL_YY};
+    double pp[2][kSlotStrides], ts[2], v[2];
+    slot_loads<2>(partials, sl, pp);
+    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, row(it.t), R);
+    slot_thread_sums<2>(pp, gridDim.x, ts);
+    block_tree<2>(ts, v);
+    const bool bad = !finite(v[0]) || !finite(v[1]);
+    omega = v[1] != 0.0 ? v[0] / v[1] : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->sig[SL_QY] = v[0];
+      sc->sig[SL_YY] = v[1];
+      sc->n_saved = 0;                 // phase A of this iteration has consumed it
+      if (bad) stop(sc, ST_NONFINITE);
+      else sc->omega = omega;
+    }
+    if (bad) return;
+  } else {
+    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, row(it.t), R);
+  }
   double acc[9];
 #pragma unroll
   for (int d = 0; d < 9; ++d) acc[d] = 0.0;
-  for (XcdWalk it(ntiles, blockIdx.x, gridDim.x); it.t < it.end; it.t += it.step) {
-    const int64_t i = (it.t * kBlock + threadIdx.x) * C;
-    T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C], n[C];
-    double x[C];
-    ldc<T, C, NT>(B.g + i, g); ldc<T, C, NT>(B.l + i, l); ldc<T, C, NT>(B.s + i, s);
-    ldc<T, C, NT && !FUSE>(B.z + i, z); ldc<T, C, NT>(B.t + i, t);
-    if (!FUSE) ldc<T, C, NT>(B.v + i, v);
-    ldc<T, C, NT>(B.rhat + i, rh); ldc<T, C, NT>(B.r + i, r); ldc<T, C, NT>(B.k + i, k);
-    ldc<T, C, NT>(B.w + i, w);
-    ldc<double, C, NT>(B.x + i, x);
-    if (PC == PC_VECTOR) ldc<T, C, NT>(B.dinv + i, d);
-#pragma unroll
-    for (int e = 0; e < C; ++e) {
-      const T de = (PC == PC_VECTOR) ? d[e] : B.dinv_s;
-      n[e] = (PC == PC_NONE) ? z[e] : de * z[e];
+  while (it.t < it.end) {
+    phaseB_update<T, PC, NT, AUTO, KIND>(B, row(it.t), R, alpha, omega, acc);
+    it.t += it.step;
+    if (it.t < it.end) {
+      phaseB_issue<T, PC, NT, KIND>(B, row(it.t), R);
+      phaseB_stencil<T, PC, KIND>(B, P, nrows, row(it.t), R);
     }
-    if constexpr (FUSE) {
-      if (i < nrows) {
-        st_apply<T, PC, KIND, 1>(P, B.z, B.dinv, B.dinv_s, (int)i, n, v);
-      } else {
-#pragma unroll
-        for (int e = 0; e < C; ++e) v[e] = T(0);          // padding rows stay zero
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < C; ++e) {
-      const T de = (PC == PC_VECTOR) ? d[e] : B.dinv_s;
-      const T m = (PC == PC_NONE) ? w[e] : de * w[e];
-      const T q = r[e] - a * s[e];
-      const T u = k[e] - a * l[e];
-      const T y = w[e] - a * z[e];
-      if (AUTO) {
-        acc[5] += x[e] * x[e];
-        acc[6] += (double)u * (double)u;
-        acc[7] += (double)n[e] * (double)n[e];
-        acc[8] += (double)v[e] * (double)v[e];
-      }
-      x[e] = (x[e] + alpha * (double)g[e]) + omega * (double)u;
-      const T rn = q - om * y;
-      const T kn = u - om * (m - a * n[e]);
-      const T wn = y - om * (t[e] - a * v[e]);
-      r[e] = rn; k[e] = kn; w[e] = wn;
-      const double rhd = (double)rh[e];
-      acc[0] += rhd * (double)rn;
-      acc[1] += rhd * (double)wn;
-      acc[2] += rhd * (double)s[e];
-      acc[3] += rhd * (double)z[e];
-      acc[4] += (double)rn * (double)rn;
-    }
-    stc<T, C, NT>(B.r + i, r); stc<T, C, NT>(B.k + i, k); stc<T, C, NT>(B.w + i, w);
-    stc<double, C, NT>(B.x + i, x);
-    if (FUSE) stc<T, C, NT>(B.v + i, v);
   }
   if (AUTO) {
     const int slots[9] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_X2, SL_U2, SL_N2, SL_V2};
@@ -390,7 +582,7 @@ static void with_fused_kind(int kind, F&& f) {
 }
 
 template <typename T, int PC>
-static void phaseA_t(Solver& S, bool tr, hipStream_t st) {
+static void phaseA_t(Solver& S, bool tr, bool pro, hipStream_t st) {
   PhaseAArgs<T> a;
   a.k = (const T*)S.vec[V_K]; a.w = (const T*)S.vec[V_W]; a.t = (T*)S.vec[V_T];
   a.r = (const T*)S.vec[V_R]; a.v = (const T*)S.vec[V_V];
@@ -407,15 +599,24 @@ static void phaseA_t(Solver& S, bool tr, hipStream_t st) {
       hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, P, S.n, S.sc, S.partials, nt);
     };
     if (S.auto_rr) {
-      if (ntm) go(k_phaseA<T, PC, true, true, K>); else go(k_phaseA<T, PC, false, true, K>);
+      if (ntm) go(k_phaseA<T, PC, true, true, K, false>);
+      else go(k_phaseA<T, PC, false, true, K, false>);
+    } else if (pro) {
+      if constexpr (K != 0) {
+        if (ntm) go(k_phaseA<T, PC, true, false, K, true>);
+        else go(k_phaseA<T, PC, false, false, K, true>);
+      } else {
+        throw std::logic_error("GLRED 2 prologue without a fused operator");
+      }
     } else {
-      if (ntm) go(k_phaseA<T, PC, true, false, K>); else go(k_phaseA<T, PC, false, false, K>);
+      if (ntm) go(k_phaseA<T, PC, true, false, K, false>);
+      else go(k_phaseA<T, PC, false, false, K, false>);
     }
   });
 }
 
 template <typename T, int PC>
-static void phaseB_t(Solver& S, bool tr, hipStream_t st) {
+static void phaseB_t(Solver& S, bool tr, bool staged, hipStream_t st) {
   PhaseBArgs<T> a;
   a.x = S.x;
   a.g = (const T*)S.vec[V_G]; a.l = (const T*)S.vec[V_L]; a.s = (const T*)S.vec[V_S];
@@ -433,9 +634,18 @@ static void phaseB_t(Solver& S, bool tr, hipStream_t st) {
       hipLaunchKernelGGL(kern, dim3(S.nblk), dim3(kBlock), 0, st, a, P, S.n, S.sc, S.partials, nt);
     };
     if (S.auto_rr) {
-      if (ntm) go(k_phaseB<T, PC, true, true, K>); else go(k_phaseB<T, PC, false, true, K>);
+      if (ntm) go(k_phaseB<T, PC, true, true, K, false>);
+      else go(k_phaseB<T, PC, false, true, K, false>);
+    } else if (staged) {
+      if constexpr (K != 0) {
+        if (ntm) go(k_phaseB<T, PC, true, false, K, true>);
+        else go(k_phaseB<T, PC, false, false, K, true>);
+      } else {
+        throw std::logic_error("staged scalars without a fused operator");
+      }
     } else {
-      if (ntm) go(k_phaseB<T, PC, true, false, K>); else go(k_phaseB<T, PC, false, false, K>);
+      if (ntm) go(k_phaseB<T, PC, true, false, K, false>);
+      else go(k_phaseB<T, PC, false, false, K, false>);
     }
   });
 }
@@ -464,8 +674,12 @@ static void clupd_t(Solver& S, hipStream_t st) {
     }                                                                       \
   } while (0)
 
-void launch_phaseA(Solver& S, bool tr, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseA_t, S, tr, st); }
-void launch_phaseB(Solver& S, bool tr, hipStream_t st) { PBCG_DISPATCH_T_PC(S, phaseB_t, S, tr, st); }
+void launch_phaseA(Solver& S, bool tr, bool pro, hipStream_t st) {
+  PBCG_DISPATCH_T_PC(S, phaseA_t, S, tr, pro, st);
+}
+void launch_phaseB(Solver& S, bool tr, bool staged, hipStream_t st) {
+  PBCG_DISPATCH_T_PC(S, phaseB_t, S, tr, staged, st);
+}
 void launch_cl_update(Solver& S, hipStream_t st) { PBCG_DISPATCH_T_PC(S, clupd_t, S, st); }
 
 void launch_cl_p(Solver& S, hipStream_t st) {

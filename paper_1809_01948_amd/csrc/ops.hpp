@@ -409,6 +409,43 @@ __host__ __device__ inline int fin_slot_count(int mode, int rr_auto) {
   return fin_slots(mode, rr_auto, 8).n;
 }
 
+// The scalar step of GLRED 2 without side effects: from the reduced sums
+// v = {(r0, r_{i+1}), (r0, w_{i+1}), (r0, s_i), (r0, z_i), (r_{i+1}, r_{i+1})}
+// and the current alpha_i, omega_i, rho_i, the stopping test and
+// beta_{i+1} = ((alpha_i / omega_i) rho_{i+1}) / rho_i,
+// alpha_{i+1} = rho_{i+1} / ((r0,w_{i+1}) + beta (r0,s_i) - (beta omega_i) (r0,z_i)).
+// run_final(FIN_BETA) applies it to the scalar struct; the phase A prologue
+// evaluates it in every thread.
+enum G2Outcome : int { G2_CONTINUE = 0, G2_NONFINITE, G2_CONVERGED, G2_BREAKDOWN_OMEGA,
+                       G2_BREAKDOWN_RHO };
+struct G2Step {
+  int outcome;
+  double rn, beta, alpha;
+};
+__device__ __forceinline__ G2Step glred2_step(const double (&v)[5], double alpha, double omega,
+                                              double rho, double tol, double nb) {
+  G2Step r{G2_CONTINUE, 0.0, 0.0, 0.0};
+  const double rho1 = v[0], rw = v[1], rs = v[2], rz = v[3], rr = v[4];
+  if (!finite(rho1) || !finite(rw) || !finite(rs) || !finite(rz) || !finite(rr)) {
+    r.outcome = G2_NONFINITE;
+    return r;
+  }
+  r.rn = sqrt(rr);
+  if (r.rn <= tol * nb) {
+    r.outcome = G2_CONVERGED;
+  } else if (omega == 0.0) {
+    r.outcome = G2_BREAKDOWN_OMEGA;
+  } else if (rho1 == 0.0 || rho == 0.0) {
+    r.outcome = G2_BREAKDOWN_RHO;
+  } else {
+    r.beta = ((alpha / omega) * rho1) / rho;
+    const double den = (rw + r.beta * rs) - (r.beta * omega) * rz;
+    if (den == 0.0) r.outcome = G2_BREAKDOWN_RHO;
+    else r.alpha = rho1 / den;
+  }
+  return r;
+}
+
 // NS sums of a final, already reduced and stored in pre[] by slot
 template <int NS>
 __device__ __forceinline__ void take_sums(const double* pre, const int (&sl)[NS], double (&v)[NS]) {
@@ -511,37 +548,32 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
           if (sc->bound_history && its >= 1 && its <= sc->bound_len)
             sc->bound_history[its - 1] = sc->fr;
         }
-        if (!finite(rho1) || !finite(rw) || !finite(rs) || !finite(rz) || !finite(rr)) {
+        const double v5[5] = {rho1, rw, rs, rz, rr};
+        const G2Step g = glred2_step(v5, sc->alpha, sc->omega, sc->rho, sc->tol, sc->nb);
+        if (g.outcome == G2_NONFINITE) {
           stop(sc, ST_NONFINITE);
         } else {
-          const double rn = sqrt(rr);
-          sc->rn = rn;
-          if (hrow) hrow[0] = rn;
-          if (rn <= sc->tol * sc->nb) {
+          sc->rn = g.rn;
+          if (hrow) hrow[0] = g.rn;
+          if (g.outcome == G2_CONVERGED) {
             sc->done = RECURSIVE_CONVERGED;          // the host confirms with ||b - A x||
           } else {
             if (sc->rr_auto) {                       // eq:criterion for the next step
-              const int f_ok = sc->fr <= sc->tau * rn;
+              const int f_ok = sc->fr <= sc->tau * g.rn;
               sc->rr_next = sc->f_ok_prev && !f_ok;
               sc->f_ok_prev = f_ok;
             }
-            if (sc->omega == 0.0) {
+            if (g.outcome == G2_BREAKDOWN_OMEGA) {
               stop(sc, ST_BREAKDOWN_OMEGA);
-            } else if (rho1 == 0.0 || sc->rho == 0.0) {
+            } else if (g.outcome == G2_BREAKDOWN_RHO) {
               stop(sc, ST_BREAKDOWN_RHO);
             } else {
-              const double beta = ((sc->alpha / sc->omega) * rho1) / sc->rho;
-              const double den = (rw + beta * rs) - (beta * sc->omega) * rz;
-              if (den == 0.0) {
-                stop(sc, ST_BREAKDOWN_RHO);
-              } else {
-                sc->beta = beta;
-                if (hrow) hrow[3] = beta;
-                sc->alpha = rho1 / den;
-                sc->rho = rho1;
-                sc->omega_prev = sc->omega;
-                if (its >= sc->maxit) stop(sc, ST_MAXIT);
-              }
+              sc->beta = g.beta;
+              if (hrow) hrow[3] = g.beta;
+              sc->alpha = g.alpha;
+              sc->rho = rho1;
+              sc->omega_prev = sc->omega;
+              if (its >= sc->maxit) stop(sc, ST_MAXIT);
             }
           }
         }

@@ -59,8 +59,8 @@ struct Solver {
   double* b = nullptr;          // right-hand side (FP64, padded)
   void* dinv = nullptr;         // Jacobi diagonal (T) when a vector is needed
   double dinv_s = 1.0;          // constant Jacobi scale for constant stencils
-  double* partials = nullptr;   // kNumSlots * kMaxBlocks
-  DevScalars* sc = nullptr;
+  double* partials = nullptr;   // kNumSlots * kMaxPartials
+  DevScalars* sc = nullptr;       // sc[0] the scalars, sc[1] staging (phase A -> phase B)
   DevScalars* h_sc = nullptr;   // pinned, 2 entries (double-buffered poll)
 
   int nblk = 8;                 // blocks of every streaming kernel (multiple of 8)
@@ -101,9 +101,12 @@ inline StParams<T> st_params(const Solver& S, const OpData& o) {
 
 // ---- launchers (kernels_vec.hip) ----
 // phase A / phase B of Algorithm 2; with a fused operator (fused_kind != 0)
-// they also compute t = A M^-1 w and v = A M^-1 z respectively
-void launch_phaseA(Solver& S, bool tr, hipStream_t st);
-void launch_phaseB(Solver& S, bool tr, hipStream_t st);
+// they also compute t = A M^-1 w and v = A M^-1 z respectively, phase B
+// runs the GLRED 1 final in its prologue, and phase A with `pro` the
+// previous iteration's GLRED 2 final (fused operators, periodic strategy),
+// staging the scalars for the phase B launched with `staged`
+void launch_phaseA(Solver& S, bool tr, bool pro, hipStream_t st);
+void launch_phaseB(Solver& S, bool tr, bool staged, hipStream_t st);
 void launch_final(Solver& S, int mode, int aux, hipStream_t st, bool force = false);
 void launch_cl_update(Solver& S, hipStream_t st);
 void launch_cl_p(Solver& S, hipStream_t st);
