@@ -270,7 +270,10 @@ def main():
     n = prob.n
     # algorithmic HBM bytes per iteration (FP64, constant-diagonal Jacobi):
     # phase A 13 streams, SPMV 2 streams, phase B 15 streams, SPMV 2 streams
-    bytes_per_iter = 32 * 8 * n
+    # algorithmic bytes of one iteration: phase A 13 streams + phase B 15 streams of
+    # 8 B per row (the products' inputs w and z are read by the phase kernels that
+    # stream them anyway; the constant stencil and the scalar Jacobi add no bytes)
+    bytes_per_iter = 28 * 8 * n
     eff_gbs = bytes_per_iter * its / dt / 1e9
 
     # roofline of the dominant kernel: phase B (15 FP64 streams per row)

@@ -90,12 +90,12 @@ struct alignas(64) DevScalars {
   double rn;
   // (end of the first 64 bytes)
   double tau, rn0, rho, nb, tol;
+  int32_t maxit;
   double tr, gap;                  // last true residual norm / last gap norm
   double sig[8];                   // last reduced sums (diagnostics)
   double sums[8];                  // FIN_SUM output
   int32_t status;                  // Status (valid when done == STOPPED)
   int32_t rr_count;                // replacements performed
-  int32_t maxit;
   int32_t hist_len, gap_len;
   int32_t gap_idx;                 // next free gap-history slot
   int32_t bad_diag;                // set by value-update kernels on a zero diagonal

@@ -125,68 +125,65 @@ __device__ __forceinline__ void phaseA_update(const PhaseAArgs<T>& A, int64_t i,
   if (FUSE) stc<T, C, NT>(A.t + i, R.t);
 }
 
-// Phase A over the block's chunks.  PRO: the GLRED 2 final of the previous
-// iteration runs first (see k_phaseA).  (Issuing the first chunk's loads
-// before the final, as phase B does, costs registers: 149 instead of 101,
-// three waves per SIMD instead of four, and measured 44.2 against 41.9 us per
-// iteration on the 1000 x 1000 Poisson problem.)
-template <typename T, int PC, bool NT, bool AUTO, int KIND, bool PRO, bool SAVED>
-__device__ __forceinline__ void phaseA_run(const PhaseAArgs<T>& A, const StParams<T>& P, int64_t n,
-                                           DevScalars* __restrict__ sc,
-                                           double* __restrict__ partials, int64_t ntiles,
-                                           double alpha, double beta, double omega_prev) {
+// Inputs of the prologue's GLRED 2 step, loaded at kernel entry
+struct G2In {
+  double omega, rho, tol, nb;
+  int done, its, maxit;
+  double pp[5][kSlotStrides];           // the GLRED 2 partials of this thread
+};
+
+// The prologue GLRED 2 step (see k_phaseA): every thread evaluates it from
+// the reduced sums with the same expressions as run_final; block 0 also runs
+// run_final on an LDS copy of the struct, with the history log, and stages
+// the copy in sc[1].  Returns whether this iteration runs (and its scalars).
+__device__ __forceinline__ bool phaseA_prologue(DevScalars* __restrict__ sc, const G2In& in,
+                                                double& alpha, double& beta, double& omega_prev) {
+  __shared__ DevScalars lsc;
+  __shared__ double pre[kNumSlots];
+  const int tid = threadIdx.x;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
+  uint32_t w0 = 0, w1 = 0;
+  if (blockIdx.x == 0) {
+    if (tid < kScWords) w0 = src[tid];
+    if (tid + kBlock < kScWords) w1 = src[tid + kBlock];
+  }
+  const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+  double ts[5], v[5];
+  slot_thread_sums<5>(in.pp, gridDim.x, ts);
+  if (blockIdx.x == 0) {
+    uint32_t* dl = reinterpret_cast<uint32_t*>(&lsc);
+    if (tid < kScWords) dl[tid] = w0;
+    if (tid + kBlock < kScWords) dl[tid + kBlock] = w1;
+  }
+  block_tree<5>(ts, v);                   // (its barriers also publish lsc)
+  const G2Step g = glred2_step(v, alpha, in.omega, in.rho, in.tol, in.nb);
+  if (blockIdx.x == 0) {
+    if (tid == 0 && !in.done) {           // (a stopped solve is staged unchanged)
+#pragma unroll
+      for (int d = 0; d < 5; ++d) pre[sl[d]] = v[d];
+      run_final(FIN_BETA, &lsc, pre, 0);
+    }
+    scalars_from_lds(sc + 1, &lsc);
+  }
+  // (with its == maxit the step is taken and the solve then stops, as in
+  // run_final, with no iteration left to run)
+  if (in.done || g.outcome != G2_CONTINUE || in.its >= in.maxit) return false;
+  beta = g.beta;
+  alpha = g.alpha;
+  omega_prev = in.omega;
+  return true;
+}
+
+// Phase A over the block's chunks
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool SAVED>
+__device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StParams<T>& P, int64_t n,
+                                            double* __restrict__ partials, int64_t ntiles,
+                                            double alpha, double beta, double omega_prev) {
   constexpr int C = V16<T>::n;
   XcdWalk it(ntiles, blockIdx.x, gridDim.x);
   auto row = [&](int64_t t) { return (t * kBlock + threadIdx.x) * C; };
-  const bool any = it.t < it.end;
   ATile<T> R;
-  if constexpr (PRO) {
-    // every thread evaluates the GLRED 2 step from the reduced sums (the
-    // same expressions as run_final, so the same values everywhere); block 0
-    // also runs run_final on an LDS copy of the struct, with the history
-    // log, and stages the copy in sc[1]
-    __shared__ DevScalars lsc;
-    __shared__ double pre[kNumSlots];
-    const int tid = threadIdx.x;
-    const double omega = sc->omega, rho = sc->rho, tol = sc->tol, nb = sc->nb;
-    const int its = sc->iter + 1, maxit = sc->maxit;
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
-    uint32_t w0 = 0, w1 = 0;
-    if (blockIdx.x == 0) {
-      if (tid < kScWords) w0 = src[tid];
-      if (tid + kBlock < kScWords) w1 = src[tid + kBlock];
-    }
-    const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
-    double pp[5][kSlotStrides], ts[5], v[5];
-    slot_loads<5>(partials, sl, pp);
-    slot_thread_sums<5>(pp, gridDim.x, ts);
-    if (blockIdx.x == 0) {
-      uint32_t* dl = reinterpret_cast<uint32_t*>(&lsc);
-      if (tid < kScWords) dl[tid] = w0;
-      if (tid + kBlock < kScWords) dl[tid + kBlock] = w1;
-    }
-    block_tree<5>(ts, v);                 // (its barriers also publish lsc)
-    const G2Step g = glred2_step(v, alpha, omega, rho, tol, nb);
-    const bool go = g.outcome == G2_CONTINUE && its < maxit;
-    if (blockIdx.x == 0) {
-      if (tid == 0) {
-#pragma unroll
-        for (int d = 0; d < 5; ++d) pre[sl[d]] = v[d];
-        run_final(FIN_BETA, &lsc, pre, 0);
-      }
-      scalars_from_lds(sc + 1, &lsc);
-    }
-    // (with its == maxit the step still runs and the solve then stops, as
-    // in run_final, but there is no iteration left to update)
-    if (!go) return;
-    beta = g.beta;
-    alpha = g.alpha;
-    omega_prev = omega;
-  } else {
-    if (any) phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
-    if (any) phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
-  }
-  if (PRO && any) {
+  if (it.t < it.end) {
     phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
     phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
   }
@@ -231,21 +228,26 @@ __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> 
   static_assert(!(PRO && AUTO), "the prologue final serves the periodic strategy only");
   // the scalars are loaded with the done flag (one round trip, not two)
   const int done = sc->done, n_saved = sc->n_saved;
-  const double alpha = sc->alpha, beta = sc->beta, omega_prev = sc->omega_prev;
-  if (done) {
-    if (PRO && blockIdx.x == 0) {        // stopped earlier: the staged copy is sc[0] itself
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(sc);
-      uint32_t* dst = reinterpret_cast<uint32_t*>(sc + 1);
-      for (int i = threadIdx.x; i < kScWords; i += kBlock) dst[i] = src[i];
-    }
-    return;
+  double alpha = sc->alpha, beta = sc->beta, omega_prev = sc->omega_prev;
+  if constexpr (PRO) {
+    // No early exit here: the prologue's loads (the GLRED 2 inputs and
+    // partials) go out at once with the ones above, and every path uses
+    // them, so none waits for the done test.  A stopped solve only copies
+    // sc[0] to the staging struct.
+    G2In in;
+    in.done = done;
+    in.omega = sc->omega; in.rho = sc->rho; in.tol = sc->tol; in.nb = sc->nb;
+    in.its = sc->iter + 1; in.maxit = sc->maxit;
+    const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
+    slot_loads<5>(partials, sl, in.pp);
+    if (!phaseA_prologue(sc, in, alpha, beta, omega_prev)) return;
+  } else {
+    if (done) return;
   }
   if (n_saved)
-    phaseA_run<T, PC, NT, AUTO, KIND, PRO, true>(A, P, n, sc, partials, ntiles, alpha, beta,
-                                                 omega_prev);
+    phaseA_body<T, PC, NT, AUTO, KIND, true>(A, P, n, partials, ntiles, alpha, beta, omega_prev);
   else
-    phaseA_run<T, PC, NT, AUTO, KIND, PRO, false>(A, P, n, sc, partials, ntiles, alpha, beta,
-                                                  omega_prev);
+    phaseA_body<T, PC, NT, AUTO, KIND, false>(A, P, n, partials, ntiles, alpha, beta, omega_prev);
 }
 
 template <typename T>
