@@ -83,3 +83,44 @@ def test_fused_kernel_timing(Solver):
         ms = S.time_kernel(k, reps=3)
         assert 0.0 < ms < 50.0, k
     S.close()
+
+
+_CHUNK_CASES = [
+    # convergence inside a chunk (the GLRED 2 step that stops runs in a prologue)
+    ("converge-mid-chunk-graph", dict(tol=1e-6, maxit=2000, rr_period=7, use_graph=True)),
+    ("converge-mid-chunk", dict(tol=1e-6, maxit=2000, rr_period=7, check_every=13)),
+    # gap logging in the middle of chunks (a one-block GLRED 2 final before it)
+    ("gap-log", dict(tol=0.0, maxit=47, rr_period=10, gap_every=5, use_graph=True)),
+    # maxit not a multiple of the chunk length
+    ("maxit-ragged", dict(tol=0.0, maxit=53, check_every=9)),
+]
+
+
+@pytest.mark.parametrize("name,sk", _CHUNK_CASES, ids=[c[0] for c in _CHUNK_CASES])
+def test_deferred_glred2_equals_separate(Solver, name, sk):
+    """Where the GLRED 2 step runs (a prologue of the next phase A, a
+    one-block kernel at a chunk's end or before a gap measurement, or the
+    first blocks of an SPMV) changes nothing: status, iteration count,
+    history, gap log and iterate agree bit for bit."""
+    p = poisson2d_c2(40)
+    out = {}
+    for fuse in (True, False):
+        S = _make(Solver, p, fuse, form="stencil", precision="fp64", precond="jacobi")
+        rows = sk["maxit"]
+        hist = history_buffer(rows)
+        gap = torch.zeros(64, dtype=torch.float64, device="cuda")
+        kw = dict(sk)
+        if kw.get("gap_every"):
+            kw["gap_history"] = gap
+        x, st = S.solve(dev(p.b), history=hist, **kw)
+        out[fuse] = (host(x), st, host(hist), host(gap))
+        S.close()
+    (xa, sa, ha, ga), (xb, sb, hb, gb) = out[True], out[False]
+    print(name, sa["status_name"], sa["iterations"], sa["replacements"])
+    assert sa["status"] == sb["status"] and sa["iterations"] == sb["iterations"]
+    assert sa["replacements"] == sb["replacements"]
+    assert np.array_equal(xa, xb) and np.array_equal(ha, hb) and np.array_equal(ga, gb)
+    if sk["tol"] > 0:
+        assert sa["status_name"] == "CONVERGED"
+    else:
+        assert sa["iterations"] == sk["maxit"]
