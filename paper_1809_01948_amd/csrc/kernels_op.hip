@@ -3,12 +3,16 @@
 // Every kernel walks rows in tiles of 256 with the XCD-aware mapping of
 // XcdWalk and applies the operator through a row visitor (ops.hpp).
 //
-// The SPMV kernel carries the global-reduction "final" as its block 0: the
-// GLRED of Algorithm 2 is reduced and turned into omega_i (or beta_{i+1},
-// alpha_{i+1}) by that one block while the other blocks compute the SPMV that
-// the reduction is meant to hide behind (the PREC + SPMV between
-// "begin global reduction" and "end reduction").  Block 0 is dispatched first,
-// so the reduction overlaps the whole product.
+// The SPMV kernels carry a global-reduction "final" in their first blocks
+// (one block per reduced sum, the last to finish computes the scalars): the
+// GLRED of Algorithm 2 is turned into omega_i (or beta_{i+1}, alpha_{i+1})
+// while the other blocks compute the SPMV that the reduction is meant to
+// hide behind (the PREC + SPMV between "begin global reduction" and "end
+// reduction").  The first blocks are dispatched first, so the reduction
+// overlaps the whole product.  For structured operators the iteration does
+// not use these SPMV kernels (the phase kernels compute the products and
+// the GLRED steps; kernels_vec.hip); they serve the initialisation, the
+// replacement and operators stored as SELL.
 
 #include <type_traits>
 
