@@ -354,6 +354,7 @@ def main():
         p3 = convdiff3d_c3(200)
         b3 = torch.from_numpy(p3.b).to(dev)
         mv = {}
+        x_fp64 = None                     # the first converged FP64 solution
         for prec, P in (("fp64", 50), ("fp64", 100), ("fp64", "auto"),
                         ("mixed", 10), ("mixed", 25), ("mixed", "auto")):
             S3 = Solver.from_problem(p3, form="stencil", precision=prec, precond="jacobi")
@@ -373,6 +374,11 @@ def main():
                        "status": st3["status_name"],
                        "rel_res_true": st3["rel_res_true"], "rel_err_vs_exact": xerr,
                        "iter_per_s": st3["iterations"] / t3}
+            if prec == "fp64" and x_fp64 is None and st3["status_name"] == "CONVERGED":
+                x_fp64 = x3.clone()
+            if prec == "mixed" and x_fp64 is not None:
+                mv[key]["rel_diff_vs_fp64"] = float(torch.linalg.norm(x3 - x_fp64) /
+                                                    torch.linalg.norm(x_fp64))
             log(f"{key}: {mv[key]}")
             S3.close()
 

@@ -170,6 +170,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __re
   }
 }
 
+// A GLRED final on its own, spread over one block per reduced slot (the
+// automated strategy's 22 sums): block b reduces slot b, the last block to
+// finish runs the scalar logic (distributed_final).
+__global__ __launch_bounds__(kBlock) void k_fin_dist(int fin_mode, DevScalars* __restrict__ sc,
+                                                     const double* __restrict__ partials, int npart) {
+  const int done = sc->done, rr_auto = sc->rr_auto;
+  if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)
+    distributed_final(fin_mode, sc, partials, npart, (int)gridDim.x, rr_auto);
+}
+
 // Algorithm 2 initialisation, first part: r_0 = b - A x_0 (FP64), r0 := r_0,
 // k_0 = M^-1 r_0, the iteration -1 vectors g, s, l, z, v set to zero, and the
 // partials (r0, r_0), (r_0, r_0), (b, b).
@@ -731,7 +741,17 @@ int fused_kind(Solver& S, bool tr) {
   return o.kind;
 }
 
-void launch_fin(Solver& S, int fin_mode, hipStream_t st) { launch_final(S, fin_mode, 0, st); }
+void launch_fin(Solver& S, int fin_mode, hipStream_t st) {
+  // up to 8 sums: one block loads them all in one round trip; more (the
+  // automated strategy's 22): one block per sum
+  const int nfin = fin_blocks(S, fin_mode);
+  if (nfin <= 8) {
+    launch_final(S, fin_mode, 0, st);
+    return;
+  }
+  hipLaunchKernelGGL(k_fin_dist, dim3(nfin), dim3(kBlock), 0, st, fin_mode, S.sc, S.partials,
+                     S.nblk);
+}
 
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
                  hipStream_t st) {

@@ -120,7 +120,7 @@ const OpData& op_of(Solver& S, bool transpose);
 // The operator kind whose products the phase kernels compute themselves
 // (OP_ST2D5, OP_ST3D7, OP_DIA5), or 0 when the iteration runs separate SPMVs.
 int fused_kind(Solver& S, bool transpose);
-// a GLRED final on its own (one block)
+// a GLRED final on its own (one block, or one block per sum beyond eight)
 void launch_fin(Solver& S, int fin_mode, hipStream_t st);
 void launch_init_res(Solver& S, bool tr, hipStream_t st);
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
