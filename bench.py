@@ -88,7 +88,8 @@ def kernel_source_hash():
     parts = (("kernels_vec.hip", ("struct PhaseBArgs", "void k_phaseB(", "void k_copy(")),
              ("common.hpp", ("double wave_sum(", "void block_partials(", "void ld16(",
                              "void st16(", "void ldc(", "void stc(")),
-             ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "void st_apply(")))
+             ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "T st_row_sum(",
+                          "void st_apply(")))
     for fname, starts in parts:
         src = open(os.path.join(HERE, "paper_1809_01948_amd/csrc", fname)).read()
         for start in starts:

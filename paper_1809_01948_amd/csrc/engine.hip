@@ -120,6 +120,8 @@ void common_setup(Solver& S, int precision, int precond) {
   if (const char* env = std::getenv("PBCG_VEC_NT")) S.vnt = std::atoi(env) & 3;
   if (const char* env = std::getenv("PBCG_SPMV_TILED")) S.spmv_tiled = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_FUSE")) S.fuse = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_MARCH3D")) S.march3d = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_MARCH_ZLEN")) S.march_zlen = std::atoi(env);
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
   hipck(hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming), "hipEventCreate");
   hipck(hipEventCreateWithFlags(&S.ev_out, hipEventDisableTiming), "hipEventCreate");

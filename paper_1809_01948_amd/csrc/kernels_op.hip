@@ -87,7 +87,7 @@ struct QVis {
 
 // out = A (M^-1 in); optional partial (r0, out); block 0 runs `fin_mode`.
 template <typename T, int PC, class Op>
-__global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in, T* __restrict__ out,
+__global__ PBCG_FINAL_CALLER void k_spmv(Op op, const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ dinv, T ds,
                                                  const T* __restrict__ rhat, int64_t n, int64_t ntiles,
                                                  int nwork, DevScalars* __restrict__ sc,
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
 // order, exactly as the row-per-thread kernel does.
 
 template <typename T, int PC, int KIND, int CH>
-__global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __restrict__ in,
+__global__ PBCG_FINAL_CALLER void k_spmv_st(StParams<T> P, const T* __restrict__ in,
                                                     T* __restrict__ out, const T* __restrict__ dinv,
                                                     T ds, int64_t n, int64_t ntiles, int nwork,
                                                     DevScalars* __restrict__ sc,
@@ -173,11 +173,93 @@ __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __re
 // A GLRED final on its own, spread over one block per reduced slot (the
 // automated strategy's 22 sums): block b reduces slot b, the last block to
 // finish runs the scalar logic (distributed_final).
-__global__ __launch_bounds__(kBlock) void k_fin_dist(int fin_mode, DevScalars* __restrict__ sc,
+__global__ PBCG_FINAL_CALLER void k_fin_dist(int fin_mode, DevScalars* __restrict__ sc,
                                                      const double* __restrict__ partials, int npart) {
   const int done = sc->done, rr_auto = sc->rr_auto;
   if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)
     distributed_final(fin_mode, sc, partials, npart, (int)gridDim.x, rr_auto);
+}
+
+// The 3D 7-point product marching through the grid planes: work item
+// (zc, c) is segment c of a plane (kBlock * R consecutive rows) in planes
+// zc*zlen .. zc*zlen + zlen - 1, visited in order.  A thread keeps the
+// chunks of the plane below, the current plane and the plane above in
+// registers (each plane's chunk is loaded once, as the next plane up), so
+// the +-plane neighbours (a plane apart, 320 KB in FP64) cost no memory
+// traffic; the +-line neighbours come from the segments next to it (L1/L2).
+// Rows are summed by st_row_sum, so the products equal k_spmv_st's bit for
+// bit.  Requires nx a multiple of R.  The first nfin blocks run the final.
+template <typename T, int PC>
+__global__ PBCG_FINAL_CALLER void k_spmv_st3m(StParams<T> P, const T* __restrict__ in,
+                                              T* __restrict__ out, const T* __restrict__ dinv,
+                                              T ds, int ncol, int nzc, int zlen,
+                                              DevScalars* __restrict__ sc,
+                                              double* __restrict__ partials, int fin_mode,
+                                              int nblk_partials, int nfin) {
+  if ((int)blockIdx.x < nfin) {
+    const int done = sc->done, rr_auto = sc->rr_auto;
+    if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)
+      distributed_final(fin_mode, sc, partials, nblk_partials, nfin, rr_auto);
+    return;
+  }
+  if (sc->done) return;
+  constexpr int R = V16<T>::n;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int nxy = nx * ny;
+  const int blk = blockIdx.x - nfin;
+  const int nwork = gridDim.x - nfin;
+  const int64_t items = (int64_t)ncol * nzc;
+  for (XcdWalk w(items, blk, nwork); w.t < w.end; w.t += w.step) {
+    const int zc = (int)(w.t / ncol);
+    const int c = (int)(w.t - (int64_t)zc * ncol);
+    const int off = c * (kBlock * R) + (int)threadIdx.x * R;
+    if (off >= nxy) continue;
+    const int iy = off / nx, ix = off - iy * nx;
+    const bool hS = iy > 0, hN = iy < ny - 1;
+    const bool hW0 = ix > 0, hEl = ix + R < nx;
+    const int z0 = zc * zlen;
+    const int z1 = z0 + zlen < nz ? z0 + zlen : nz;
+    T xd[R], xc[R], xu[R];
+    if (z0 > 0) {
+      load_chunk<T, PC>(in, dinv, ds, (int64_t)(z0 - 1) * nxy + off, xd);
+    } else {
+#pragma unroll
+      for (int e = 0; e < R; ++e) xd[e] = T(0);           // (no plane below: unused)
+    }
+    load_chunk<T, PC>(in, dinv, ds, (int64_t)z0 * nxy + off, xc);
+    for (int k = z0; k < z1; ++k) {
+      const int64_t p = (int64_t)k * nxy + off;
+      const bool hD = k > 0, hU = k < nz - 1;
+      if (hU) {
+        load_chunk<T, PC>(in, dinv, ds, p + nxy, xu);
+      } else {
+#pragma unroll
+        for (int e = 0; e < R; ++e) xu[e] = T(0);         // (no plane above: unused)
+      }
+      T xs[R], xn[R];
+      load_chunk<T, PC>(in, dinv, ds, hS ? p - nx : p, xs);
+      load_chunk<T, PC>(in, dinv, ds, hN ? p + nx : p, xn);
+      const int64_t jw = hW0 ? p - 1 : p, je = hEl ? p + R : p;
+      const T xw0 = prec1<T, PC>(in[jw], dinv, ds, jw);
+      const T xeR = prec1<T, PC>(in[je], dinv, ds, je);
+      T res[R];
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        const T xw = e == 0 ? xw0 : xc[e - 1];
+        const T xe = e == R - 1 ? xeR : xc[e + 1];
+        const bool vw = e == 0 ? hW0 : true;
+        const bool ve = e == R - 1 ? hEl : true;
+        res[e] = st_row_sum<T, OP_ST3D7>(P, hD, hS, vw, ve, hN, hU, xd[e], xs[e], xw, xc[e], xe,
+                                         xn[e], xu[e], T(0), T(0), T(0), T(0), T(0));
+      }
+      st16(out + p, res);
+#pragma unroll
+      for (int e = 0; e < R; ++e) {
+        xd[e] = xc[e];
+        xc[e] = xu[e];
+      }
+    }
+  }
 }
 
 // Algorithm 2 initialisation, first part: r_0 = b - A x_0 (FP64), r0 := r_0,
@@ -690,9 +772,30 @@ static bool spmv_structured(Solver& S, const OpData& o, const void* in, void* ou
                             hipStream_t st) {
   constexpr int R = V16<T>::n;
   if (o.kind == OP_SELL || o.dims[0] % R != 0) return false;
+  const int nwork = S.nspmv;
+  if (o.kind == OP_ST3D7 && S.march3d) {
+    // plane-marching 3D product; z-chunks long enough that the work items
+    // (segments x z-chunks) about fill the grid once
+    const StParams<T> P = st_params<T>(S, o);
+    const int64_t nxy = (int64_t)o.dims[0] * o.dims[1];
+    const int seg = kBlock * R;
+    const int ncol = (int)((nxy + seg - 1) / seg);
+    const int nz = o.dims[2];
+    int zlen = (int)std::max<int64_t>(1, ((int64_t)ncol * nz + nwork - 1) / nwork);
+    if (S.march_zlen > 0) zlen = std::min(S.march_zlen, nz);
+    const int nzc = (nz + zlen - 1) / zlen;
+    const int nfin = fin_blocks(S, fin_mode);
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(nwork + nfin), dim3(kBlock), 0, st, P, (const T*)in, (T*)out,
+                         (const T*)S.dinv, (T)S.dinv_s, ncol, nzc, zlen, S.sc, S.partials,
+                         fin_mode, S.nblk, nfin);
+    };
+    if (S.pc != PC_NONE) go(k_spmv_st3m<T, PC_SCALAR>);
+    else go(k_spmv_st3m<T, PC_NONE>);
+    return true;
+  }
   // two 16-byte chunks per thread (twice the bytes in flight per load wave)
   // when grid lines allow it and the grid still has two tiles per block
-  const int nwork = S.nspmv;
   const bool two = o.dims[0] % (2 * R) == 0 &&
                    S.n / ((int64_t)kBlock * 2 * R) >= 2 * (int64_t)nwork;
   const StParams<T> P = st_params<T>(S, o);

@@ -177,6 +177,40 @@ struct StParams {
   int64_t ld;
 };
 
+// One row of a structured operator applied to preconditioned values: the
+// stored entries in ascending column order (D, S, W, C, E, N, U in 3D; S, W,
+// C, E, N in 2D), one rounding per operation; entries outside the grid are
+// skipped.  Every structured product (st_apply, the plane-marching 3D
+// SpMV) sums through this function, so they agree bit for bit.
+template <typename T, int KIND>
+__device__ __forceinline__ T st_row_sum(const StParams<T>& P, bool hD, bool hS, bool vw, bool ve,
+                                        bool hN, bool hU, T xd, T xs, T xw, T xc, T xe, T xn,
+                                        T xu, T cS, T cW, T cC, T cE, T cN) {
+  T sum = T(0);
+  if (KIND == OP_DIA5) {
+    if (hS) sum += cS * xs;
+    if (vw) sum += cW * xw;
+    sum += cC * xc;
+    if (ve) sum += cE * xe;
+    if (hN) sum += cN * xn;
+  } else if (KIND == OP_ST3D7) {
+    if (hD) sum += P.c[0] * xd;
+    if (hS) sum += P.c[1] * xs;
+    if (vw) sum += P.c[2] * xw;
+    sum += P.c[3] * xc;
+    if (ve) sum += P.c[4] * xe;
+    if (hN) sum += P.c[5] * xn;
+    if (hU) sum += P.c[6] * xu;
+  } else {
+    if (hS) sum += P.c[0] * xs;
+    if (vw) sum += P.c[1] * xw;
+    sum += P.c[2] * xc;
+    if (ve) sum += P.c[3] * xe;
+    if (hN) sum += P.c[4] * xn;
+  }
+  return sum;
+}
+
 // Rows p .. p + R*CH - 1 of A M^-1 z for a structured operator (constant 2D
 // 5-point or 3D 7-point stencil, or DIA5), R = elements per 16-byte chunk.
 // The caller passes the centre values xc = (M^-1 z)[p ..] it already holds;
@@ -261,29 +295,11 @@ __device__ __forceinline__ void st_apply(const StParams<T>& P, const T* __restri
     const T xe = e == RR - 1 ? xeR : xc[e + 1];
     const bool vw = e == 0 ? hW0 : true;
     const bool ve = e == RR - 1 ? hEl : true;
-    T sum = T(0);
-    if (KIND == OP_DIA5) {
-      if (hS) sum += cS[e] * xs[e];
-      if (vw) sum += cW[e] * xw;
-      sum += cC[e] * xc[e];
-      if (ve) sum += cE[e] * xe;
-      if (hN) sum += cN[e] * xn[e];
-    } else if (THREE) {
-      if (hD) sum += P.c[0] * xd[e];
-      if (hS) sum += P.c[1] * xs[e];
-      if (vw) sum += P.c[2] * xw;
-      sum += P.c[3] * xc[e];
-      if (ve) sum += P.c[4] * xe;
-      if (hN) sum += P.c[5] * xn[e];
-      if (hU) sum += P.c[6] * xu[e];
-    } else {
-      if (hS) sum += P.c[0] * xs[e];
-      if (vw) sum += P.c[1] * xw;
-      sum += P.c[2] * xc[e];
-      if (ve) sum += P.c[3] * xe;
-      if (hN) sum += P.c[4] * xn[e];
-    }
-    res[e] = sum;
+    res[e] = st_row_sum<T, KIND>(P, hD, hS, vw, ve, hN, hU, THREE ? xd[e] : T(0), xs[e], xw,
+                                 xc[e], xe, xn[e], THREE ? xu[e] : T(0),
+                                 KIND == OP_DIA5 ? cS[e] : T(0), KIND == OP_DIA5 ? cW[e] : T(0),
+                                 KIND == OP_DIA5 ? cC[e] : T(0), KIND == OP_DIA5 ? cE[e] : T(0),
+                                 KIND == OP_DIA5 ? cN[e] : T(0));
   }
 }
 
@@ -674,6 +690,14 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
       break;
   }
 }
+
+// Launch bounds of the kernels that call distributed_final: four waves per
+// SIMD (at most 128 VGPRs).  The final is one function shared by its callers,
+// so without the limit its register count (184, from the one-thread scalar
+// logic) becomes every caller's and halves the waves an SPMV keeps in flight;
+// under it the scalar logic keeps a few arrays in scratch memory, touched only
+// by the one thread that runs it.
+#define PBCG_FINAL_CALLER __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 
 // A final spread over the first `fb` blocks of a kernel: block b reduces
 // slots b, b + fb, ... of the mode (each with the fixed-order tree of

@@ -72,6 +72,8 @@ struct Solver {
   int mu_row = 1, mu_col = 1;   // max stored entries per row / per column
   bool spmv_tiled = true;       // several consecutive rows per thread for structured operators
   bool fuse = true;             // phase kernels compute the SPMVs of structured operators
+  bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
+  int march_zlen = 0;           // planes per work item of k_spmv_st3m (0: sized to the grid)
   int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
   int64_t rtiles = 0;           // tiles of 256 rows
 
