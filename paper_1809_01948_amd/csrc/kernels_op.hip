@@ -87,7 +87,7 @@ struct QVis {
 
 // out = A (M^-1 in); optional partial (r0, out); block 0 runs `fin_mode`.
 template <typename T, int PC, class Op>
-__global__ PBCG_FINAL_CALLER void k_spmv(Op op, const T* __restrict__ in, T* __restrict__ out,
+__global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ dinv, T ds,
                                                  const T* __restrict__ rhat, int64_t n, int64_t ntiles,
                                                  int nwork, DevScalars* __restrict__ sc,
@@ -131,7 +131,7 @@ __global__ PBCG_FINAL_CALLER void k_spmv(Op op, const T* __restrict__ in, T* __r
 // order, exactly as the row-per-thread kernel does.
 
 template <typename T, int PC, int KIND, int CH>
-__global__ PBCG_FINAL_CALLER void k_spmv_st(StParams<T> P, const T* __restrict__ in,
+__global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __restrict__ in,
                                                     T* __restrict__ out, const T* __restrict__ dinv,
                                                     T ds, int64_t n, int64_t ntiles, int nwork,
                                                     DevScalars* __restrict__ sc,
@@ -173,7 +173,7 @@ __global__ PBCG_FINAL_CALLER void k_spmv_st(StParams<T> P, const T* __restrict__
 // A GLRED final on its own, spread over one block per reduced slot (the
 // automated strategy's 22 sums): block b reduces slot b, the last block to
 // finish runs the scalar logic (distributed_final).
-__global__ PBCG_FINAL_CALLER void k_fin_dist(int fin_mode, DevScalars* __restrict__ sc,
+__global__ __launch_bounds__(kBlock) void k_fin_dist(int fin_mode, DevScalars* __restrict__ sc,
                                                      const double* __restrict__ partials, int npart) {
   const int done = sc->done, rr_auto = sc->rr_auto;
   if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)
@@ -190,12 +190,11 @@ __global__ PBCG_FINAL_CALLER void k_fin_dist(int fin_mode, DevScalars* __restric
 // Rows are summed by st_row_sum, so the products equal k_spmv_st's bit for
 // bit.  Requires nx a multiple of R.  The first nfin blocks run the final.
 template <typename T, int PC>
-__global__ PBCG_FINAL_CALLER void k_spmv_st3m(StParams<T> P, const T* __restrict__ in,
-                                              T* __restrict__ out, const T* __restrict__ dinv,
-                                              T ds, int ncol, int nzc, int zlen,
-                                              DevScalars* __restrict__ sc,
-                                              double* __restrict__ partials, int fin_mode,
-                                              int nblk_partials, int nfin) {
+__global__ __launch_bounds__(kBlock)
+void k_spmv_st3m(StParams<T> P, const T* __restrict__ in, T* __restrict__ out,
+                 const T* __restrict__ dinv, T ds, int ncol, int nzc, int zlen,
+                 DevScalars* __restrict__ sc, double* __restrict__ partials, int fin_mode,
+                 int nblk_partials, int nfin) {
   if ((int)blockIdx.x < nfin) {
     const int done = sc->done, rr_auto = sc->rr_auto;
     if (fin_mode == FIN_INIT || fin_mode == FIN_REDO || !done)

@@ -691,22 +691,17 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
   }
 }
 
-// Launch bounds of the kernels that call distributed_final: four waves per
-// SIMD (at most 128 VGPRs).  The final is one function shared by its callers,
-// so without the limit its register count (184, from the one-thread scalar
-// logic) becomes every caller's and halves the waves an SPMV keeps in flight;
-// under it the scalar logic keeps a few arrays in scratch memory, touched only
-// by the one thread that runs it.
-#define PBCG_FINAL_CALLER __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
-
 // A final spread over the first `fb` blocks of a kernel: block b reduces
 // slots b, b + fb, ... of the mode (each with the fixed-order tree of
 // block_sum_slots, so the sums are bitwise those of a one-block final),
 // stores them, and arrives at a counter; the last block to arrive runs the
-// scalar logic on the stored sums.  No block waits for another.
-__device__ inline void distributed_final(int mode, DevScalars* __restrict__ sc,
-                                         const double* __restrict__ partials, int nblk, int fb,
-                                         int rr_auto) {
+// scalar logic on the stored sums.  No block waits for another.  Inlined
+// into each caller: compiled as one shared function it took 184 VGPRs, and a
+// kernel's count includes its callees', which left every SPMV at two waves
+// per SIMD; inlined, the SPMVs need 108 (four waves).
+__device__ __forceinline__ void distributed_final(int mode, DevScalars* __restrict__ sc,
+                                                  const double* __restrict__ partials, int nblk,
+                                                  int fb, int rr_auto) {
   const FinSlots fs = fin_slots(mode, rr_auto, 0);
   for (int d = blockIdx.x; d < fs.n; d += fb) {
     const int slot = fs.s[d];
