@@ -60,10 +60,13 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only launch phase B and the copy kernel on the workload (the short "
                          "program that the rocprofv3 counter runs profile)")
-    ap.add_argument("--kernels-workload", choices=("poisson1000", "convdiff200"),
+    ap.add_argument("--kernels-workload",
+                    choices=("poisson1000", "convdiff200", "random2m", "kappa2048"),
                     default="poisson1000",
-                    help="workload of --kernels-only: the 1000^2 Poisson step or the 200^3 "
-                         "convection-diffusion problem (HBM-resident working set)")
+                    help="workload of --kernels-only: the 1000^2 Poisson step, the 200^3 "
+                         "convection-diffusion problem (HBM-resident working set), the 2e6-row "
+                         "random matrix with 27 entries per row (sliced ELL), or the 2048^2 "
+                         "variable-coefficient DIA5 operator with its gradients")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "--kernels-only into the traffic summary under profiles/")
@@ -204,6 +207,53 @@ def cpu_baseline(prob, iters):
             "host_cpus": os.cpu_count(), "cpu_model": cpu}
 
 
+def kernels_other(which, dev):
+    """Kernel times of the sliced-ELL (2e6 rows x 27) or DIA5 (2048^2) iteration in FP64
+    and with FP32 storage, with algorithmic bytes per row; on the DIA5 operator also the
+    two gradient passes.  One JSON line."""
+    import torch
+    from paper_1809_01948_amd.solver import Solver
+    from workloads import inverse_problem_c5, random_banded_c4
+    if which == "random2m":
+        p, form, slots = random_banded_c4(), "csr", 27
+    else:
+        p, form, slots = inverse_problem_c5(), "dia5", 5
+    b = torch.from_numpy(p.b).to(dev)
+    out = {"workload": which, "n": p.n, "bytes_per_row": {}, "ms": {}, "GBps": {}}
+    for prec, bv in (("fp64", 8), ("mixed", 4)):
+        S = Solver.from_problem(p, form=form, precision=prec, precond="jacobi")
+        S.solve(b, tol=1e-10, maxit=50, rr_period=50)       # realistic vector contents
+        if form == "csr":
+            # separate products; Jacobi with a dinv vector, applied by the phase
+            # kernels, which also write the products' input M^-1 z (M^-1 w); values
+            # in the storage precision plus int32 columns
+            byts = {"phaseA": 15 * bv, "phaseB": 15 * bv + 16,
+                    "spmv1": 2 * bv + slots * (bv + 4)}
+        else:
+            # products fused into the phase kernels; five coefficient arrays
+            byts = {"phaseA": 14 * bv + slots * bv, "phaseB": 14 * bv + 16 + slots * bv}
+        for k, bpr in byts.items():
+            ms = S.time_kernel(k, reps=KERNELS_ONLY_REPS)
+            out["bytes_per_row"][f"{prec}_{k}"] = bpr
+            out["ms"][f"{prec}_{k}"] = ms
+            out["GBps"][f"{prec}_{k}"] = bpr * p.n / (ms * 1e-3) / 1e9
+        out["ms"][f"{prec}_iteration"] = S.time_kernel("iteration", reps=KERNELS_ONLY_REPS)
+        if form == "dia5" and prec == "fp64":
+            lam = torch.randn(p.n, dtype=torch.float64, device=dev)
+            x = torch.randn(p.n, dtype=torch.float64, device=dev)
+            for name, fn in (("grad_values", lambda: S.grad_values(lam, x)),
+                             ("kappa_grad", lambda: S.kappa_grad(lam, x))):
+                fn()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(KERNELS_ONLY_REPS):
+                    fn()
+                torch.cuda.synchronize()
+                out["ms"][name] = (time.perf_counter() - t0) / KERNELS_ONLY_REPS * 1e3
+        S.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -219,6 +269,9 @@ def main():
     from workloads import convdiff3d_c3, poisson2d_c2
 
     dev = torch.device("cuda:0")
+    if args.kernels_only and args.kernels_workload in ("random2m", "kappa2048"):
+        kernels_other(args.kernels_workload, dev)
+        return
     if args.kernels_only and args.kernels_workload == "convdiff200":
         p3 = convdiff3d_c3(200)
         S3 = Solver.from_problem(p3, form="stencil", precision="fp64", precond="jacobi")

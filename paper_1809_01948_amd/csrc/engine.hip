@@ -121,6 +121,7 @@ void common_setup(Solver& S, int precision, int precond) {
   if (const char* env = std::getenv("PBCG_SPMV_TILED")) S.spmv_tiled = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_FUSE")) S.fuse = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_MARCH3D")) S.march3d = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_PREMULT")) S.premult = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_MARCH_ZLEN")) S.march_zlen = std::atoi(env);
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
   hipck(hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming), "hipEventCreate");
@@ -427,13 +428,13 @@ bool enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_
   const bool gap = o.gap_every > 0 && (i + 1) % o.gap_every == 0;
   const bool defer = fused && !o.rr_auto && !last_of_chunk && !gap;
   launch_phaseA(S, tr, pending, st);
-  if (!fused) launch_spmv(S, tr, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, st);
+  if (!fused) launch_iter_spmv(S, tr, V_Z, V_V, FIN_OMEGA, st);
   launch_phaseB(S, tr, pending, st);
   if (o.rr_auto || (o.rr_period > 0 && (i + 1) % o.rr_period == 0)) {
     launch_rr1(S, tr, false, st);      // predicated on the device (eq:criterion or the period)
     launch_rr2(S, tr, false, st);
   }
-  if (!fused) launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_BETA, false, st);
+  if (!fused) launch_iter_spmv(S, tr, V_W, V_T, FIN_BETA, st);
   else if (!defer) launch_fin(S, FIN_BETA, st);
   if (gap) {
     launch_gap(S, tr, st);
@@ -1138,15 +1139,15 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
         case 0: launch_phaseA(S, false, false, S.s1); break;
         case 1:
           if (fused) launch_fin(S, FIN_OMEGA, S.s1);
-          else launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_OMEGA, false, S.s1);
+          else launch_iter_spmv(S, false, V_Z, V_V, FIN_OMEGA, S.s1);
           break;
         case 2: launch_phaseB(S, false, false, S.s1); break;
         case 3:
           if (fused) launch_fin(S, FIN_PROBE, S.s1);
-          else launch_spmv(S, false, S.vec[V_W], S.vec[V_T], FIN_PROBE, false, S.s1);
+          else launch_iter_spmv(S, false, V_W, V_T, FIN_PROBE, S.s1);
           break;
         case 5: launch_copy(S, S.x, S.b, S.s1); break;
-        case 6: launch_spmv(S, false, S.vec[V_Z], S.vec[V_V], FIN_NONE, false, S.s1); break;
+        case 6: launch_iter_spmv(S, false, V_Z, V_V, FIN_NONE, S.s1); break;
         case 7: launch_fin(S, FIN_PROBE, S.s1); break;
       }
     };

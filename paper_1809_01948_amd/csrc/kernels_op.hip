@@ -365,11 +365,12 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
 // computed n_i = M^-1 z_i of this iteration is not replaced (only the six
 // quantities of eq:rr are), and v_i = A n_i keeps its value; so the
 // pre-replacement z_i is kept in `zsave` for the next phase A, which forms
-// n_i from it.
+// n_i from it.  With `pm`, also M^-1 w (dinv a vector) for the next product.
 template <typename T, int PC, class Op>
 __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, const T* __restrict__ l,
                                                 T* __restrict__ w, T* __restrict__ z,
-                                                T* __restrict__ zsave,
+                                                T* __restrict__ zsave, T* __restrict__ pm,
+                                                const T* __restrict__ dinv,
                                                 const T* __restrict__ rhat, const T* __restrict__ r,
                                                 const T* __restrict__ s, int64_t n, int64_t ntiles,
                                                 int nwork, DevScalars* __restrict__ sc,
@@ -388,6 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
       zsave[i] = z[i];
       w[i] = wi;
       z[i] = zi;
+      if (pm) pm[i] = dinv[i] * wi;
       const double rh = (double)rhat[i], ri = (double)r[i];
       acc[0] += rh * ri;
       acc[1] += rh * (double)wi;
@@ -855,9 +857,21 @@ void launch_fin(Solver& S, int fin_mode, hipStream_t st) {
                      S.nblk);
 }
 
+bool pre_multiplied(Solver& S, bool tr) {
+  return S.premult && S.pc == PC_VECTOR && op_of(S, tr).kind == OP_SELL &&
+         fused_kind(S, tr) == 0;
+}
+
+void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode, hipStream_t st) {
+  if (pre_multiplied(S, tr))
+    launch_spmv(S, tr, S.vec[V_PM], S.vec[out_vec], fin_mode, false, st, true);
+  else
+    launch_spmv(S, tr, S.vec[in_vec], S.vec[out_vec], fin_mode, false, st);
+}
+
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
-                 hipStream_t st) {
-  if (!dot_rhat && S.spmv_tiled) {
+                 hipStream_t st, bool pre) {
+  if (!dot_rhat && S.spmv_tiled && !pre) {
     const OpData& o = op_of(S, tr);
     const bool done = S.precision == 0 ? spmv_structured<double>(S, o, in, out, fin_mode, st)
                                        : spmv_structured<float>(S, o, in, out, fin_mode, st);
@@ -866,7 +880,7 @@ void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bo
   const int nfin = fin_blocks(S, fin_mode);
   // the (r0, out) partials are indexed by work block and reduced over nblk
   const int nwork = dot_rhat ? S.nblk : S.nspmv;
-  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+  with_op(S, tr, !pre, [&]<typename T, int PC, class Op>(const Op& op) {
     hipLaunchKernelGGL((k_spmv<T, PC, Op>), dim3(nwork + nfin), dim3(kBlock), 0, st, op,
                        (const T*)in, (T*)out, (const T*)S.dinv, (T)S.dinv_s,
                        (const T*)S.vec[V_RHAT], S.n, S.rtiles, nwork, S.sc, S.partials, fin_mode,
@@ -899,7 +913,8 @@ void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st) {
     const int g = rr_grid(S);
     hipLaunchKernelGGL((k_rr2<T, PC, Op>), dim3(g), dim3(kBlock), 0, st, op, (const T*)S.vec[V_K],
                        (const T*)S.vec[V_L], (T*)S.vec[V_W], (T*)S.vec[V_Z], (T*)S.vec[V_TMP],
-                       (const T*)S.vec[V_RHAT], (const T*)S.vec[V_R], (const T*)S.vec[V_S], S.n,
+                       pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : (T*)nullptr,
+                       (const T*)S.dinv, (const T*)S.vec[V_RHAT], (const T*)S.vec[V_R], (const T*)S.vec[V_S], S.n,
                        S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk);
   });
 }

@@ -25,6 +25,7 @@ struct PhaseAArgs {
   T* __restrict__ l;
   T* __restrict__ z;
   const T* __restrict__ zsave;     // pre-replacement z_{i-1} (when a replacement preceded)
+  T* __restrict__ pm;               // n_i = M^-1 z_i for the next product, or null
   const T* __restrict__ dinv;
   T dinv_s;
 };
@@ -123,6 +124,14 @@ __device__ __forceinline__ void phaseA_update(const PhaseAArgs<T>& A, int64_t i,
   stc<T, C, NT>(A.g + i, R.g); stc<T, C, NT>(A.s + i, R.s); stc<T, C, NT>(A.l + i, R.l);
   stc<T, C, NT>(A.z + i, R.z);
   if (FUSE) stc<T, C, NT>(A.t + i, R.t);
+  if constexpr (!FUSE && PC == PC_VECTOR) {
+    if (A.pm) {                       // n_i = M^-1 z_i, the next product's input
+      T pn[C];
+#pragma unroll
+      for (int e = 0; e < C; ++e) pn[e] = R.d[e] * R.z[e];
+      stc<T, C, NT>(A.pm + i, pn);
+    }
+  }
 }
 
 // Inputs of the prologue's GLRED 2 step, loaded at kernel entry
@@ -263,6 +272,7 @@ struct PhaseBArgs {
   T* __restrict__ r;
   T* __restrict__ k;
   T* __restrict__ w;
+  T* __restrict__ pm;               // m_{i+1} = M^-1 w_{i+1} for the next product, or null
   const T* __restrict__ dinv;
   T dinv_s;
 };
@@ -359,6 +369,14 @@ __device__ __forceinline__ void phaseB_update(const PhaseBArgs<T>& B, int64_t i,
   stc<T, C, NT>(B.r + i, R.r); stc<T, C, NT>(B.k + i, R.k); stc<T, C, NT>(B.w + i, R.w);
   stc<double, C, NT>(B.x + i, R.x);
   if (FUSE) stc<T, C, NT>(B.v + i, R.v);
+  if constexpr (!FUSE && PC == PC_VECTOR) {
+    if (B.pm) {                       // m_{i+1} = M^-1 w_{i+1}, the next product's input
+      T pw[C];
+#pragma unroll
+      for (int e = 0; e < C; ++e) pw[e] = R.d[e] * R.w[e];
+      stc<T, C, NT>(B.pm + i, pw);
+    }
+  }
 }
 
 // STAGED: phase A ran the previous GLRED 2 final in its prologue and left
@@ -590,6 +608,7 @@ static void phaseA_t(Solver& S, bool tr, bool pro, hipStream_t st) {
   a.r = (const T*)S.vec[V_R]; a.v = (const T*)S.vec[V_V];
   a.g = (T*)S.vec[V_G]; a.s = (T*)S.vec[V_S]; a.l = (T*)S.vec[V_L]; a.z = (T*)S.vec[V_Z];
   a.zsave = (const T*)S.vec[V_TMP];
+  a.pm = pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : nullptr;
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
   const int kind = fused_kind(S, tr);
   const StParams<T> P = st_params<T>(S, op_of(S, tr));
@@ -625,6 +644,7 @@ static void phaseB_t(Solver& S, bool tr, bool staged, hipStream_t st) {
   a.z = (const T*)S.vec[V_Z]; a.t = (const T*)S.vec[V_T]; a.v = (T*)S.vec[V_V];
   a.rhat = (const T*)S.vec[V_RHAT];
   a.r = (T*)S.vec[V_R]; a.k = (T*)S.vec[V_K]; a.w = (T*)S.vec[V_W];
+  a.pm = pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : nullptr;
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
   const int kind = fused_kind(S, tr);
   const StParams<T> P = st_params<T>(S, op_of(S, tr));

@@ -72,6 +72,7 @@ struct Solver {
   int mu_row = 1, mu_col = 1;   // max stored entries per row / per column
   bool spmv_tiled = true;       // several consecutive rows per thread for structured operators
   bool fuse = true;             // phase kernels compute the SPMVs of structured operators
+  bool premult = true;          // sliced-ELL products read V_PM (pre_multiplied)
   bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
   int march_zlen = 0;           // planes per work item of k_spmv_st3m (0: sized to the grid)
   int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
@@ -86,7 +87,9 @@ struct Solver {
 };
 
 enum VecId : int {
-  V_RHAT = 0, V_R, V_G, V_S, V_L, V_Z, V_K, V_W, V_T, V_V, V_TMP, V_COUNT
+  V_RHAT = 0, V_R, V_G, V_S, V_L, V_Z, V_K, V_W, V_T, V_V, V_TMP,
+  V_PM,       // M^-1 of the next product's input (sliced ELL with a Jacobi vector)
+  V_COUNT
 };
 
 // Parameters of a structured operator (stencil or DIA5) for the kernels.
@@ -125,8 +128,18 @@ int fused_kind(Solver& S, bool transpose);
 // a GLRED final on its own (one block, or one block per sum beyond eight)
 void launch_fin(Solver& S, int fin_mode, hipStream_t st);
 void launch_init_res(Solver& S, bool tr, hipStream_t st);
+// out = A M^-1 in; with `pre` the input already holds M^-1 applied (V_PM)
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,
-                 hipStream_t st);
+                 hipStream_t st, bool pre = false);
+// Whether the iteration's two products read V_PM, the copy of their input
+// multiplied by the Jacobi vector that phase A, phase B and the replacement
+// write beside z and w: sliced ELL with a Jacobi vector, whose product would
+// otherwise gather dinv_j beside every z_j (measured: the 2e6 x 27 random
+// matrix's product 365 -> ~235 us in FP64).  The products are bitwise those
+// of the gathering form (the same multiplication dinv_j * z_j, done once).
+bool pre_multiplied(Solver& S, bool transpose);
+// the iteration's product on z (V_Z -> V_V) or w (V_W -> V_T)
+void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode, hipStream_t st);
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_true_res(Solver& S, bool tr, hipStream_t st);
