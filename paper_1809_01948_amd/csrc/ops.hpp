@@ -26,7 +26,10 @@ struct SellOp {
   const int64_t* __restrict__ sptr;
   const int32_t* __restrict__ col;
   const T* __restrict__ val;
-  static constexpr int kGroup = 8;   // entries whose loads are issued together
+  // entries whose loads are issued together: nine (the 2e6 x 27 random
+  // matrix's product 231 -> 212 us against eight; sixteen, or eight waves per
+  // SIMD, were slower: the gathers' L1 hit rate falls)
+  static constexpr int kGroup = 9;
   template <class Vis>
   __device__ __forceinline__ void row(int64_t i, Vis& vis) const {
     const int64_t s = i >> 6;
