@@ -68,6 +68,48 @@ __device__ __forceinline__ void phaseA_issue(const PhaseAArgs<T>& A, int64_t i, 
   if (PC == PC_VECTOR) ldc<T, C, NT>(A.dinv + i, R.d);
 }
 
+// The first tile of a phase A with the GLRED 2 prologue: its eight streams
+// k, w, r, v, g, s, l, z are loaded straight into LDS (16-byte global-to-LDS
+// loads, no registers held) before the prologue's reduction, so the
+// reduction and the tile's loads overlap.  LDS: one 4 KiB slab per stream,
+// lane l of wave v at byte 1024 v + 16 l (the order the loads write).
+constexpr int kPfArrays = 8;
+constexpr int kPfBytes = kPfArrays * kBlock * 16;
+
+template <typename T>
+__device__ __forceinline__ void phaseA_prefetch(const PhaseAArgs<T>& A, int64_t i, char* pf) {
+  char* wave = pf + (threadIdx.x >> 6) * 1024;
+  const T* src[kPfArrays] = {A.k, A.w, A.r, A.v, A.g, A.s, A.l, A.z};
+#pragma unroll
+  for (int a = 0; a < kPfArrays; ++a)
+    __builtin_amdgcn_global_load_lds((const void*)(src[a] + i),
+                                     (__attribute__((address_space(3))) void*)(wave + a * kBlock * 16),
+                                     16, 0, 0);
+}
+
+// waits for the prefetch (vmcnt counts it) before the LDS copies are read
+__device__ __forceinline__ void prefetch_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// the prefetched streams from LDS, then the loads that were not prefetched
+template <typename T, int PC, bool NT, int KIND, bool SAVED>
+__device__ __forceinline__ void phaseA_take(const PhaseAArgs<T>& A, int64_t i, const char* pf,
+                                            ATile<T>& R) {
+  constexpr int C = V16<T>::n;
+  typedef typename V16<T>::type VT;
+  prefetch_wait();
+  const char* me = pf + threadIdx.x * 16;
+  T* dst[kPfArrays] = {R.k, R.w, R.r, R.v, R.g, R.s, R.l, R.z};
+#pragma unroll
+  for (int a = 0; a < kPfArrays; ++a) {
+    const VT x = *reinterpret_cast<const VT*>(me + a * kBlock * 16);
+#pragma unroll
+    for (int e = 0; e < C; ++e) dst[a][e] = x[e];
+  }
+  if (KIND == 0) ldc<T, C, NT>(A.t + i, R.t);
+  if (SAVED) ldc<T, C, NT>(A.zsave + i, R.zp);
+  if (PC == PC_VECTOR) ldc<T, C, NT>(A.dinv + i, R.d);
+}
+
 // m = M^-1 w of one chunk and, fused, t = A m from the neighbours of w
 template <typename T, int PC, int KIND>
 __device__ __forceinline__ void phaseA_stencil(const PhaseAArgs<T>& A, const StParams<T>& P,
@@ -184,16 +226,18 @@ __device__ __forceinline__ bool phaseA_prologue(DevScalars* __restrict__ sc, con
 }
 
 // Phase A over the block's chunks
-template <typename T, int PC, bool NT, bool AUTO, int KIND, bool SAVED>
+template <typename T, int PC, bool NT, bool AUTO, int KIND, bool SAVED, bool PF>
 __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StParams<T>& P, int64_t n,
                                             double* __restrict__ partials, int64_t ntiles,
-                                            double alpha, double beta, double omega_prev) {
+                                            double alpha, double beta, double omega_prev,
+                                            const char* pf) {
   constexpr int C = V16<T>::n;
   XcdWalk it(ntiles, blockIdx.x, gridDim.x);
   auto row = [&](int64_t t) { return (t * kBlock + threadIdx.x) * C; };
   ATile<T> R;
   if (it.t < it.end) {
-    phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
+    if constexpr (PF) phaseA_take<T, PC, NT, KIND, SAVED>(A, row(it.t), pf, R);
+    else phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
     phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
   }
   const T a = (T)alpha, b = (T)beta, wp = (T)omega_prev;
@@ -235,6 +279,14 @@ __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> 
                                                    DevScalars* __restrict__ sc,
                                                    double* __restrict__ partials, int64_t ntiles) {
   static_assert(!(PRO && AUTO), "the prologue final serves the periodic strategy only");
+  // the first tile goes to LDS ahead of the prologue (cached streams only)
+  constexpr bool PF = PRO && !NT;
+  __shared__ __attribute__((aligned(16))) char pf[PF ? kPfBytes : 16];
+  if constexpr (PF) {
+    const XcdWalk first(ntiles, blockIdx.x, gridDim.x);
+    if (first.t < first.end)
+      phaseA_prefetch<T>(A, (first.t * kBlock + threadIdx.x) * V16<T>::n, pf);
+  }
   // the scalars are loaded with the done flag (one round trip, not two)
   const int done = sc->done, n_saved = sc->n_saved;
   double alpha = sc->alpha, beta = sc->beta, omega_prev = sc->omega_prev;
@@ -249,14 +301,19 @@ __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> 
     in.its = sc->iter + 1; in.maxit = sc->maxit;
     const int sl[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
     slot_loads<5>(partials, sl, in.pp);
-    if (!phaseA_prologue(sc, in, alpha, beta, omega_prev)) return;
+    if (!phaseA_prologue(sc, in, alpha, beta, omega_prev)) {
+      if constexpr (PF) prefetch_wait();      // no LDS write may land after the block ends
+      return;
+    }
   } else {
     if (done) return;
   }
   if (n_saved)
-    phaseA_body<T, PC, NT, AUTO, KIND, true>(A, P, n, partials, ntiles, alpha, beta, omega_prev);
+    phaseA_body<T, PC, NT, AUTO, KIND, true, PF>(A, P, n, partials, ntiles, alpha, beta,
+                                                  omega_prev, pf);
   else
-    phaseA_body<T, PC, NT, AUTO, KIND, false>(A, P, n, partials, ntiles, alpha, beta, omega_prev);
+    phaseA_body<T, PC, NT, AUTO, KIND, false, PF>(A, P, n, partials, ntiles, alpha, beta,
+                                                   omega_prev, pf);
 }
 
 template <typename T>
