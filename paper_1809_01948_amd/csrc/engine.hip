@@ -478,10 +478,15 @@ DevScalars run_iterations(Solver& S, bool tr, int start, const pbcg_opts& o) {
   // long (the early-exit launches after convergence cost ~1 us each)
   int K = o.check_every > 0 ? o.check_every : (o.use_graph ? 32 : 8);
   if (o.use_graph && o.rr_period > 0 && !o.rr_auto) {
-    // chunk length dividing the replacement period keeps the captured variants few
+    // chunk length dividing the replacement period keeps the captured variants
+    // few: by default the longest such chunk up to 64 iterations (1000^2
+    // Poisson, every 50: 39.6 -> 39.3 ms per 1000 iterations against 25),
+    // else the divisor closest to the requested polling interval
     int best = 1;
     for (int d = 1; d <= std::min(o.rr_period, 64); ++d)
-      if (o.rr_period % d == 0 && std::abs(d - K) < std::abs(best - K)) best = d;
+      if (o.rr_period % d == 0 &&
+          (o.check_every > 0 ? std::abs(d - K) < std::abs(best - K) : d > best))
+        best = d;
     K = best;
   }
   int it = start;
