@@ -248,6 +248,9 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream);
  * time those kernels (phase B then includes the GLRED 1 final), 1 a
  * stand-alone GLRED 1 final for reference, 3 the GLRED 2 final kernel, 4
  * phase A + phase B + GLRED 2 final, and 6 the stand-alone product.
+ * With a sliced-ELL matrix and a Jacobi vector the products 1, 3 and 6 read
+ * the copy of their input that the phase kernels have already multiplied by
+ * M^-1 (as the iteration does), not z or w and dinv.
  * The solver vectors are overwritten (run it after, not between, the solves
  * whose results are needed); every later solve reinitialises them.
  */
