@@ -121,6 +121,7 @@ void common_setup(Solver& S, int precision, int precond) {
   if (const char* env = std::getenv("PBCG_SPMV_TILED")) S.spmv_tiled = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_FUSE")) S.fuse = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_MARCH3D")) S.march3d = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_MARCH_PHASE")) S.march_phase = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_PREMULT")) S.premult = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_MARCH_ZLEN")) S.march_zlen = std::atoi(env);
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");

@@ -53,14 +53,17 @@ template <typename T>
 struct ATile {
   static constexpr int C = V16<T>::n;
   T k[C], w[C], t[C], r[C], v[C], g[C], s[C], l[C], z[C], zp[C], d[C], m[C];
+  T pd[C], pu[C];     // plane march, 3D: w a plane below and above (as stored)
 };
 
 // the loads of one chunk
 template <typename T, int PC, bool NT, int KIND, bool SAVED>
-__device__ __forceinline__ void phaseA_issue(const PhaseAArgs<T>& A, int64_t i, ATile<T>& R) {
+__device__ __forceinline__ void phaseA_issue(const PhaseAArgs<T>& A, int64_t i, ATile<T>& R,
+                                             bool have_w = false) {
   constexpr int C = V16<T>::n;
   constexpr bool FUSE = KIND != 0;
-  ldc<T, C, NT>(A.k + i, R.k); ldc<T, C, NT && !FUSE>(A.w + i, R.w);
+  ldc<T, C, NT>(A.k + i, R.k);
+  if (!have_w) ldc<T, C, NT && !FUSE>(A.w + i, R.w);
   if (!FUSE) ldc<T, C, NT>(A.t + i, R.t);
   ldc<T, C, NT>(A.r + i, R.r); ldc<T, C, NT>(A.v + i, R.v); ldc<T, C, NT>(A.g + i, R.g);
   ldc<T, C, NT>(A.s + i, R.s); ldc<T, C, NT>(A.l + i, R.l); ldc<T, C, NT>(A.z + i, R.z);
@@ -110,6 +113,28 @@ __device__ __forceinline__ void phaseA_take(const PhaseAArgs<T>& A, int64_t i, c
   if (PC == PC_VECTOR) ldc<T, C, NT>(A.dinv + i, R.d);
 }
 
+// Whether a phase kernel can march (3D products fused, or none fused: the
+// separate-product kernels follow the same order); the 2D kernels keep the
+// row order compiled in
+template <int KIND>
+__device__ __forceinline__ constexpr bool marchable() {
+  return KIND == OP_ST3D7 || KIND == 0;
+}
+template <int KIND, typename T>
+__device__ __forceinline__ auto tile_seq(int64_t ntiles, int C, const StParams<T>& P) {
+  if constexpr (marchable<KIND>()) return TileSeq(ntiles, C, P.nx, P.ny, P.nz, P.mz);
+  else return RowSeq(ntiles, C);
+}
+
+// Whether a phase kernel computes a 3D product with the planes below and
+// above in registers: plane march over a 3D grid, the product fused (a 3D
+// stencil's Jacobi scale is a scalar, never a vector)
+template <int KIND, int PC, typename T>
+__device__ __forceinline__ bool march_fused(const StParams<T>& P) {
+  if constexpr (KIND == OP_ST3D7 && PC != PC_VECTOR) return P.mz > 0;
+  return false;
+}
+
 // m = M^-1 w of one chunk and, fused, t = A m from the neighbours of w
 template <typename T, int PC, int KIND>
 __device__ __forceinline__ void phaseA_stencil(const PhaseAArgs<T>& A, const StParams<T>& P,
@@ -121,13 +146,43 @@ __device__ __forceinline__ void phaseA_stencil(const PhaseAArgs<T>& A, const StP
     R.m[e] = (PC == PC_NONE) ? R.w[e] : de * R.w[e];
   }
   if constexpr (KIND != 0) {
-    if (i < n) {
+    if (march_fused<KIND, PC>(P)) {
+      // plane march: the planes below and above come from registers
+      T xd[C], xu[C];
+#pragma unroll
+      for (int e = 0; e < C; ++e) {
+        xd[e] = prec1<T, PC>(R.pd[e], nullptr, A.dinv_s, 0);
+        xu[e] = prec1<T, PC>(R.pu[e], nullptr, A.dinv_s, 0);
+      }
+      st_apply3_planes<T, PC>(P, A.w, A.dinv, A.dinv_s, (int)i, xd, R.m, xu, R.t);
+    } else if (i < n) {
       st_apply<T, PC, KIND, 1>(P, A.w, A.dinv, A.dinv_s, (int)i, R.m, R.t);
     } else {
 #pragma unroll
       for (int e = 0; e < C; ++e) R.t[e] = T(0);          // padding rows stay zero
     }
   }
+}
+
+// Plane march over a 3D grid with the product fused: w of the tile a plane
+// below and above.  A tile that continues its item takes its own w and the
+// plane below from the previous tile's registers (`have_w`), so each plane
+// of w is loaded once per item, plus the plane before it.
+template <typename T>
+__device__ __forceinline__ void march_rotate(T (&w)[V16<T>::n], T (&pd)[V16<T>::n],
+                                             T (&pu)[V16<T>::n]) {
+#pragma unroll
+  for (int e = 0; e < V16<T>::n; ++e) {
+    pd[e] = w[e];
+    w[e] = pu[e];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void march_planes(const T* __restrict__ w, const TileSeq& it,
+                                             T (&pd)[V16<T>::n], T (&pu)[V16<T>::n]) {
+  constexpr int C = V16<T>::n;
+  if (!it.cont && it.k > 0) ldc<T, C, false>(w + it.row() - it.nxy, pd);
+  if (it.k < it.nz - 1) ldc<T, C, false>(w + it.row() + it.nxy, pu);
 }
 
 // the recurrences of one chunk and their partials
@@ -232,24 +287,28 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StPara
                                             double alpha, double beta, double omega_prev,
                                             const char* pf) {
   constexpr int C = V16<T>::n;
-  XcdWalk it(ntiles, blockIdx.x, gridDim.x);
-  auto row = [&](int64_t t) { return (t * kBlock + threadIdx.x) * C; };
+  auto it = tile_seq<KIND>(ntiles, C, P);
+  const bool mw = march_fused<KIND, PC>(P);      // fused 3D product, planes in registers
   ATile<T> R;
-  if (it.t < it.end) {
-    if constexpr (PF) phaseA_take<T, PC, NT, KIND, SAVED>(A, row(it.t), pf, R);
-    else phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
-    phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
+  if (it.valid() && it.has) {
+    if constexpr (PF) phaseA_take<T, PC, NT, KIND, SAVED>(A, it.row(), pf, R);
+    else phaseA_issue<T, PC, NT, KIND, SAVED>(A, it.row(), R);
+    if constexpr (marchable<KIND>()) if (mw) march_planes<T>(A.w, it, R.pd, R.pu);
+    phaseA_stencil<T, PC, KIND>(A, P, n, it.row(), R);
   }
   const T a = (T)alpha, b = (T)beta, wp = (T)omega_prev;
   double acc[12];
 #pragma unroll
   for (int d = 0; d < 12; ++d) acc[d] = 0.0;
-  while (it.t < it.end) {
-    phaseA_update<T, PC, NT, AUTO, KIND, SAVED>(A, row(it.t), R, a, b, wp, acc);
-    it.t += it.step;
-    if (it.t < it.end) {
-      phaseA_issue<T, PC, NT, KIND, SAVED>(A, row(it.t), R);
-      phaseA_stencil<T, PC, KIND>(A, P, n, row(it.t), R);
+  while (it.valid()) {
+    if (it.has) phaseA_update<T, PC, NT, AUTO, KIND, SAVED>(A, it.row(), R, a, b, wp, acc);
+    it.next();
+    if (it.valid() && it.has) {
+      const bool carry = mw && it.cont;
+      if (carry) march_rotate<T>(R.w, R.pd, R.pu);
+      phaseA_issue<T, PC, NT, KIND, SAVED>(A, it.row(), R, carry);
+      if constexpr (marchable<KIND>()) if (mw) march_planes<T>(A.w, it, R.pd, R.pu);
+      phaseA_stencil<T, PC, KIND>(A, P, n, it.row(), R);
     }
   }
   if (AUTO) {
@@ -283,9 +342,8 @@ __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> 
   constexpr bool PF = PRO && !NT;
   __shared__ __attribute__((aligned(16))) char pf[PF ? kPfBytes : 16];
   if constexpr (PF) {
-    const XcdWalk first(ntiles, blockIdx.x, gridDim.x);
-    if (first.t < first.end)
-      phaseA_prefetch<T>(A, (first.t * kBlock + threadIdx.x) * V16<T>::n, pf);
+    const auto first = tile_seq<KIND>(ntiles, V16<T>::n, P);
+    if (first.valid() && first.has) phaseA_prefetch<T>(A, first.row(), pf);
   }
   // the scalars are loaded with the done flag (one round trip, not two)
   const int done = sc->done, n_saved = sc->n_saved;
@@ -355,15 +413,18 @@ struct BTile {
   static constexpr int C = V16<T>::n;
   T g[C], l[C], s[C], z[C], t[C], v[C], rh[C], r[C], k[C], w[C], d[C], n[C];
   double x[C];
+  T pd[C], pu[C];     // plane march, 3D: z a plane below and above (as stored)
 };
 
 // the loads of one chunk
 template <typename T, int PC, bool NT, int KIND>
-__device__ __forceinline__ void phaseB_issue(const PhaseBArgs<T>& B, int64_t i, BTile<T>& R) {
+__device__ __forceinline__ void phaseB_issue(const PhaseBArgs<T>& B, int64_t i, BTile<T>& R,
+                                             bool have_z = false) {
   constexpr int C = V16<T>::n;
   constexpr bool FUSE = KIND != 0;
   ldc<T, C, NT>(B.g + i, R.g); ldc<T, C, NT>(B.l + i, R.l); ldc<T, C, NT>(B.s + i, R.s);
-  ldc<T, C, NT && !FUSE>(B.z + i, R.z); ldc<T, C, NT>(B.t + i, R.t);
+  if (!have_z) ldc<T, C, NT && !FUSE>(B.z + i, R.z);
+  ldc<T, C, NT>(B.t + i, R.t);
   if (!FUSE) ldc<T, C, NT>(B.v + i, R.v);
   ldc<T, C, NT>(B.rhat + i, R.rh); ldc<T, C, NT>(B.r + i, R.r); ldc<T, C, NT>(B.k + i, R.k);
   ldc<T, C, NT>(B.w + i, R.w);
@@ -382,7 +443,15 @@ __device__ __forceinline__ void phaseB_stencil(const PhaseBArgs<T>& B, const StP
     R.n[e] = (PC == PC_NONE) ? R.z[e] : de * R.z[e];
   }
   if constexpr (KIND != 0) {
-    if (i < nrows) {
+    if (march_fused<KIND, PC>(P)) {
+      T xd[C], xu[C];
+#pragma unroll
+      for (int e = 0; e < C; ++e) {
+        xd[e] = prec1<T, PC>(R.pd[e], nullptr, B.dinv_s, 0);
+        xu[e] = prec1<T, PC>(R.pu[e], nullptr, B.dinv_s, 0);
+      }
+      st_apply3_planes<T, PC>(P, B.z, B.dinv, B.dinv_s, (int)i, xd, R.n, xu, R.v);
+    } else if (i < nrows) {
       st_apply<T, PC, KIND, 1>(P, B.z, B.dinv, B.dinv_s, (int)i, R.n, R.v);
     } else {
 #pragma unroll
@@ -455,13 +524,16 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> 
     __syncthreads();
   }
   if (done) return;
-  XcdWalk it(ntiles, blockIdx.x, gridDim.x);
+  auto it = tile_seq<KIND>(ntiles, C, P);
+  const bool mw = march_fused<KIND, PC>(P);      // fused 3D product, planes in registers
   BTile<T> R;
-  auto row = [&](int64_t t) { return (t * kBlock + threadIdx.x) * C; };
-  const bool any = it.t < it.end;
+  const bool any = it.valid() && it.has;
   // The first chunk's loads do not depend on omega: they go out together
   // with the loads of the GLRED 1 partials (one memory round trip for both).
-  if (any) phaseB_issue<T, PC, NT, KIND>(B, row(it.t), R);
+  if (any) {
+    phaseB_issue<T, PC, NT, KIND>(B, it.row(), R);
+    if constexpr (marchable<KIND>()) if (mw) march_planes<T>(B.z, it, R.pd, R.pu);
+  }
   if constexpr (KIND != 0) {
     // GLRED 1 final (omega_i = (q_i, y_i) / (y_i, y_i)), reduced by every
     // block from phase A's partials with the fixed-order tree of
@@ -471,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> 
     const int sl[2] = {SL_QY, SL_YY};
     double pp[2][kSlotStrides], ts[2], v[2];
     slot_loads<2>(partials, sl, pp);
-    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, row(it.t), R);
+    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, it.row(), R);
     slot_thread_sums<2>(pp, gridDim.x, ts);
     block_tree<2>(ts, v);
     const bool bad = !finite(v[0]) || !finite(v[1]);
@@ -485,17 +557,20 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> 
     }
     if (bad) return;
   } else {
-    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, row(it.t), R);
+    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, it.row(), R);
   }
   double acc[9];
 #pragma unroll
   for (int d = 0; d < 9; ++d) acc[d] = 0.0;
-  while (it.t < it.end) {
-    phaseB_update<T, PC, NT, AUTO, KIND>(B, row(it.t), R, alpha, omega, acc);
-    it.t += it.step;
-    if (it.t < it.end) {
-      phaseB_issue<T, PC, NT, KIND>(B, row(it.t), R);
-      phaseB_stencil<T, PC, KIND>(B, P, nrows, row(it.t), R);
+  while (it.valid()) {
+    if (it.has) phaseB_update<T, PC, NT, AUTO, KIND>(B, it.row(), R, alpha, omega, acc);
+    it.next();
+    if (it.valid() && it.has) {
+      const bool carry = mw && it.cont;
+      if (carry) march_rotate<T>(R.z, R.pd, R.pu);
+      phaseB_issue<T, PC, NT, KIND>(B, it.row(), R, carry);
+      if constexpr (marchable<KIND>()) if (mw) march_planes<T>(B.z, it, R.pd, R.pu);
+      phaseB_stencil<T, PC, KIND>(B, P, nrows, it.row(), R);
     }
   }
   if (AUTO) {
@@ -668,7 +743,8 @@ static void phaseA_t(Solver& S, bool tr, bool pro, hipStream_t st) {
   a.pm = pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : nullptr;
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
   const int kind = fused_kind(S, tr);
-  const StParams<T> P = st_params<T>(S, op_of(S, tr));
+  StParams<T> P = st_params<T>(S, op_of(S, tr));
+  P.mz = phase_march_planes(S, tr);
   const int64_t nt = S.npad / (kBlock * V16<T>::n);
   const bool ntm = (S.vnt & 1) != 0;
   with_fused_kind<PC>(kind, [&](auto kc) {
@@ -704,7 +780,8 @@ static void phaseB_t(Solver& S, bool tr, bool staged, hipStream_t st) {
   a.pm = pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : nullptr;
   a.dinv = (const T*)S.dinv; a.dinv_s = (T)S.dinv_s;
   const int kind = fused_kind(S, tr);
-  const StParams<T> P = st_params<T>(S, op_of(S, tr));
+  StParams<T> P = st_params<T>(S, op_of(S, tr));
+  P.mz = phase_march_planes(S, tr);
   const int64_t nt = S.npad / (kBlock * V16<T>::n);
   const bool ntm = (S.vnt & 2) != 0;
   with_fused_kind<PC>(kind, [&](auto kc) {

@@ -178,6 +178,83 @@ struct StParams {
   T c[7];            // constant coefficients (ascending column order)
   const T* __restrict__ dia;
   int64_t ld;
+  int mz;            // phase kernels: planes per work item of the plane march (0: row order)
+};
+
+// The order in which a phase kernel's block visits its tiles.  Row order
+// (mz == 0): tiles of kBlock * C consecutive rows, XCD-aware (XcdWalk).
+// Plane march (3D grids): work items (z-chunk of mz planes, segment of
+// kBlock * C rows of one plane), XCD-aware over the items, an item's planes
+// in ascending order, so that a tile's neighbours a plane away are the
+// previous and next tiles of the same item; in the last segment of a plane
+// the threads past the plane's end have no row (`has`).
+struct TileSeq {
+  int64_t t, end, step;    // tiles (row order) or items (march) of this block
+  int64_t r;               // this thread's first row of the current tile
+  int mz, nz, nxy, ncol, seg, k, z1;
+  bool has;
+  bool cont;               // march: this tile is the next plane of the previous tile's item
+  __device__ TileSeq(int64_t ntiles, int C, int nx, int ny, int nz_, int mz_) {
+    mz = mz_;
+    nz = nz_;
+    seg = kBlock * C;
+    if (mz > 0) {
+      nxy = nx * ny;
+      ncol = (nxy + seg - 1) / seg;
+      const int64_t items = (int64_t)ncol * ((nz + mz - 1) / mz);
+      const XcdWalk w(items, blockIdx.x, gridDim.x);
+      t = w.t; end = w.end; step = w.step;
+      if (t < end) start_item();
+    } else {
+      const XcdWalk w(ntiles, blockIdx.x, gridDim.x);
+      t = w.t; end = w.end; step = w.step;
+      r = (t * kBlock + threadIdx.x) * C;
+      has = true;
+    }
+    cont = false;
+  }
+  __device__ void start_item() {
+    const int zc = (int)(t / ncol);
+    const int c = (int)(t - (int64_t)zc * ncol);
+    const int off = c * seg + (int)threadIdx.x * (seg / kBlock);
+    k = zc * mz;
+    z1 = k + mz < nz ? k + mz : nz;
+    has = off < nxy;
+    r = (int64_t)k * nxy + off;
+    cont = false;
+  }
+  __device__ int64_t row() const { return r; }
+  __device__ bool valid() const { return t < end; }
+  __device__ void next() {
+    if (mz > 0) {
+      if (++k < z1) {
+        r += nxy;
+        cont = true;
+        return;
+      }
+      t += step;
+      if (t < end) start_item();
+    } else {
+      t += step;
+      r += (int64_t)step * seg;
+    }
+  }
+};
+
+// Row order alone (the kernels that never march: 2D and DIA5 products), the
+// interface of TileSeq with the row computed from the tile index
+struct RowSeq {
+  int64_t t, end, step;
+  int C;
+  static constexpr bool has = true;
+  static constexpr bool cont = false;
+  __device__ RowSeq(int64_t ntiles, int C_) : C(C_) {
+    const XcdWalk w(ntiles, blockIdx.x, gridDim.x);
+    t = w.t; end = w.end; step = w.step;
+  }
+  __device__ int64_t row() const { return (t * kBlock + threadIdx.x) * C; }
+  __device__ bool valid() const { return t < end; }
+  __device__ void next() { t += step; }
 };
 
 // One row of a structured operator applied to preconditioned values: the
@@ -303,6 +380,44 @@ __device__ __forceinline__ void st_apply(const StParams<T>& P, const T* __restri
                                  KIND == OP_DIA5 ? cS[e] : T(0), KIND == OP_DIA5 ? cW[e] : T(0),
                                  KIND == OP_DIA5 ? cC[e] : T(0), KIND == OP_DIA5 ? cE[e] : T(0),
                                  KIND == OP_DIA5 ? cN[e] : T(0));
+  }
+}
+
+// The 3D 7-point product of one chunk whose neighbours a plane below and
+// above are given (preconditioned, xd and xu: the plane march carries them in
+// registers); the grid-line and row neighbours are loaded as in st_apply.
+// Sums through st_row_sum, so the result equals st_apply's bit for bit.
+template <typename T, int PC>
+__device__ __forceinline__ void st_apply3_planes(const StParams<T>& P, const T* __restrict__ z,
+                                                 const T* __restrict__ dinv, T ds, int p,
+                                                 const T (&xd)[V16<T>::n],
+                                                 const T (&xc)[V16<T>::n],
+                                                 const T (&xu)[V16<T>::n],
+                                                 T (&res)[V16<T>::n]) {
+  constexpr int R = V16<T>::n;
+  const int nx = P.nx, ny = P.ny, nz = P.nz;
+  const int nxy = nx * ny;
+  const int iz = p / nxy;
+  const int rem = p - iz * nxy;
+  const int iy = rem / nx;
+  const int ix = rem - iy * nx;
+  const bool hS = iy > 0, hN = iy < ny - 1;
+  const bool hD = iz > 0, hU = iz < nz - 1;
+  const bool hW0 = ix > 0, hEl = ix + R < nx;
+  T xs[R], xn[R];
+  load_chunk<T, PC>(z, dinv, ds, hS ? p - nx : p, xs);
+  load_chunk<T, PC>(z, dinv, ds, hN ? p + nx : p, xn);
+  const int jw = hW0 ? p - 1 : p, je = hEl ? p + R : p;
+  const T xw0 = prec1<T, PC>(z[jw], dinv, ds, jw);
+  const T xeR = prec1<T, PC>(z[je], dinv, ds, je);
+#pragma unroll
+  for (int e = 0; e < R; ++e) {
+    const T xw = e == 0 ? xw0 : xc[e - 1];
+    const T xe = e == R - 1 ? xeR : xc[e + 1];
+    const bool vw = e == 0 ? hW0 : true;
+    const bool ve = e == R - 1 ? hEl : true;
+    res[e] = st_row_sum<T, OP_ST3D7>(P, hD, hS, vw, ve, hN, hU, xd[e], xs[e], xw, xc[e], xe,
+                                     xn[e], xu[e], T(0), T(0), T(0), T(0), T(0));
   }
 }
 

@@ -74,6 +74,7 @@ struct Solver {
   bool fuse = true;             // phase kernels compute the SPMVs of structured operators
   bool premult = true;          // sliced-ELL products read V_PM (pre_multiplied)
   bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
+  bool march_phase = true;      // phase kernels visit a 3D grid's tiles plane by plane (TileSeq)
   int march_zlen = 0;           // planes per work item of k_spmv_st3m (0: sized to the grid)
   int64_t vtiles = 0;           // tiles of 256 x (16 bytes / sizeof(T)) elements
   int64_t rtiles = 0;           // tiles of 256 rows
@@ -101,6 +102,7 @@ inline StParams<T> st_params(const Solver& S, const OpData& o) {
   for (int d = 0; d < 7; ++d) P.c[d] = sizeof(T) == 8 ? (T)o.c64[d] : (T)o.c32[d];
   P.dia = (const T*)o.dia;
   P.ld = S.npad;
+  P.mz = 0;
   return P;
 }
 
@@ -125,6 +127,10 @@ const OpData& op_of(Solver& S, bool transpose);
 // The operator kind whose products the phase kernels compute themselves
 // (OP_ST2D5, OP_ST3D7, OP_DIA5), or 0 when the iteration runs separate SPMVs.
 int fused_kind(Solver& S, bool transpose);
+// Planes per work item when the phase kernels march through a 3D grid
+// (TileSeq; 0: row order).  Fused and separate phase kernels use the same
+// count, so their dot products are summed in the same order.
+int phase_march_planes(Solver& S, bool transpose);
 // a GLRED final on its own (one block, or one block per sum beyond eight)
 void launch_fin(Solver& S, int fin_mode, hipStream_t st);
 void launch_init_res(Solver& S, bool tr, hipStream_t st);

@@ -14,7 +14,7 @@ import pytest
 import scipy.sparse as sp
 import torch
 
-from gpu_util import dev, history_buffer, host, oracle_ops, rel, split_history
+from gpu_util import dev, history_buffer, host, oracle_ops, rel, solver_env, split_history
 from oracle import STATUS, Float64Ops, pipelined_bicgstab
 from oracle.adjoint import dense_adjoint_grads, kappa_gradient
 from workloads import (convdiff3d_c3, dia5_from_kappa, dia5_to_csr, inverse_problem_c5,
@@ -63,14 +63,21 @@ def test_c3_small_vectors_and_trace(Solver, c3_64, form):
 
 
 def test_c3_small_stencil_equals_csr(Solver, c3_64):
+    """Bitwise with the phase kernels in row order, as a CSR matrix's are (the
+    phase kernels march through a 3D grid's planes with FP32 storage only, so
+    in FP64 the march switch changes nothing; the last check guards that)."""
     out = {}
-    for form in ("stencil", "csr"):
-        S = Solver.from_problem(c3_64, form=form)
+    for form, march in (("stencil", 0), ("csr", 0), ("stencil", 1)):
+        with solver_env(PBCG_MARCH_PHASE=march):
+            S = Solver.from_problem(c3_64, form=form)
         x, st = S.solve(dev(c3_64.b), tol=0.0, maxit=150, rr_period=50)
-        out[form] = (host(x), st["iterations"])
+        out[(form, march)] = (host(x), st["iterations"], st["rel_res_true"])
         S.close()
-    assert out["stencil"][1] == out["csr"][1] == 150
-    assert np.array_equal(out["stencil"][0], out["csr"][0])
+    assert out[("stencil", 0)][1] == out[("csr", 0)][1] == out[("stencil", 1)][1] == 150
+    assert np.array_equal(out[("stencil", 0)][0], out[("csr", 0)][0])
+    # marching: a different summation order, the same convergence
+    rm, rr = out[("stencil", 1)][2], out[("csr", 0)][2]
+    assert rm <= max(10.0 * rr, 1e-12) and rr <= max(10.0 * rm, 1e-12)
 
 
 @pytest.fixture(scope="module")
@@ -83,14 +90,16 @@ def test_full_size_structured_equals_csr(Solver, c3_full, case):
     """At full size the structured SPMV gives each thread two 16-byte chunks
     of a grid line; its products are still bitwise those of the row-wise CSR
     kernel (same ascending column order), so three iterations in the two
-    forms agree bit for bit."""
+    forms agree bit for bit (the phase kernels in row order, as a CSR
+    matrix's are)."""
     if case == "c3":
         p, form = c3_full, "stencil"
     else:
         p, form = inverse_problem_c5(2048, with_csr=True), "dia5"
     out = {}
     for f in (form, "csr"):
-        S = Solver.from_problem(p, form=f)
+        with solver_env(PBCG_MARCH_PHASE=0):
+            S = Solver.from_problem(p, form=f)
         x, st = S.solve(dev(p.b), tol=0.0, maxit=3)
         out[f] = (host(x), host(S.get_vector("v")), host(S.get_vector("w")), st["iterations"])
         S.close()
