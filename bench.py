@@ -88,11 +88,16 @@ def kernel_source_hash():
     is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    parts = (("kernels_vec.hip", ("struct PhaseBArgs", "void k_phaseB(", "void k_copy(")),
+    parts = (("kernels_vec.hip", ("struct PhaseBArgs", "struct BTile", "void phaseB_issue(",
+                                  "void phaseB_stencil(", "void phaseB_update(", "void k_phaseB(",
+                                  "void k_copy(", "bool marchable(", "auto tile_seq(",
+                                  "bool march_fused(", "void march_rotate(",
+                                  "void march_planes(")),
              ("common.hpp", ("double wave_sum(", "void block_partials(", "void ld16(",
-                             "void st16(", "void ldc(", "void stc(")),
-             ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "T st_row_sum(",
-                          "void st_apply(")))
+                             "void st16(", "void ldc(", "void stc(", "struct XcdWalk")),
+             ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "struct TileSeq",
+                          "struct RowSeq", "T st_row_sum(", "void st_apply(",
+                          "void st_apply3_planes(")))
     for fname, starts in parts:
         src = open(os.path.join(HERE, "paper_1809_01948_amd/csrc", fname)).read()
         for start in starts:
