@@ -140,6 +140,28 @@ typedef struct {
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*
+ * Tuning switches, read from the environment when a solver is created (for
+ * measurements and tests; the defaults are the measured best choices):
+ *   PBCG_NBLK=n           blocks of the streaming kernels (rounded to a
+ *                         multiple of 8, at most 1024)
+ *   PBCG_SPMV_BLOCKS=n    work blocks of a stand-alone product (at most 2048)
+ *   PBCG_VEC_NT=0..3      non-temporal vector streams (bit 0 phase A, bit 1
+ *                         phase B; default on above 192 MB of vectors)
+ *   PBCG_SPMV_TILED=0|1   structured products on 16-byte chunks of grid lines
+ *   PBCG_FUSE=0|1         structured products inside the phase kernels
+ *   PBCG_MARCH3D=0|1      the stand-alone 3D product marching through planes
+ *   PBCG_MARCH_ZLEN=n     planes per work item of that product (0: sized to
+ *                         the grid)
+ *   PBCG_MARCH_PHASE=0|1  phase kernels visiting a 3D grid plane by plane
+ *                         (FP32 storage only)
+ *   PBCG_PREMULT=0|1      sliced-ELL products reading the M^-1 z, M^-1 w that
+ *                         the phase kernels write (Jacobi vector)
+ *   PBCG_VEC_STAGGER=b    vectors in one allocation, b bytes apart
+ * None changes a result bit except PBCG_NBLK and PBCG_MARCH_PHASE, which set
+ * the order in which the dot products are summed.
+ */
+
+/*
  * Create a solver for a CSR matrix (Section 1: A sparse, N x N).
  *   n, nnz          : dimension and number of stored entries (n >= 1)
  *   rowptr, col, val: host arrays, rowptr[n+1] (rowptr[0] = 0, nondecreasing,
