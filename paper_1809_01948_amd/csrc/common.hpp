@@ -121,9 +121,43 @@ struct alignas(64) DevScalars {
 // reductions
 // ----------------------------------------------------------------------------
 
+// The value of lane (lane ^ OFF), for the xor butterfly below: DPP quad
+// permutations for 1 and 2 (VALU moves), swizzles within 32 lanes for 4, 8
+// and 16 (no address computation), gfx950's permlane32 swap for 32 (after
+// the swap of a register with itself, lanes 0-31 find lane + 32 in the
+// second result and lanes 32-63 find lane - 32 in the first).
+template <int OFF>
+__device__ __forceinline__ double lane_xor(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int plo, phi;
+  if constexpr (OFF == 1 || OFF == 2) {
+    constexpr int ctrl = OFF == 1 ? 0xB1 : 0x4E;        // quad_perm [1,0,3,2] / [2,3,0,1]
+    plo = __builtin_amdgcn_update_dpp(0, lo, ctrl, 0xF, 0xF, false);
+    phi = __builtin_amdgcn_update_dpp(0, hi, ctrl, 0xF, 0xF, false);
+  } else if constexpr (OFF == 4 || OFF == 8 || OFF == 16) {
+    constexpr int pattern = (OFF << 10) | 0x1F;         // bit mode: xor OFF, and 0x1F
+    plo = __builtin_amdgcn_ds_swizzle(lo, pattern);
+    phi = __builtin_amdgcn_ds_swizzle(hi, pattern);
+  } else {
+    static_assert(OFF == 32, "butterfly partners are 1, 2, 4, 8, 16, 32");
+    const auto slo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto shi = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const bool low = (threadIdx.x & 63) < 32;
+    plo = (int)(low ? slo[1] : slo[0]);
+    phi = (int)(low ? shi[1] : shi[0]);
+  }
+  return __hiloint2double(phi, plo);
+}
+
+// Sum over the 64 lanes of a wavefront as an xor butterfly (partners 32, 16,
+// 8, 4, 2, 1): every lane ends with the same bits.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v += lane_xor<32>(v);
+  v += lane_xor<16>(v);
+  v += lane_xor<8>(v);
+  v += lane_xor<4>(v);
+  v += lane_xor<2>(v);
+  v += lane_xor<1>(v);
   return v;
 }
 
