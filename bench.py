@@ -93,8 +93,9 @@ def kernel_source_hash():
                                   "void k_copy(", "bool marchable(", "auto tile_seq(",
                                   "bool march_fused(", "void march_rotate(",
                                   "void march_planes(")),
-             ("common.hpp", ("double wave_sum(", "void block_partials(", "void ld16(",
-                             "void st16(", "void ldc(", "void stc(", "struct XcdWalk")),
+             ("common.hpp", ("double lane_xor(", "double wave_sum(", "void block_partials(",
+                             "void ld16(", "void st16(", "void ldc(", "void stc(",
+                             "struct XcdWalk")),
              ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "struct TileSeq",
                           "struct RowSeq", "T st_row_sum(", "void st_apply(",
                           "void st_apply3_planes(")))
