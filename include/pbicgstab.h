@@ -86,7 +86,9 @@ typedef struct {
                             true residual fails the confirmation.  0 disables it.
                             Ignored by classic_bicgstab_solve. */
   double rr_tau;         /* replacement cutoff; 0 selects sqrt(2^-53) */
-  int32_t check_every;   /* iterations between host polls of the device state (0: default) */
+  int32_t check_every;   /* iterations between host polls of the device state (0: default:
+                            with HIP graphs and periodic replacement as many periods as fit
+                            in 128 iterations, else 32 with graphs and 8 without) */
   int32_t transpose;     /* nonzero: solve A^T x = b (the adjoint system) */
   double* history;       /* optional device buffer of 4*history_len doubles; row i (0-based)
                             holds the scalars of iteration i: ||r_{i+1}||, alpha_i,

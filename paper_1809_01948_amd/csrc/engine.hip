@@ -478,17 +478,27 @@ DevScalars run_iterations(Solver& S, bool tr, int start, const pbcg_opts& o) {
   // with graphs, a graph launch: about 15 us per chunk, so graph chunks are
   // long (the early-exit launches after convergence cost ~1 us each)
   int K = o.check_every > 0 ? o.check_every : (o.use_graph ? 32 : 8);
+  // With periodic replacement a chunk is a whole number of periods or a
+  // divisor of the period, so that one or a few captured variants serve the
+  // whole solve.  By default: as many periods as fit in 128 iterations
+  // (1000^2 Poisson, every 50, ms per 1000 iterations: chunks of 25 39.6, 50
+  // 39.0, 100 38.8, 200 38.75; a longer chunk costs only the early-exit
+  // launches after convergence), for longer periods the longest divisor up to
+  // 64; a requested polling interval is kept if it is a multiple of the
+  // period, else the closest divisor is taken.
   if (o.use_graph && o.rr_period > 0 && !o.rr_auto) {
-    // chunk length dividing the replacement period keeps the captured variants
-    // few: by default the longest such chunk up to 64 iterations (1000^2
-    // Poisson, every 50: 39.6 -> 39.3 ms per 1000 iterations against 25),
-    // else the divisor closest to the requested polling interval
-    int best = 1;
-    for (int d = 1; d <= std::min(o.rr_period, 64); ++d)
-      if (o.rr_period % d == 0 &&
-          (o.check_every > 0 ? std::abs(d - K) < std::abs(best - K) : d > best))
-        best = d;
-    K = best;
+    if (o.check_every > 0 && o.check_every % o.rr_period == 0) {
+      K = o.check_every;
+    } else if (o.check_every <= 0 && o.rr_period <= 128) {
+      K = o.rr_period * (128 / o.rr_period);
+    } else {
+      int best = 1;
+      for (int d = 1; d <= std::min(o.rr_period, 64); ++d)
+        if (o.rr_period % d == 0 &&
+            (o.check_every > 0 ? std::abs(d - K) < std::abs(best - K) : d > best))
+          best = d;
+      K = best;
+    }
   }
   int it = start;
   int chunk = 0;
