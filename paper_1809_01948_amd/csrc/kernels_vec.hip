@@ -79,6 +79,8 @@ __device__ __forceinline__ void phaseA_issue(const PhaseAArgs<T>& A, int64_t i, 
 constexpr int kPfArrays = 8;
 constexpr int kPfBytes = kPfArrays * kBlock * 16;
 
+typedef __attribute__((address_space(3))) void lds_void;   // an LDS address
+
 template <typename T>
 __device__ __forceinline__ void phaseA_prefetch(const PhaseAArgs<T>& A, int64_t i, char* pf) {
   char* wave = pf + (threadIdx.x >> 6) * 1024;
@@ -86,8 +88,7 @@ __device__ __forceinline__ void phaseA_prefetch(const PhaseAArgs<T>& A, int64_t 
 #pragma unroll
   for (int a = 0; a < kPfArrays; ++a)
     __builtin_amdgcn_global_load_lds((const void*)(src[a] + i),
-                                     (__attribute__((address_space(3))) void*)(wave + a * kBlock * 16),
-                                     16, 0, 0);
+                                     (lds_void*)(wave + a * kBlock * 16), 16, 0, 0);
 }
 
 // waits for the prefetch (vmcnt counts it) before the LDS copies are read
