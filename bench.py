@@ -5,12 +5,14 @@ One *step* is one pbicgstab_solve call of 1000 iterations on the 2D Poisson
 workload (1000 x 1000 grid, N = 1e6, 5-point stencil, FP64, Jacobi
 preconditioner, residual replacement every 50 iterations, tolerance 1e-10
 on the relative residual): initialisation, 1000 iterations of Algorithm 2
-(phase A, PREC+SPMV with the GLRED 1 final, phase B, the 20 replacements,
-PREC+SPMV with the GLRED 2 final, the device-side stopping test) and the
-final FP64 true residual.  The tolerance is not reached within 1000
-iterations (the workload needs ~2400 classic or ~3900 pipelined iterations,
-and with replacement every 50 the pipelined iteration does not reach 1e-10
-at all), so every step performs exactly 1000 full iterations.  Full solves
+(two kernels each: phase A with t = A M^-1 w and the previous iteration's
+GLRED 2 step, phase B with v = A M^-1 z and the GLRED 1 step; the 20
+replacements; the device-side stopping test; replayed from HIP graphs in
+chunks of 100 iterations) and the final FP64 true residual.  The tolerance
+is not reached within 1000 iterations (the workload needs ~2400 classic or
+~4900 pipelined iterations with automated replacement, and with replacement
+every 50 the pipelined iteration does not reach 1e-10 at all), so every
+step performs exactly 1000 full iterations.  Full solves
 to 1e-10 are reported separately (`solve_to_tol`).  The right-hand side
 lives in HBM before the timed region starts.
 
