@@ -137,7 +137,7 @@ __device__ __forceinline__ bool march_fused(const StParams<T>& P) {
 }
 
 // m = M^-1 w of one chunk and, fused, t = A m from the neighbours of w
-template <typename T, int PC, int KIND>
+template <typename T, int PC, int KIND, bool NT>
 __device__ __forceinline__ void phaseA_stencil(const PhaseAArgs<T>& A, const StParams<T>& P,
                                                int64_t n, int64_t i, ATile<T>& R) {
   constexpr int C = V16<T>::n;
@@ -157,7 +157,8 @@ __device__ __forceinline__ void phaseA_stencil(const PhaseAArgs<T>& A, const StP
       }
       st_apply3_planes<T, PC>(P, A.w, A.dinv, A.dinv_s, (int)i, xd, R.m, xu, R.t);
     } else if (i < n) {
-      st_apply<T, PC, KIND, 1>(P, A.w, A.dinv, A.dinv_s, (int)i, R.m, R.t);
+      st_apply<T, PC, KIND, 1, NT && sizeof(T) == 8>(P, A.w, A.dinv, A.dinv_s, (int)i, R.m,
+                                                     R.t);
     } else {
 #pragma unroll
       for (int e = 0; e < C; ++e) R.t[e] = T(0);          // padding rows stay zero
@@ -295,7 +296,7 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StPara
     if constexpr (PF) phaseA_take<T, PC, NT, KIND, SAVED>(A, it.row(), pf, R);
     else phaseA_issue<T, PC, NT, KIND, SAVED>(A, it.row(), R);
     if constexpr (marchable<KIND>()) if (mw) march_planes<T>(A.w, it, R.pd, R.pu);
-    phaseA_stencil<T, PC, KIND>(A, P, n, it.row(), R);
+    phaseA_stencil<T, PC, KIND, NT>(A, P, n, it.row(), R);
   }
   const T a = (T)alpha, b = (T)beta, wp = (T)omega_prev;
   double acc[12];
@@ -309,7 +310,7 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StPara
       if (carry) march_rotate<T>(R.w, R.pd, R.pu);
       phaseA_issue<T, PC, NT, KIND, SAVED>(A, it.row(), R, carry);
       if constexpr (marchable<KIND>()) if (mw) march_planes<T>(A.w, it, R.pd, R.pu);
-      phaseA_stencil<T, PC, KIND>(A, P, n, it.row(), R);
+      phaseA_stencil<T, PC, KIND, NT>(A, P, n, it.row(), R);
     }
   }
   if (AUTO) {
@@ -434,7 +435,7 @@ __device__ __forceinline__ void phaseB_issue(const PhaseBArgs<T>& B, int64_t i, 
 }
 
 // n = M^-1 z of one chunk and, fused, v = A n from the neighbours of z
-template <typename T, int PC, int KIND>
+template <typename T, int PC, int KIND, bool NT>
 __device__ __forceinline__ void phaseB_stencil(const PhaseBArgs<T>& B, const StParams<T>& P,
                                                int64_t nrows, int64_t i, BTile<T>& R) {
   constexpr int C = V16<T>::n;
@@ -453,7 +454,8 @@ __device__ __forceinline__ void phaseB_stencil(const PhaseBArgs<T>& B, const StP
       }
       st_apply3_planes<T, PC>(P, B.z, B.dinv, B.dinv_s, (int)i, xd, R.n, xu, R.v);
     } else if (i < nrows) {
-      st_apply<T, PC, KIND, 1>(P, B.z, B.dinv, B.dinv_s, (int)i, R.n, R.v);
+      st_apply<T, PC, KIND, 1, NT && sizeof(T) == 8>(P, B.z, B.dinv, B.dinv_s, (int)i, R.n,
+                                                     R.v);
     } else {
 #pragma unroll
       for (int e = 0; e < C; ++e) R.v[e] = T(0);          // padding rows stay zero
@@ -544,7 +546,7 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> 
     const int sl[2] = {SL_QY, SL_YY};
     double pp[2][kSlotStrides], ts[2], v[2];
     slot_loads<2>(partials, sl, pp);
-    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, it.row(), R);
+    if (any) phaseB_stencil<T, PC, KIND, NT>(B, P, nrows, it.row(), R);
     slot_thread_sums<2>(pp, gridDim.x, ts);
     block_tree<2>(ts, v);
     const bool bad = !finite(v[0]) || !finite(v[1]);
@@ -558,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> 
     }
     if (bad) return;
   } else {
-    if (any) phaseB_stencil<T, PC, KIND>(B, P, nrows, it.row(), R);
+    if (any) phaseB_stencil<T, PC, KIND, NT>(B, P, nrows, it.row(), R);
   }
   double acc[9];
 #pragma unroll
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_phaseB(PhaseBArgs<T> B, StParams<T> 
       if (carry) march_rotate<T>(R.z, R.pd, R.pu);
       phaseB_issue<T, PC, NT, KIND>(B, it.row(), R, carry);
       if constexpr (marchable<KIND>()) if (mw) march_planes<T>(B.z, it, R.pd, R.pu);
-      phaseB_stencil<T, PC, KIND>(B, P, nrows, it.row(), R);
+      phaseB_stencil<T, PC, KIND, NT>(B, P, nrows, it.row(), R);
     }
   }
   if (AUTO) {

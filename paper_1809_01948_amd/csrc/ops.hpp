@@ -299,7 +299,10 @@ __device__ __forceinline__ T st_row_sum(const StParams<T>& P, bool hD, bool hS, 
 // column order with one rounding per operation, which is the CSR product of
 // the same matrix bit for bit; the result does not depend on CH or on which
 // kernel calls this.
-template <typename T, int PC, int KIND, int CH>
+// NTC: the DIA5 coefficient rows are loaded non-temporally (FP64 kernels
+// whose vector streams are: 2048^2 DIA5 phase kernels 120 -> 100 us and
+// 132 -> 111 us; with FP32 storage cached loads were faster, 47 -> 51 us).
+template <typename T, int PC, int KIND, int CH, bool NTC = false>
 __device__ __forceinline__ void st_apply(const StParams<T>& P, const T* __restrict__ z,
                                          const T* __restrict__ dinv, T ds, int p,
                                          const T (&xc)[V16<T>::n * CH],
@@ -352,19 +355,19 @@ __device__ __forceinline__ void st_apply(const StParams<T>& P, const T* __restri
     for (int c = 0; c < CH; ++c) {
       T t[R];
       const int64_t q = p + c * R;
-      ld16(P.dia + q, t);
+      ldc<T, R, NTC>(P.dia + q, t);
 #pragma unroll
       for (int e = 0; e < R; ++e) cS[c * R + e] = t[e];
-      ld16(P.dia + P.ld + q, t);
+      ldc<T, R, NTC>(P.dia + P.ld + q, t);
 #pragma unroll
       for (int e = 0; e < R; ++e) cW[c * R + e] = t[e];
-      ld16(P.dia + 2 * P.ld + q, t);
+      ldc<T, R, NTC>(P.dia + 2 * P.ld + q, t);
 #pragma unroll
       for (int e = 0; e < R; ++e) cC[c * R + e] = t[e];
-      ld16(P.dia + 3 * P.ld + q, t);
+      ldc<T, R, NTC>(P.dia + 3 * P.ld + q, t);
 #pragma unroll
       for (int e = 0; e < R; ++e) cE[c * R + e] = t[e];
-      ld16(P.dia + 4 * P.ld + q, t);
+      ldc<T, R, NTC>(P.dia + 4 * P.ld + q, t);
 #pragma unroll
       for (int e = 0; e < R; ++e) cN[c * R + e] = t[e];
     }
