@@ -44,8 +44,11 @@ struct SellOp {
 #pragma unroll
       for (int u = 0; u < kGroup; ++u) {
         const int jj = min(j0 + u, w - 1);
-        cj[u] = c[(int64_t)jj * kSellC];
-        aj[u] = a[(int64_t)jj * kSellC];
+        // the matrix streams through once: non-temporal, so that the L2 keeps
+        // the gathered x (2e6 x 27 random matrix: 212 -> 204 us FP64, 146 ->
+        // 141 us FP32 storage)
+        cj[u] = __builtin_nontemporal_load(c + (int64_t)jj * kSellC);
+        aj[u] = __builtin_nontemporal_load(a + (int64_t)jj * kSellC);
       }
       typename Vis::V xv[kGroup];
 #pragma unroll
