@@ -70,6 +70,13 @@ STATUS = {
 }
 
 
+# A recursive convergence whose true residual misses the tolerance is
+# followed by a replacement and more iterations at most this many times per
+# solve; the next failure ends the solve with TRUE_RES_NOT_MET (the attainable
+# accuracy is then above the tolerance, e.g. with FP32 recurrences).
+MAX_FORCED_REPLACEMENTS = 3
+
+
 def unit_roundoff(dtype=np.float64) -> float:
     """Unit roundoff u = 2^-(p) of a binary format with p-bit significand
     (the epsilon of Section 2 read as u; 2^-53 for double)."""
@@ -309,12 +316,23 @@ class _GapBound:
 
     The local rounding errors of iteration i are bounded with
     eq:errbounds1-4 (epsilon = `eps`, mu = max nonzeros per row of A,
-    mu~ = 1 for a diagonal M^-1, ||A|| and ||M^-1|| upper bounds), the gap
-    norms ||Delta^s||, ||Delta^w||, ||Delta^z|| by the triangle inequality
-    applied to eq:Ds, eq:Dw, eq:Dz, and f^r accumulates them as eq:DDr_bound
-    does, one iteration at a time.  A replacement resets the bounds to the
-    errors of the explicit recomputation (the initial-gap bounds of
-    Section 3.2)."""
+    mu~ = 1 for a diagonal M^-1, ||A|| and ||M^-1|| upper bounds); the gap
+    norms ||Delta^s_i||, ||Delta^w_i||, ||Delta^z_i|| are bounded the same
+    way from eq:DDs, eq:DDw, eq:DDz, i.e. by the triangle inequality applied
+    to eq:Ds, eq:Dw, eq:Dz one iteration at a time, and f^r accumulates them
+    as eq:DDr_bound does.  (This is the printed bound with the moduli of the
+    coefficients of each of its sums: products of the moduli of the error
+    propagation matrices of eq:all_matrices.  ``oracle.gapbound_matrix``
+    evaluates the same number from those matrices.)
+
+    Initial gaps as in Section 3.2: ||Delta^r_0|| <= ((mu sqrt(N) + 1) ||A||
+    ||x_0|| + ||b||) eps, ||Delta^w_0|| <= mu sqrt(N) ||A|| ||k_0|| eps,
+    ||Delta^s_0|| <= mu sqrt(N) ||A|| ||g_0|| eps and ||Delta^z_0|| <=
+    mu sqrt(N) ||A|| ||l_0|| eps; iteration 0's s_0 = w_0 and z_0 = t_0
+    (beta_0 = 0) add no local error of their own.  A replacement restarts
+    the bounds from the same expressions evaluated for the explicit
+    recomputation (x_{i+1}, k_{i+1}, g_i, l_i), in the arithmetic of the
+    recomputation (epsilon ``eps_replace``)."""
 
     def __init__(self, N, mu, nA, nM, eps, nb, estimate=False, eps_replace=None):
         self.N, self.mu, self.nA, self.nM, self.eps, self.nb = N, mu, nA, nM, eps, nb
@@ -325,53 +343,81 @@ class _GapBound:
         self.cmut = 1.0 if estimate else math.sqrt(N)                   # mu~ sqrt(N), mu~ = 1
         self.smu = self.cmu * nA
         self.smut = self.cmut * nM
-        self.prev = dict(g=0.0, s=0.0, l=0.0, z=0.0, n=0.0, v=0.0)
-        self.ds_prev = 0.0
-        self.dz_prev = 0.0
 
     def start(self, nx, nk):
-        """f^r_0 and ||Delta^w_0|| for r_0 = b - A x_0, w_0 = A k_0."""
-        return self.reset(nx, nk, 0.0, 0.0)
+        """f^r_0 and ||Delta^w_0|| for r_0 = b - A x_0, w_0 = A k_0; the
+        initial s and z gaps are set by the first ``step``."""
+        e = self.eps
+        self.f = ((self.cmu + 1.0) * self.nA * nx + self.nb) * e
+        self.dw = self.smu * nk * e
+        self.ds_prev = self.dz_prev = 0.0
+        self.first = True
+        self.prev = dict(g=0.0, s=0.0, l=0.0, z=0.0, n=0.0, v=0.0)
+        return self.f
+
+    def local_bounds(self, a, b, w, wp, nm):
+        """eq:errbounds1-4 for iteration i (without the factor epsilon).
+        ``nm`` holds the norms of the iteration-i vectors; the iteration i-1
+        ones are kept from the previous step; a, b, w, wp are |alpha_i|,
+        |beta_i|, |omega_i|, |omega_{i-1}|."""
+        nA, smu, smut = self.nA, self.smu, self.smut
+        P = self.prev
+        return dict(
+            x=2 * nm["x"] + 3 * a * nm["g"] + 2 * w * nm["u"],
+            r=nm["q"] + 2 * w * nm["y"],
+            q=nm["r"] + 2 * a * nm["s"],
+            u=nm["k"] + 2 * a * nm["l"],
+            y=nm["w"] + 2 * a * nm["z"],
+            g=nm["k"] + 3 * b * P["g"] + 4 * b * wp * P["l"],
+            s=nm["w"] + 3 * b * P["s"] + 4 * b * wp * P["z"],
+            l=(nm["m"] + smut * nm["w"] + 3 * b * P["l"] + 4 * b * wp * P["n"]
+               + smut * b * wp * P["z"]),
+            z=(nm["t"] + smu * nm["m"] + smut * nA * nm["w"] + 3 * b * P["z"]
+               + 4 * b * wp * P["v"] + smu * b * wp * P["n"] + smut * nA * b * wp * P["z"]),
+            k=(nm["u"] + 3 * w * nm["m"] + smut * w * nm["w"] + 4 * w * a * nm["n"]
+               + smut * w * a * nm["z"]),
+            w_=(nm["y"] + 3 * w * nm["t"] + smu * w * nm["m"] + smut * nA * w * nm["w"]
+                + 4 * w * a * nm["v"] + smu * w * a * nm["n"] + smut * nA * w * a * nm["z"]),
+        )
 
     def step(self, a, b, w, wp, nm):
         """Advance over iteration i.  `nm` holds the norms of the iteration-i
         vectors x, g, u, q, y, r, s, k, l, w, z, m, t, n, v; a, b, w, wp are
-        |alpha_i|, |beta_i|, |omega_i|, |omega_{i-1}|.  Returns f^r_{i+1}."""
-        e, nA, smu, smut = self.eps, self.nA, self.smu, self.smut
-        P = self.prev
-        d_x = (2 * nm["x"] + 3 * a * nm["g"] + 2 * w * nm["u"]) * e
-        d_r = (nm["q"] + 2 * w * nm["y"]) * e
-        d_q = (nm["r"] + 2 * a * nm["s"]) * e
-        d_u = (nm["k"] + 2 * a * nm["l"]) * e
-        d_y = (nm["w"] + 2 * a * nm["z"]) * e
-        d_g = (nm["k"] + 3 * b * P["g"] + 4 * b * wp * P["l"]) * e
-        d_s = (nm["w"] + 3 * b * P["s"] + 4 * b * wp * P["z"]) * e
-        d_l = (nm["m"] + smut * nm["w"] + 3 * b * P["l"] + 4 * b * wp * P["n"]
-               + smut * b * wp * P["z"]) * e
-        d_z = (nm["t"] + smu * nm["m"] + smut * nA * nm["w"] + 3 * b * P["z"]
-               + 4 * b * wp * P["v"] + smu * b * wp * P["n"] + smut * nA * b * wp * P["z"]) * e
-        d_k = (nm["u"] + 3 * w * nm["m"] + smut * w * nm["w"] + 4 * w * a * nm["n"]
-               + smut * w * a * nm["z"]) * e
-        d_w = (nm["y"] + 3 * w * nm["t"] + smu * w * nm["m"] + smut * nA * w * nm["w"]
-               + 4 * w * a * nm["v"] + smu * w * a * nm["n"] + smut * nA * w * a * nm["z"]) * e
-        dz = b * self.dz_prev + nA * d_l + d_z                                   # eq:Dz
-        ds = self.dw + b * self.ds_prev + b * wp * self.dz_prev + nA * d_g + d_s  # eq:Ds
-        f = (self.f + a * ds + w * self.dw + w * a * dz + nA * d_x + d_r          # eq:Dr
-             + w * nA * d_u + d_q + w * d_y)
-        dw = self.dw + a * dz + nA * d_k + d_w + nA * d_u + d_y                  # eq:Dw
+        alpha_i, beta_i, omega_i, omega_{i-1} (their moduli are used).
+        Returns f^r_{i+1}."""
+        a, b, w, wp = abs(a), abs(b), abs(w), abs(wp)
+        e, nA = self.eps, self.nA
+        d = {key: val * e for key, val in self.local_bounds(a, b, w, wp, nm).items()}
+        if self.first:          # Delta^s_0 and Delta^z_0: the initial gaps
+            ds = self.smu * nm["g"] * e
+            dz = self.smu * nm["l"] * e
+            self.first = False
+        else:
+            dz = b * self.dz_prev + nA * d["l"] + d["z"]                            # eq:Dz
+            ds = self.dw + b * self.ds_prev + b * wp * self.dz_prev + nA * d["g"] + d["s"]  # eq:Ds
+        f = (self.f + a * ds + w * self.dw + w * a * dz + nA * d["x"] + d["r"]      # eq:Dr
+             + w * nA * d["u"] + d["q"] + w * d["y"])
+        dw = self.dw + a * dz + nA * d["k"] + d["w_"] + nA * d["u"] + d["y"]      # eq:Dw
         self.f, self.dw, self.ds_prev, self.dz_prev = f, dw, ds, dz
         self.prev = dict(g=nm["g"], s=nm["s"], l=nm["l"], z=nm["z"], n=nm["n"], v=nm["v"])
         return f
 
-    def reset(self, nx, nk, ng, nl):
+    def reset(self, nx, nk, ng, nl, ns=None, nz=None):
         """After a replacement (eq:rr) from x_{i+1} and g_i: the errors of the
         explicit recomputation, in the arithmetic of the recomputation
-        (epsilon ``eps_replace``)."""
+        (epsilon ``eps_replace``).  The next iteration's local bounds use the
+        replaced s_i, l_i, z_i (norms ``ns``, ``nl``, ``nz``)."""
         e = self.eps_r
         self.f = ((self.cmu + 1.0) * self.nA * nx + self.nb) * e
         self.dw = self.smu * nk * e
         self.ds_prev = self.smu * ng * e
         self.dz_prev = self.smu * nl * e
+        self.first = False
+        self.prev["l"] = nl
+        if ns is not None:
+            self.prev["s"] = ns
+        if nz is not None:
+            self.prev["z"] = nz
         return self.f
 
 
@@ -442,6 +488,7 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     g, s, l, z, n, v = (ops.zeros() for _ in range(6))   # iteration -1 values (taken as 0)
     gb = None
     rr_next = False
+    forced = 0                                # replacements forced by a failed confirmation
     if auto:
         gb = _GapBound(ops.n, ops.max_row_nnz(), ops.norm_bound_A(), ops.norm_bound_M(), eps, nb,
                        estimate=rr_estimate)
@@ -492,8 +539,7 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
         x, r, k, w = x_new, r_new, k_new, w_new
         replaced = False
         if auto:
-            f_next = gb.step(abs(float(alpha)), abs(float(beta)), abs(float(omega)),
-                             abs(float(omega_prev)), nm)
+            f_next = gb.step(float(alpha), float(beta), float(omega), float(omega_prev), nm)
         due = (rr_next if auto else
                (rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0))
         if due:
@@ -504,7 +550,8 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
             if snap is not None:
                 snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
             if auto:
-                f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l))
+                f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l),
+                                  ops.norm(s), ops.norm(z))
         rho_new = ops.dot(rhat, r)                     # GLRED 2 begins: (r0, r_{i+1}),
         rw = ops.dot(rhat, w)                          #   (r0, w_{i+1}), (r0, s_i),
         rs = ops.dot(rhat, s)                          #   (r0, z_i) and (r_{i+1}, r_{i+1})
@@ -525,19 +572,23 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                     snap["replaced"] = replaced
                     res.snapshots.append(snap)
                 return _finish(res, x, STATUS["CONVERGED"], i + 1, ops, b)
-            if rr_period <= 0 and not auto:
+            if (rr_period <= 0 and not auto) or forced >= MAX_FORCED_REPLACEMENTS:
                 res.alpha.append(alpha)
                 res.omega.append(omega)
                 res.rnorm.append(rn)
+                if auto:
+                    res.fr.append(f_next)
                 return _finish(res, x, STATUS["TRUE_RES_NOT_MET"], i + 1, ops, b)
             r, k, w, s, l, z = replace(x, g)           # confirm failed: replace and go on
+            forced += 1
             res.replacements += 1
             res.rr_iters.append(i)
             replaced = True
             if snap is not None:
                 snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
             if auto:
-                f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l))
+                f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l),
+                                  ops.norm(s), ops.norm(z))
             rho_new = ops.dot(rhat, r)
             rw = ops.dot(rhat, w)
             rs = ops.dot(rhat, s)

@@ -37,15 +37,18 @@ import math
 
 import numpy as np
 
-from .krylov import STATUS, SolveResult, _GapBound
+from .krylov import MAX_FORCED_REPLACEMENTS, STATUS, SolveResult, _GapBound
 
 
 def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None, tol=1e-10,
                                maxit=1000, rr_period=0, rr_tau=None, rr_mode="periodic",
-                               rr_estimate=None, record=False):
+                               rr_estimate=None, record=False, dot_order="blas"):
     """Algorithm 2 with `store`-precision vectors (see the module docstring).
 
     A: scipy CSR (FP64 values, rounded here to `store`); b, x0: FP64.
+    ``dot_order``: "blas" (numpy.dot) or "fsum" (the correctly rounded sum of
+    the products, ``math.fsum``) -- two summation orders of the same dot
+    products, for measuring how fast rounding-order differences grow.
     Returns a ``krylov.SolveResult`` (x in FP64)."""
     S = np.dtype(store).type
     f64 = np.float64
@@ -65,8 +68,14 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
     def spmv_wide(v):                      # FP64-accumulated SPMV of A_s
         return A_w @ np.asarray(v, dtype=f64)
 
-    def dot(u, v):
-        return float(np.dot(np.asarray(u, dtype=f64), np.asarray(v, dtype=f64)))
+    if dot_order == "blas":
+        def dot(u, v):
+            return float(np.dot(np.asarray(u, dtype=f64), np.asarray(v, dtype=f64)))
+    elif dot_order == "fsum":
+        def dot(u, v):
+            return math.fsum(np.asarray(u, dtype=f64) * np.asarray(v, dtype=f64))
+    else:
+        raise ValueError(dot_order)
 
     def norm(v):
         return math.sqrt(dot(v, v))
@@ -102,6 +111,7 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
     alpha = rho / rw
     beta = 0.0
     omega_prev = 0.0
+    forced = 0                             # replacements forced by a failed confirmation
     if auto:
         absA = abs(A)
         nA = math.sqrt(float(absA.sum(axis=0).max()) * float(absA.sum(axis=1).max()))
@@ -150,7 +160,7 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
         w = y - om_s * (t - a_s * v)                       # w_{i+1}
         replaced = False
         if auto:
-            f_next = gb.step(abs(alpha), abs(beta), abs(omega), abs(omega_prev), nm)
+            f_next = gb.step(alpha, beta, omega, omega_prev, nm)
         due = (rr_next if auto else
                (rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0))
         if due:
@@ -159,7 +169,7 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
             res.rr_iters.append(i)
             replaced = True
             if auto:
-                f_next = gb.reset(norm(x), norm(k), norm(g), norm(l))
+                f_next = gb.reset(norm(x), norm(k), norm(g), norm(l), norm(s), norm(z))
         rho_new = dot(rhat, r)
         rw = dot(rhat, w)
         rs = dot(rhat, s)
@@ -174,7 +184,7 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
                         s=s.copy(), l=l.copy(), z=z.copy(), v=v.copy(), replaced=replaced)
         if rn <= tol * nb:
             tr = norm(b - spmv_wide(x))
-            if tr <= tol * nb or (rr_period <= 0 and not auto):
+            if tr <= tol * nb or (rr_period <= 0 and not auto) or forced >= MAX_FORCED_REPLACEMENTS:
                 res.alpha.append(alpha)
                 res.omega.append(omega)
                 res.rnorm.append(rn)
@@ -185,10 +195,11 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
                 st = "CONVERGED" if tr <= tol * nb else "TRUE_RES_NOT_MET"
                 return _done(res, x, STATUS[st], i + 1, A_w, b)
             r, k, w, s, l, z = replace(x, g)           # confirmation failed: replace, go on
+            forced += 1
             res.replacements += 1
             res.rr_iters.append(i)
             if auto:
-                f_next = gb.reset(norm(x), norm(k), norm(g), norm(l))
+                f_next = gb.reset(norm(x), norm(k), norm(g), norm(l), norm(s), norm(z))
             rho_new = dot(rhat, r)
             rw = dot(rhat, w)
             rs = dot(rhat, s)
