@@ -46,6 +46,7 @@ enum Slot : int {
   SL_Z2 = 15, SL_Q2 = 16, SL_Y2 = 17,          // phase A: k, w, t, m, g, s, l, z, q, y
   SL_X2 = 18, SL_U2 = 19, SL_N2 = 20, SL_V2 = 21,  // phase B: x, u, n, v
   SL_RX2 = 22, SL_RK2 = 23, SL_RL2 = 24,           // replacement: x, k, l after eq:rr
+  SL_RS2 = 25, SL_RZ2 = 26,                        // replacement: s, z after eq:rr
 };
 
 // final-reduction modes (run by one extra block of an operator kernel, or by
@@ -103,6 +104,7 @@ struct alignas(64) DevScalars {
   int32_t rr_hit;                  // a replacement ran in the current iteration
   int32_t f_ok_prev;               // f^r_i <= tau ||r_i|| at the previous reduction
   int32_t rr_est;                  // 1: square-root estimate instead of the worst-case bound
+  int32_t gb_first;                // 1: the next bound step is iteration 0 (initial s, z gaps)
   double eps_b, eps_r;             // epsilon of the recurrences / of a replacement
   double nA, nM, mu, nN;           // ||A||, ||M^-1|| bounds, max nnz per row, N
   double fr, dw, ds_prev, dz_prev; // f^r and the gap-norm bounds

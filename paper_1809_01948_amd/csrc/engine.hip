@@ -81,6 +81,11 @@ void* dalloc(Solver& S, size_t bytes) {
 
 int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
+// A recursive convergence whose FP64 true residual misses the tolerance is
+// followed by a replacement and more iterations at most this many times per
+// solve; the next such failure ends it with TRUE_RES_NOT_MET.
+constexpr int kMaxForcedReplacements = 3;
+
 void common_setup(Solver& S, int precision, int precond) {
   if (precision != PBCG_FP64 && precision != PBCG_MIXED) fail(PBCG_ERR_INVALID_ARG, "precision must be PBCG_FP64 or PBCG_MIXED");
   if (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI) fail(PBCG_ERR_INVALID_ARG, "precond must be PBCG_PC_NONE or PBCG_PC_JACOBI");
@@ -295,6 +300,32 @@ void norms_grid(Solver& S, const double* dia /* 5*n or null */) {
     mr = std::max(mr, cnt);
   }
   set_norm_bounds(S, rs, cs, mr, mr);
+}
+
+// After the DIA5 coefficients changed on the device: the host copy and the
+// bounds of the automated criterion (||A|| from the row and column sums,
+// ||M^-1|| = max |1 / a_ii|) from the stored coefficients.
+void refresh_dia5_bounds(Solver& S) {
+  const int64_t n = S.n;
+  std::vector<double> host(5 * n);
+  if (S.precision == PBCG_FP64) {
+    std::vector<double> t(5 * S.npad);
+    hipck(hipMemcpy(t.data(), S.A.dia, t.size() * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+    for (int d = 0; d < 5; ++d)
+      for (int64_t i = 0; i < n; ++i) host[d * n + i] = t[d * S.npad + i];
+  } else {
+    std::vector<float> t(5 * S.npad);
+    hipck(hipMemcpy(t.data(), S.A.dia, t.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    for (int d = 0; d < 5; ++d)
+      for (int64_t i = 0; i < n; ++i) host[d * n + i] = (double)t[d * S.npad + i];
+  }
+  S.h_dia = std::move(host);
+  norms_grid(S, S.h_dia.data());
+  if (S.precond) {
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i) m = std::max(m, std::fabs(1.0 / S.h_dia[2 * n + i]));
+    S.normM = m;
+  }
 }
 
 void build_transpose(Solver& S) {
@@ -615,24 +646,24 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
       status = PBCG_CONVERGED;
       break;
     }
-    if ((o.rr_period <= 0 && !o.rr_auto) || forced >= 3) {
+    if ((o.rr_period <= 0 && !o.rr_auto) || forced >= kMaxForcedReplacements) {
       status = PBCG_TRUE_RES_NOT_MET;
       break;
     }
-    // replace (eq:rr) and recompute GLRED 2, then continue
+    // replace (eq:rr) and recompute GLRED 2, then continue; the replaced
+    // residual is not tested against the tolerance in this iteration.  When a
+    // replacement already ran in this iteration, its saved pre-replacement z
+    // (for n_i) is kept.
     ++forced;
+    const bool save_z = d.n_saved == 0;
     launch_set_done(S, RUNNING, S.s1);
     launch_rr1(S, tr, true, S.s1);
-    launch_rr2(S, tr, true, S.s1);
+    launch_rr2(S, tr, true, S.s1, save_z);
     launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_REDO, false, S.s1);
     hipck(hipGetLastError(), "replacement launch");
     d = read_scalars(S);
     if (d.done == STOPPED) {
       status = d.status;
-      break;
-    }
-    if (d.done == RECURSIVE_CONVERGED) {
-      status = PBCG_TRUE_RES_NOT_MET;
       break;
     }
     start = d.iter;
@@ -1079,6 +1110,7 @@ int pbicgstab_dia5_assemble_kappa(pbcg_handle h, const double* kappa, double cx,
     hipck(hipMemcpyAsync(&bad, &S.sc->bad_diag, 4, hipMemcpyDeviceToHost, S.s1), "hipMemcpyAsync");
     hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
     if (bad && S.precond) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after assembly");
+    refresh_dia5_bounds(S);
     hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
     hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
     return PBCG_OK;

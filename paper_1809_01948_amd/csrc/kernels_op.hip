@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_st(StParams<T> P, const T* __re
 }
 
 // A GLRED final on its own, spread over one block per reduced slot (the
-// automated strategy's 22 sums): block b reduces slot b, the last block to
+// automated strategy's 24 sums): block b reduces slot b, the last block to
 // finish runs the scalar logic (distributed_final).
 __global__ __launch_bounds__(kBlock) void k_fin_dist(int fin_mode, DevScalars* __restrict__ sc,
                                                      const double* __restrict__ partials, int npart) {
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
     sc->rr_count += 1;
     sc->rr_hit = 1;
   }
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (XcdWalk w(ntiles, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
     const int64_t i = w.t * kBlock + threadIdx.x;
     if (i < n) {
@@ -353,11 +353,12 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
       acc[0] += x[i] * x[i];
       acc[1] += (double)ki * (double)ki;
       acc[2] += (double)li * (double)li;
+      acc[3] += (double)si * (double)si;
     }
   }
-  const int slots[3] = {SL_RX2, SL_RK2, SL_RL2};
-  block_partials<3>(acc, slots, partials, blockIdx.x);
-  zero_partials<3>(slots, partials, npart);
+  const int slots[4] = {SL_RX2, SL_RK2, SL_RL2, SL_RS2};
+  block_partials<4>(acc, slots, partials, blockIdx.x);
+  zero_partials<4>(slots, partials, npart);
 }
 
 // Residual replacement, second half: w = A k, z = A l (FP64 products), and
@@ -365,7 +366,9 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
 // computed n_i = M^-1 z_i of this iteration is not replaced (only the six
 // quantities of eq:rr are), and v_i = A n_i keeps its value; so the
 // pre-replacement z_i is kept in `zsave` for the next phase A, which forms
-// n_i from it.  With `pm`, also M^-1 w (dinv a vector) for the next product.
+// n_i from it (`save_z` = 0 when an earlier replacement of the same iteration
+// has saved it already).  With `pm`, also M^-1 w (dinv a vector) for the next
+// product.  Also the partial of ||z||^2 for the automated bound.
 template <typename T, int PC, class Op>
 __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, const T* __restrict__ l,
                                                 T* __restrict__ w, T* __restrict__ z,
@@ -375,10 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
                                                 const T* __restrict__ s, int64_t n, int64_t ntiles,
                                                 int nwork, DevScalars* __restrict__ sc,
                                                 double* __restrict__ partials, int force,
-                                                int npart) {
+                                                int npart, int save_z) {
   if (!force && !rr_due(sc)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->n_saved = 1;
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (XcdWalk wk(ntiles, blockIdx.x, nwork); wk.t < wk.end; wk.t += wk.step) {
     const int64_t i = wk.t * kBlock + threadIdx.x;
     if (i < n) {
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
       op.row(i, vis);
       const T wi = (T)vis.sx;
       const T zi = (T)vis.sy;
-      zsave[i] = z[i];
+      if (save_z) zsave[i] = z[i];
       w[i] = wi;
       z[i] = zi;
       if (pm) pm[i] = dinv[i] * wi;
@@ -396,11 +399,12 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
       acc[2] += rh * (double)s[i];
       acc[3] += rh * (double)zi;
       acc[4] += ri * ri;
+      acc[5] += (double)zi * (double)zi;
     }
   }
-  const int slots[5] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR};
-  block_partials<5>(acc, slots, partials, blockIdx.x);
-  zero_partials<5>(slots, partials, npart);
+  const int slots[6] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_RZ2};
+  block_partials<6>(acc, slots, partials, blockIdx.x);
+  zero_partials<6>(slots, partials, npart);
 }
 
 // partial of ||b - A x||^2 (FP64)
@@ -878,7 +882,7 @@ int phase_march_planes(Solver& S, bool tr) {
 
 void launch_fin(Solver& S, int fin_mode, hipStream_t st) {
   // up to 8 sums: one block loads them all in one round trip; more (the
-  // automated strategy's 22): one block per sum
+  // automated strategy's 24): one block per sum
   const int nfin = fin_blocks(S, fin_mode);
   if (nfin <= 8) {
     launch_final(S, fin_mode, 0, st);
@@ -939,14 +943,14 @@ void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st) {
   });
 }
 
-void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st) {
+void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z) {
   with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
     const int g = rr_grid(S);
     hipLaunchKernelGGL((k_rr2<T, PC, Op>), dim3(g), dim3(kBlock), 0, st, op, (const T*)S.vec[V_K],
                        (const T*)S.vec[V_L], (T*)S.vec[V_W], (T*)S.vec[V_Z], (T*)S.vec[V_TMP],
                        pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : (T*)nullptr,
                        (const T*)S.dinv, (const T*)S.vec[V_RHAT], (const T*)S.vec[V_R], (const T*)S.vec[V_S], S.n,
-                       S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk);
+                       S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk, save_z ? 1 : 0);
   });
 }
 

@@ -334,7 +334,7 @@ __device__ __forceinline__ void phaseA_body(const PhaseAArgs<T>& A, const StPara
 // it, so block 0 writes the updated copy to the staging struct sc[1] (and
 // the history row); phase B, which follows, reads its scalars from there and
 // its block 0 commits sc[1] to sc[0].  Used without the automated criterion
-// only (its 22 reduced slots are too many to load in every block).
+// only (its 24 reduced slots are too many to load in every block).
 template <typename T, int PC, bool NT, bool AUTO, int KIND, bool PRO>
 __global__ __launch_bounds__(kBlock) void k_phaseA(PhaseAArgs<T> A, StParams<T> P, int64_t n,
                                                    DevScalars* __restrict__ sc,

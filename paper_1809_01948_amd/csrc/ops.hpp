@@ -470,8 +470,15 @@ __device__ inline double gap_bound_step(DevScalars* sc, double a, double b, doub
                       smut * w * a * nm.z) * e;
   const double d_w = (nm.y + 3 * w * nm.t + smu * w * nm.m + smut * nA * w * nm.w +
                       4 * w * a * nm.v + smu * w * a * nm.n + smut * nA * w * a * nm.z) * e;
-  const double dz = b * sc->dz_prev + nA * d_l + d_z;                                  // eq:Dz
-  const double ds = sc->dw + b * sc->ds_prev + b * wp * sc->dz_prev + nA * d_g + d_s;  // eq:Ds
+  double dz, ds;
+  if (sc->gb_first) {   // Delta^s_0, Delta^z_0: the initial gaps of Section 3.2 (g_0 = k_0, l_0 = m_0)
+    ds = smu * nm.g * e;
+    dz = smu * nm.l * e;
+    sc->gb_first = 0;
+  } else {
+    dz = b * sc->dz_prev + nA * d_l + d_z;                                    // eq:Dz
+    ds = sc->dw + b * sc->ds_prev + b * wp * sc->dz_prev + nA * d_g + d_s;    // eq:Ds
+  }
   const double f = sc->fr + a * ds + w * sc->dw + w * a * dz + nA * d_x + d_r +       // eq:Dr
                    w * nA * d_u + d_q + w * d_y;
   const double dw = sc->dw + a * dz + nA * d_k + d_w + nA * d_u + d_y;                 // eq:Dw
@@ -480,9 +487,24 @@ __device__ inline double gap_bound_step(DevScalars* sc, double a, double b, doub
   return f;
 }
 
+// Bounds at the start of Algorithm 2 (Section 3.2): ||Delta^r_0|| <=
+// ((mu sqrt(N) + 1) ||A|| ||x_0|| + ||b||) eps, ||Delta^w_0|| <= mu sqrt(N)
+// ||A|| ||k_0|| eps; the s and z gaps of iteration 0 are set by its step.
+__device__ inline void gap_bound_start(DevScalars* sc, double nx, double nk) {
+  const double e = sc->eps_b;
+  const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
+  sc->fr = ((cmu + 1.0) * sc->nA * nx + sc->nb) * e;
+  sc->dw = cmu * sc->nA * nk * e;
+  sc->ds_prev = sc->dz_prev = 0.0;
+  sc->gb_first = 1;
+  sc->pg = sc->ps = sc->pl = sc->pz = sc->pn = sc->pv = 0.0;
+}
+
 // bounds right after an explicit recomputation of r, k, w from x and s, l, z
-// from g, in the arithmetic of the recomputation (FP64: eps_r)
-__device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, double ng, double nl) {
+// from g, in the arithmetic of the recomputation (FP64: eps_r); the next
+// step's local bounds use the replaced s, l, z
+__device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, double ng, double nl,
+                                       double ns, double nz) {
   const double e = sc->eps_r;
   const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
   const double smu = cmu * sc->nA;
@@ -490,11 +512,15 @@ __device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, dou
   sc->dw = smu * nk * e;
   sc->ds_prev = smu * ng * e;
   sc->dz_prev = smu * nl * e;
+  sc->gb_first = 0;
+  sc->pl = nl;
+  sc->ps = ns;
+  sc->pz = nz;
 }
 
 // Slots each final mode reduces.  GLRED 2 in automated mode adds the norms
 // of the gap bound; FIN_SUM reduces slots 0 .. aux-1.
-constexpr int kMaxFinSlots = 22;
+constexpr int kMaxFinSlots = 24;
 
 struct FinSlots {
   int n;
@@ -519,7 +545,7 @@ __host__ __device__ inline FinSlots fin_slots(int mode, int rr_auto, int aux) {
       if (rr_auto && mode != FIN_PROBE) {
         put(SL_K2); put(SL_W2); put(SL_T2); put(SL_M2); put(SL_G2); put(SL_S2); put(SL_L2);
         put(SL_Z2); put(SL_Q2); put(SL_Y2); put(SL_X2); put(SL_U2); put(SL_N2); put(SL_V2);
-        put(SL_RX2); put(SL_RK2); put(SL_RL2);
+        put(SL_RX2); put(SL_RK2); put(SL_RL2); put(SL_RS2); put(SL_RZ2);
       }
       break;
     case FIN_TRUE:
@@ -563,7 +589,8 @@ struct G2Step {
   double rn, beta, alpha;
 };
 __device__ __forceinline__ G2Step glred2_step(const double (&v)[5], double alpha, double omega,
-                                              double rho, double tol, double nb) {
+                                              double rho, double tol, double nb,
+                                              bool test_tol = true) {
   G2Step r{G2_CONTINUE, 0.0, 0.0, 0.0};
   const double rho1 = v[0], rw = v[1], rs = v[2], rz = v[3], rr = v[4];
   if (!finite(rho1) || !finite(rw) || !finite(rs) || !finite(rz) || !finite(rr)) {
@@ -571,7 +598,7 @@ __device__ __forceinline__ G2Step glred2_step(const double (&v)[5], double alpha
     return r;
   }
   r.rn = sqrt(rr);
-  if (r.rn <= tol * nb) {
+  if (test_tol && r.rn <= tol * nb) {
     r.outcome = G2_CONVERGED;
   } else if (omega == 0.0) {
     r.outcome = G2_BREAKDOWN_OMEGA;
@@ -614,9 +641,7 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
         sc->omega_prev = 0.0;
         sc->n_saved = 0;                       // the iteration count is set by the host
         if (sc->rr_auto) {
-          // f^r_0 = ((mu sqrt(N) + 1) ||A|| ||x_0|| + ||b||) eps, ||Delta^w_0|| <= mu sqrt(N) ||A|| ||k_0|| eps
-          gap_bound_reset(sc, sqrt(v[4]), sqrt(v[5]), 0.0, 0.0);
-          sc->pg = sc->ps = sc->pl = sc->pz = sc->pn = sc->pv = 0.0;
+          gap_bound_start(sc, sqrt(v[4]), sqrt(v[5]));
           sc->f_ok_prev = sc->fr <= sc->tau * sc->rn0;
           sc->rr_next = 0;
           sc->rr_hit = 0;
@@ -649,10 +674,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
       // GLRED 2: beta_{i+1} = (alpha_i/omega_i) (r0,r_{i+1})/(r0,r_i),
       // alpha_{i+1} = (r0,r_{i+1}) / ((r0,w_{i+1}) + beta (r0,s_i) - beta omega (r0,z_i))
       // In automated mode the norms of the bound are reduced in the same pass.
-      constexpr int NS = 22;
+      constexpr int NS = 24;
       const int sl[NS] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_K2, SL_W2, SL_T2,
                           SL_M2, SL_G2, SL_S2, SL_L2, SL_Z2, SL_Q2, SL_Y2, SL_X2,
-                          SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2};
+                          SL_U2, SL_N2, SL_V2, SL_RX2, SL_RK2, SL_RL2, SL_RS2, SL_RZ2};
       double v[NS];
       if (sc->rr_auto) {
         take_sums<NS>(pre, sl, v);
@@ -682,14 +707,18 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
                            fabs(sc->omega_prev), nm);
           }
           if (sc->rr_hit) {
-            gap_bound_reset(sc, sqrt(v[19]), sqrt(v[20]), sqrt(v[9]), sqrt(v[21]));
+            gap_bound_reset(sc, sqrt(v[19]), sqrt(v[20]), sqrt(v[9]), sqrt(v[21]), sqrt(v[22]),
+                            sqrt(v[23]));
             sc->rr_hit = 0;
           }
           if (sc->bound_history && its >= 1 && its <= sc->bound_len)
             sc->bound_history[its - 1] = sc->fr;
         }
         const double v5[5] = {rho1, rw, rs, rz, rr};
-        const G2Step g = glred2_step(v5, sc->alpha, sc->omega, sc->rho, sc->tol, sc->nb);
+        // after a forced replacement the replaced residual is not tested against
+        // the tolerance: the next iteration's recursive residual decides
+        const G2Step g = glred2_step(v5, sc->alpha, sc->omega, sc->rho, sc->tol, sc->nb,
+                                     mode == FIN_BETA);
         if (g.outcome == G2_NONFINITE) {
           stop(sc, ST_NONFINITE);
         } else {

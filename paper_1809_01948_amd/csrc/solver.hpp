@@ -147,7 +147,7 @@ bool pre_multiplied(Solver& S, bool transpose);
 // the iteration's product on z (V_Z -> V_V) or w (V_W -> V_T)
 void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode, hipStream_t st);
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
-void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st);
+void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z = true);
 void launch_true_res(Solver& S, bool tr, hipStream_t st);
 void launch_gap(Solver& S, bool tr, hipStream_t st, bool force = false);
 void launch_cl_init(Solver& S, bool tr, hipStream_t st);

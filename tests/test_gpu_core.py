@@ -121,6 +121,7 @@ def test_vectors_after_k_iterations(Solver, k):
     for name, want in pairs.items():
         got = host(S.get_vector(name))
         assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want), name
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)), name
     assert np.array_equal(host(x), host(S.get_vector("x")))
     S.close()
 
@@ -204,6 +205,7 @@ def test_c2_vectors_after_k(Solver, c2, k):
                        "v": sn["v"]}.items():
         got = host(S.get_vector(name))
         assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want), name
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)), name
     S.close()
 
 
@@ -450,23 +452,27 @@ def test_automated_bound_trace(Solver, case, variant):
 @pytest.mark.parametrize("case", ["c1-64", "poisson-200"])
 def test_automated_replacement_converges(Solver, case):
     """Automated replacement on a larger unsymmetric problem without
-    preconditioner (oracle: 178 iterations, 7 replacements to 1e-12) and on
-    Poisson 200^2 with Jacobi (oracle: 994 iterations, 13 replacements to
-    1e-10).  Past the first tens of iterations the trajectories depend on
-    the dot-product summation order, so the counts are compared loosely;
-    convergence and the true residual are checked exactly."""
+    preconditioner (tolerance 1e-12) and on Poisson 200^2 with Jacobi (1e-10),
+    full solves.  Past the first tens of iterations the trajectories depend
+    on the dot-product summation order (the bound's per-iteration agreement is
+    checked by test_automated_bound_trace), so iteration and replacement
+    counts are not parity quantities: both sides must converge, the GPU's
+    solution must meet the tolerance on the oracle's own FP64 product, and
+    the counts are printed beside the oracle's (computed here)."""
     from workloads import poisson2d_c2
     if case == "c1-64":
-        p, tol, form, pc, ref_its, ref_rr = convdiff2d_c1(64), 1e-12, "csr", "none", 178, 7
+        p, tol, form, pc = convdiff2d_c1(64), 1e-12, "csr", "none"
     else:
-        p, tol, form, pc, ref_its, ref_rr = poisson2d_c2(200), 1e-10, "stencil", "jacobi", 994, 13
-    A = p.scipy_csr()
+        p, tol, form, pc = poisson2d_c2(200), 1e-10, "stencil", "jacobi"
+    A, ops = oracle_ops(p, pc)
+    ref = pipelined_bicgstab(ops, p.b, tol=tol, maxit=6000, rr_mode="auto")
     S = Solver.from_problem(p, form=form, precond=pc)
     x, st = S.solve(dev(p.b), tol=tol, maxit=6000, rr_auto=True)
+    print(f"{case}: GPU {st['status_name']} {st['iterations']} iterations, "
+          f"{st['replacements']} replacements; oracle {ref.status_name} {ref.iterations}, "
+          f"{ref.replacements}", flush=True)
+    assert ref.status == 0 and ref.replacements >= 1
     assert st["status"] == 0, st
-    # measured spread of the GPU runs (different reduction orders of the
-    # replacement sums): 455-762 iterations against the oracle's 994
-    assert 1 <= st["replacements"] <= 3 * ref_rr
-    assert 0.4 * ref_its <= st["iterations"] <= 2.0 * ref_its
+    assert st["replacements"] >= 1
     assert np.linalg.norm(p.b - A @ host(x)) <= tol * np.linalg.norm(p.b)
     S.close()

@@ -59,6 +59,7 @@ def test_c3_small_vectors_and_trace(Solver, c3_64, form):
                        "v": sn["v"]}.items():
         got = host(S.get_vector(name))
         assert np.linalg.norm(got - want) <= 1e-9 * np.linalg.norm(want), name
+        assert np.max(np.abs(got - want)) <= 1e-9 * np.max(np.abs(want)), name
     S.close()
 
 
