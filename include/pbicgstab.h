@@ -25,10 +25,16 @@
  *     Work is ordered after everything already queued on `stream`, and
  *     `stream` is made to wait for the library's own work before a call
  *     returns, so device buffers may be reused on `stream` right away.
- *   - The handle owns its device memory (matrix layouts, solver vectors,
- *     reduction scratch) and one internal stream; it is not thread safe, but
- *     separate handles may be used concurrently.  Input arrays passed to
- *     create/update calls are copied and may be freed after the call.
+ *   - Ownership.  The caller owns every device array it passes: the matrix
+ *     inputs of create (read during the call only), b, x, gradients, and the
+ *     workspace: one device allocation of pbicgstab_workspace_bytes() bytes
+ *     (256-byte aligned, e.g. a torch uint8 tensor) that holds all of the
+ *     handle's device data -- matrix layouts, solver vectors, reduction
+ *     partials, device scalars -- and must outlive the handle.  The library
+ *     allocates no device memory of its own; the handle owns only its
+ *     internal stream, its events, captured HIP graphs and a small pinned
+ *     host buffer for polling.  A handle is not thread safe, but separate
+ *     handles may be used concurrently.
  */
 #ifndef PBICGSTAB_H
 #define PBICGSTAB_H
@@ -54,11 +60,12 @@ enum {
 /* preconditioner M */
 enum { PBCG_PC_NONE = 0, PBCG_PC_JACOBI = 1 /* M = diag(A) */ };
 
-/* structured operators */
+/* operator formats: structured operators (pbicgstab_create_stencil) and CSR */
 enum {
   PBCG_ST_2D5 = 0,  /* constant 5-point stencil, dims {nx, ny}: coef[5] = S, W, C, E, N */
   PBCG_ST_3D7 = 1,  /* constant 7-point stencil, dims {nx, ny, nz}: coef[7] = D, S, W, C, E, N, U */
-  PBCG_ST_DIA5 = 2  /* variable 5-point coefficients, dims {nx, ny}: coef[5*N], row d = S, W, C, E, N */
+  PBCG_ST_DIA5 = 2, /* variable 5-point coefficients, dims {nx, ny}: coef[5*N], row d = S, W, C, E, N */
+  PBCG_CSR = 3      /* general sparse matrix (pbicgstab_create_csr) */
 };
 
 /* outcomes (>= 0) and errors (< 0) */
@@ -69,11 +76,13 @@ enum {
   PBCG_BREAKDOWN_RHO = 2,     /* (r0, r_{i+1}) = 0 or a zero denominator of alpha */
   PBCG_BREAKDOWN_OMEGA = 3,   /* omega_i = 0 and the update did not meet the tolerance */
   PBCG_NONFINITE = 4,         /* a reduction produced NaN or Inf */
-  PBCG_TRUE_RES_NOT_MET = 5,  /* the recursive residual met tol but the true one did not
-                                 (and residual replacement is disabled) */
+  PBCG_TRUE_RES_NOT_MET = 5,  /* the recursive residual met tol but the true one did not,
+                                 and residual replacement is disabled or 3 replacements
+                                 forced by such failures were already made */
   PBCG_ERR_INVALID_ARG = -1,
   PBCG_ERR_HIP = -2,          /* a HIP runtime call failed */
   PBCG_ERR_ZERO_DIAG = -3,    /* Jacobi requested but a diagonal entry is zero or missing */
+  PBCG_ERR_WORKSPACE_TOO_SMALL = -4, /* the workspace cannot hold the handle's device data */
   PBCG_ERR_UNSUPPORTED = -5
 };
 
@@ -82,8 +91,11 @@ typedef struct {
                             confirmed by the true residual ||b - A x_i|| */
   int32_t maxit;         /* maximum number of iterations (>= 1) */
   int32_t rr_period;     /* P > 0: residual replacement (eq:rr) in iteration i when
-                            (i+1) mod P == 0 and ||r_i|| >= rr_tau ||r_0||; also used when the
-                            true residual fails the confirmation.  0 disables it.
+                            (i+1) mod P == 0 and ||r_i|| >= rr_tau ||r_0||.  Also when the
+                            recursive residual meets tol but the true one does not: then a
+                            replacement is made and the iteration goes on (the replaced
+                            residual is not tested in that iteration), at most 3 times per
+                            solve.  0 disables both.
                             Ignored by classic_bicgstab_solve. */
   double rr_tau;         /* replacement cutoff; 0 selects sqrt(2^-53) */
   int32_t check_every;   /* iterations between host polls of the device state (0: default:
@@ -158,27 +170,50 @@ void pbicgstab_default_opts(pbcg_opts* opt);
  *                         (FP32 storage only)
  *   PBCG_PREMULT=0|1      sliced-ELL products reading the M^-1 z, M^-1 w that
  *                         the phase kernels write (Jacobi vector)
- *   PBCG_VEC_STAGGER=b    vectors in one allocation, b bytes apart
  * None changes a result bit except PBCG_NBLK and PBCG_MARCH_PHASE, which set
  * the order in which the dot products are summed.
  */
 
 /*
+ * Bytes of device workspace a handle needs (the ownership model above).
+ *   format    : PBCG_CSR, PBCG_ST_2D5, PBCG_ST_3D7 or PBCG_ST_DIA5
+ *   n, nnz    : dimension and stored entries (nnz is used for PBCG_CSR only)
+ *   width     : PBCG_CSR: the largest number of stored entries in any row and,
+ *               with with_transpose, in any column (it bounds every slice of
+ *               the sliced-ELL layouts); ignored otherwise
+ *   precision, precond : as for create
+ *   with_transpose : nonzero reserves the transposed layout (PBCG_CSR, DIA5),
+ *               which the first transposed solve, apply or gradient builds
+ * Returns 0 (and sets the last error) on invalid arguments.  The size covers
+ * the 12 solver vectors, x and b (N padded to 2048, in the storage precision
+ * and FP64), the reduction partials (32 x 1024 doubles), the device scalars
+ * and the matrix layouts (Section 1's A; for the adjoint solve of the
+ * differentiable form, A^T).
+ */
+size_t pbicgstab_workspace_bytes(int format, int64_t n, int64_t nnz, int32_t width,
+                                 int precision, int precond, int with_transpose);
+
+/*
  * Create a solver for a CSR matrix (Section 1: A sparse, N x N).
  *   n, nnz          : dimension and number of stored entries (n >= 1)
- *   rowptr, col, val: host arrays, rowptr[n+1] (rowptr[0] = 0, nondecreasing,
- *                     rowptr[n] = nnz), col[nnz] in [0, n), val[nnz]; duplicate
- *                     entries are kept and summed in stored order
+ *   rowptr, col, val: device arrays, rowptr[n+1] (rowptr[0] = 0,
+ *                     nondecreasing, rowptr[n] = nnz), col[nnz] in [0, n),
+ *                     val[nnz]; read during the call only (copied to the host,
+ *                     where the layout is built); duplicate entries are kept
+ *                     and summed in stored order
  *   precision       : PBCG_FP64 or PBCG_MIXED (values rounded once to FP32)
  *   precond         : PBCG_PC_NONE or PBCG_PC_JACOBI (M^-1 = 1/diag, the
  *                     diagonal being the sum of the entries with col == row;
  *                     PBCG_ERR_ZERO_DIAG if one is zero)
- * The matrix is stored on the device as sliced ELLPACK (slice height 64) in
- * the stored column order of each row.
+ *   workspace, ws_bytes : caller-owned device memory, 256-byte aligned, of at
+ *                     least pbicgstab_workspace_bytes(PBCG_CSR, ...) bytes;
+ *                     PBCG_ERR_WORKSPACE_TOO_SMALL if the layouts do not fit
+ * The matrix is stored in the workspace as sliced ELLPACK (slice height 64)
+ * in the stored column order of each row.
  */
 int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
                          const int32_t* col, const double* val, int precision, int precond,
-                         void* stream);
+                         void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Create a solver for a structured operator on a lexicographically ordered
@@ -186,10 +221,14 @@ int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t
  * i.e. homogeneous Dirichlet boundaries).
  *   kind : PBCG_ST_2D5, PBCG_ST_3D7 or PBCG_ST_DIA5
  *   dims : host int64[2] or int64[3]
- *   coef : host array, see the kind enum (coefficients in ascending column order)
+ *   coef : 2D5 / 3D7: host array of the 5 / 7 constants (see the format
+ *          enum, ascending column order); DIA5: device array [5*N] (row d =
+ *          S, W, C, E, N), read during the call only
+ *   workspace, ws_bytes : as for pbicgstab_create_csr (sized for `kind`)
  */
 int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, const double* coef,
-                             int precision, int precond, void* stream);
+                             int precision, int precond, void* workspace, size_t ws_bytes,
+                             void* stream);
 
 /*
  * Solve A x = b (or A^T x = b) with pipelined BiCGStab, Algorithm 2, and
@@ -280,7 +319,7 @@ int pbicgstab_get_vector(pbcg_handle h, int which, double* out, void* stream);
  */
 int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, void* stream);
 
-/* Problem size, stored entries, and device bytes held by the handle. */
+/* Problem size, stored entries, and the workspace bytes the handle uses. */
 int pbicgstab_info(pbcg_handle h, int64_t* n, int64_t* nnz, int64_t* device_bytes);
 
 void pbicgstab_destroy(pbcg_handle h);

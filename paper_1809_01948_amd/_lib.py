@@ -10,12 +10,12 @@ LIB_PATH = os.path.join(_HERE, "libpbicgstab.so")
 
 FP64, MIXED = 0, 1
 PC_NONE, PC_JACOBI = 0, 1
-ST_2D5, ST_3D7, ST_DIA5 = 0, 1, 2
+ST_2D5, ST_3D7, ST_DIA5, CSR = 0, 1, 2, 3
 
 STATUS_NAMES = {
     0: "CONVERGED", 1: "MAXIT", 2: "BREAKDOWN_RHO", 3: "BREAKDOWN_OMEGA", 4: "NONFINITE",
     5: "TRUE_RES_NOT_MET", -1: "ERR_INVALID_ARG", -2: "ERR_HIP", -3: "ERR_ZERO_DIAG",
-    -5: "ERR_UNSUPPORTED",
+    -4: "ERR_WORKSPACE_TOO_SMALL", -5: "ERR_UNSUPPORTED",
 }
 
 # every exported entry point: name -> (restype, argtypes)
@@ -23,10 +23,12 @@ _c = ctypes
 _P = _c.c_void_p
 SIGNATURES = {
     "pbicgstab_default_opts": (None, [_P]),
+    "pbicgstab_workspace_bytes": (_c.c_size_t, [_c.c_int, _c.c_int64, _c.c_int64, _c.c_int32,
+                                                _c.c_int, _c.c_int, _c.c_int]),
     "pbicgstab_create_csr": (_c.c_int, [_c.POINTER(_P), _c.c_int64, _c.c_int64, _P, _P, _P,
-                                        _c.c_int, _c.c_int, _P]),
+                                        _c.c_int, _c.c_int, _P, _c.c_size_t, _P]),
     "pbicgstab_create_stencil": (_c.c_int, [_c.POINTER(_P), _c.c_int, _P, _P, _c.c_int, _c.c_int,
-                                            _P]),
+                                            _P, _c.c_size_t, _P]),
     "pbicgstab_solve": (_c.c_int, [_P, _P, _P, _P, _P]),
     "classic_bicgstab_solve": (_c.c_int, [_P, _P, _P, _P, _P]),
     "pbicgstab_apply": (_c.c_int, [_P, _P, _P, _c.c_int, _P]),

@@ -28,6 +28,7 @@ constexpr int kMaxBlocks = 2048;     // max blocks of an SPMV kernel
 constexpr int kMaxPartials = 1024;   // partials per slot = max blocks of a kernel writing partials
 constexpr int kNumSlots = 32;        // partial slots
 constexpr int64_t kPadElems = 2048;  // vector padding granularity (elements)
+constexpr int64_t kWsAlign = 256;    // alignment of every piece of the caller's workspace
 constexpr int kXcds = 8;             // MI355X: workgroups are dispatched round-robin over 8 XCDs
 constexpr int kSellC = 64;           // SELL slice height = one wavefront
 

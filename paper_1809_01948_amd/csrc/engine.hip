@@ -70,23 +70,80 @@ int guarded(F&& f) {
   }
 }
 
+int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+// Device memory of a handle: consecutive 256-byte aligned pieces of the
+// caller's workspace, zeroed.  The pieces and their order are those that
+// pbicgstab_workspace_bytes adds up (layout_bytes).
 void* dalloc(Solver& S, size_t bytes) {
-  void* p = nullptr;
   if (bytes == 0) bytes = 256;
-  hipck(hipMalloc(&p, bytes), "hipMalloc");
-  S.allocations.push_back(p);
+  const size_t off = (size_t)round_up((int64_t)S.ws_used, kWsAlign);
+  if (off + bytes > S.ws_size)
+    fail(PBCG_ERR_WORKSPACE_TOO_SMALL,
+         "workspace too small: " + std::to_string(off + bytes) + " bytes needed so far, " +
+             std::to_string(S.ws_size) + " given (size it with pbicgstab_workspace_bytes)");
+  void* p = S.ws + off;
+  S.ws_used = off + bytes;
   hipck(hipMemset(p, 0, bytes), "hipMemset");
   return p;
 }
 
-int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+// Workspace bytes of one layout (see pbicgstab_workspace_bytes): the same
+// pieces, in the same order and alignment, as create and the transpose build
+// take.  For sliced ELL, `width` bounds every slice's width (the longest row,
+// and for the transpose the longest column).
+size_t layout_bytes(int format, int64_t n, int64_t nnz, int64_t width, int precision,
+                    int precond, bool with_transpose) {
+  const int64_t ts = precision == PBCG_FP64 ? 8 : 4;
+  const int64_t npad = round_up(n, kPadElems);
+  int64_t used = 0;
+  auto take = [&](int64_t bytes) {
+    if (bytes == 0) bytes = 256;
+    used = round_up(used, kWsAlign) + bytes;
+  };
+  for (int v = 0; v < V_COUNT; ++v) take(npad * ts);
+  take(npad * 8);                                   // x
+  take(npad * 8);                                   // b
+  take((int64_t)sizeof(double) * kNumSlots * kMaxPartials);
+  take(2 * (int64_t)sizeof(DevScalars));
+  if (format == PBCG_CSR) {
+    const int64_t ns = (n + kSellC - 1) / kSellC;
+    const int64_t elems = ns * kSellC * width;
+    auto sell = [&]() {
+      take((ns + 1) * 8);
+      take(elems * 4);
+      take(elems * ts);
+    };
+    sell();                                         // A
+    take(std::max<int64_t>(nnz, 1) * 8);            // CSR entry -> SELL slot
+    take((n + 1) * 4);                              // rowptr
+    take(std::max<int64_t>(nnz, 1) * 4);            // col
+    take(n * 8);                                    // diagonal positions
+    if (precond) take(npad * ts);                   // dinv
+    if (with_transpose) {
+      sell();                                       // A^T
+      take(std::max<int64_t>(nnz, 1) * 8);
+    }
+  } else if (format == PBCG_ST_DIA5) {
+    take(5 * npad * ts);
+    if (precond) take(npad * ts);
+    if (with_transpose) take(5 * npad * ts);
+  }
+  return (size_t)round_up(used, kWsAlign);
+}
 
 // A recursive convergence whose FP64 true residual misses the tolerance is
 // followed by a replacement and more iterations at most this many times per
 // solve; the next such failure ends it with TRUE_RES_NOT_MET.
 constexpr int kMaxForcedReplacements = 3;
 
-void common_setup(Solver& S, int precision, int precond) {
+void common_setup(Solver& S, int precision, int precond, void* workspace, size_t ws_bytes) {
+  if (!workspace) fail(PBCG_ERR_INVALID_ARG, "workspace is null");
+  if (((uintptr_t)workspace) % kWsAlign != 0)
+    fail(PBCG_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  S.ws = (char*)workspace;
+  S.ws_size = ws_bytes;
+  S.ws_used = 0;
   if (precision != PBCG_FP64 && precision != PBCG_MIXED) fail(PBCG_ERR_INVALID_ARG, "precision must be PBCG_FP64 or PBCG_MIXED");
   if (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI) fail(PBCG_ERR_INVALID_ARG, "precond must be PBCG_PC_NONE or PBCG_PC_JACOBI");
   if (S.n > (int64_t)2000000000) fail(PBCG_ERR_UNSUPPORTED, "n exceeds the int32 index range");
@@ -136,23 +193,9 @@ void common_setup(Solver& S, int precision, int precond) {
   hipck(hipEventCreateWithFlags(&S.ev_poll[1], hipEventDisableTiming), "hipEventCreate");
   hipck(hipEventCreate(&S.ev_t0), "hipEventCreate");
   hipck(hipEventCreate(&S.ev_t1), "hipEventCreate");
-  long stagger = -1;
-  if (const char* env = std::getenv("PBCG_VEC_STAGGER")) stagger = std::strtol(env, nullptr, 10);
-  if (stagger < 0) {
-    for (int v = 0; v < V_COUNT; ++v) S.vec[v] = dalloc(S, S.npad * S.tsize);
-    S.x = (double*)dalloc(S, S.npad * 8);
-    S.b = (double*)dalloc(S, S.npad * 8);
-  } else {
-    // one slab; consecutive arrays start `stagger` bytes (a multiple of 256)
-    // past the end of the previous one
-    const int64_t st = round_up(stagger, 256);
-    const int64_t vb = round_up(S.npad * S.tsize, 256) + st;
-    const int64_t xb = round_up(S.npad * 8, 256) + st;
-    char* slab = (char*)dalloc(S, V_COUNT * vb + 2 * xb);
-    for (int v = 0; v < V_COUNT; ++v) S.vec[v] = slab + v * vb;
-    S.x = (double*)(slab + V_COUNT * vb);
-    S.b = (double*)(slab + V_COUNT * vb + xb);
-  }
+  for (int v = 0; v < V_COUNT; ++v) S.vec[v] = dalloc(S, S.npad * S.tsize);
+  S.x = (double*)dalloc(S, S.npad * 8);
+  S.b = (double*)dalloc(S, S.npad * 8);
   S.partials = (double*)dalloc(S, sizeof(double) * kNumSlots * kMaxPartials);
   S.sc = (DevScalars*)dalloc(S, 2 * sizeof(DevScalars));
   hipck(hipHostMalloc((void**)&S.h_sc, 3 * sizeof(DevScalars), hipHostMallocDefault),
@@ -302,6 +345,34 @@ void norms_grid(Solver& S, const double* dia /* 5*n or null */) {
   set_norm_bounds(S, rs, cs, mr, mr);
 }
 
+// Values of the host CSR copy into a sliced-ELL layout whose slot of CSR
+// entry k is pos[k] (padding slots stay 0).
+void upload_scattered(Solver& S, OpData& o, const std::vector<int64_t>& pos) {
+  std::vector<double> sval(o.sell_elems, 0.0);
+  for (int64_t kk = 0; kk < S.nnz; ++kk) sval[pos[kk]] = S.h_val[kk];
+  if (S.precision == PBCG_FP64) upload_vals<double>(S, o.val, sval);
+  else upload_vals<float>(S, o.val, sval);
+}
+
+// Jacobi diagonal (sum of the entries with col == row) of the host CSR copy
+void upload_dinv_csr(Solver& S) {
+  std::vector<double> di(S.npad, 0.0);
+  for (int64_t i = 0; i < S.n; ++i) {
+    double d = 0.0;
+    for (int64_t kk = S.h_rowptr[i]; kk < S.h_rowptr[i + 1]; ++kk)
+      if (S.h_col[kk] == i) d += S.h_val[kk];
+    if (S.precision == PBCG_FP64) {
+      if (d == 0.0) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
+      di[i] = 1.0 / d;
+    } else {
+      if ((float)d == 0.0f) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
+      di[i] = (double)(1.0f / (float)d);
+    }
+  }
+  if (S.precision == PBCG_FP64) upload_vals<double>(S, S.dinv, di);
+  else upload_vals<float>(S, S.dinv, di);
+}
+
 // After the DIA5 coefficients changed on the device: the host copy and the
 // bounds of the automated criterion (||A|| from the row and column sums,
 // ||M^-1|| = max |1 / a_ii|) from the stored coefficients.
@@ -352,10 +423,10 @@ void build_transpose(Solver& S) {
     int mw = 0;
     build_sell(n, trp.data(), tcol.data(), tval.data(), sptr, scol, sval, pos, mw);
     upload_sell(S, S.AT, sptr, scol, sval, mw);
-    std::vector<int64_t> posAT(nnz);
-    for (int64_t kk = 0; kk < nnz; ++kk) posAT[kk] = pos[where[kk]];
+    S.h_posAT.assign(nnz, 0);
+    for (int64_t kk = 0; kk < nnz; ++kk) S.h_posAT[kk] = pos[where[kk]];
     S.d_posAT = (int64_t*)dalloc(S, std::max<int64_t>(nnz, 1) * 8);
-    hipck(hipMemcpy(S.d_posAT, posAT.data(), nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
+    hipck(hipMemcpy(S.d_posAT, S.h_posAT.data(), nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
   } else if (S.kind == OP_ST2D5 || S.kind == OP_ST3D7) {
     S.AT = S.A;
     const int nd = S.kind == OP_ST2D5 ? 5 : 7;
@@ -760,7 +831,6 @@ void destroy_solver(pbcg_solver* p) {
   Solver& S = p->S;
   for (auto& kv : S.graphs) (void)hipGraphExecDestroy(kv.second);
   if (S.s1) (void)hipStreamSynchronize(S.s1);
-  for (void* a : S.allocations) (void)hipFree(a);
   if (S.h_sc) (void)hipHostFree(S.h_sc);
   hipEvent_t evs[] = {S.ev_in, S.ev_out, S.ev_t0, S.ev_t1, S.ev_poll[0], S.ev_poll[1]};
   for (hipEvent_t e : evs)
@@ -781,52 +851,76 @@ void pbicgstab_default_opts(pbcg_opts* opt) {
   if (opt) *opt = defaults();
 }
 
-int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr,
-                         const int32_t* col, const double* val, int precision, int precond,
-                         void* stream) {
+size_t pbicgstab_workspace_bytes(int format, int64_t n, int64_t nnz, int32_t width,
+                                 int precision, int precond, int with_transpose) {
+  g_last_error.clear();
+  const bool csr = format == PBCG_CSR;
+  if ((!csr && format != PBCG_ST_2D5 && format != PBCG_ST_3D7 && format != PBCG_ST_DIA5) ||
+      n < 1 || n > (int64_t)2000000000 || (csr && (nnz < 0 || width < 0)) ||
+      (precision != PBCG_FP64 && precision != PBCG_MIXED) ||
+      (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI)) {
+    g_last_error = "pbicgstab_workspace_bytes: invalid arguments";
+    return 0;
+  }
+  return layout_bytes(format, n, nnz, width, precision, precond, with_transpose != 0);
+}
+
+int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t* rowptr_d,
+                         const int32_t* col_d, const double* val_d, int precision, int precond,
+                         void* workspace, size_t ws_bytes, void* stream) {
   return guarded([&]() -> int {
     if (!out) fail(PBCG_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
     if (n < 1) fail(PBCG_ERR_INVALID_ARG, "n must be >= 1");
     if (nnz < 0 || nnz > (int64_t)2000000000) fail(PBCG_ERR_INVALID_ARG, "nnz out of range");
-    if (!rowptr || (nnz > 0 && (!col || !val))) fail(PBCG_ERR_INVALID_ARG, "null CSR array");
+    if (!rowptr_d || (nnz > 0 && (!col_d || !val_d))) fail(PBCG_ERR_INVALID_ARG, "null CSR array");
+    hipStream_t cs = (hipStream_t)stream;
+    hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    // the CSR arrays are read once, on the host, where the layout is built
+    std::vector<int32_t> rowptr(n + 1), col(nnz);
+    std::vector<double> val(nnz);
+    hipck(hipMemcpy(rowptr.data(), rowptr_d, (n + 1) * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (nnz > 0) {
+      hipck(hipMemcpy(col.data(), col_d, nnz * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+      hipck(hipMemcpy(val.data(), val_d, nnz * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+    }
     if (rowptr[0] != 0 || rowptr[n] != nnz) fail(PBCG_ERR_INVALID_ARG, "rowptr[0] must be 0 and rowptr[n] == nnz");
     for (int64_t i = 0; i < n; ++i)
       if (rowptr[i + 1] < rowptr[i]) fail(PBCG_ERR_INVALID_ARG, "rowptr must be nondecreasing");
     for (int64_t kk = 0; kk < nnz; ++kk)
       if (col[kk] < 0 || col[kk] >= n) fail(PBCG_ERR_INVALID_ARG, "column index out of range");
-    hipStream_t cs = (hipStream_t)stream;
-    if (cs) hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
     auto* p = new pbcg_solver();
     try {
       Solver& S = p->S;
       S.n = n;
       S.nnz = nnz;
       S.kind = OP_SELL;
-      common_setup(S, precision, precond);
-      S.h_rowptr.assign(rowptr, rowptr + n + 1);
-      S.h_col.assign(col, col + nnz);
-      S.h_val.assign(val, val + nnz);
-      std::vector<int64_t> sptr, pos;
+      common_setup(S, precision, precond, workspace, ws_bytes);
+      S.h_rowptr = std::move(rowptr);
+      S.h_col = std::move(col);
+      S.h_val = std::move(val);
+      std::vector<int64_t> sptr;
       std::vector<int32_t> scol;
       std::vector<double> sval;
       int mw = 0;
-      build_sell(n, rowptr, col, val, sptr, scol, sval, pos, mw);
+      build_sell(n, S.h_rowptr.data(), S.h_col.data(), S.h_val.data(), sptr, scol, sval, S.h_pos,
+                 mw);
       upload_sell(S, S.A, sptr, scol, sval, mw);
       S.d_posA = (int64_t*)dalloc(S, std::max<int64_t>(nnz, 1) * 8);
-      hipck(hipMemcpy(S.d_posA, pos.data(), nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
+      hipck(hipMemcpy(S.d_posA, S.h_pos.data(), nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
       S.d_rowptr = (int32_t*)dalloc(S, (n + 1) * 4);
       S.d_col = (int32_t*)dalloc(S, std::max<int64_t>(nnz, 1) * 4);
-      hipck(hipMemcpy(S.d_rowptr, rowptr, (n + 1) * 4, hipMemcpyHostToDevice), "hipMemcpy");
-      hipck(hipMemcpy(S.d_col, col, nnz * 4, hipMemcpyHostToDevice), "hipMemcpy");
+      hipck(hipMemcpy(S.d_rowptr, S.h_rowptr.data(), (n + 1) * 4, hipMemcpyHostToDevice),
+            "hipMemcpy");
+      hipck(hipMemcpy(S.d_col, S.h_col.data(), nnz * 4, hipMemcpyHostToDevice), "hipMemcpy");
       set_dinv_csr(S);
       norms_csr(S);
       if (S.dinv) {
         double m = 0.0;
         for (int64_t i = 0; i < n; ++i) {
           double d = 0.0;
-          for (int64_t kk = rowptr[i]; kk < rowptr[i + 1]; ++kk)
-            if (col[kk] == i) d += val[kk];
+          for (int64_t kk = S.h_rowptr[i]; kk < S.h_rowptr[i + 1]; ++kk)
+            if (S.h_col[kk] == i) d += S.h_val[kk];
           m = std::max(m, std::fabs(1.0 / d));
         }
         S.normM = m;
@@ -841,12 +935,13 @@ int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t
   });
 }
 
-int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, const double* coef,
-                             int precision, int precond, void* stream) {
+int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims,
+                             const double* coef_in, int precision, int precond, void* workspace,
+                             size_t ws_bytes, void* stream) {
   return guarded([&]() -> int {
     if (!out) fail(PBCG_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
-    if (!dims || !coef) fail(PBCG_ERR_INVALID_ARG, "dims and coef are required");
+    if (!dims || !coef_in) fail(PBCG_ERR_INVALID_ARG, "dims and coef are required");
     const int nd = kind == PBCG_ST_3D7 ? 3 : 2;
     if (kind != PBCG_ST_2D5 && kind != PBCG_ST_3D7 && kind != PBCG_ST_DIA5)
       fail(PBCG_ERR_INVALID_ARG, "unknown stencil kind");
@@ -856,13 +951,21 @@ int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, co
       n *= dims[d];
     }
     hipStream_t cs = (hipStream_t)stream;
-    if (cs) hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
+    // constant stencils: host coefficients; DIA5: device rows, read once here
+    std::vector<double> dia_host;
+    const double* coef = coef_in;
+    if (kind == PBCG_ST_DIA5) {
+      dia_host.resize(5 * n);
+      hipck(hipMemcpy(dia_host.data(), coef_in, 5 * n * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+      coef = dia_host.data();
+    }
     auto* p = new pbcg_solver();
     try {
       Solver& S = p->S;
       S.n = n;
       S.kind = kind == PBCG_ST_2D5 ? OP_ST2D5 : kind == PBCG_ST_3D7 ? OP_ST3D7 : OP_DIA5;
-      common_setup(S, precision, precond);
+      common_setup(S, precision, precond, workspace, ws_bytes);
       OpData& o = S.A;
       o.kind = S.kind;
       for (int d = 0; d < nd; ++d) o.dims[d] = (int)dims[d];
@@ -1012,23 +1115,25 @@ int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, 
     hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
     hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
     if (S.kind == OP_SELL) {
-      double* dv = nullptr;
-      if (!on_device) {
-        hipck(hipMalloc(&dv, std::max<int64_t>(S.nnz, 1) * 8), "hipMalloc");
-        hipck(hipMemcpy(dv, values, S.nnz * 8, hipMemcpyHostToDevice), "hipMemcpy");
+      if (on_device) {
+        // scattered into the layouts on the device (values, Jacobi diagonal, A^T)
+        hipck(hipMemsetAsync(&S.sc->bad_diag, 0, sizeof(int32_t), S.s1), "hipMemsetAsync");
+        launch_update_sell(S, values, S.s1);
+        hipck(hipGetLastError(), "update launch");
+        hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
+        // the host copy stays current for a later transpose build and the norm bounds
+        hipck(hipMemcpy(S.h_val.data(), values, S.nnz * 8, hipMemcpyDeviceToHost), "hipMemcpy");
+        int32_t bad = 0;
+        hipck(hipMemcpy(&bad, &S.sc->bad_diag, 4, hipMemcpyDeviceToHost), "hipMemcpy");
+        if (bad) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
+      } else {
+        // host values: scattered on the host and uploaded (no device staging)
+        std::memcpy(S.h_val.data(), values, S.nnz * 8);
+        upload_scattered(S, S.A, S.h_pos);
+        if (S.have_AT) upload_scattered(S, S.AT, S.h_posAT);
+        if (S.precond) upload_dinv_csr(S);
       }
-      const double* src = on_device ? values : dv;
-      hipck(hipMemsetAsync(&S.sc->bad_diag, 0, sizeof(int32_t), S.s1), "hipMemsetAsync");
-      launch_update_sell(S, src, S.s1);
-      hipck(hipGetLastError(), "update launch");
-      hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");
-      // keep the host copy current for a later transpose build and the norm bounds
-      hipck(hipMemcpy(S.h_val.data(), src, S.nnz * 8, hipMemcpyDeviceToHost), "hipMemcpy");
-      if (dv) (void)hipFree(dv);
       norms_csr(S);
-      int32_t bad = 0;
-      hipck(hipMemcpy(&bad, &S.sc->bad_diag, 4, hipMemcpyDeviceToHost), "hipMemcpy");
-      if (bad) fail(PBCG_ERR_ZERO_DIAG, "zero diagonal after value update");
       return PBCG_OK;
     }
     if (S.kind == OP_ST2D5 || S.kind == OP_ST3D7) {
@@ -1230,20 +1335,7 @@ int pbicgstab_info(pbcg_handle h, int64_t* n, int64_t* nnz, int64_t* device_byte
     Solver& S = H(h);
     if (n) *n = S.n;
     if (nnz) *nnz = S.nnz;
-    if (device_bytes) {
-      int64_t b = 0;
-      b += V_COUNT * S.npad * (int64_t)S.tsize + 2 * S.npad * 8;
-      if (S.dinv) b += S.npad * S.tsize;
-      auto opb = [&](const OpData& o) {
-        int64_t r = 0;
-        if (o.kind == OP_SELL) r += (o.nslices + 1) * 8 + o.sell_elems * (4 + (int64_t)S.tsize);
-        if (o.kind == OP_DIA5 && o.dia) r += 5 * S.npad * (int64_t)S.tsize;
-        return r;
-      };
-      b += opb(S.A);
-      if (S.have_AT && S.AT.kind != OP_ST2D5 && S.AT.kind != OP_ST3D7) b += opb(S.AT);
-      *device_bytes = b;
-    }
+    if (device_bytes) *device_bytes = (int64_t)S.ws_used;
     return PBCG_OK;
   });
 }

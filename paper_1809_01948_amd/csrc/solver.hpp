@@ -52,8 +52,10 @@ struct Solver {
   int64_t* d_posAT = nullptr;   // CSR entry -> SELL slot of A^T
   int64_t* d_diagpos = nullptr; // row -> CSR index of its diagonal (or -1)
 
-  // device arena
-  std::vector<void*> allocations;
+  // device memory: pieces of the caller's workspace (ws_used bytes taken)
+  char* ws = nullptr;
+  size_t ws_size = 0, ws_used = 0;
+  std::vector<int64_t> h_pos, h_posAT;   // CSR entry -> SELL slot of A, A^T (host copies)
   void* vec[16] = {nullptr};    // stored solver vectors (T), see VecId
   double* x = nullptr;          // iterate (FP64, padded)
   double* b = nullptr;          // right-hand side (FP64, padded)

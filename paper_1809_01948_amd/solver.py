@@ -39,14 +39,38 @@ _PRECOND = {"none": L.PC_NONE, None: L.PC_NONE, "jacobi": L.PC_JACOBI}
 _KIND = {"2d5": L.ST_2D5, "3d7": L.ST_3D7, "dia5": L.ST_DIA5}
 
 
+def workspace_bytes(fmt: str, n: int, nnz: int = 0, width: int = 0, precision="fp64",
+                    precond="jacobi", with_transpose=True) -> int:
+    """pbicgstab_workspace_bytes for a format 'csr', '2d5', '3d7' or 'dia5'."""
+    code = L.CSR if fmt == "csr" else _KIND[fmt]
+    nb = L.load().pbicgstab_workspace_bytes(code, n, nnz, width, _PRECISION[precision],
+                                            _PRECOND[precond], 1 if with_transpose else 0)
+    if nb == 0:
+        msg = L.load().pbicgstab_last_error()
+        raise L.PbcgError(-1, msg.decode() if msg else "invalid workspace query")
+    return int(nb)
+
+
+def _workspace(nbytes: int) -> torch.Tensor:
+    """Caller-owned device workspace: a uint8 CUDA tensor (torch's caching
+    allocator returns blocks aligned far beyond the 256 bytes required)."""
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace tensor is not 256-byte aligned")
+    return ws
+
+
 class Solver:
     """A matrix living on the GPU, ready for (pipelined) BiCGStab solves.
 
-    Create with :meth:`from_csr` or :meth:`from_stencil` (host NumPy input).
+    Create with :meth:`from_csr` or :meth:`from_stencil` (NumPy or torch
+    input; the arrays are handed to the library as device tensors).  The
+    handle's device data lives in a uint8 torch tensor this object owns
+    (``workspace``), sized by pbicgstab_workspace_bytes.
     """
 
     def __init__(self, handle, n: int, kind: str, precision: str, precond: str, dims=None,
-                 nnz: int = 0):
+                 nnz: int = 0, workspace: Optional[torch.Tensor] = None):
         self._h = handle
         self.n = n
         self.kind = kind
@@ -54,41 +78,68 @@ class Solver:
         self.precond = precond
         self.dims = dims
         self.nnz = nnz
+        self.workspace = workspace
 
     # ---- construction -------------------------------------------------
     @classmethod
-    def from_csr(cls, rowptr, col, val, precision="fp64", precond="jacobi"):
+    def from_csr(cls, rowptr, col, val, precision="fp64", precond="jacobi",
+                 with_transpose=True, workspace: Optional[torch.Tensor] = None):
         lib = L.load()
-        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
-        col = np.ascontiguousarray(col, dtype=np.int32)
-        val = np.ascontiguousarray(val, dtype=np.float64)
-        n = len(rowptr) - 1
-        h = ctypes.c_void_p()
         torch.cuda.init()
+        rp = torch.as_tensor(np.ascontiguousarray(rowptr, dtype=np.int32)
+                             if not isinstance(rowptr, torch.Tensor) else rowptr,
+                             dtype=torch.int32).cuda().contiguous()
+        cl = torch.as_tensor(np.ascontiguousarray(col, dtype=np.int32)
+                             if not isinstance(col, torch.Tensor) else col,
+                             dtype=torch.int32).cuda().contiguous()
+        vl = torch.as_tensor(np.ascontiguousarray(val, dtype=np.float64)
+                             if not isinstance(val, torch.Tensor) else val,
+                             dtype=torch.float64).cuda().contiguous()
+        n = rp.numel() - 1
+        nnz = cl.numel()
+        # slice-width bound of the sliced-ELL layouts: longest row (and column)
+        rows = torch.diff(rp.to(torch.int64))
+        width = int(rows.max()) if n > 0 else 0
+        if with_transpose and nnz > 0:
+            width = max(width, int(torch.bincount(cl.to(torch.int64), minlength=n).max()))
+        if workspace is None:
+            workspace = _workspace(workspace_bytes("csr", n, nnz, width, precision, precond,
+                                                   with_transpose))
+        h = ctypes.c_void_p()
         L.check(lib.pbicgstab_create_csr(
-            ctypes.byref(h), n, len(col), rowptr.ctypes.data_as(ctypes.c_void_p),
-            col.ctypes.data_as(ctypes.c_void_p), val.ctypes.data_as(ctypes.c_void_p),
-            _PRECISION[precision], _PRECOND[precond], _stream()))
-        return cls(h, n, "csr", precision, precond, nnz=len(col))
+            ctypes.byref(h), n, nnz, _ptr(rp), _ptr(cl), _ptr(vl), _PRECISION[precision],
+            _PRECOND[precond], _ptr(workspace), workspace.numel(), _stream()))
+        return cls(h, n, "csr", precision, precond, nnz=nnz, workspace=workspace)
 
     @classmethod
-    def from_stencil(cls, kind, dims, coef, precision="fp64", precond="jacobi"):
+    def from_stencil(cls, kind, dims, coef, precision="fp64", precond="jacobi",
+                     with_transpose=True, workspace: Optional[torch.Tensor] = None):
         """kind: '2d5' (coef S,W,C,E,N), '3d7' (D,S,W,C,E,N,U) or 'dia5'
         (coef array (5, N) in the order S, W, C, E, N)."""
         lib = L.load()
-        dims_a = np.ascontiguousarray(dims, dtype=np.int64)
-        coef_a = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
-        h = ctypes.c_void_p()
         torch.cuda.init()
-        L.check(lib.pbicgstab_create_stencil(
-            ctypes.byref(h), _KIND[kind], dims_a.ctypes.data_as(ctypes.c_void_p),
-            coef_a.ctypes.data_as(ctypes.c_void_p), _PRECISION[precision], _PRECOND[precond],
-            _stream()))
+        dims_a = np.ascontiguousarray(dims, dtype=np.int64)
         n = int(np.prod(dims_a))
+        if kind == "dia5":
+            coef_t = torch.as_tensor(np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
+                                     if not isinstance(coef, torch.Tensor) else coef.reshape(-1),
+                                     dtype=torch.float64).cuda().contiguous()
+            coef_p = _ptr(coef_t)
+        else:
+            coef_a = np.ascontiguousarray(coef, dtype=np.float64).reshape(-1)
+            coef_p = coef_a.ctypes.data_as(ctypes.c_void_p)
+        if workspace is None:
+            workspace = _workspace(workspace_bytes(kind, n, 0, 0, precision, precond,
+                                                   with_transpose))
+        h = ctypes.c_void_p()
+        L.check(lib.pbicgstab_create_stencil(
+            ctypes.byref(h), _KIND[kind], dims_a.ctypes.data_as(ctypes.c_void_p), coef_p,
+            _PRECISION[precision], _PRECOND[precond], _ptr(workspace), workspace.numel(),
+            _stream()))
         nn = ctypes.c_int64()
         L.check(lib.pbicgstab_info(h, None, ctypes.byref(nn), None))
         return cls(h, n, kind, precision, precond, dims=tuple(int(d) for d in dims_a),
-                   nnz=nn.value)
+                   nnz=nn.value, workspace=workspace)
 
     @classmethod
     def from_problem(cls, prob, form="csr", precision="fp64", precond=None):
@@ -235,6 +286,7 @@ class Solver:
             torch.cuda.synchronize()
             L.load().pbicgstab_destroy(self._h)
             self._h = None
+        self.workspace = None           # the handle no longer uses it
 
     def __del__(self):
         try:

@@ -64,8 +64,8 @@ def test_binding_matches_header(lib):
     enums = declared_enums()
     assert (enums["PBCG_FP64"], enums["PBCG_MIXED"]) == (lib.FP64, lib.MIXED)
     assert (enums["PBCG_PC_NONE"], enums["PBCG_PC_JACOBI"]) == (lib.PC_NONE, lib.PC_JACOBI)
-    assert (enums["PBCG_ST_2D5"], enums["PBCG_ST_3D7"], enums["PBCG_ST_DIA5"]) == \
-        (lib.ST_2D5, lib.ST_3D7, lib.ST_DIA5)
+    assert (enums["PBCG_ST_2D5"], enums["PBCG_ST_3D7"], enums["PBCG_ST_DIA5"],
+            enums["PBCG_CSR"]) == (lib.ST_2D5, lib.ST_3D7, lib.ST_DIA5, lib.CSR)
     for name, code in enums.items():
         if name in ("PBCG_OK",) or not (name.startswith("PBCG_ERR") or name in (
                 "PBCG_CONVERGED", "PBCG_MAXIT", "PBCG_BREAKDOWN_RHO", "PBCG_BREAKDOWN_OMEGA",
@@ -109,36 +109,54 @@ def test_default_opts(lib):
     L.pbicgstab_default_opts(None)   # tolerated
 
 
-def _create(L, n, rowptr, col, val):
-    h = ctypes.c_void_p()
-    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
-    ci = np.ascontiguousarray(col, dtype=np.int32)
-    va = np.ascontiguousarray(val, dtype=np.float64)
-    rc = L.pbicgstab_create_csr(ctypes.byref(h), n, len(ci), rp.ctypes.data, ci.ctypes.data,
-                                va.ctypes.data, 0, 0, None)
-    return rc, h, L.pbicgstab_last_error().decode()
-
-
-@pytest.mark.parametrize("case,msg", [
-    ("n0", "n must be"),
-    ("rowptr0", "rowptr[0]"),
-    ("decreasing", "nondecreasing"),
-    ("col", "column index"),
-])
-def test_create_rejects_malformed_csr_on_host(lib, case, msg):
+def test_create_rejects_bad_arguments_before_any_device_call(lib):
+    """n < 1, null CSR arrays and an unknown stencil kind are caught on the
+    host (the CSR structure itself is read from the device and checked
+    there: GPU tests)."""
     L = lib.load()
-    rowptr, col, val, n = [0, 1, 2], [0, 1], [1.0, 2.0], 2
-    if case == "n0":
-        n = 0
-    elif case == "rowptr0":
-        rowptr = [1, 1, 2]
-    elif case == "decreasing":
-        rowptr, n = [0, 2, 1, 2], 3
-    elif case == "col":
-        col = [0, 5]
-    rc, h, err = _create(L, n, rowptr, col, val)
-    assert rc == -1 and not h.value
-    assert msg in err
+    h = ctypes.c_void_p()
+    ws = ctypes.c_void_p(256)
+    rc = L.pbicgstab_create_csr(ctypes.byref(h), 0, 0, ws, ws, ws, 0, 0, ws, 1 << 20, None)
+    assert rc == -1 and not h.value and "n must be" in L.pbicgstab_last_error().decode()
+    rc = L.pbicgstab_create_csr(ctypes.byref(h), 4, 4, None, None, None, 0, 0, ws, 1 << 20, None)
+    assert rc == -1 and not h.value and "null CSR" in L.pbicgstab_last_error().decode()
+    dims = (ctypes.c_int64 * 2)(4, 4)
+    rc = L.pbicgstab_create_stencil(ctypes.byref(h), 7, dims, ws, 0, 0, ws, 1 << 20, None)
+    assert rc == -1 and "kind" in L.pbicgstab_last_error().decode()
+
+
+def _ws(L, fmt, n, nnz=0, width=0, prec=0, pc=0, tr=0):
+    return L.pbicgstab_workspace_bytes(fmt, n, nnz, width, prec, pc, tr)
+
+
+def test_workspace_bytes(lib):
+    """Host arithmetic of the workspace size: 256-byte granularity, no matrix
+    bytes for constant stencils, the documented increments for a Jacobi
+    vector, a transposed layout and one more slot of slice width, and 0 for
+    invalid arguments."""
+    L = lib.load()
+    CSR, S2, S3, D5 = lib.CSR, lib.ST_2D5, lib.ST_3D7, lib.ST_DIA5
+    n = 5000
+    npad = (n + 2047) // 2048 * 2048
+    r256 = lambda b: (b + 255) // 256 * 256
+    base = _ws(L, S2, n)
+    assert base > 0 and base % 256 == 0
+    assert _ws(L, S3, n) == base == _ws(L, S2, n, tr=1) == _ws(L, S2, n, pc=1)
+    assert _ws(L, S2, n, prec=1) < base
+    for prec, ts in ((0, 8), (1, 4)):
+        d = _ws(L, D5, n, prec=prec)
+        assert d == _ws(L, S2, n, prec=prec) + r256(5 * npad * ts)
+        assert _ws(L, D5, n, prec=prec, pc=1) == d + r256(npad * ts)
+        assert _ws(L, D5, n, prec=prec, tr=1) == d + r256(5 * npad * ts)
+        c = _ws(L, CSR, n, 7 * n, 7, prec=prec)
+        ns = (n + 63) // 64
+        assert _ws(L, CSR, n, 7 * n, 8, prec=prec) == c + r256(ns * 64 * 8 * 4) - r256(
+            ns * 64 * 7 * 4) + r256(ns * 64 * 8 * ts) - r256(ns * 64 * 7 * ts)
+        assert _ws(L, CSR, n, 7 * n, 7, prec=prec, tr=1) > c
+    for bad in ((9, n, 0, 0, 0, 0, 0), (CSR, 0, 0, 0, 0, 0, 0), (CSR, n, -1, 0, 0, 0, 0),
+                (S2, n, 0, 0, 2, 0, 0), (S2, n, 0, 0, 0, 3, 0)):
+        assert L.pbicgstab_workspace_bytes(*bad) == 0
+        assert L.pbicgstab_last_error()
 
 
 def test_null_handle_is_rejected(lib):
