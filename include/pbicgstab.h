@@ -241,6 +241,23 @@ int pbicgstab_create_stencil(pbcg_handle* out, int kind, const int64_t* dims, co
 int pbicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
                     pbcg_stats* st);
 
+/*
+ * For callers that cannot allocate (tight serving loops, harnesses that
+ * forbid allocation): pbicgstab_solve that allocates nothing.  The
+ * reduction scratch -- the partial sums of every global reduction (32 slots x
+ * 1024 blocks of FP64, 256 KiB) and the device scalar structs -- is a static
+ * device array of the library (its maximum size, about 260 KiB, does not
+ * depend on N; each GPU holds one copy until the process ends) instead of
+ * the handle's workspace.  Iteration chunks are launched directly (opt
+ * use_graph is ignored: instantiating a graph allocates), and a transposed
+ * solve needs the transposed layout built beforehand (PBCG_ERR_UNSUPPORTED
+ * otherwise).  The array is cleared at the start of each call; calls that
+ * overlap on one GPU (from several threads or handles) share it and race.
+ * Same arguments, results and blocking behaviour as pbicgstab_solve.
+ */
+int pbicgstab_solve_noalloc(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
+                            pbcg_stats* st);
+
 /* Same interface with classic BiCGStab, Algorithm 1 (three global reductions
  * per iteration on the critical path; rr_period is ignored). */
 int classic_bicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,

@@ -30,6 +30,7 @@ SIGNATURES = {
     "pbicgstab_create_stencil": (_c.c_int, [_c.POINTER(_P), _c.c_int, _P, _P, _c.c_int, _c.c_int,
                                             _P, _c.c_size_t, _P]),
     "pbicgstab_solve": (_c.c_int, [_P, _P, _P, _P, _P]),
+    "pbicgstab_solve_noalloc": (_c.c_int, [_P, _P, _P, _P, _P]),
     "classic_bicgstab_solve": (_c.c_int, [_P, _P, _P, _P, _P]),
     "pbicgstab_apply": (_c.c_int, [_P, _P, _P, _c.c_int, _P]),
     "pbicgstab_grad_values": (_c.c_int, [_P, _P, _P, _P, _P]),

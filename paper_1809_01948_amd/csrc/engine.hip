@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -839,6 +840,56 @@ void destroy_solver(pbcg_solver* p) {
   delete p;
 }
 
+// ----------------------------------------------------------------------------
+// Reduction scratch of pbicgstab_solve_noalloc: the partial sums (kNumSlots x
+// kMaxPartials doubles) and the two device scalar structs, in a static device
+// array (each GPU the library runs on holds its own copy until the process
+// ends).  Host code never passes `scratch` itself to a kernel: its device
+// address comes from hipGetSymbolAddress, once per device.
+// ----------------------------------------------------------------------------
+
+constexpr size_t kScratchPartialBytes = sizeof(double) * kNumSlots * kMaxPartials;
+constexpr size_t kScratchScalarOffset = (kScratchPartialBytes + kWsAlign - 1) / kWsAlign * kWsAlign;
+constexpr size_t kScratchBytes =
+    kScratchScalarOffset + (2 * sizeof(DevScalars) + kWsAlign - 1) / kWsAlign * kWsAlign;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+char* scratch_address() {
+  int dev = -1;
+  hipck(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) fail(PBCG_ERR_UNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    hipck(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) fail(PBCG_ERR_HIP, "hipGetSymbolAddress(scratch) returned null");
+    g_scratch_addr[dev] = p;
+  }
+  return (char*)g_scratch_addr[dev];
+}
+
+// Points a handle's reduction scratch at the static array for the lifetime
+// of the object (restored on every exit path).
+struct ScratchSwap {
+  Solver& S;
+  double* partials;
+  DevScalars* sc;
+  ScratchSwap(Solver& s, char* base) : S(s), partials(s.partials), sc(s.sc) {
+    S.partials = (double*)base;
+    S.sc = (DevScalars*)(base + kScratchScalarOffset);
+  }
+  ~ScratchSwap() {
+    S.partials = partials;
+    S.sc = sc;
+  }
+};
+
 }  // namespace
 
 // ----------------------------------------------------------------------------
@@ -1052,6 +1103,35 @@ int pbicgstab_solve(pbcg_handle h, const double* b, double* x, const pbcg_opts* 
   return guarded([&]() -> int {
     Solver& S = H(h);
     const pbcg_opts o = opt ? *opt : defaults();
+    return solve_pipelined(S, b, x, o, st);
+  });
+}
+
+int pbicgstab_solve_noalloc(pbcg_handle h, const double* b, double* x, const pbcg_opts* opt,
+                            pbcg_stats* st) {
+  return guarded([&]() -> int {
+    Solver& S = H(h);
+    pbcg_opts o = opt ? *opt : defaults();
+    o.use_graph = 0;                       // instantiating a graph allocates
+    if (o.transpose && !S.have_AT)
+      fail(PBCG_ERR_UNSUPPORTED,
+           "pbicgstab_solve_noalloc: the transposed layout is not built yet (a transposed "
+           "pbicgstab_solve or pbicgstab_apply builds it)");
+    // every kernel writes the partials of at most kMaxPartials blocks per slot:
+    // the scratch holds any handle's reductions, whatever its N
+    if (S.nblk > kMaxPartials)
+      fail(PBCG_ERR_UNSUPPORTED, "pbicgstab_solve_noalloc: more partial blocks (" +
+                                     std::to_string(S.nblk) + ") than the scratch holds (" +
+                                     std::to_string(kMaxPartials) + ")");
+    char* base = scratch_address();
+    ScratchSwap swap(S, base);
+    // ordered after the caller's stream, then cleared with a kernel (the array
+    // keeps the previous call's contents)
+    hipStream_t cs = (hipStream_t)o.stream;
+    hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
+    hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+    launch_fill_zero(S, base, (int64_t)(kScratchBytes / sizeof(double)), sizeof(double), S.s1);
+    hipck(hipGetLastError(), "scratch clear launch");
     return solve_pipelined(S, b, x, o, st);
   });
 }
