@@ -79,23 +79,110 @@ def test_tp2_periodic_replacement_restores_accuracy(solver, tp2):
 
 
 def test_tp2_automated_replacement(solver, tp2):
-    """Automated replacement (Section 3.6) on TP2.  The logged bound f^r and
-    the first replacements (iterations 10, 26, 43 with the worst-case bound)
-    coincide with the oracle's; later the replacement schedule is as
-    sensitive to rounding as the iterates: with the square-root estimate the
-    oracle converges to 1e-13 after 17 replacements (paper: 10) while GPU
-    trajectories make ~200 and end anywhere between 6e-11 and 3e-2 after 3000
-    iterations (measured 6e-11, 4e-9 and 3.2e-2 on three builds: in the last
-    the replacements every ~16 iterations kept the Krylov process from
-    converging); with the worst-case bound both stop replacing after 7-8 (its
-    restart value then exceeds tau ||r||) and the gap grows.  Asserted: both
-    variants replace, and with the estimate the true residual stays at the
-    recursive one (the gap is kept in check, which is what the strategy is
-    for) or below 1e-7."""
-    x, st = solver.solve(dev(tp2.b), tol=1e-13, maxit=3000, rr_auto="estimate")
-    print("automated (estimate)", st, flush=True)
-    assert st["replacements"] >= 2
-    assert st["rel_res_true"] <= max(1e-7, 1.01 * st["rel_res_recursive"])
-    x2, st2 = solver.solve(dev(tp2.b), tol=1e-13, maxit=3000, rr_auto="bound")
-    print("automated (bound)", st2, flush=True)
-    assert 3 <= st2["replacements"] <= 20
+    """Automated replacement (Section 3.6, worst-case bound eq:DDr_bound and
+    eq:criterion) on TP2.  The paper reports ten replacements, all early, and
+    an attainable accuracy near classic's (~1e-13).  Checked here: a few
+    replacements, all while the residual is large (the bound's restart value
+    after a replacement, ((mu sqrt(N) + 1) ||A|| ||x|| + ||b||) eps, exceeds
+    tau ||r|| once ||r|| < 7e-3 ||b||, so the criterion cannot fire later),
+    and a best true residual along the run at least as good as p-BiCGStab's
+    without replacement (~3e-11 here, ~1e-10 in the paper).  Not reproduced:
+    the paper's ~1e-13 -- after the last replacement this run's gap grows
+    (the design notes list the oracle's outcomes for several grid sizes and
+    both readings of the bound)."""
+    b = dev(tp2.b)
+    x, st = solver.solve(b, tol=1e-13, maxit=1500, rr_auto="bound")
+    print("automated (bound)", st, flush=True)
+    assert 3 <= st["replacements"] <= 20
+    true = []
+    for k in range(100, 1001, 100):
+        _, sk = solver.solve(b, tol=0.0, maxit=k, rr_auto="bound")
+        true.append(sk["rel_res_true"])
+        if sk["iterations"] < k:
+            break
+    print("true residual every 100 iterations", true, flush=True)
+    assert min(true) <= 1e-10
+    # the replacements are made early: at least three within the first 300
+    # iterations (relative residual ~1e-7 by then)
+    _, s300 = solver.solve(b, tol=0.0, maxit=300, rr_auto="bound")
+    assert s300["replacements"] >= 3
+
+
+# -----------------------------------------------------------------------------
+# TP3: the indefinite Helmholtz problem of Table tab:specs (500 x 500, shift
+# 5e-4, ||A||_2 = 1, b = A 1/sqrt(N), no preconditioner, as in the timed runs
+# of Section 4.1).  Section 4.6 reports (120 ranks): classic ~1e-8 after ~4000
+# iterations; p-BiCGStab stuck near 1e-4 early on, 8e-5 after ~4000 and
+# ~1e-9 only after ~7000; with replacement every 200 ~1e-8 after ~4000.
+# -----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def tp3():
+    from workloads import tp3_helmholtz
+    return tp3_helmholtz(500)
+
+
+def _true_after(S, b, k, **kw):
+    """True residual of the same (bitwise repeatable) run stopped after k
+    iterations."""
+    _, st = S.solve(b, tol=0.0, maxit=k, **kw)
+    return st["iterations"], st["rel_res_true"]
+
+
+def test_tp3_accuracy_orders_of_magnitude(tp3):
+    from paper_1809_01948_amd.solver import Solver
+    S = Solver.from_problem(tp3, form="stencil", precond="none")
+    b = dev(tp3.b)
+    ks = range(500, 8001, 500)
+    classic = [_true_after(S, b, k, method="classic") for k in ks]
+    plain = [_true_after(S, b, k) for k in ks]
+    rr = [_true_after(S, b, k, rr_period=200) for k in ks]
+    print("classic", classic, "\np", plain, "\np-rr200", rr, flush=True)
+    best = lambda run: min(r for _, r in run)
+    # classic reaches the paper's accuracy (or better) within ~4000 iterations
+    assert min(r for k, r in classic if k <= 4000) <= 1e-8
+    # without replacement p-BiCGStab plateaus early (its residual after 1000
+    # iterations is still at the 1e-4 level) and never gets near classic's
+    # accuracy; past its best point the true residual grows again
+    assert dict(plain)[1000] >= 1e-5
+    assert best(plain) >= 10 * best(classic)
+    assert plain[-1][1] >= 10 * best(plain)
+    # with replacement every 200 it reaches classic's order of accuracy
+    assert best(rr) <= 1e-8
+    assert best(rr) <= 100 * best(classic)
+    S.close()
+
+
+# -----------------------------------------------------------------------------
+# Section 3.3's error propagation matrices from a GPU run's recorded scalars
+# -----------------------------------------------------------------------------
+
+def test_propagation_norms_from_gpu_history():
+    """The column maximum norms of the nine products of eq:all_error_matrices,
+    built from the alpha, omega, beta a GPU solve records, equal those built
+    from the oracle's scalars over the iterations where the two runs agree
+    (the scalars agree to 1e-10 over the first 12 iterations; the oracle
+    against itself with another summation order agrees that long), and they
+    grow several orders of magnitude above one as Section 4.4 describes."""
+    from oracle import Float64Ops, pipelined_bicgstab
+    from paper_1809_01948_amd import diagnostics
+    from paper_1809_01948_amd.solver import Solver
+    from workloads import tp2_unsymmetric
+    p = tp2_unsymmetric(200)
+    A = p.scipy_csr()
+    its = 150
+    ref = pipelined_bicgstab(Float64Ops(A), p.b, tol=0.0, maxit=its)
+    S = Solver.from_problem(p, form="stencil", precond="none")
+    hist = history_buffer(its)
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=its, history=hist)
+    assert st["iterations"] == its == ref.iterations
+    rn, al, om, be = split_history(hist, its)
+    k = 12
+    gpu = diagnostics.column_max_norms(al[:k], om[:k], be[:k])
+    ora = diagnostics.column_max_norms(ref.alpha[:k], ref.omega[:k], ref.beta[:k])
+    for name in diagnostics.PRODUCTS:
+        assert np.allclose(gpu[name], ora[name], rtol=1e-8, atol=0), name
+    full = diagnostics.column_max_norms(al, om, be)
+    top = max(float(np.max(full[name])) for name in diagnostics.PRODUCTS)
+    assert top >= 1e3, top
+    S.close()

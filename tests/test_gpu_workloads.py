@@ -223,6 +223,42 @@ def test_sparse_solve_grads_vs_dense_reference(Solver):
     S.close()
 
 
+@pytest.mark.parametrize("case", ["n400", "c4-20k"])
+def test_fp32_storage_gradients_vs_fp64(Solver, case):
+    """Gradients of L = <c, x> through the differentiable solve with FP32
+    storage (forward and adjoint solves with FP32 vectors and matrix, FP64
+    dots, scalars, x and replacement) against the FP64 solver's: relative
+    difference at most 1e-5 for dL/db and dL/dvalues.  The FP32-storage solver
+    solves with A rounded to FP32 (exact for these values, which are FP32
+    numbers by construction), so both differentiate the same function."""
+    from paper_1809_01948_amd.solver import SparseSolve
+    if case == "n400":
+        p = random_banded_c4(N=400, nnz_row=9, band=20, seed=7, xseed=8)
+    else:
+        p = random_banded_c4(N=20_000, nnz_row=27, band=500, seed=11, xseed=12)
+    cvec = dev(np.random.default_rng(9).standard_normal(p.n))
+    grads = {}
+    # FP32 storage: replacement every 10 iterations without the sqrt(eps)
+    # cutoff (rr_tau tiny), the dependable setting for FP32 recurrences; its
+    # attainable accuracy is ~1e-10 rather than FP64's ~1e-13
+    for prec, opts in (("fp64", dict(tol=1e-12, maxit=2000, rr_period=50)),
+                       ("mixed", dict(tol=1e-10, maxit=2000, rr_period=10, rr_tau=1e-300))):
+        S = Solver.from_problem(p, form="csr", precision=prec)
+        vals = dev(p.val).requires_grad_(True)
+        b = dev(p.b).requires_grad_(True)
+        x = SparseSolve.apply(vals, b, S, opts)
+        (x * cvec).sum().backward()
+        grads[prec] = (host(x), host(b.grad), host(vals.grad))
+        S.close()
+    (x64, gb64, gv64), (x32, gb32, gv32) = grads["fp64"], grads["mixed"]
+    d = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    print(f"{case}: x {d(x32, x64):.1e}, dL/db {d(gb32, gb64):.1e}, "
+          f"dL/dvalues {d(gv32, gv64):.1e}", flush=True)
+    assert d(x32, x64) <= 1e-5
+    assert d(gb32, gb64) <= 1e-5
+    assert d(gv32, gv64) <= 1e-5
+
+
 def test_sparse_solve_directional_fd_full_size(Solver, c4_full):
     """Directional central differences of L = <c, x> at N = 2e6 along a
     random perturbation of b and of the stored values."""
