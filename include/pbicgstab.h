@@ -58,7 +58,21 @@ enum {
 };
 
 /* preconditioner M */
-enum { PBCG_PC_NONE = 0, PBCG_PC_JACOBI = 1 /* M = diag(A) */ };
+enum {
+  PBCG_PC_NONE = 0,
+  PBCG_PC_JACOBI = 1,               /* M = diag(A) */
+  PBCG_PC_BLOCK_JACOBI_BASE = 256   /* see PBCG_PC_BLOCK_JACOBI */
+};
+/* Block-Jacobi (CSR handles; a block preconditioner of the kind Section 4.1
+ * names as keeping the overlap): M = the block diagonal of A with blocks of b
+ * consecutive rows and columns, 2 <= b <= 64 (the last block ragged).  The
+ * handle stores A M^-1 (each diagonal block inverted on the host) and runs
+ * the iteration on it from y_0 = M x_0, returning x = M^-1 y: the same
+ * residuals, scalars and iterates as Algorithm 2 with PREC = M^-1 in exact
+ * arithmetic.  Transposed solves, gradients, value updates and the
+ * automated replacement are not supported on such handles
+ * (PBCG_ERR_UNSUPPORTED). */
+#define PBCG_PC_BLOCK_JACOBI(b) (PBCG_PC_BLOCK_JACOBI_BASE | (b))
 
 /* operator formats: structured operators (pbicgstab_create_stencil) and CSR */
 enum {
@@ -180,7 +194,9 @@ void pbicgstab_default_opts(pbcg_opts* opt);
  *   n, nnz    : dimension and stored entries (nnz is used for PBCG_CSR only)
  *   width     : PBCG_CSR: the largest number of stored entries in any row and,
  *               with with_transpose, in any column (it bounds every slice of
- *               the sliced-ELL layouts); ignored otherwise
+ *               the sliced-ELL layouts); ignored otherwise.  With
+ *               PBCG_PC_BLOCK_JACOBI(b) the stored A M^-1 is bounded by
+ *               width * b entries per row (no transposed layout)
  *   precision, precond : as for create
  *   with_transpose : nonzero reserves the transposed layout (PBCG_CSR, DIA5),
  *               which the first transposed solve, apply or gradient builds
@@ -202,9 +218,11 @@ size_t pbicgstab_workspace_bytes(int format, int64_t n, int64_t nnz, int32_t wid
  *                     where the layout is built); duplicate entries are kept
  *                     and summed in stored order
  *   precision       : PBCG_FP64 or PBCG_MIXED (values rounded once to FP32)
- *   precond         : PBCG_PC_NONE or PBCG_PC_JACOBI (M^-1 = 1/diag, the
+ *   precond         : PBCG_PC_NONE, PBCG_PC_JACOBI (M^-1 = 1/diag, the
  *                     diagonal being the sum of the entries with col == row;
- *                     PBCG_ERR_ZERO_DIAG if one is zero)
+ *                     PBCG_ERR_ZERO_DIAG if one is zero) or
+ *                     PBCG_PC_BLOCK_JACOBI(b) (PBCG_ERR_ZERO_DIAG if a
+ *                     diagonal block is singular)
  *   workspace, ws_bytes : caller-owned device memory, 256-byte aligned, of at
  *                     least pbicgstab_workspace_bytes(PBCG_CSR, ...) bytes;
  *                     PBCG_ERR_WORKSPACE_TOO_SMALL if the layouts do not fit

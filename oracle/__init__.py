@@ -26,6 +26,7 @@ module docstrings and exercised by ``tests/test_oracle_*.py``.
 
 from .krylov import (  # noqa: F401
     STATUS,
+    BlockJacobiOps,
     Float64Ops,
     ExactOps,
     SolveResult,

@@ -9,7 +9,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpbicgstab.so")
 
 FP64, MIXED = 0, 1
-PC_NONE, PC_JACOBI = 0, 1
+PC_NONE, PC_JACOBI, PC_BLOCK_JACOBI_BASE = 0, 1, 256
 ST_2D5, ST_3D7, ST_DIA5, CSR = 0, 1, 2, 3
 
 STATUS_NAMES = {

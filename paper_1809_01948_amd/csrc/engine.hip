@@ -89,6 +89,13 @@ void* dalloc(Solver& S, size_t bytes) {
   return p;
 }
 
+// Block size encoded in a precond argument (PBCG_PC_BLOCK_JACOBI(b)), else 0.
+int64_t block_size_of(int precond) {
+  if ((precond & ~0xff) != PBCG_PC_BLOCK_JACOBI_BASE) return 0;
+  const int b = precond & 0xff;
+  return (b >= 2 && b <= 64) ? b : 0;
+}
+
 // Workspace bytes of one layout (see pbicgstab_workspace_bytes): the same
 // pieces, in the same order and alignment, as create and the transpose build
 // take.  For sliced ELL, `width` bounds every slice's width (the longest row,
@@ -107,6 +114,23 @@ size_t layout_bytes(int format, int64_t n, int64_t nnz, int64_t width, int preci
   take(npad * 8);                                   // b
   take((int64_t)sizeof(double) * kNumSlots * kMaxPartials);
   take(2 * (int64_t)sizeof(DevScalars));
+  const int64_t block = block_size_of(precond);
+  if (format == PBCG_CSR && block > 0) {
+    // A M^-1 (each stored entry spreads over one block of columns), then
+    // M and M^-1 in FP64 and the FP64 scratch vector
+    const int64_t ns = (n + kSellC - 1) / kSellC;
+    const int64_t wt = std::min<int64_t>(n, width * block);
+    take((ns + 1) * 8);
+    take(ns * kSellC * wt * 4);
+    take(ns * kSellC * wt * ts);
+    for (int k = 0; k < 2; ++k) {
+      take((ns + 1) * 8);
+      take(ns * kSellC * block * 4);
+      take(ns * kSellC * block * 8);
+    }
+    take(npad * 8);
+    return (size_t)round_up(used, kWsAlign);
+  }
   if (format == PBCG_CSR) {
     const int64_t ns = (n + kSellC - 1) / kSellC;
     const int64_t elems = ns * kSellC * width;
@@ -146,7 +170,9 @@ void common_setup(Solver& S, int precision, int precond, void* workspace, size_t
   S.ws_size = ws_bytes;
   S.ws_used = 0;
   if (precision != PBCG_FP64 && precision != PBCG_MIXED) fail(PBCG_ERR_INVALID_ARG, "precision must be PBCG_FP64 or PBCG_MIXED");
-  if (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI) fail(PBCG_ERR_INVALID_ARG, "precond must be PBCG_PC_NONE or PBCG_PC_JACOBI");
+  if (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI)
+    fail(PBCG_ERR_INVALID_ARG, "precond must be PBCG_PC_NONE, PBCG_PC_JACOBI or (CSR only) "
+                               "PBCG_PC_BLOCK_JACOBI(b) with 2 <= b <= 64");
   if (S.n > (int64_t)2000000000) fail(PBCG_ERR_UNSUPPORTED, "n exceeds the int32 index range");
   S.precision = precision;
   S.precond = precond;
@@ -241,17 +267,18 @@ void upload_vals(Solver& S, void* dst, const std::vector<double>& v) {
 }
 
 void upload_sell(Solver& S, OpData& o, const std::vector<int64_t>& sptr,
-                 const std::vector<int32_t>& scol, const std::vector<double>& sval, int mw) {
+                 const std::vector<int32_t>& scol, const std::vector<double>& sval, int mw,
+                 bool fp64 = false) {
   o.kind = OP_SELL;
   o.nslices = (int64_t)sptr.size() - 1;
   o.sell_elems = sptr.back();
   o.max_width = mw;
   o.sptr = (int64_t*)dalloc(S, sptr.size() * 8);
   o.col = (int32_t*)dalloc(S, scol.size() * 4);
-  o.val = dalloc(S, sval.size() * S.tsize);
+  o.val = dalloc(S, sval.size() * (fp64 ? 8 : S.tsize));
   hipck(hipMemcpy(o.sptr, sptr.data(), sptr.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
   hipck(hipMemcpy(o.col, scol.data(), scol.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
-  if (S.precision == PBCG_FP64) upload_vals<double>(S, o.val, sval);
+  if (fp64 || S.precision == PBCG_FP64) upload_vals<double>(S, o.val, sval);
   else upload_vals<float>(S, o.val, sval);
 }
 
@@ -344,6 +371,117 @@ void norms_grid(Solver& S, const double* dia /* 5*n or null */) {
     mr = std::max(mr, cnt);
   }
   set_norm_bounds(S, rs, cs, mr, mr);
+}
+
+// Block-Jacobi set-up on the host from the input CSR (rowptr, col, val):
+// the diagonal blocks of `bs` consecutive rows and columns (the last one
+// ragged) are inverted by Gauss-Jordan elimination with partial pivoting; the
+// operator stored for the iteration is A M^-1 (row i: every stored a_ij
+// spread over the columns of j's block with the weights of row j of M^-1,
+// summed per column in ascending order), and M, M^-1 are stored as FP64
+// sliced ELL.  Right preconditioning then needs no PREC step inside the
+// iteration: Algorithm 2 on A M^-1 with y_0 = M x_0 gives the same residuals,
+// scalars and x_i = M^-1 y_i in exact arithmetic.
+void setup_block_jacobi(Solver& S, int bs, std::vector<int32_t>& rowptr, std::vector<int32_t>& col,
+                        std::vector<double>& val) {
+  const int64_t n = S.n, nblk = (n + bs - 1) / bs;
+  std::vector<double> inv((size_t)nblk * bs * bs, 0.0), mblk((size_t)nblk * bs * bs, 0.0);
+  std::vector<double> a((size_t)bs * 2 * bs);
+  for (int64_t blk = 0; blk < nblk; ++blk) {
+    const int64_t lo = blk * bs, m = std::min<int64_t>(bs, n - lo);
+    double* M = &mblk[(size_t)blk * bs * bs];
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t kk = rowptr[lo + r]; kk < rowptr[lo + r + 1]; ++kk)
+        if (col[kk] >= lo && col[kk] < lo + m) M[r * bs + (col[kk] - lo)] += val[kk];
+    // [M | I] -> [I | M^-1]
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t c = 0; c < 2 * m; ++c)
+        a[r * 2 * bs + c] = c < m ? M[r * bs + c] : (c - m == r ? 1.0 : 0.0);
+    for (int64_t c = 0; c < m; ++c) {
+      int64_t piv = c;
+      for (int64_t r = c + 1; r < m; ++r)
+        if (std::fabs(a[r * 2 * bs + c]) > std::fabs(a[piv * 2 * bs + c])) piv = r;
+      if (a[piv * 2 * bs + c] == 0.0)
+        fail(PBCG_ERR_ZERO_DIAG, "singular diagonal block at rows " + std::to_string(lo) + ".." +
+                                     std::to_string(lo + m - 1));
+      if (piv != c)
+        for (int64_t k = 0; k < 2 * m; ++k) std::swap(a[c * 2 * bs + k], a[piv * 2 * bs + k]);
+      const double d = a[c * 2 * bs + c];
+      for (int64_t k = 0; k < 2 * m; ++k) a[c * 2 * bs + k] /= d;
+      for (int64_t r = 0; r < m; ++r) {
+        if (r == c) continue;
+        const double f = a[r * 2 * bs + c];
+        if (f == 0.0) continue;
+        for (int64_t k = 0; k < 2 * m; ++k) a[r * 2 * bs + k] -= f * a[c * 2 * bs + k];
+      }
+    }
+    double* I = &inv[(size_t)blk * bs * bs];
+    for (int64_t r = 0; r < m; ++r)
+      for (int64_t c = 0; c < m; ++c) I[r * bs + c] = a[r * 2 * bs + m + c];
+  }
+  // A M^-1
+  std::vector<int32_t> trp(n + 1, 0), tcol;
+  std::vector<double> tval;
+  std::vector<double> acc(n, 0.0);
+  std::vector<int32_t> touched;
+  std::vector<char> seen(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    touched.clear();
+    for (int64_t kk = rowptr[i]; kk < rowptr[i + 1]; ++kk) {
+      const int64_t j = col[kk], blk = j / bs, lo = blk * bs, m = std::min<int64_t>(bs, n - lo);
+      const double* I = &inv[(size_t)blk * bs * bs + (size_t)(j - lo) * bs];
+      for (int64_t c = 0; c < m; ++c) {
+        if (!seen[lo + c]) {
+          seen[lo + c] = 1;
+          touched.push_back((int32_t)(lo + c));
+        }
+        acc[lo + c] += val[kk] * I[c];
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int32_t c : touched) {
+      tcol.push_back(c);
+      tval.push_back(acc[c]);
+      acc[c] = 0.0;
+      seen[c] = 0;
+    }
+    trp[i + 1] = (int32_t)tcol.size();
+  }
+  // M and M^-1 as sliced ELL (row i: the columns of its block)
+  auto block_sell = [&](const std::vector<double>& src, OpData& o) {
+    std::vector<int32_t> brp(n + 1, 0), bcol;
+    std::vector<double> bval;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t blk = i / bs, lo = blk * bs, m = std::min<int64_t>(bs, n - lo);
+      for (int64_t c = 0; c < m; ++c) {
+        bcol.push_back((int32_t)(lo + c));
+        bval.push_back(src[(size_t)blk * bs * bs + (size_t)(i - lo) * bs + c]);
+      }
+      brp[i + 1] = (int32_t)bcol.size();
+    }
+    std::vector<int64_t> sptr, pos;
+    std::vector<int32_t> scol;
+    std::vector<double> sval;
+    int mw = 0;
+    build_sell(n, brp.data(), bcol.data(), bval.data(), sptr, scol, sval, pos, mw);
+    upload_sell(S, o, sptr, scol, sval, mw, true);
+  };
+  {
+    std::vector<int64_t> sptr, pos;
+    std::vector<int32_t> scol;
+    std::vector<double> sval;
+    int mw = 0;
+    build_sell(n, trp.data(), tcol.data(), tval.data(), sptr, scol, sval, pos, mw);
+    upload_sell(S, S.A, sptr, scol, sval, mw);
+  }
+  block_sell(mblk, S.Mb);
+  block_sell(inv, S.Bi);
+  S.ytmp = (double*)dalloc(S, S.npad * 8);
+  rowptr = std::move(trp);
+  col = std::move(tcol);
+  val = std::move(tval);
+  S.nnz = (int64_t)col.size();
+  S.block = bs;
 }
 
 // Values of the host CSR copy into a sliced-ELL layout whose slot of CSR
@@ -490,12 +628,22 @@ void begin_solve(Solver& S, const double* b, const double* x, const pbcg_opts& o
   hipck(hipMemcpyAsync(S.sc, &S.h_sc[2], sizeof(DevScalars), hipMemcpyHostToDevice, S.s1),
         "hipMemcpyAsync");
   hipck(hipMemcpyAsync(S.b, b, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
-  hipck(hipMemcpyAsync(S.x, x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  if (S.block) {          // the iterate of A M^-1 y = b: y_0 = M x_0
+    launch_apply_op(S, S.Mb, x, S.x, S.s1);
+    hipck(hipGetLastError(), "block-Jacobi y_0 launch");
+  } else {
+    hipck(hipMemcpyAsync(S.x, x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  }
   hipck(hipEventRecord(S.ev_t0, S.s1), "hipEventRecord");
 }
 
 void end_solve(Solver& S, double* x, hipStream_t cs) {
-  hipck(hipMemcpyAsync(x, S.x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  if (S.block) {          // x = M^-1 y
+    launch_apply_op(S, S.Bi, S.x, x, S.s1);
+    hipck(hipGetLastError(), "block-Jacobi x launch");
+  } else {
+    hipck(hipMemcpyAsync(x, S.x, S.n * 8, hipMemcpyDeviceToDevice, S.s1), "hipMemcpyAsync");
+  }
   hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
   hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
 }
@@ -655,8 +803,18 @@ int finish_stats(Solver& S, bool tr, const DevScalars& d, int status, pbcg_stats
   return status;
 }
 
+// What block-Jacobi handles (which store A M^-1) cannot do.
+void check_block(const Solver& S, bool transpose, bool rr_auto) {
+  if (!S.block) return;
+  if (transpose)
+    fail(PBCG_ERR_UNSUPPORTED, "block-Jacobi handles do not solve with the transpose");
+  if (rr_auto)
+    fail(PBCG_ERR_UNSUPPORTED, "block-Jacobi handles do not support the automated replacement");
+}
+
 int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, pbcg_stats* st) {
   validate_opts(o);
+  check_block(S, o.transpose != 0, o.rr_auto != 0);
   const bool tr = o.transpose != 0;
   S.auto_rr = o.rr_auto != 0;
   if (tr) build_transpose(S);
@@ -755,6 +913,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
 
 int solve_classic(Solver& S, const double* b, double* x, const pbcg_opts& o, pbcg_stats* st) {
   validate_opts(o);
+  check_block(S, o.transpose != 0, false);
   S.auto_rr = false;
   const bool tr = o.transpose != 0;
   if (tr) build_transpose(S);
@@ -909,7 +1068,8 @@ size_t pbicgstab_workspace_bytes(int format, int64_t n, int64_t nnz, int32_t wid
   if ((!csr && format != PBCG_ST_2D5 && format != PBCG_ST_3D7 && format != PBCG_ST_DIA5) ||
       n < 1 || n > (int64_t)2000000000 || (csr && (nnz < 0 || width < 0)) ||
       (precision != PBCG_FP64 && precision != PBCG_MIXED) ||
-      (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI)) {
+      (precond != PBCG_PC_NONE && precond != PBCG_PC_JACOBI &&
+       !(csr && block_size_of(precond) > 0))) {
     g_last_error = "pbicgstab_workspace_bytes: invalid arguments";
     return 0;
   }
@@ -940,13 +1100,25 @@ int pbicgstab_create_csr(pbcg_handle* out, int64_t n, int64_t nnz, const int32_t
       if (rowptr[i + 1] < rowptr[i]) fail(PBCG_ERR_INVALID_ARG, "rowptr must be nondecreasing");
     for (int64_t kk = 0; kk < nnz; ++kk)
       if (col[kk] < 0 || col[kk] >= n) fail(PBCG_ERR_INVALID_ARG, "column index out of range");
+    const int bs = (int)block_size_of(precond);
     auto* p = new pbcg_solver();
     try {
       Solver& S = p->S;
       S.n = n;
       S.nnz = nnz;
       S.kind = OP_SELL;
-      common_setup(S, precision, precond, workspace, ws_bytes);
+      common_setup(S, precision, bs > 0 ? PBCG_PC_NONE : precond, workspace, ws_bytes);
+      if (bs > 0) {
+        // block-Jacobi: the handle iterates on A M^-1 (see setup_block_jacobi)
+        setup_block_jacobi(S, bs, rowptr, col, val);
+        S.h_rowptr = std::move(rowptr);
+        S.h_col = std::move(col);
+        S.h_val = std::move(val);
+        norms_csr(S);
+        hipck(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        *out = p;
+        return PBCG_OK;
+      }
       S.h_rowptr = std::move(rowptr);
       S.h_col = std::move(col);
       S.h_val = std::move(val);
@@ -1153,11 +1325,17 @@ int pbicgstab_apply(pbcg_handle h, const double* x, double* y, int transpose, vo
   return guarded([&]() -> int {
     Solver& S = H(h);
     if (!x || !y) fail(PBCG_ERR_INVALID_ARG, "null vector");
+    check_block(S, transpose != 0, false);
     if (transpose) build_transpose(S);
     hipStream_t cs = (hipStream_t)stream;
     hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
     hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
-    launch_apply(S, transpose != 0, x, y, S.s1);
+    if (S.block) {        // A x = (A M^-1) (M x)
+      launch_apply_op(S, S.Mb, x, S.ytmp, S.s1);
+      launch_apply(S, false, S.ytmp, y, S.s1);
+    } else {
+      launch_apply(S, transpose != 0, x, y, S.s1);
+    }
     hipck(hipGetLastError(), "apply launch");
     hipck(hipEventRecord(S.ev_out, S.s1), "hipEventRecord");
     hipck(hipStreamWaitEvent(cs, S.ev_out, 0), "hipStreamWaitEvent");
@@ -1170,6 +1348,7 @@ int pbicgstab_grad_values(pbcg_handle h, const double* lambda, const double* x, 
   return guarded([&]() -> int {
     Solver& S = H(h);
     if (!lambda || !x || !grad) fail(PBCG_ERR_INVALID_ARG, "null vector");
+    if (S.block) fail(PBCG_ERR_UNSUPPORTED, "block-Jacobi handles have no value gradient");
     hipStream_t cs = (hipStream_t)stream;
     hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
     hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
@@ -1191,6 +1370,7 @@ int pbicgstab_update_values(pbcg_handle h, const double* values, int on_device, 
   return guarded([&]() -> int {
     Solver& S = H(h);
     if (!values) fail(PBCG_ERR_INVALID_ARG, "null values");
+    if (S.block) fail(PBCG_ERR_UNSUPPORTED, "block-Jacobi handles do not update values");
     hipStream_t cs = (hipStream_t)stream;
     hipck(hipStreamSynchronize(cs), "hipStreamSynchronize");
     hipck(hipStreamSynchronize(S.s1), "hipStreamSynchronize");

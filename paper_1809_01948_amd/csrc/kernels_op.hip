@@ -999,6 +999,15 @@ void launch_apply(Solver& S, bool tr, const double* x, double* y, hipStream_t st
   });
 }
 
+// y = o x for an FP64 sliced-ELL operator other than the solver's own (the
+// block-Jacobi M and M^-1)
+void launch_apply_op(Solver& S, const OpData& o, const double* x, double* y, hipStream_t st) {
+  auto f = [&]<typename T, int PC, class Op>(const Op& op) {
+    hipLaunchKernelGGL((k_apply<T, Op>), PBCG_GRID_OP, op, x, y, S.n, S.rtiles, S.nblk);
+  };
+  with_op_t<double>(S, o, false, f);
+}
+
 static int grid_for(int64_t count) {
   int64_t b = (count + kBlock - 1) / kBlock;
   if (b > 8192) b = 8192;

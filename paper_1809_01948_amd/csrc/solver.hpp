@@ -39,6 +39,12 @@ struct Solver {
   size_t tsize = 8;             // bytes per stored vector element
   OpData A, AT;
   bool have_AT = false;
+  // block-Jacobi (block > 0): A holds A M^-1 (M = block diagonal of the
+  // input matrix, blocks of `block` rows); Mb = M and Bi = M^-1 as FP64 sliced
+  // ELL map the caller's x to the iterate y = M x and back; ytmp is FP64 scratch
+  int block = 0;
+  OpData Mb, Bi;
+  double* ytmp = nullptr;
 
   // host copies kept for the transpose (built on first use) and value updates
   std::vector<int32_t> h_rowptr, h_col;
@@ -150,6 +156,7 @@ bool pre_multiplied(Solver& S, bool transpose);
 void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode, hipStream_t st);
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z = true);
+void launch_apply_op(Solver& S, const OpData& o, const double* x, double* y, hipStream_t st);
 void launch_true_res(Solver& S, bool tr, hipStream_t st);
 void launch_gap(Solver& S, bool tr, hipStream_t st, bool force = false);
 void launch_cl_init(Solver& S, bool tr, hipStream_t st);

@@ -36,6 +36,14 @@ def _stream():
 
 _PRECISION = {"fp64": L.FP64, "mixed": L.MIXED}
 _PRECOND = {"none": L.PC_NONE, None: L.PC_NONE, "jacobi": L.PC_JACOBI}
+
+
+def _pc_code(precond) -> int:
+    """'none', 'jacobi' or 'block<b>' (block-Jacobi with blocks of b rows,
+    CSR only: PBCG_PC_BLOCK_JACOBI(b))."""
+    if isinstance(precond, str) and precond.startswith("block"):
+        return L.PC_BLOCK_JACOBI_BASE | int(precond[len("block"):])
+    return _PRECOND[precond]
 _KIND = {"2d5": L.ST_2D5, "3d7": L.ST_3D7, "dia5": L.ST_DIA5}
 
 
@@ -44,7 +52,7 @@ def workspace_bytes(fmt: str, n: int, nnz: int = 0, width: int = 0, precision="f
     """pbicgstab_workspace_bytes for a format 'csr', '2d5', '3d7' or 'dia5'."""
     code = L.CSR if fmt == "csr" else _KIND[fmt]
     nb = L.load().pbicgstab_workspace_bytes(code, n, nnz, width, _PRECISION[precision],
-                                            _PRECOND[precond], 1 if with_transpose else 0)
+                                            _pc_code(precond), 1 if with_transpose else 0)
     if nb == 0:
         msg = L.load().pbicgstab_last_error()
         raise L.PbcgError(-1, msg.decode() if msg else "invalid workspace query")
@@ -97,6 +105,8 @@ class Solver:
                              dtype=torch.float64).cuda().contiguous()
         n = rp.numel() - 1
         nnz = cl.numel()
+        if isinstance(precond, str) and precond.startswith("block"):
+            with_transpose = False          # block-Jacobi handles have no transpose
         # slice-width bound of the sliced-ELL layouts: longest row (and column)
         rows = torch.diff(rp.to(torch.int64))
         width = int(rows.max()) if n > 0 else 0
@@ -108,7 +118,7 @@ class Solver:
         h = ctypes.c_void_p()
         L.check(lib.pbicgstab_create_csr(
             ctypes.byref(h), n, nnz, _ptr(rp), _ptr(cl), _ptr(vl), _PRECISION[precision],
-            _PRECOND[precond], _ptr(workspace), workspace.numel(), _stream()))
+            _pc_code(precond), _ptr(workspace), workspace.numel(), _stream()))
         return cls(h, n, "csr", precision, precond, nnz=nnz, workspace=workspace)
 
     @classmethod

@@ -63,7 +63,9 @@ def test_binding_matches_header(lib):
     assert set(lib.SIGNATURES) == declared_functions()
     enums = declared_enums()
     assert (enums["PBCG_FP64"], enums["PBCG_MIXED"]) == (lib.FP64, lib.MIXED)
-    assert (enums["PBCG_PC_NONE"], enums["PBCG_PC_JACOBI"]) == (lib.PC_NONE, lib.PC_JACOBI)
+    assert (enums["PBCG_PC_NONE"], enums["PBCG_PC_JACOBI"],
+            enums["PBCG_PC_BLOCK_JACOBI_BASE"]) == (lib.PC_NONE, lib.PC_JACOBI,
+                                                    lib.PC_BLOCK_JACOBI_BASE)
     assert (enums["PBCG_ST_2D5"], enums["PBCG_ST_3D7"], enums["PBCG_ST_DIA5"],
             enums["PBCG_CSR"]) == (lib.ST_2D5, lib.ST_3D7, lib.ST_DIA5, lib.CSR)
     for name, code in enums.items():
@@ -153,8 +155,19 @@ def test_workspace_bytes(lib):
         assert _ws(L, CSR, n, 7 * n, 8, prec=prec) == c + r256(ns * 64 * 8 * 4) - r256(
             ns * 64 * 7 * 4) + r256(ns * 64 * 8 * ts) - r256(ns * 64 * 7 * ts)
         assert _ws(L, CSR, n, 7 * n, 7, prec=prec, tr=1) > c
+    # block-Jacobi (CSR only): A M^-1 bounded by width * b entries per row, M and
+    # M^-1 in FP64 with b entries per row, one FP64 scratch vector; no transpose
+    blk = lib.PC_BLOCK_JACOBI_BASE | 4
+    cb = _ws(L, CSR, n, 5 * n, 5, pc=blk)
+    ns = (n + 63) // 64
+    assert cb == _ws(L, CSR, n, 5 * n, 5, pc=blk, tr=1)
+    assert cb > _ws(L, CSR, n, 5 * n, 5) and cb % 256 == 0
+    assert _ws(L, CSR, n, 5 * n, 6, pc=blk) - cb == r256(ns * 64 * 24 * 4) - r256(
+        ns * 64 * 20 * 4) + r256(ns * 64 * 24 * 8) - r256(ns * 64 * 20 * 8)
     for bad in ((9, n, 0, 0, 0, 0, 0), (CSR, 0, 0, 0, 0, 0, 0), (CSR, n, -1, 0, 0, 0, 0),
-                (S2, n, 0, 0, 2, 0, 0), (S2, n, 0, 0, 0, 3, 0)):
+                (S2, n, 0, 0, 2, 0, 0), (S2, n, 0, 0, 0, 3, 0), (S2, n, 0, 0, 0, blk, 0),
+                (CSR, n, 5 * n, 5, 0, lib.PC_BLOCK_JACOBI_BASE | 1, 0),
+                (CSR, n, 5 * n, 5, 0, lib.PC_BLOCK_JACOBI_BASE | 65, 0)):
         assert L.pbicgstab_workspace_bytes(*bad) == 0
         assert L.pbicgstab_last_error()
 

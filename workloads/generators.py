@@ -382,15 +382,19 @@ def inverse_problem_c5(n: int = 2048, seed: int = 5, target_seed: int = 55,
 # -----------------------------------------------------------------------------
 
 def _norm2_estimate(rowptr, col, val, n, iters=200, seed=0):
-    """||A||_2 estimated by power iteration on A^T A (problem set-up only)."""
+    """||A||_2 estimated by power iteration on A^T A (problem set-up only).
+    Norms are correctly rounded sums (math.fsum), so the estimate -- and the
+    normalised matrix -- is the same bits whatever BLAS threading is used."""
+    import math
+
     import scipy.sparse as sp
     A = sp.csr_matrix((val, col, rowptr), shape=(n, n))
     v = np.random.default_rng(seed).standard_normal(n)
-    v /= np.linalg.norm(v)
+    v /= math.sqrt(math.fsum(v * v))
     s = 0.0
     for _ in range(iters):
         w = A.T @ (A @ v)
-        s = np.linalg.norm(w)
+        s = math.sqrt(math.fsum(w * w))
         v = w / s
     return float(np.sqrt(s))
 
