@@ -31,6 +31,7 @@ constexpr int64_t kPadElems = 2048;  // vector padding granularity (elements)
 constexpr int64_t kWsAlign = 256;    // alignment of every piece of the caller's workspace
 constexpr int kXcds = 8;             // MI355X: workgroups are dispatched round-robin over 8 XCDs
 constexpr int kSellC = 64;           // SELL slice height = one wavefront
+constexpr int kLdsRows = 1024;       // rows (and threads) of a block of the LDS-window SELL product
 
 // partial slots
 enum Slot : int {

@@ -120,9 +120,12 @@ size_t layout_bytes(int format, int64_t n, int64_t nnz, int64_t width, int preci
     // M and M^-1 in FP64 and the FP64 scratch vector
     const int64_t ns = (n + kSellC - 1) / kSellC;
     const int64_t wt = std::min<int64_t>(n, width * block);
+    const int64_t nlb = (n + kLdsRows - 1) / kLdsRows;
     take((ns + 1) * 8);
     take(ns * kSellC * wt * 4);
     take(ns * kSellC * wt * ts);
+    take(nlb * 4);
+    take(nlb * 4);
     for (int k = 0; k < 2; ++k) {
       take((ns + 1) * 8);
       take(ns * kSellC * block * 4);
@@ -134,10 +137,13 @@ size_t layout_bytes(int format, int64_t n, int64_t nnz, int64_t width, int preci
   if (format == PBCG_CSR) {
     const int64_t ns = (n + kSellC - 1) / kSellC;
     const int64_t elems = ns * kSellC * width;
+    const int64_t nlb = (n + kLdsRows - 1) / kLdsRows;
     auto sell = [&]() {
       take((ns + 1) * 8);
       take(elems * 4);
       take(elems * ts);
+      take(nlb * 4);                                // LDS windows: first column
+      take(nlb * 4);                                //   and length
     };
     sell();                                         // A
     take(std::max<int64_t>(nnz, 1) * 8);            // CSR entry -> SELL slot
@@ -212,6 +218,14 @@ void common_setup(Solver& S, int precision, int precond, void* workspace, size_t
   if (const char* env = std::getenv("PBCG_MARCH3D")) S.march3d = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_MARCH_PHASE")) S.march_phase = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_PREMULT")) S.premult = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_SELL_LDS")) S.sell_lds = std::atoi(env) != 0;
+  {
+    int dev = 0, cap = 0;
+    hipck(hipGetDevice(&dev), "hipGetDevice");
+    hipck(hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+          "hipDeviceGetAttribute");
+    S.lds_cap = cap;
+  }
   if (const char* env = std::getenv("PBCG_MARCH_ZLEN")) S.march_zlen = std::atoi(env);
   hipck(hipStreamCreateWithFlags(&S.s1, hipStreamNonBlocking), "hipStreamCreate");
   hipck(hipEventCreateWithFlags(&S.ev_in, hipEventDisableTiming), "hipEventCreate");
@@ -280,6 +294,31 @@ void upload_sell(Solver& S, OpData& o, const std::vector<int64_t>& sptr,
   hipck(hipMemcpy(o.col, scol.data(), scol.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
   if (fp64 || S.precision == PBCG_FP64) upload_vals<double>(S, o.val, sval);
   else upload_vals<float>(S, o.val, sval);
+  if (fp64) return;
+  // column window of each block of kLdsRows rows: the columns its entries
+  // read and the rows themselves (a padding entry reads its own row)
+  const int64_t n = S.n, nlb = (n + kLdsRows - 1) / kLdsRows;
+  std::vector<int32_t> wlo(nlb), wlen(nlb);
+  int wmax = 0;
+  for (int64_t t = 0; t < nlb; ++t) {
+    int64_t lo = t * kLdsRows, hi = std::min<int64_t>(n, lo + kLdsRows) - 1;
+    const int64_t s0 = t * (kLdsRows / kSellC);
+    const int64_t s1 = std::min<int64_t>(o.nslices, s0 + kLdsRows / kSellC);
+    for (int64_t e = sptr[s0]; e < sptr[s1]; ++e)
+      if (scol[e] >= 0) {
+        lo = std::min<int64_t>(lo, scol[e]);
+        hi = std::max<int64_t>(hi, scol[e]);
+      }
+    wlo[t] = (int32_t)lo;
+    wlen[t] = (int32_t)(hi - lo + 1);
+    wmax = std::max(wmax, wlen[t]);
+  }
+  o.nlb = nlb;
+  o.win_max = wmax;
+  o.win_lo = (int32_t*)dalloc(S, nlb * 4);
+  o.win_len = (int32_t*)dalloc(S, nlb * 4);
+  hipck(hipMemcpy(o.win_lo, wlo.data(), nlb * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  hipck(hipMemcpy(o.win_len, wlen.data(), nlb * 4, hipMemcpyHostToDevice), "hipMemcpy");
 }
 
 // Jacobi diagonal (sum of the entries with col == row) from the host CSR

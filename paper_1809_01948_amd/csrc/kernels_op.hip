@@ -117,6 +117,48 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Op op, const T* __restrict__ in
   }
 }
 
+// sum_j a_ij w_j with w the block's column window of M^-1 z, staged in LDS
+template <typename T>
+struct LdsVis {
+  typedef T V;
+  const T* win;
+  int64_t lo;
+  T sum;
+  __device__ __forceinline__ V load(int64_t j) const { return win[j - lo]; }
+  __device__ __forceinline__ void add(T a, V x) { sum += a * x; }
+};
+
+// out = A (M^-1 in) for a sliced-ELL A whose blocks of kLdsRows rows read a
+// narrow column window (banded matrices): each block loads its window of
+// M^-1 in once, coalesced, into LDS and the gathers of its rows read LDS
+// instead of going through the L1 and L2 one line per lane.  The rows are
+// summed by the same SellOp::row in the same order as k_spmv: bitwise the
+// same products.  Blocks walk the row blocks XCD-aware (consecutive row
+// blocks, whose windows overlap, on one XCD's L2).
+template <typename T, int PC>
+__global__ __launch_bounds__(kLdsRows) void k_spmv_sell_lds(
+    SellOp<T> op, const int32_t* __restrict__ win_lo, const int32_t* __restrict__ win_len,
+    const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ dinv, T ds, int64_t n,
+    int64_t nlb, int nwork, const DevScalars* __restrict__ sc) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* win = (T*)lds_raw;
+  if (sc->done) return;
+  for (XcdWalk w(nlb, blockIdx.x, nwork); w.t < w.end; w.t += w.step) {
+    const int64_t lo = win_lo[w.t];
+    const int len = win_len[w.t];
+    for (int e = threadIdx.x; e < len; e += kLdsRows)
+      win[e] = prec1<T, PC>(in[lo + e], dinv, ds, lo + e);
+    __syncthreads();
+    const int64_t i = w.t * kLdsRows + threadIdx.x;
+    if (i < n) {
+      LdsVis<T> vis{win, lo, T(0)};
+      op.row(i, vis);
+      out[i] = vis.sum;
+    }
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------------------
 // structured SPMV, CH x R consecutive rows per thread
 // ----------------------------------------------------------------------------
@@ -897,7 +939,41 @@ bool pre_multiplied(Solver& S, bool tr) {
          fused_kind(S, tr) == 0;
 }
 
+bool sell_lds_ok(const Solver& S, const OpData& o) {
+  return S.sell_lds && o.kind == OP_SELL && o.win_lo && o.win_max > 0 &&
+         (int64_t)o.win_max * (int64_t)S.tsize <= S.lds_cap;
+}
+
+// The LDS-window product; the GLRED final (if any) runs first as its own
+// kernel (the same reduction tree, so the same bits).
+static void launch_spmv_lds(Solver& S, bool tr, const void* in, void* out, int fin_mode,
+                            hipStream_t st, bool pre) {
+  if (fin_mode != FIN_NONE) launch_fin(S, fin_mode, st);
+  const OpData& o = op_of(S, tr);
+  const int64_t nw = std::min<int64_t>(o.nlb, 256);
+  const int nwork = (int)std::max<int64_t>(kXcds, nw / kXcds * kXcds);
+  const size_t shmem = (size_t)o.win_max * S.tsize;
+  with_op(S, tr, !pre, [&]<typename T, int PC, class Op>(const Op& op) {
+    if constexpr (std::is_same_v<Op, SellOp<T>>) {
+      static bool attr = false;
+      if (!attr) {
+        hipFuncSetAttribute((const void*)k_spmv_sell_lds<T, PC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S.lds_cap);
+        attr = true;
+      }
+      hipLaunchKernelGGL((k_spmv_sell_lds<T, PC>), dim3(nwork), dim3(kLdsRows), shmem, st, op,
+                         o.win_lo, o.win_len, (const T*)in, (T*)out, (const T*)S.dinv,
+                         (T)S.dinv_s, S.n, o.nlb, nwork, S.sc);
+    }
+  });
+}
+
 void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode, hipStream_t st) {
+  if (sell_lds_ok(S, op_of(S, tr))) {
+    const bool pre = pre_multiplied(S, tr);
+    launch_spmv_lds(S, tr, pre ? S.vec[V_PM] : S.vec[in_vec], S.vec[out_vec], fin_mode, st, pre);
+    return;
+  }
   if (pre_multiplied(S, tr))
     launch_spmv(S, tr, S.vec[V_PM], S.vec[out_vec], fin_mode, false, st, true);
   else

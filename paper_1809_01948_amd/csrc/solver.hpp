@@ -22,6 +22,13 @@ struct OpData {
   void* val = nullptr;          // T
   int64_t sell_elems = 0;
   int max_width = 0;
+  // column window of each block of kLdsRows rows (the columns its rows read
+  // and the rows themselves): first column and length, for the product that
+  // stages the window in LDS; win_max = the longest window
+  int32_t* win_lo = nullptr;
+  int32_t* win_len = nullptr;
+  int64_t nlb = 0;
+  int win_max = 0;
   // stencils
   int dims[3] = {1, 1, 1};
   double c64[7] = {0};
@@ -81,6 +88,8 @@ struct Solver {
   bool spmv_tiled = true;       // several consecutive rows per thread for structured operators
   bool fuse = true;             // phase kernels compute the SPMVs of structured operators
   bool premult = true;          // sliced-ELL products read V_PM (pre_multiplied)
+  bool sell_lds = true;         // sliced-ELL iteration products stage their column window in LDS
+  int64_t lds_cap = 0;          // bytes of LDS one block may use (device attribute)
   bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
   bool march_phase = true;      // phase kernels visit a 3D grid's tiles plane by plane (TileSeq)
   int march_zlen = 0;           // planes per work item of k_spmv_st3m (0: sized to the grid)
@@ -157,6 +166,7 @@ void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode,
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z = true);
 void launch_apply_op(Solver& S, const OpData& o, const double* x, double* y, hipStream_t st);
+bool sell_lds_ok(const Solver& S, const OpData& o);
 void launch_true_res(Solver& S, bool tr, hipStream_t st);
 void launch_gap(Solver& S, bool tr, hipStream_t st, bool force = false);
 void launch_cl_init(Solver& S, bool tr, hipStream_t st);

@@ -64,3 +64,42 @@ def test_premultiplied_kernel_timing(Solver):
     for k in ("spmv1", "spmv2", "spmv_bare", "iteration"):
         assert S.time_kernel(k, reps=3) > 0.0
     S.close()
+
+
+# The sliced-ELL iteration products stage each block's column window of
+# their input in LDS (banded matrices: the window of 1024 rows spans the band
+# plus the rows); the rows are summed in the same order as the gathering
+# kernel, so solves agree bit for bit with PBCG_SELL_LDS=0.  The last case's
+# window (the whole 40000-row range) exceeds the LDS of a block, so it takes
+# the gathering kernel either way.
+_LDS_CASES = _CASES + [
+    ("fp64-gather-input", 20000, "fp64", dict(tol=0.0, maxit=30, rr_period=10)),
+    ("fp64-wide-window", 40000, "fp64", dict(tol=0.0, maxit=10, rr_period=5)),
+]
+
+
+@pytest.mark.parametrize("name,rows,prec,sk", _LDS_CASES, ids=[c[0] for c in _LDS_CASES])
+def test_lds_window_equals_global_gathers(Solver, name, rows, prec, sk):
+    band = 40000 if name == "fp64-wide-window" else 300
+    p = random_banded_c4(rows, band=band)
+    pre = 0 if name == "fp64-gather-input" else 1
+    out = {}
+    for lds in (1, 0):
+        with solver_env(PBCG_SELL_LDS=lds, PBCG_PREMULT=pre):
+            S = Solver.from_problem(p, form="csr", precision=prec, precond="jacobi")
+        hist = history_buffer(sk["maxit"])
+        x, st = S.solve(dev(p.b), history=hist, **sk)
+        # (t of the stopping iteration is not compared: its product is skipped
+        # once the GLRED 2 final has stopped the solve -- entirely here, by the
+        # blocks that start after the final in the fused form)
+        vecs = {v: host(S.get_vector(v)) for v in ("r", "w", "z", "v")}
+        out[lds] = (host(x), st, host(hist), vecs)
+        S.close()
+    (xa, sa, ha, va), (xb, sb, hb, vb) = out[1], out[0]
+    print(name, sa["status_name"], sa["iterations"], sa["replacements"])
+    assert sa["iterations"] == sb["iterations"] and sa["status"] == sb["status"]
+    assert sa["iterations"] > 0
+    assert np.array_equal(xa, xb)
+    assert np.array_equal(ha, hb)
+    for v in va:
+        assert np.array_equal(va[v], vb[v]), v
