@@ -63,8 +63,25 @@ PHASEB_FP64_BYTES_ROW = 15 * 8
 PHASEB_FP32_BYTES_ROW = 13 * 4 + 16
 
 
+# counted kernel per workload: (file prefix, hash key, kernel-name key per
+# storage precision, algorithmic bytes per row per precision, rows)
+_C4_ROWS, _C4_SLOTS = 2_000_000, 27
+COUNTED = {
+    "convdiff200": ("phaseB", "phaseB", {"fp64": "k_phaseB", "mixed": "k_phaseB"},
+                    {"fp64": 15 * 8, "mixed": 13 * 4 + 16}, 200 ** 3),
+    "poisson1000": ("phaseB", "phaseB", {"fp64": "k_phaseB", "mixed": "k_phaseB"},
+                    {"fp64": 15 * 8, "mixed": 13 * 4 + 16}, 1000 ** 2),
+    # the sliced-ELL product reading M^-1 z: the input and output vectors and
+    # 27 (value, int32 column) slots per row
+    "random2m": ("spmv_sell_lds", "spmv_sell_lds",
+                 {"fp64": "k_spmv_sell_lds<double", "mixed": "k_spmv_sell_lds<float"},
+                 {"fp64": 2 * 8 + _C4_SLOTS * 12, "mixed": 2 * 4 + _C4_SLOTS * 8}, _C4_ROWS),
+}
+
+
 def traffic_file(workload, precision):
-    return os.path.join(HERE, "profiles", f"phaseB_{workload}_{precision}_traffic.txt")
+    return os.path.join(HERE, "profiles",
+                        f"{COUNTED[workload][0]}_{workload}_{precision}_traffic.txt")
 
 
 def parse():
@@ -99,25 +116,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the device code phase B and the copy kernel are built from
-    (their definitions, the shared device helpers and the stencil product
-    phase B computes): a stored counter reading is used only while that code
-    is unchanged."""
+_HASH_COMMON = ("common.hpp", ("double lane_xor(", "double wave_sum(", "void block_partials(",
+                                "void ld16(", "void st16(", "void ldc(", "void stc(",
+                                "struct XcdWalk"))
+_HASH_PARTS = {
+    "phaseB": (("kernels_vec.hip", ("struct PhaseBArgs", "struct BTile", "void phaseB_issue(",
+                                    "void phaseB_stencil(", "void phaseB_update(",
+                                    "void k_phaseB(", "void k_copy(", "bool marchable(",
+                                    "auto tile_seq(", "bool march_fused(", "void march_rotate(",
+                                    "void march_planes(")),
+               _HASH_COMMON,
+               ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "struct TileSeq",
+                            "struct RowSeq", "T st_row_sum(", "void st_apply(",
+                            "void st_apply3_planes("))),
+    "spmv_sell_lds": (("kernels_op.hip", ("struct LdsVis", "void k_spmv_sell_lds(",
+                                          "void launch_spmv_lds(")),
+                      ("kernels_vec.hip", ("void k_copy(",)),
+                      _HASH_COMMON,
+                      ("ops.hpp", ("struct SellOp",))),
+}
+
+
+def kernel_source_hash(kernel="phaseB"):
+    """Hash of the device code a counted kernel and the copy kernel are built
+    from (their definitions and the shared device helpers): a stored counter
+    reading is used only while that code is unchanged."""
     import hashlib
     h = hashlib.sha256()
-    parts = (("kernels_vec.hip", ("struct PhaseBArgs", "struct BTile", "void phaseB_issue(",
-                                  "void phaseB_stencil(", "void phaseB_update(", "void k_phaseB(",
-                                  "void k_copy(", "bool marchable(", "auto tile_seq(",
-                                  "bool march_fused(", "void march_rotate(",
-                                  "void march_planes(")),
-             ("common.hpp", ("double lane_xor(", "double wave_sum(", "void block_partials(",
-                             "void ld16(", "void st16(", "void ldc(", "void stc(",
-                             "struct XcdWalk")),
-             ("ops.hpp", ("T prec1(", "void load_chunk(", "struct StParams", "struct TileSeq",
-                          "struct RowSeq", "T st_row_sum(", "void st_apply(",
-                          "void st_apply3_planes(")))
-    for fname, starts in parts:
+    for fname, starts in _HASH_PARTS[kernel]:
         src = open(os.path.join(HERE, "paper_1809_01948_amd/csrc", fname)).read()
         for start in starts:
             i = src.index(start)
@@ -143,53 +169,56 @@ def read_pmc_dir(path, counter):
     return out
 
 
-WORKLOAD_N = {"convdiff200": 200 ** 3, "poisson1000": 1000 ** 2}
-
-
 def summarize_pmc(fetch_dir, write_dir, workload, precision):
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of phase B and of the
-    plain copy kernel; the copy's known bytes calibrate each counter."""
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the workload's counted
+    kernel and of the plain copy kernel; the copy's known bytes calibrate
+    each counter."""
     fetch = read_pmc_dir(fetch_dir, "FETCH_SIZE")
     write = read_pmc_dir(write_dir, "WRITE_SIZE")
+    label, hkey, keys, per_row, n = COUNTED[workload]
+    key = keys[precision]
 
     def pick(d, key):
+        # dispatches of a converged solve's last graph chunk exit at once
+        # (a few bytes each): only full launches are averaged
         vals = [v for k, vs in d.items() if key in k for v in vs]
         if not vals:
             raise SystemExit(f"no dispatch of {key} in the counter output")
+        vals = [v for v in vals if v >= 0.5 * max(vals)]
         return sum(vals) / len(vals), len(vals)
 
-    n = WORKLOAD_N[workload]
     npad = (n + 2047) // 2048 * 2048
     copy_bytes = 8 * npad                               # read once, written once
-    f_b, nf = pick(fetch, "k_phaseB")
-    w_b, nw = pick(write, "k_phaseB")
+    f_b, nf = pick(fetch, key)
+    w_b, nw = pick(write, key)
     f_c, _ = pick(fetch, "k_copy")
     w_c, _ = pick(write, "k_copy")
     kf = copy_bytes / (f_c * 1024.0)
     kw = copy_bytes / (w_c * 1024.0)
     traffic = f_b * 1024.0 * kf + w_b * 1024.0 * kw
-    per_row = PHASEB_FP64_BYTES_ROW if precision == "fp64" else PHASEB_FP32_BYTES_ROW
-    algo = per_row * npad
+    algo = per_row[precision] * (npad if label == "phaseB" else n)
     kflag = "" if workload == "convdiff200" else f" --kernels-workload {workload}"
-    pflag = "" if precision == "fp64" else f" --kernels-precision {precision}"
+    pflag = "" if precision == "fp64" or workload == "random2m" \
+        else f" --kernels-precision {precision}"
     fd, wd = os.path.relpath(fetch_dir, HERE), os.path.relpath(write_dir, HERE)
     lines = [
-        f"# phase B, {workload} {precision}: HBM traffic per launch",
-        f"source_hash {kernel_source_hash()}",
+        f"# {label} ({key}), {workload} {precision}: HBM traffic per launch",
+        f"source_hash {kernel_source_hash(hkey)}",
         "commands (from the repository root R; the profiler runs from /tmp):",
         f"  rocprofv3 --pmc FETCH_SIZE --output-format csv -d R/{fd} -- "
         f"python R/bench.py --kernels-only{kflag}{pflag}",
         f"  rocprofv3 --pmc WRITE_SIZE --output-format csv -d R/{wd} -- "
         f"python R/bench.py --kernels-only{kflag}{pflag}",
-        f"  python bench.py --summarize-pmc {fd} {wd}{kflag}{pflag}",
-        f"dispatches phaseB fetch {nf} write {nw}",
-        f"FETCH_SIZE_KiB phaseB {f_b:.1f} copy {f_c:.1f}",
-        f"WRITE_SIZE_KiB phaseB {w_b:.1f} copy {w_c:.1f}",
+        f"  python bench.py --summarize-pmc {fd} {wd}{kflag}"
+        f"{'' if precision == 'fp64' else ' --kernels-precision ' + precision}",
+        f"full_dispatches {label} fetch {nf} write {nw}",
+        f"FETCH_SIZE_KiB {label} {f_b:.1f} copy {f_c:.1f}",
+        f"WRITE_SIZE_KiB {label} {w_b:.1f} copy {w_c:.1f}",
         f"copy_algorithmic_bytes_each_way {copy_bytes}",
         f"calibration_fetch {kf:.4f}",
         f"calibration_write {kw:.4f}",
-        f"phaseB_algorithmic_bytes {algo}",
-        f"phaseB_traffic_bytes {traffic:.0f}",
+        f"{label}_algorithmic_bytes {algo}",
+        f"{label}_traffic_bytes {traffic:.0f}",
         f"traffic_over_algorithmic {traffic / algo:.4f}",
     ]
     with open(traffic_file(workload, precision), "w") as f:
@@ -207,9 +236,10 @@ def stored_traffic(workload, precision):
                 parts = line.split()
                 if len(parts) == 2:
                     kv[parts[0]] = parts[1]
-        if kv.get("source_hash") != kernel_source_hash():
+        label, hkey = COUNTED[workload][:2]
+        if kv.get("source_hash") != kernel_source_hash(hkey):
             return None
-        return float(kv["phaseB_traffic_bytes"])
+        return float(kv[f"{label}_traffic_bytes"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -487,6 +517,8 @@ def other_kernels(which, dev):
             # products fused into the phase kernels; five coefficient arrays
             byts = {"phaseA": 14 * bv + slots * bv, "phaseB": 14 * bv + 16 + slots * bv}
             it_bytes = byts["phaseA"] + byts["phaseB"]
+        # the copy kernel calibrates the HBM byte counters of the product
+        out["ms"][f"{prec}_copy"] = S.time_kernel("copy", reps=KERNELS_ONLY_REPS)
         for k, bpr in byts.items():
             ms = S.time_kernel(k, reps=KERNELS_ONLY_REPS)
             out["bytes_per_row"][f"{prec}_{k}"] = bpr

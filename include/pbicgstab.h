@@ -184,6 +184,10 @@ void pbicgstab_default_opts(pbcg_opts* opt);
  *                         (FP32 storage only)
  *   PBCG_PREMULT=0|1      sliced-ELL products reading the M^-1 z, M^-1 w that
  *                         the phase kernels write (Jacobi vector)
+ *   PBCG_SELL_LDS=0|1     sliced-ELL iteration products staging each 1024-row
+ *                         block's column window in LDS (when it fits)
+ *   PBCG_LDS_BLOCKS=n     blocks of that product (0: 256 per window that takes
+ *                         more than half a block's LDS, else 512)
  * None changes a result bit except PBCG_NBLK and PBCG_MARCH_PHASE, which set
  * the order in which the dot products are summed.
  */

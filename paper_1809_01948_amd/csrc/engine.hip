@@ -219,6 +219,7 @@ void common_setup(Solver& S, int precision, int precond, void* workspace, size_t
   if (const char* env = std::getenv("PBCG_MARCH_PHASE")) S.march_phase = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_PREMULT")) S.premult = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_SELL_LDS")) S.sell_lds = std::atoi(env) != 0;
+  if (const char* env = std::getenv("PBCG_LDS_BLOCKS")) S.lds_blocks = std::atoi(env);
   {
     int dev = 0, cap = 0;
     hipck(hipGetDevice(&dev), "hipGetDevice");

@@ -950,9 +950,13 @@ static void launch_spmv_lds(Solver& S, bool tr, const void* in, void* out, int f
                             hipStream_t st, bool pre) {
   if (fin_mode != FIN_NONE) launch_fin(S, fin_mode, st);
   const OpData& o = op_of(S, tr);
-  const int64_t nw = std::min<int64_t>(o.nlb, 256);
-  const int nwork = (int)std::max<int64_t>(kXcds, nw / kXcds * kXcds);
   const size_t shmem = (size_t)o.win_max * S.tsize;
+  // one block per CU when the window takes more than half a block's LDS,
+  // else two (2e6 x 27 banded matrix, 88 KB FP64 windows: 256 blocks 124 us,
+  // 512 126 us; 44 KB FP32 windows: 256 blocks 83 us, 512 78 us)
+  const int64_t per_cu = shmem * 2 > (size_t)S.lds_cap ? 1 : 2;
+  const int64_t nw = std::min<int64_t>(o.nlb, S.lds_blocks > 0 ? S.lds_blocks : 256 * per_cu);
+  const int nwork = (int)std::max<int64_t>(kXcds, nw / kXcds * kXcds);
   with_op(S, tr, !pre, [&]<typename T, int PC, class Op>(const Op& op) {
     if constexpr (std::is_same_v<Op, SellOp<T>>) {
       static bool attr = false;
