@@ -146,6 +146,15 @@ typedef struct {
                             x_0 := x_{i+1}, which also renews the shadow residual), at most this
                             many times; the iteration count continues.  0 (default): stop with
                             PBCG_BREAKDOWN_RHO as the paper's method does. */
+  const double* rhat;    /* not in the paper: optional device array of n doubles, a fixed shadow
+                            vector used in place of r_0 in every (r_0, .) dot of Algorithms 1
+                            and 2 (also after a restart; rounded to FP32 in mixed precision).
+                            NULL (default): r_0 = b - A x_0, as in the paper.  Any vector with
+                            (rhat, r_0) != 0 is admissible; r_0 breaks down when it is constant
+                            and the operator's interior column sums vanish (a conservative
+                            discretisation with a constant source): (r_0, r_i) then tends to 0
+                            long before r_i does.  Read by the initialisation kernels only;
+                            the caller keeps it alive until the solve returns. */
 } pbcg_opts;
 
 typedef struct {
@@ -164,7 +173,7 @@ typedef struct {
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
  * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
- * rr_eps 0, no bound history, restarts 0. */
+ * rr_eps 0, no bound history, restarts 0, rhat NULL. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

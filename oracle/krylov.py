@@ -273,17 +273,18 @@ def _finish(res, x, status, its, ops, b):
 # Algorithm 1: classic preconditioned BiCGStab
 # -----------------------------------------------------------------------------
 
-def classic_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, record=False):
+def classic_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, record=False, rhat=None):
     """Algorithm 1 (classic preconditioned BiCGStab), Section 2.1.
 
     Three global reductions per iteration: (r0, s_i); (q_i, y_i), (y_i, y_i);
     (r0, r_{i+1}) together with (r_{i+1}, r_{i+1}) for the stopping test.
     No residual replacement (Section 4.3 performs none for the classic
-    method)."""
+    method).  ``rhat`` (not in the paper, default r_0): the fixed vector
+    the dots are taken against in place of r_0."""
     b = ops.copy(b)
     x = ops.zeros() if x0 is None else ops.copy(x0)
     r = b - ops.spmv(x)                       # r_0 := b - A x_0
-    rhat = ops.copy(r)                        # the shadow residual r_0
+    rhat = ops.copy(r) if rhat is None else ops.copy(rhat)   # the shadow residual
     p = ops.copy(r)                           # p_0 := r_0
     rho = ops.dot(rhat, r)                    # (r_0, r_i)
     nb = ops.norm(b)
@@ -456,7 +457,7 @@ class _GapBound:
 
 def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                        rr_tau=None, rr_mode="periodic", rr_eps=None, rr_estimate=False,
-                       restarts=0, record=False):
+                       restarts=0, record=False, rhat=None):
     """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with residual
     replacement (Section 3.6, eq:rr):
 
@@ -481,8 +482,16 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     alpha-denominator breakdown in iteration i, up to this many times, the
     method starts again from x_{i+1}: the initialisation of Algorithm 2 is
     repeated with x_0 := x_{i+1} (new r_0 = b - A x_{i+1}, which is also the
-    new shadow residual), the iteration count continues."""
+    new shadow residual), the iteration count continues.
+
+    ``rhat`` (not in the paper, default r_0): a fixed shadow vector that
+    replaces r_0 in every dot (r_0, .) of the algorithm, also after a
+    restart.  BiCGStab admits any such vector with (rhat, r_0) != 0; r_0
+    itself breaks down when the operator's column sums vanish and r_0 is a
+    constant vector, since (1, b - A x_i) then depends on the boundary
+    values of x_i alone and tends to zero long before r_i does."""
     auto = rr_mode == "auto"
+    rhat_in = None if rhat is None else ops.copy(rhat)
     if rr_mode not in ("periodic", "auto"):
         raise ValueError(rr_mode)
     eps = unit_roundoff() if rr_eps is None else rr_eps
@@ -493,7 +502,8 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     def initialise(x):
         """The two lines before the loop of Algorithm 2."""
         r = b - ops.spmv(x)                   # r_0 := b - A x_0
-        rhat = ops.copy(r)                    # shadow residual r_0 (never replaced)
+        # shadow residual r_0 (never replaced), or the caller's fixed vector
+        rhat = ops.copy(r) if rhat_in is None else rhat_in
         k = ops.prec(r)                       # k_0 := M^-1 r_0
         w = ops.spmv(k)                       # w_0 := A k_0
         m = ops.prec(w)                       # m_0 := M^-1 w_0

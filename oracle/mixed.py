@@ -42,13 +42,15 @@ from .krylov import MAX_FORCED_REPLACEMENTS, STATUS, SolveResult, _GapBound
 
 def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None, tol=1e-10,
                                maxit=1000, rr_period=0, rr_tau=None, rr_mode="periodic",
-                               rr_estimate=None, record=False, dot_order="blas"):
+                               rr_estimate=None, record=False, dot_order="blas", rhat=None):
     """Algorithm 2 with `store`-precision vectors (see the module docstring).
 
     A: scipy CSR (FP64 values, rounded here to `store`); b, x0: FP64.
     ``dot_order``: "blas" (numpy.dot) or "fsum" (the correctly rounded sum of
     the products, ``math.fsum``) -- two summation orders of the same dot
     products, for measuring how fast rounding-order differences grow.
+    ``rhat``: a fixed shadow vector in place of r_0 (not in the paper; see
+    krylov.pipelined_bicgstab), stored in the storage precision.
     Returns a ``krylov.SolveResult`` (x in FP64)."""
     S = np.dtype(store).type
     f64 = np.float64
@@ -88,7 +90,7 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
 
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=f64)
     r = (b - spmv_wide(x)).astype(S)       # r_0 = b - A x_0 (FP64), stored
-    rhat = r.copy()
+    rhat = r.copy() if rhat is None else np.asarray(rhat, dtype=f64).astype(S)
     k = prec(r)                            # k_0 = M^-1 r_0
     w = spmv(prec(r))                      # w_0 = A k_0
     m = prec(w)                            # m_0 = M^-1 w_0

@@ -66,6 +66,7 @@ class Opts(ctypes.Structure):
         ("bound_history", _P),
         ("bound_len", _c.c_int32),
         ("restarts", _c.c_int32),
+        ("rhat", _P),
     ]
 
 

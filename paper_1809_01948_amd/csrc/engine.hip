@@ -664,6 +664,7 @@ void begin_solve(Solver& S, const double* b, const double* x, const pbcg_opts& o
   if (!b || !x) fail(PBCG_ERR_INVALID_ARG, "b and x must be device pointers");
   hipck(hipEventRecord(S.ev_in, cs), "hipEventRecord");
   hipck(hipStreamWaitEvent(S.s1, S.ev_in, 0), "hipStreamWaitEvent");
+  S.rhat_in = o.rhat;
   S.h_sc[2] = initial_scalars(S, o, o.transpose != 0);
   hipck(hipMemcpyAsync(S.sc, &S.h_sc[2], sizeof(DevScalars), hipMemcpyHostToDevice, S.s1),
         "hipMemcpyAsync");

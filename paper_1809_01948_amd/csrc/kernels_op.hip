@@ -313,7 +313,8 @@ __global__ __launch_bounds__(kBlock) void k_init_res(Op op, const double* __rest
                                                      T* __restrict__ g, T* __restrict__ s,
                                                      T* __restrict__ l, T* __restrict__ z,
                                                      T* __restrict__ v, const T* __restrict__ dinv,
-                                                     T ds, int64_t n, int64_t ntiles, int nwork,
+                                                     T ds, const double* __restrict__ rhat_in,
+                                                     int64_t n, int64_t ntiles, int nwork,
                                                      double* __restrict__ partials) {
   const int blk = blockIdx.x;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -324,11 +325,12 @@ __global__ __launch_bounds__(kBlock) void k_init_res(Op op, const double* __rest
       op.row(i, vis);
       const T ri = (T)(b[i] - vis.sum);
       const T ki = prec1<T, PC>(ri, dinv, ds, i);
+      const T hi = rhat_in ? (T)rhat_in[i] : ri;     // the shadow residual
       r[i] = ri;
-      rhat[i] = ri;
+      rhat[i] = hi;
       k[i] = ki;
       g[i] = T(0); s[i] = T(0); l[i] = T(0); z[i] = T(0); v[i] = T(0);
-      acc[0] += (double)ri * (double)ri;
+      acc[0] += (double)hi * (double)ri;
       acc[1] += (double)ri * (double)ri;
       acc[2] += b[i] * b[i];
       acc[3] += x[i] * x[i];
@@ -495,7 +497,8 @@ __global__ __launch_bounds__(kBlock) void k_gap(Op op, const double* __restrict_
 template <typename T, class Op>
 __global__ __launch_bounds__(kBlock) void k_cl_init(Op op, const double* __restrict__ x,
                                                     const double* __restrict__ b, T* __restrict__ r,
-                                                    T* __restrict__ rhat, T* __restrict__ p, int64_t n,
+                                                    T* __restrict__ rhat, T* __restrict__ p,
+                                                    const double* __restrict__ rhat_in, int64_t n,
                                                     int64_t ntiles, int nwork,
                                                     double* __restrict__ partials) {
   double acc[3] = {0.0, 0.0, 0.0};
@@ -505,8 +508,9 @@ __global__ __launch_bounds__(kBlock) void k_cl_init(Op op, const double* __restr
       ResVis<T> vis{x, 0.0};
       op.row(i, vis);
       const T ri = (T)(b[i] - vis.sum);
-      r[i] = ri; rhat[i] = ri; p[i] = ri;
-      acc[0] += (double)ri * (double)ri;
+      const T hi = rhat_in ? (T)rhat_in[i] : ri;     // the shadow residual
+      r[i] = ri; rhat[i] = hi; p[i] = ri;
+      acc[0] += (double)hi * (double)ri;
       acc[1] += (double)ri * (double)ri;
       acc[2] += b[i] * b[i];
     }
@@ -1008,8 +1012,8 @@ void launch_init_res(Solver& S, bool tr, hipStream_t st) {
     hipLaunchKernelGGL((k_init_res<T, PC, Op>), PBCG_GRID_OP, op, (const double*)S.x,
                        (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_RHAT], (T*)S.vec[V_K],
                        (T*)S.vec[V_G], (T*)S.vec[V_S], (T*)S.vec[V_L], (T*)S.vec[V_Z],
-                       (T*)S.vec[V_V], (const T*)S.dinv, (T)S.dinv_s, S.n, S.rtiles, S.nblk,
-                       S.partials);
+                       (T*)S.vec[V_V], (const T*)S.dinv, (T)S.dinv_s, S.rhat_in, S.n, S.rtiles,
+                       S.nblk, S.partials);
   });
 }
 
@@ -1052,8 +1056,8 @@ void launch_gap(Solver& S, bool tr, hipStream_t st, bool force) {
 void launch_cl_init(Solver& S, bool tr, hipStream_t st) {
   with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
     hipLaunchKernelGGL((k_cl_init<T, Op>), PBCG_GRID_OP, op, (const double*)S.x,
-                       (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_RHAT], (T*)S.vec[V_G], S.n,
-                       S.rtiles, S.nblk, S.partials);
+                       (const double*)S.b, (T*)S.vec[V_R], (T*)S.vec[V_RHAT], (T*)S.vec[V_G],
+                       S.rhat_in, S.n, S.rtiles, S.nblk, S.partials);
   });
 }
 

@@ -90,7 +90,8 @@ struct Solver {
   bool premult = true;          // sliced-ELL products read V_PM (pre_multiplied)
   bool sell_lds = true;         // sliced-ELL iteration products stage their column window in LDS
   int64_t lds_cap = 0;          // bytes of LDS one block may use (device attribute)
-  int lds_blocks = 0;           // blocks of the LDS-window product (0: 256)
+  int lds_blocks = 0;           // blocks of the LDS-window product (0: from the window size)
+  const double* rhat_in = nullptr;  // the solve's caller shadow vector (null: r_0)
   bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
   bool march_phase = true;      // phase kernels visit a 3D grid's tiles plane by plane (TileSeq)
   int march_zlen = 0;           // planes per work item of k_spmv_st3m (0: sized to the grid)

@@ -205,14 +205,17 @@ class Solver:
               history: Optional[torch.Tensor] = None, gap_every=0,
               gap_history: Optional[torch.Tensor] = None, use_graph=False,
               method="pipelined", out: Optional[torch.Tensor] = None, rr_auto=False,
-              rr_eps=0.0, bound_history: Optional[torch.Tensor] = None, restarts=0):
+              rr_eps=0.0, bound_history: Optional[torch.Tensor] = None, restarts=0,
+              rhat: Optional[torch.Tensor] = None):
         """Solve A x = b (A^T x = b with transpose).  Returns (x, stats dict).
 
         method: 'pipelined' (Algorithm 2 with residual replacement: every
         ``rr_period`` iterations, or automated with ``rr_auto``) or 'classic'
-        (Algorithm 1)."""
+        (Algorithm 1).  ``rhat``: a fixed shadow vector in place of r_0 (not
+        in the paper; None keeps r_0)."""
         lib = L.load()
         b = _dev_vec(b, self.n, "b")
+        rhat = None if rhat is None else _dev_vec(rhat, self.n, "rhat")
         if out is None:
             out = torch.zeros_like(b) if x0 is None else _dev_vec(x0, self.n, "x0").clone()
         elif x0 is not None:
@@ -223,6 +226,8 @@ class Solver:
                 raise TypeError(f"{nm} must be a contiguous CUDA float64 tensor")
         o = self._opts(tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
                        gap_history, use_graph, rr_auto, rr_eps, bound_history, restarts)
+        if rhat is not None:
+            o.rhat = rhat.data_ptr()
         st = L.Stats()
         fn = lib.pbicgstab_solve if method == "pipelined" else lib.classic_bicgstab_solve
         code = fn(self._h, _ptr(b), _ptr(out), ctypes.byref(o), ctypes.byref(st))

@@ -400,3 +400,71 @@ def test_block_jacobi_classic_equals_pipelined_early():
     rel = lambda a, b: np.max(np.abs(np.array(a) - np.array(b)) / np.abs(np.array(b)))
     assert rel(pi.alpha, cl.alpha) <= 1e-10 and rel(pi.omega, cl.omega) <= 1e-10
     assert rel(pi.rnorm, cl.rnorm) <= 1e-10
+
+
+# -----------------------------------------------------------------------------
+# a fixed shadow vector in place of r_0 (an option outside the paper)
+# -----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fn", [classic_bicgstab, pipelined_bicgstab])
+def test_shadow_vector_r0_is_the_default(fn):
+    """Passing r_0 itself as the shadow vector changes nothing, bit for bit."""
+    p = convdiff2d_c1(16)
+    ops = Float64Ops(p.scipy_csr())
+    kw = dict(rr_period=7) if fn is pipelined_bicgstab else {}
+    a = fn(ops, p.b, tol=1e-12, maxit=300, record=True, **kw)
+    b = fn(ops, p.b, tol=1e-12, maxit=300, record=True, rhat=p.b.copy(), **kw)
+    assert a.iterations == b.iterations and a.status == b.status
+    assert a.alpha == b.alpha and a.omega == b.omega and a.beta == b.beta
+    assert np.array_equal(a.x, b.x)
+
+
+@pytest.mark.parametrize("case", ["dense6", "stencil4x4"])
+def test_exact_classic_equals_pipelined_with_shadow_vector(case):
+    """The exact-arithmetic identity of Algorithms 1 and 2 holds for any
+    shadow vector (the derivation of Algorithm 2 never uses rhat = r_0), and
+    it differs from the run with r_0."""
+    A, b, dinv, xex = _exact_case(case)
+    its = 5
+    rh = np.random.default_rng(3).integers(-4, 5, size=A.shape[0]).astype(float)
+    ops = ExactOps(A, dinv)
+    rc = classic_bicgstab(ops, b, tol=0.0, maxit=its, record=True, rhat=rh)
+    rp = pipelined_bicgstab(ops, b, tol=0.0, maxit=its, record=True, rhat=rh)
+    assert rc.iterations == rp.iterations == its
+    assert rc.alpha == rp.alpha and rc.omega == rp.omega and rc.beta == rp.beta
+    for sc, sp_ in zip(rc.snapshots, rp.snapshots):
+        assert list(sc["x1"]) == list(sp_["x1"])
+    r0 = pipelined_bicgstab(ops, b, tol=0.0, maxit=its)
+    assert r0.alpha != rp.alpha
+
+
+def test_shadow_vector_avoids_the_exact_breakdown():
+    """The 3x3 system whose (r_0, r_1) vanishes exactly: with another shadow
+    vector the iteration does not break down and reaches A^-1 b exactly
+    (finite termination in rational arithmetic) without a restart.  (Not
+    every vector will do: (1, 2, 3) is orthogonal to A r_0 = (2, 2, -2), so
+    its first alpha-denominator vanishes.)"""
+    A = sp.csr_matrix(_BD_A)
+    bad = pipelined_bicgstab(ExactOps(A), _BD_B, tol=0.0, maxit=6,
+                             rhat=np.array([1.0, 2.0, 3.0]))
+    assert bad.status == STATUS["BREAKDOWN_RHO"] and bad.iterations == 0
+    res = pipelined_bicgstab(ExactOps(A), _BD_B, tol=0.0, maxit=6,
+                             rhat=np.array([1.0, 1.0, 1.0]))
+    assert res.status == STATUS["CONVERGED"] and res.restarts == 0
+    assert res.iterations <= 3
+    assert list(res.x) == [Fraction(3, 4), Fraction(1, 4), Fraction(-1)]
+    resc = classic_bicgstab(ExactOps(A), _BD_B, tol=0.0, maxit=6,
+                            rhat=np.array([1.0, 1.0, 1.0]))
+    assert list(resc.x) == list(res.x)
+
+
+def test_mixed_shadow_vector_r0_is_the_default():
+    """The FP32-storage oracle: r_0 (as stored) passed as the shadow vector
+    is the default, bit for bit."""
+    from oracle.mixed import pipelined_bicgstab_lowprec
+    p = convdiff2d_c1(16)
+    A = p.scipy_csr()
+    a = pipelined_bicgstab_lowprec(A, p.b, jacobi=True, tol=1e-6, maxit=200, rr_period=10)
+    b = pipelined_bicgstab_lowprec(A, p.b, jacobi=True, tol=1e-6, maxit=200, rr_period=10,
+                                   rhat=p.b.astype(np.float32).astype(np.float64))
+    assert a.iterations == b.iterations and np.array_equal(a.x, b.x)

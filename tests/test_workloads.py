@@ -69,6 +69,12 @@ def test_c5_dia5_matches_csr_and_faces():
     # row sums equal the boundary-face coefficients (interior rows sum to 0)
     rs = np.asarray(A.sum(axis=1)).ravel().reshape(n, n)
     assert np.allclose(rs[1:-1, 1:-1], 0.0, atol=1e-13)
+    # so do the interior column sums (the convection terms cancel pairwise):
+    # with the constant b the shadow residual r_0 = b gives
+    # (r_0, r_i) = h^2 (1^T b - c^T x_i), c = A^T 1 nonzero on the boundary only
+    cs = np.asarray(A.sum(axis=0)).ravel().reshape(n, n)
+    assert np.allclose(cs[1:-1, 1:-1], 0.0, atol=1e-13)
+    assert np.all(np.abs(cs[0, :]) > 1e-3)
     p = inverse_problem_c5(64)
     assert p.dia5.shape == (5, 64 * 64) and np.allclose(p.b, p.extra["h"] ** 2)
 
