@@ -365,16 +365,23 @@ def _kappa_fd_check(Solver, n, opts, eps=1e-2):
     return gd, fd
 
 
-@pytest.mark.skip(reason="full-size adjoint: classic BiCGStab stopped at rho' = 0 in two of "
-                         "three runs (after 57 and 2992 iterations; residual peaks of 800 x "
-                         "||g||); reported in the design notes, not asserted")
 def test_c5_full_size_forward_adjoint_classic(Solver):
-    """2048^2 coefficient-field problem, forward + adjoint to a 1e-6 relative
-    residual.  At this size only classic BiCGStab reaches 1e-6: pipelined
-    BiCGStab without replacement stalls with a true residual of 0.17 (its
-    residual gap) and every replacement variant ends in a rho' = 0 breakdown
-    (the oracle shows the same trend on 256^2 and 512^2 instances)."""
-    gd, fd = _kappa_fd_check(Solver, 2048, dict(tol=1e-6, maxit=30000, method="classic"))
+    """2048^2 coefficient-field problem, forward + adjoint to a 1e-7 relative
+    residual (the solution error is ~64x that of the 256^2 instance at the
+    same residual: at 1e-6 the central difference is off by 6.5%, which is
+    the solves' error, not the gradient's), dL/dkappa along a random
+    direction against central differences.  Classic BiCGStab with a random fixed shadow vector (an
+    option outside the paper): with r_0 = b = h^2 1 the operator's vanishing
+    interior column sums drive (r_0, r_i) to zero long before r_i (a
+    rho' = 0 breakdown or a stall above the tolerance).  Pipelined BiCGStab
+    does not reach 1e-6 at this size with either shadow vector: without
+    replacement its residual gap stalls the true residual, and every
+    replacement variant ends in a breakdown (the oracle shows the same trend
+    on the 1024^2 instance)."""
+    import torch
+    n = 2048
+    rh = torch.from_numpy(np.random.default_rng(56).standard_normal(n * n)).cuda()
+    gd, fd = _kappa_fd_check(Solver, n, dict(tol=1e-7, maxit=30000, method="classic", rhat=rh))
     assert abs(fd - gd) <= 1e-2 * abs(gd)
 
 
