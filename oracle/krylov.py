@@ -455,9 +455,148 @@ class _GapBound:
         return self.f
 
 
+class _GapBoundProducts(_GapBound):
+    """The other reading of Section 3.6's computation of f^r: the moduli of
+    the entries of the nine products of eq:all_error_matrices (column i),
+    each times the bound of the local error group it multiplies, summed over
+    the columns (the sources j of the errors).  ``_GapBound`` takes the
+    printed eq:DDr_bound instead, where each gap norm is bounded first and
+    the moduli of the propagation matrices are multiplied; this reading keeps
+    the signs inside each product and is never larger.
+
+    The products are those of eq:matrix_expr: the residual gap collects the
+    R errors through U; the S errors through BA; the W errors through UEA
+    and UC; the Z errors through BAEA, BPA, BAC and BD (A, B, C, D, E, P, U
+    of eq:all_matrices, built from the signed alpha, beta, omega).  Column c
+    of every partial product is kept as a vector over the sources and moved
+    to column c+1 with the recursions the matrices obey:
+
+    * a product ending in A, C or D gains, in column c+1, its left factor's
+      column c times -alpha_c, -omega_c or omega_c alpha_c;
+    * one ending in E, B or P is scaled by beta_{c+1} and gains the left
+      factor's column c+1 (E, B) or column c times -omega_c (P);
+    * U accumulates: every source enters with coefficient 1.
+
+    The A/C/D step needs alpha_c, omega_c only (so f^r_{c+1} is known at the
+    end of iteration c); the E/B/P step waits for beta_{c+1}, which the next
+    iteration brings.  Column 0 holds the initial gaps (Section 3.2); R and W
+    sources of iteration c sit in column c+1, S and Z sources in column c.
+    A replacement starts a new system whose column 0 holds the recomputed s
+    and z gaps, with alpha_0 = 0 and the recomputed r and w gaps in column 1.
+    The local error bounds are the same as ``_GapBound``'s."""
+
+    _PRODUCTS = ("B", "BA", "BD", "BAC", "BAE", "BAEA", "BP", "BPA", "U", "UE", "UEA", "UC")
+
+    def _segment(self):
+        cap = 64
+        self.M = {k: np.zeros(cap) for k in self._PRODUCTS}
+        self.th = {k: np.zeros(cap) for k in "RSWZ"}
+        self.M["B"][0] = 1.0
+        self.M["U"][0] = 1.0
+        self.c = 0                                     # current column (sources 0..c)
+
+    def _grow(self):
+        if self.c + 2 <= len(self.M["B"]):
+            return
+        for d in (self.M, self.th):
+            for k in d:
+                d[k] = np.concatenate([d[k], np.zeros(len(d[k]))])
+
+    def _step_acd(self, alpha, omega):
+        """Column c -> c+1 of the products that end in A, C, D or U."""
+        M, c = self.M, self.c
+        self._grow()
+        sl = slice(0, c + 1)
+        old_ba = M["BA"][sl].copy()
+        M["BA"][sl] -= alpha * M["B"][sl]
+        M["BD"][sl] += omega * alpha * M["B"][sl]
+        M["BAC"][sl] -= omega * old_ba
+        M["BAEA"][sl] -= alpha * M["BAE"][sl]
+        M["BPA"][sl] -= alpha * M["BP"][sl]
+        M["UEA"][sl] -= alpha * M["UE"][sl]
+        M["UC"][sl] -= omega * M["U"][sl]
+        M["U"][c + 1] = 1.0                            # the new source row c+1
+
+    def _step_ebp(self, beta, omega_prev):
+        """Column c -> c+1 of the products that end in B, E or P (after
+        ``_step_acd`` moved the A/U products to column c+1)."""
+        M, c = self.M, self.c
+        sl = slice(0, c + 1)
+        M["BP"][sl] = beta * (M["BP"][sl] - omega_prev * M["B"][sl])
+        M["B"][sl] *= beta
+        M["B"][c + 1] = 1.0
+        sl1 = slice(0, c + 2)
+        M["BAE"][sl1] = beta * M["BAE"][sl1] + M["BA"][sl1]
+        M["UE"][sl1] = beta * M["UE"][sl1] + M["U"][sl1]
+        self.c = c + 1
+
+    def _value(self):
+        M, th, n = self.M, self.th, self.c + 2       # sources 0..c+1 of column c+1
+        a = np.abs
+        f = (np.sum(th["R"][:n])
+             + np.sum(th["S"][:n] * a(M["BA"][:n]))
+             + np.sum(th["W"][:n] * (a(M["UEA"][:n]) + a(M["UC"][:n])))
+             + np.sum(th["Z"][:n] * (a(M["BAEA"][:n]) + a(M["BPA"][:n]) + a(M["BAC"][:n])
+                                     + a(M["BD"][:n]))))
+        return float(f)
+
+    def start(self, nx, nk):
+        e = self.eps
+        self._segment()
+        self.th["R"][0] = ((self.cmu + 1.0) * self.nA * nx + self.nb) * e
+        self.th["W"][0] = self.smu * nk * e
+        self.first = True
+        self.pending = False
+        self.prev = dict(g=0.0, s=0.0, l=0.0, z=0.0, n=0.0, v=0.0)
+        self.f = float(self.th["R"][0])
+        return self.f
+
+    def step(self, a, b, w, wp, nm):
+        e, nA = self.eps, self.nA
+        d = {key: val * e for key, val in
+             self.local_bounds(abs(a), abs(b), abs(w), abs(wp), nm).items()}
+        if self.first:          # Delta^s_0 and Delta^z_0: the initial gaps
+            self.th["S"][0] = self.smu * nm["g"] * e
+            self.th["Z"][0] = self.smu * nm["l"] * e
+            self.first = False
+        else:
+            if self.pending:    # column c of the B/E/P products needs beta_c
+                self._step_ebp(b, wp)
+            c = self.c
+            self.th["S"][c] = nA * d["g"] + d["s"]
+            self.th["Z"][c] = nA * d["l"] + d["z"]
+        self._step_acd(a, w)
+        c = self.c
+        self.th["R"][c + 1] = (nA * d["x"] + d["r"] + abs(w) * nA * d["u"] + d["q"]
+                               + abs(w) * d["y"])
+        self.th["W"][c + 1] = nA * d["k"] + d["w_"] + nA * d["u"] + d["y"]
+        self.pending = True
+        self.f = self._value()
+        self.prev = dict(g=nm["g"], s=nm["s"], l=nm["l"], z=nm["z"], n=nm["n"], v=nm["v"])
+        return self.f
+
+    def reset(self, nx, nk, ng, nl, ns=None, nz=None):
+        e = self.eps_r
+        self._segment()
+        self.th["S"][0] = self.smu * ng * e
+        self.th["Z"][0] = self.smu * nl * e
+        self._step_acd(0.0, 0.0)                       # the leading step: alpha = 0
+        self.th["R"][1] = ((self.cmu + 1.0) * self.nA * nx + self.nb) * e
+        self.th["W"][1] = self.smu * nk * e
+        self.first = False
+        self.pending = True
+        self.prev["l"] = nl
+        if ns is not None:
+            self.prev["s"] = ns
+        if nz is not None:
+            self.prev["z"] = nz
+        self.f = self._value()
+        return self.f
+
+
 def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                        rr_tau=None, rr_mode="periodic", rr_eps=None, rr_estimate=False,
-                       restarts=0, record=False, rhat=None):
+                       rr_reading="nested", restarts=0, record=False, rhat=None):
     """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with residual
     replacement (Section 3.6, eq:rr):
 
@@ -468,7 +607,10 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
       roundoff) and the criterion eq:criterion: replace in step i when
       f^r_{i-1} <= tau ||r_{i-1}|| and f^r_i > tau ||r_i||, tau = sqrt(eps);
       with ``rr_estimate`` the square-root estimate of the bound (Section
-      3.6 suggests it as a less pessimistic alternative).
+      3.6 suggests it as a less pessimistic alternative); ``rr_reading``
+      "nested" evaluates eq:DDr_bound as printed (``_GapBound``), "products"
+      the moduli of the products of eq:all_error_matrices
+      (``_GapBoundProducts``).
 
     Two global reductions per iteration, each overlapped (on parallel
     hardware) by one PREC + SPMV: (q_i, y_i), (y_i, y_i) with
@@ -533,8 +675,9 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     rr_next = False
     forced = 0                                # replacements forced by a failed confirmation
     if auto:
-        gb = _GapBound(ops.n, ops.max_row_nnz(), ops.norm_bound_A(), ops.norm_bound_M(), eps, nb,
-                       estimate=rr_estimate)
+        cls = {"nested": _GapBound, "products": _GapBoundProducts}[rr_reading]
+        gb = cls(ops.n, ops.max_row_nnz(), ops.norm_bound_A(), ops.norm_bound_M(), eps, nb,
+                 estimate=rr_estimate)
         f_cur = gb.start(ops.norm(x), ops.norm(k))
         f_ok_prev = f_cur <= tau * rn0
 

@@ -37,12 +37,13 @@ import math
 
 import numpy as np
 
-from .krylov import MAX_FORCED_REPLACEMENTS, STATUS, SolveResult, _GapBound
+from .krylov import MAX_FORCED_REPLACEMENTS, STATUS, SolveResult, _GapBound, _GapBoundProducts
 
 
 def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None, tol=1e-10,
                                maxit=1000, rr_period=0, rr_tau=None, rr_mode="periodic",
-                               rr_estimate=None, record=False, dot_order="blas", rhat=None):
+                               rr_estimate=None, record=False, dot_order="blas", rhat=None,
+                               rr_reading="nested"):
     """Algorithm 2 with `store`-precision vectors (see the module docstring).
 
     A: scipy CSR (FP64 values, rounded here to `store`); b, x0: FP64.
@@ -119,7 +120,8 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
         nA = math.sqrt(float(absA.sum(axis=0).max()) * float(absA.sum(axis=1).max()))
         nM = float(np.max(np.abs(1.0 / diag))) if jacobi else 1.0
         mu = int(np.max(np.diff(A.indptr)))
-        gb = _GapBound(n, mu, nA, nM, eps_s, nb, estimate=estimate, eps_replace=eps_64)
+        cls = {"nested": _GapBound, "products": _GapBoundProducts}[rr_reading]
+        gb = cls(n, mu, nA, nM, eps_s, nb, estimate=estimate, eps_replace=eps_64)
         f_next = gb.start(norm(x), norm(k))
         f_ok_prev = f_next <= tau * rn0
         rr_next = False

@@ -33,13 +33,13 @@ def _problem(name):
     raise ValueError(name)
 
 
-def _run(name, replacements, maxit=80):
+def _run(name, replacements, maxit=80, reading="nested"):
     p, A, dinv = _problem(name)
     ops = Float64Ops(A, dinv)
     # rr_tau = 1e300: the criterion never fires, f^r is still evaluated
     tau = None if replacements else 1e300
     res = pipelined_bicgstab(ops, p.b, tol=1e-300, maxit=maxit, rr_mode="auto", rr_tau=tau,
-                             record=True)
+                             record=True, rr_reading=reading)
     nM = ops.norm_bound_M()
     return p, A, ops, res, nM
 
@@ -51,14 +51,18 @@ def _matrix_form(ops, res, n, nM, reading="nested"):
 
 @pytest.mark.parametrize("name", ["c1_6_jacobi", "tp2_50"])
 @pytest.mark.parametrize("replacements", [False, True])
-def test_recursion_equals_matrix_form(name, replacements):
-    p, A, ops, res, nM = _run(name, replacements)
+@pytest.mark.parametrize("reading", ["nested", "products"])
+def test_recursion_equals_matrix_form(name, replacements, reading):
+    """The running bound of either reading (``_GapBound``: gap norms carried
+    one iteration at a time; ``_GapBoundProducts``: the columns of the nine
+    products moved one column at a time) equals the explicit matrices."""
+    p, A, ops, res, nM = _run(name, replacements, reading=reading)
     assert res.iterations == 80 and len(res.fr) == 80
     if replacements:
         assert res.replacements >= 1
     else:
         assert res.replacements == 0
-    fm = _matrix_form(ops, res, p.n, nM)
+    fm = _matrix_form(ops, res, p.n, nM, reading)
     rel = np.abs(fm - np.array(res.fr)) / np.array(res.fr)
     assert rel.max() <= 1e-12, rel.max()
 
@@ -83,11 +87,40 @@ class _WrongCoefficient(K._GapBound):
         return d
 
 
-@pytest.mark.parametrize("planted", [_DroppedTerm, _WrongCoefficient])
-def test_planted_mistake_breaks_agreement(monkeypatch, planted):
-    monkeypatch.setattr(K, "_GapBound", planted)
-    p, A, ops, res, nM = _run("tp2_50", False, maxit=60)
-    fm = _matrix_form(ops, res, p.n, nM)
+class _ProductsWrongIndex(K._GapBoundProducts):
+    """The products reading with BAC's column c+1 formed from BA's column
+    c+1 instead of column c (an index shifted by one: C multiplied after A's
+    new column).  (A sign error that flips a whole product cannot show: the
+    reading takes its moduli.)"""
+
+    def _step_acd(self, alpha, omega):
+        c = self.c
+        before = self.M["BA"][:c + 1].copy()
+        super()._step_acd(alpha, omega)
+        self.M["BAC"][:c + 1] += omega * before - omega * self.M["BA"][:c + 1]
+
+
+class _ProductsDroppedPath(K._GapBoundProducts):
+    """The products reading without the BPA product (the P path of the z
+    gap into the s gap)."""
+
+    def _value(self):
+        keep = self.M["BPA"].copy()
+        self.M["BPA"][:] = 0.0
+        f = super()._value()
+        self.M["BPA"][:] = keep
+        return f
+
+
+@pytest.mark.parametrize("planted,reading", [(_DroppedTerm, "nested"),
+                                             (_WrongCoefficient, "nested"),
+                                             (_ProductsWrongIndex, "products"),
+                                             (_ProductsDroppedPath, "products")])
+def test_planted_mistake_breaks_agreement(monkeypatch, planted, reading):
+    name = "_GapBound" if reading == "nested" else "_GapBoundProducts"
+    monkeypatch.setattr(K, name, planted)
+    p, A, ops, res, nM = _run("tp2_50", False, maxit=60, reading=reading)
+    fm = _matrix_form(ops, res, p.n, nM, reading)
     rel = np.abs(fm - np.array(res.fr)) / fm
     assert rel.max() > 1e-6, rel.max()
 

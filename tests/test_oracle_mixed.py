@@ -25,7 +25,7 @@ def _cases():
 
 
 @pytest.mark.parametrize("name,p,jacobi", _cases(), ids=[c[0] for c in _cases()])
-@pytest.mark.parametrize("mode", ["periodic", "auto"])
+@pytest.mark.parametrize("mode", ["periodic", "auto", "auto-products"])
 def test_float64_storage_is_the_fp64_oracle(name, p, jacobi, mode):
     A = p.scipy_csr()
     ops = Float64Ops(A, 1.0 / A.diagonal() if jacobi else None)
@@ -34,6 +34,8 @@ def test_float64_storage_is_the_fp64_oracle(name, p, jacobi, mode):
         kw["rr_period"] = 7
     else:
         kw["rr_mode"] = "auto"
+        if mode == "auto-products":
+            kw["rr_reading"] = "products"
     ref = pipelined_bicgstab(ops, p.b, **kw)
     got = pipelined_bicgstab_lowprec(A, p.b, jacobi=jacobi, store=np.float64, **kw)
     assert got.status == ref.status and got.iterations == ref.iterations
