@@ -33,36 +33,40 @@ def _problem(name):
     raise ValueError(name)
 
 
-def _run(name, replacements, maxit=80, reading="nested"):
+def _run(name, replacements, maxit=80, reading="nested", estimate=False):
     p, A, dinv = _problem(name)
     ops = Float64Ops(A, dinv)
     # rr_tau = 1e300: the criterion never fires, f^r is still evaluated
     tau = None if replacements else 1e300
     res = pipelined_bicgstab(ops, p.b, tol=1e-300, maxit=maxit, rr_mode="auto", rr_tau=tau,
-                             record=True, rr_reading=reading)
+                             record=True, rr_reading=reading, rr_estimate=estimate)
     nM = ops.norm_bound_M()
     return p, A, ops, res, nM
 
 
-def _matrix_form(ops, res, n, nM, reading="nested"):
+def _matrix_form(ops, res, n, nM, reading="nested", estimate=False):
     return np.array(GM.bound_history_from_run(res, ops.norm_bound_A(), nM, ops.max_row_nnz(), n,
-                                              res.bnorm, reading=reading))
+                                              res.bnorm, reading=reading, estimate=estimate))
 
 
 @pytest.mark.parametrize("name", ["c1_6_jacobi", "tp2_50"])
 @pytest.mark.parametrize("replacements", [False, True])
 @pytest.mark.parametrize("reading", ["nested", "products"])
-def test_recursion_equals_matrix_form(name, replacements, reading):
+@pytest.mark.parametrize("estimate", [False, True])
+def test_recursion_equals_matrix_form(name, replacements, reading, estimate):
     """The running bound of either reading (``_GapBound``: gap norms carried
     one iteration at a time; ``_GapBoundProducts``: the columns of the nine
-    products moved one column at a time) equals the explicit matrices."""
-    p, A, ops, res, nM = _run(name, replacements, reading=reading)
+    products moved one column at a time) equals the explicit matrices, for
+    the worst-case bound and its square-root estimate (mu sqrt(N) -> sqrt(mu)
+    and mu~ sqrt(N) -> 1, applied by the generic rounding model to its
+    operator terms)."""
+    p, A, ops, res, nM = _run(name, replacements, reading=reading, estimate=estimate)
     assert res.iterations == 80 and len(res.fr) == 80
     if replacements:
         assert res.replacements >= 1
     else:
         assert res.replacements == 0
-    fm = _matrix_form(ops, res, p.n, nM, reading)
+    fm = _matrix_form(ops, res, p.n, nM, reading, estimate)
     rel = np.abs(fm - np.array(res.fr)) / np.array(res.fr)
     assert rel.max() <= 1e-12, rel.max()
 
