@@ -133,8 +133,14 @@ typedef struct {
                             roundoff, the arithmetic of the replacement), replaces in step i
                             when f^r_{i-1} <= tau ||r_{i-1}|| and f^r_i > tau ||r_i||
                             (eq:criterion), tau = rr_tau or sqrt(rr_eps).
-                            1: the worst-case bound; 2: its square-root estimate (mu sqrt(N)
-                            -> sqrt(mu), mu~ sqrt(N) -> 1); 0: periodic replacement */
+                            1: the worst-case bound as eq:DDr_bound prints it (each gap norm
+                            bounded first: products of the moduli of the error propagation
+                            matrices); 2: its square-root estimate (mu sqrt(N) -> sqrt(mu),
+                            mu~ sqrt(N) -> 1); 3: the moduli of the products of the error
+                            propagation matrices of eq:all_error_matrices, column by column,
+                            times the local error bounds (never larger than variant 1's;
+                            needs bound_state); 4: 3 with the estimate's local bounds;
+                            0: periodic replacement */
   double rr_eps;         /* epsilon of the bound; 0 selects the unit roundoff of the storage
                             precision (2^-53 FP64, 2^-24 mixed) */
   double* bound_history; /* optional device buffer of bound_len doubles: with rr_auto, entry i
@@ -155,6 +161,11 @@ typedef struct {
                             discretisation with a constant source): (r_0, r_i) then tends to 0
                             long before r_i does.  Read by the initialisation kernels only;
                             the caller keeps it alive until the solve returns. */
+  double* bound_state;   /* rr_auto 3 or 4: caller-owned device scratch for the bound's state,
+                            16 doubles per iteration since the last replacement: at least
+                            16 * (maxit + 2) doubles (PBCG_ERR_INVALID_ARG otherwise); contents
+                            on entry are ignored, on return unspecified */
+  int64_t bound_state_len; /* doubles in bound_state */
 } pbcg_opts;
 
 typedef struct {
@@ -173,7 +184,7 @@ typedef struct {
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
  * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
- * rr_eps 0, no bound history, restarts 0, rhat NULL. */
+ * rr_eps 0, no bound history, restarts 0, rhat NULL, no bound state. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

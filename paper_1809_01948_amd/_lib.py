@@ -67,6 +67,8 @@ class Opts(ctypes.Structure):
         ("bound_len", _c.c_int32),
         ("restarts", _c.c_int32),
         ("rhat", _P),
+        ("bound_state", _P),
+        ("bound_state_len", _c.c_int64),
     ]
 
 

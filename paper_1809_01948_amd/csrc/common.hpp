@@ -31,6 +31,7 @@ constexpr int64_t kPadElems = 2048;  // vector padding granularity (elements)
 constexpr int64_t kWsAlign = 256;    // alignment of every piece of the caller's workspace
 constexpr int kXcds = 8;             // MI355X: workgroups are dispatched round-robin over 8 XCDs
 constexpr int kSellC = 64;           // SELL slice height = one wavefront
+constexpr int kBoundStateArrays = 16;  // arrays of the products reading's per-source state
 constexpr int kLdsRows = 1024;       // rows (and threads) of a block of the LDS-window SELL product
 
 // partial slots
@@ -119,7 +120,25 @@ struct alignas(64) DevScalars {
   int32_t fin_arrive;
   int32_t bound_len;               // entries of bound_history
   double* bound_history;           // optional f^r per iteration (automated mode)
+  // the products reading of f^r (moduli of the products of the error
+  // propagation matrices): a state per error source in the caller's buffer
+  // pr_state, advanced by k_bound_products after each final that moves it
+  int32_t gb_prod;                 // 1: products reading (else the nested one above)
+  int32_t pr_op;                   // pending work: PR_START | PR_STEP | PR_RESET | PR_CRIT
+  int32_t pr_c;                    // current column c (sources 0 .. c+1 in use)
+  int32_t pr_first, pr_pending;    // iteration 0 next / B, E, P products await beta
+  int32_t pr_its;                  // iteration index for the bound history
+  int64_t pr_cap;                  // sources the buffer holds
+  double pr_a, pr_b, pr_w, pr_wp;  // signed alpha_i, beta_i, omega_i, omega_{i-1}
+  double pr_R, pr_W, pr_S, pr_Z;   // local error group bounds of the step
+  double pr_S0, pr_Z0;             // initial s and z gaps (iteration 0)
+  double pr_rR, pr_rW, pr_rS, pr_rZ; // gaps of a replacement's recomputation
+  double pr_rn;                    // ||r_{i+1}|| for eq:criterion
+  double* pr_state;                // 16 arrays of pr_cap doubles
 };
+
+// pending work flags of the products reading
+enum : int32_t { PR_START = 1, PR_STEP = 2, PR_RESET = 4, PR_CRIT = 8 };
 
 // ----------------------------------------------------------------------------
 // reductions

@@ -631,7 +631,10 @@ DevScalars initial_scalars(const Solver& S, const pbcg_opts& o, bool tr) {
   d.bound_history = o.bound_history;
   d.bound_len = o.bound_history ? o.bound_len : 0;
   d.rr_auto = o.rr_auto ? 1 : 0;
-  d.rr_est = o.rr_auto == 2 ? 1 : 0;
+  d.rr_est = (o.rr_auto == 2 || o.rr_auto == 4) ? 1 : 0;
+  d.gb_prod = o.rr_auto >= 3 ? 1 : 0;
+  d.pr_state = o.rr_auto >= 3 ? o.bound_state : nullptr;
+  d.pr_cap = o.rr_auto >= 3 ? o.bound_state_len / kBoundStateArrays : 0;
   d.eps_b = o.rr_eps > 0 ? o.rr_eps : std::ldexp(1.0, S.precision == PBCG_FP64 ? -53 : -24);
   d.eps_r = std::ldexp(1.0, -53);     // replacements are computed in FP64
   if (o.rr_auto && !(o.rr_tau > 0)) d.tau = std::sqrt(d.eps_b);
@@ -656,6 +659,11 @@ void validate_opts(const pbcg_opts& o) {
   if (o.check_every < 0) fail(PBCG_ERR_INVALID_ARG, "check_every must be >= 0");
   if (o.history_len < 0 || o.gap_len < 0 || o.gap_every < 0 || o.bound_len < 0)
     fail(PBCG_ERR_INVALID_ARG, "negative history length");
+  if (o.rr_auto < 0 || o.rr_auto > 4) fail(PBCG_ERR_INVALID_ARG, "rr_auto must be 0 .. 4");
+  if (o.rr_auto >= 3 &&
+      (!o.bound_state || o.bound_state_len < kBoundStateArrays * ((int64_t)o.maxit + 2)))
+    fail(PBCG_ERR_INVALID_ARG, "rr_auto 3 or 4 needs bound_state of at least 16 * (maxit + 2) "
+                               "doubles");
 }
 
 // Upload scalars, copy b and x0 into the padded internal vectors.
@@ -729,6 +737,7 @@ bool enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_
   }
   if (!fused) launch_iter_spmv(S, tr, V_W, V_T, FIN_BETA, st);
   else if (!defer) launch_fin(S, FIN_BETA, st);
+  launch_bound_products(S, st);
   if (gap) {
     launch_gap(S, tr, st);
     launch_final(S, FIN_GAP, 0, st);
@@ -858,6 +867,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
   check_block(S, o.transpose != 0, o.rr_auto != 0);
   const bool tr = o.transpose != 0;
   S.auto_rr = o.rr_auto != 0;
+  S.bound_prod = o.rr_auto >= 3;
   if (tr) build_transpose(S);
   hipStream_t cs = (hipStream_t)o.stream;
   begin_solve(S, b, x, o, cs);
@@ -865,6 +875,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
   launch_init_res(S, tr, S.s1);
   launch_spmv(S, tr, S.vec[V_R], S.vec[V_W], FIN_NONE, true, S.s1);
   launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_INIT, false, S.s1);
+  launch_bound_products(S, S.s1);
   hipck(hipGetLastError(), "init launch");
   DevScalars d = read_scalars(S);
   int status = -1;
@@ -895,6 +906,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
       launch_init_res(S, tr, S.s1);
       launch_spmv(S, tr, S.vec[V_R], S.vec[V_W], FIN_NONE, true, S.s1);
       launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_INIT, false, S.s1);
+      launch_bound_products(S, S.s1);
       hipck(hipGetLastError(), "restart launch");
       d = read_scalars(S);
       if (d.done != STOPPED) {
@@ -931,6 +943,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
     launch_rr1(S, tr, true, S.s1);
     launch_rr2(S, tr, true, S.s1, save_z);
     launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_REDO, false, S.s1);
+    launch_bound_products(S, S.s1);
     hipck(hipGetLastError(), "replacement launch");
     d = read_scalars(S);
     if (d.done == STOPPED) {
@@ -956,6 +969,7 @@ int solve_classic(Solver& S, const double* b, double* x, const pbcg_opts& o, pbc
   validate_opts(o);
   check_block(S, o.transpose != 0, false);
   S.auto_rr = false;
+  S.bound_prod = false;
   const bool tr = o.transpose != 0;
   if (tr) build_transpose(S);
   hipStream_t cs = (hipStream_t)o.stream;
@@ -1581,6 +1595,7 @@ int pbicgstab_time_kernel(pbcg_handle h, int kernel, int reps, double* avg_ms, v
     o.tol = 0.0;
     o.maxit = 1 << 30;
     S.auto_rr = false;
+    S.bound_prod = false;
     S.h_sc[2] = initial_scalars(S, o, false);
     S.h_sc[2].alpha = 0.5;
     S.h_sc[2].beta = 0.5;

@@ -702,6 +702,141 @@ void launch_copy(Solver& S, const double* src, double* dst, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(S.nblk), dim3(kBlock), 0, st, src, dst, S.npad / (kBlock * 2));
 }
 
+// The products reading of the gap bound f^r (Section 3.6): the moduli of the
+// entries of the products of the error propagation matrices of
+// eq:all_error_matrices that carry each group of local errors into the
+// residual gap (R through U; S through BA; W through UEA and UC; Z through
+// BAEA, BPA, BAC and BD, with A, B, C, D, E, P, U of eq:all_matrices built
+// from the signed alpha, beta, omega), times the bound of the group.  The
+// state is one row per source j of local errors: the current column of the
+// twelve partial products and the four group bounds.  Every update is
+// elementwise in j: a product ending in A, C or D gains its left factor's
+// column times -alpha_c, -omega_c or omega_c alpha_c; one ending in B, E or
+// P is scaled by beta_{c+1} and gains the left factor's new column (B, E) or
+// its old column times -omega_c (P).  The A/C/D step needs alpha_c, omega_c
+// only, so f^r_{c+1} is known at the end of iteration c; the B/E/P step waits
+// for beta_{c+1}, which the next iteration's final brings.  Column 0 holds
+// the initial gaps (Section 3.2); R and W sources of iteration c sit in row
+// c+1, S and Z sources in row c.  A replacement starts a new system whose
+// row 0 holds the recomputed s and z gaps and row 1 the recomputed r and w
+// gaps (alpha_0 = 0).  One block; the sum over the rows uses a fixed tree.
+constexpr int kProdThreads = 1024;
+enum : int {
+  PB_B = 0, PB_BA, PB_BD, PB_BAC, PB_BAE, PB_BAEA, PB_BP, PB_BPA, PB_U, PB_UE, PB_UEA, PB_UC,
+  PB_TR, PB_TS, PB_TW, PB_TZ, PB_COUNT
+};
+
+__global__ __launch_bounds__(kProdThreads) void k_bound_products(DevScalars* __restrict__ sc) {
+  __shared__ double wsum[kProdThreads / 64];
+  const int op = sc->pr_op;
+  if (op == 0) return;
+  double* __restrict__ st = sc->pr_state;
+  const int64_t cap = sc->pr_cap;
+  int64_t c = sc->pr_c;
+  int first = sc->pr_first, pending = sc->pr_pending;
+  const double fr_in = sc->fr, dw_in = sc->dw;
+  const int tid = threadIdx.x;
+  __syncthreads();                        // every thread has read the state
+  double f = fr_in;
+  if (op & PR_RESET) {
+    // a new system: row 0 the recomputed s, z gaps; row 1 the recomputed r, w
+    // gaps, entering with the leading alpha_0 = 0 step
+    if (tid < 2) {
+      for (int k = 0; k < PB_COUNT; ++k) st[k * cap + tid] = 0.0;
+      st[PB_U * cap + tid] = 1.0;
+      if (tid == 0) {
+        st[PB_B * cap] = 1.0;
+        st[PB_TS * cap] = sc->pr_rS;
+        st[PB_TZ * cap] = sc->pr_rZ;
+      } else {
+        st[PB_TR * cap + 1] = sc->pr_rR;
+        st[PB_TW * cap + 1] = sc->pr_rW;
+      }
+    }
+    c = 0; first = 0; pending = 1;
+    f = sc->pr_rR;
+  } else if (op & PR_START) {
+    if (tid == 0) {
+      for (int k = 0; k < PB_COUNT; ++k) st[k * cap] = 0.0;
+      st[PB_B * cap] = 1.0;
+      st[PB_U * cap] = 1.0;
+      st[PB_TR * cap] = fr_in;             // ||Delta^r_0|| and ||Delta^w_0||
+      st[PB_TW * cap] = dw_in;
+    }
+    c = 0; first = 1; pending = 0;
+    f = fr_in;
+  } else if (op & PR_STEP) {
+    const double a = sc->pr_a, b = sc->pr_b, w = sc->pr_w, wp = sc->pr_wp;
+    const double tSc = first ? sc->pr_S0 : sc->pr_S, tZc = first ? sc->pr_Z0 : sc->pr_Z;
+    const double tRn = sc->pr_R, tWn = sc->pr_W;
+    const bool ebp = !first && pending;
+    const int64_t cn = ebp ? c + 1 : c;    // the column of this step's S and Z sources
+    double acc = 0.0;
+    for (int64_t j = tid; j <= cn + 1; j += kProdThreads) {
+      if (j == cn + 1) {                   // the new row: this step's R and W sources
+        for (int k = 0; k < PB_COUNT; ++k) st[k * cap + j] = 0.0;
+        st[PB_U * cap + j] = 1.0;
+        st[PB_TR * cap + j] = tRn;
+        st[PB_TW * cap + j] = tWn;
+        acc += tRn;
+        continue;
+      }
+      double v[PB_COUNT];
+#pragma unroll
+      for (int k = 0; k < PB_COUNT; ++k) v[k] = st[k * cap + j];
+      if (ebp) {                           // column c -> c+1 of the B, E, P products
+        v[PB_BP] = b * (v[PB_BP] - wp * v[PB_B]);
+        v[PB_B] = j == cn ? 1.0 : b * v[PB_B];
+        v[PB_BAE] = b * v[PB_BAE] + v[PB_BA];
+        v[PB_UE] = b * v[PB_UE] + v[PB_U];
+      }
+      if (j == cn) {
+        v[PB_TS] = tSc;
+        v[PB_TZ] = tZc;
+      }
+      const double ba = v[PB_BA];          // column cn -> cn+1 of the A, C, D products
+      v[PB_BA] = ba - a * v[PB_B];
+      v[PB_BD] = v[PB_BD] + w * a * v[PB_B];
+      v[PB_BAC] = v[PB_BAC] - w * ba;
+      v[PB_BAEA] = v[PB_BAEA] - a * v[PB_BAE];
+      v[PB_BPA] = v[PB_BPA] - a * v[PB_BP];
+      v[PB_UEA] = v[PB_UEA] - a * v[PB_UE];
+      v[PB_UC] = v[PB_UC] - w * v[PB_U];
+#pragma unroll
+      for (int k = 0; k < PB_COUNT; ++k) st[k * cap + j] = v[k];
+      acc += v[PB_TR] + v[PB_TS] * fabs(v[PB_BA]) +
+             v[PB_TW] * (fabs(v[PB_UEA]) + fabs(v[PB_UC])) +
+             v[PB_TZ] * (fabs(v[PB_BAEA]) + fabs(v[PB_BPA]) + fabs(v[PB_BAC]) + fabs(v[PB_BD]));
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+    __syncthreads();
+    f = 0.0;
+    for (int k = 0; k < kProdThreads / 64; ++k) f += wsum[k];
+    c = cn; first = 0; pending = 1;
+  }
+  if (tid == 0) {
+    sc->pr_c = (int32_t)c;
+    sc->pr_first = first;
+    sc->pr_pending = pending;
+    sc->fr = f;
+    const int its = sc->pr_its;
+    if ((op & (PR_STEP | PR_RESET)) && sc->bound_history && its >= 1 && its <= sc->bound_len)
+      sc->bound_history[its - 1] = f;
+    if (op & PR_CRIT) {                    // eq:criterion for the next step
+      const int f_ok = f <= sc->tau * sc->pr_rn;
+      sc->rr_next = sc->f_ok_prev && !f_ok;
+      sc->f_ok_prev = f_ok;
+    }
+    sc->pr_op = 0;
+  }
+}
+
+void launch_bound_products(Solver& S, hipStream_t st) {
+  if (!S.bound_prod) return;
+  hipLaunchKernelGGL(k_bound_products, dim3(1), dim3(kProdThreads), 0, st, S.sc);
+}
+
 __global__ void k_set_done(DevScalars* sc, int value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sc->done = value;
 }

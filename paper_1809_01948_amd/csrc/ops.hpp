@@ -450,41 +450,68 @@ struct IterNorms {
   double x, g, u, q, y, r, s, k, l, w, z, m, t, n, v;
 };
 
-__device__ inline double gap_bound_step(DevScalars* sc, double a, double b, double w, double wp,
-                                        const IterNorms& nm) {
+// Bounds of the local rounding errors of iteration i (eq:errbounds1-4).
+// a, b, w, wp are |alpha_i|, |beta_i|, |omega_i|, |omega_{i-1}|.
+struct LocalBounds {
+  double x, r, q, u, y, g, s, l, z, k, w;
+};
+__device__ inline LocalBounds gap_local_bounds(const DevScalars* sc, double a, double b, double w,
+                                               double wp, const IterNorms& nm) {
   const double e = sc->eps_b, nA = sc->nA;
   const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
   const double smut = (sc->rr_est ? 1.0 : sqrt(sc->nN)) * sc->nM;
-  const double d_x = (2 * nm.x + 3 * a * nm.g + 2 * w * nm.u) * e;
-  const double d_r = (nm.q + 2 * w * nm.y) * e;
-  const double d_q = (nm.r + 2 * a * nm.s) * e;
-  const double d_u = (nm.k + 2 * a * nm.l) * e;
-  const double d_y = (nm.w + 2 * a * nm.z) * e;
-  const double d_g = (nm.k + 3 * b * sc->pg + 4 * b * wp * sc->pl) * e;
-  const double d_s = (nm.w + 3 * b * sc->ps + 4 * b * wp * sc->pz) * e;
-  const double d_l = (nm.m + smut * nm.w + 3 * b * sc->pl + 4 * b * wp * sc->pn +
-                      smut * b * wp * sc->pz) * e;
-  const double d_z = (nm.t + smu * nm.m + smut * nA * nm.w + 3 * b * sc->pz + 4 * b * wp * sc->pv +
-                      smu * b * wp * sc->pn + smut * nA * b * wp * sc->pz) * e;
-  const double d_k = (nm.u + 3 * w * nm.m + smut * w * nm.w + 4 * w * a * nm.n +
-                      smut * w * a * nm.z) * e;
-  const double d_w = (nm.y + 3 * w * nm.t + smu * w * nm.m + smut * nA * w * nm.w +
-                      4 * w * a * nm.v + smu * w * a * nm.n + smut * nA * w * a * nm.z) * e;
-  double dz, ds;
-  if (sc->gb_first) {   // Delta^s_0, Delta^z_0: the initial gaps of Section 3.2 (g_0 = k_0, l_0 = m_0)
-    ds = smu * nm.g * e;
-    dz = smu * nm.l * e;
-    sc->gb_first = 0;
+  LocalBounds d;
+  d.x = (2 * nm.x + 3 * a * nm.g + 2 * w * nm.u) * e;
+  d.r = (nm.q + 2 * w * nm.y) * e;
+  d.q = (nm.r + 2 * a * nm.s) * e;
+  d.u = (nm.k + 2 * a * nm.l) * e;
+  d.y = (nm.w + 2 * a * nm.z) * e;
+  d.g = (nm.k + 3 * b * sc->pg + 4 * b * wp * sc->pl) * e;
+  d.s = (nm.w + 3 * b * sc->ps + 4 * b * wp * sc->pz) * e;
+  d.l = (nm.m + smut * nm.w + 3 * b * sc->pl + 4 * b * wp * sc->pn + smut * b * wp * sc->pz) * e;
+  d.z = (nm.t + smu * nm.m + smut * nA * nm.w + 3 * b * sc->pz + 4 * b * wp * sc->pv +
+         smu * b * wp * sc->pn + smut * nA * b * wp * sc->pz) * e;
+  d.k = (nm.u + 3 * w * nm.m + smut * w * nm.w + 4 * w * a * nm.n + smut * w * a * nm.z) * e;
+  d.w = (nm.y + 3 * w * nm.t + smu * w * nm.m + smut * nA * w * nm.w + 4 * w * a * nm.v +
+         smu * w * a * nm.n + smut * nA * w * a * nm.z) * e;
+  return d;
+}
+
+// One iteration of the bound.  Nested reading: f^r_{i+1} from the running
+// gap-norm bounds (eq:DDr_bound as printed).  Products reading: the bounds of
+// the local error groups entering the r, w, s and z gaps (eq:Dr, eq:Dw,
+// eq:Ds, eq:Dz) and the signed scalars are handed to k_bound_products.
+__device__ inline void gap_bound_step(DevScalars* sc, double as, double bs, double ws,
+                                      double wps, const IterNorms& nm) {
+  const double a = fabs(as), b = fabs(bs), w = fabs(ws), wp = fabs(wps);
+  const LocalBounds d = gap_local_bounds(sc, a, b, w, wp, nm);
+  const double e = sc->eps_b, nA = sc->nA;
+  const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
+  if (sc->gb_prod) {
+    sc->pr_a = as; sc->pr_b = bs; sc->pr_w = ws; sc->pr_wp = wps;
+    sc->pr_R = nA * d.x + d.r + w * nA * d.u + d.q + w * d.y;
+    sc->pr_W = nA * d.k + d.w + nA * d.u + d.y;
+    sc->pr_S = nA * d.g + d.s;
+    sc->pr_Z = nA * d.l + d.z;
+    sc->pr_S0 = smu * nm.g * e;
+    sc->pr_Z0 = smu * nm.l * e;
+    sc->pr_op |= PR_STEP;
   } else {
-    dz = b * sc->dz_prev + nA * d_l + d_z;                                    // eq:Dz
-    ds = sc->dw + b * sc->ds_prev + b * wp * sc->dz_prev + nA * d_g + d_s;    // eq:Ds
+    double dz, ds;
+    if (sc->gb_first) {   // Delta^s_0, Delta^z_0: the initial gaps of Section 3.2 (g_0 = k_0, l_0 = m_0)
+      ds = smu * nm.g * e;
+      dz = smu * nm.l * e;
+      sc->gb_first = 0;
+    } else {
+      dz = b * sc->dz_prev + nA * d.l + d.z;                                    // eq:Dz
+      ds = sc->dw + b * sc->ds_prev + b * wp * sc->dz_prev + nA * d.g + d.s;    // eq:Ds
+    }
+    const double f = sc->fr + a * ds + w * sc->dw + w * a * dz + nA * d.x + d.r +   // eq:Dr
+                     w * nA * d.u + d.q + w * d.y;
+    const double dw = sc->dw + a * dz + nA * d.k + d.w + nA * d.u + d.y;             // eq:Dw
+    sc->fr = f; sc->dw = dw; sc->ds_prev = ds; sc->dz_prev = dz;
   }
-  const double f = sc->fr + a * ds + w * sc->dw + w * a * dz + nA * d_x + d_r +       // eq:Dr
-                   w * nA * d_u + d_q + w * d_y;
-  const double dw = sc->dw + a * dz + nA * d_k + d_w + nA * d_u + d_y;                 // eq:Dw
-  sc->fr = f; sc->dw = dw; sc->ds_prev = ds; sc->dz_prev = dz;
   sc->pg = nm.g; sc->ps = nm.s; sc->pl = nm.l; sc->pz = nm.z; sc->pn = nm.n; sc->pv = nm.v;
-  return f;
 }
 
 // Bounds at the start of Algorithm 2 (Section 3.2): ||Delta^r_0|| <=
@@ -498,6 +525,7 @@ __device__ inline void gap_bound_start(DevScalars* sc, double nx, double nk) {
   sc->ds_prev = sc->dz_prev = 0.0;
   sc->gb_first = 1;
   sc->pg = sc->ps = sc->pl = sc->pz = sc->pn = sc->pv = 0.0;
+  if (sc->gb_prod) sc->pr_op = PR_START;    // column 0: the initial r and w gaps (fr, dw)
 }
 
 // bounds right after an explicit recomputation of r, k, w from x and s, l, z
@@ -516,6 +544,10 @@ __device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, dou
   sc->pl = nl;
   sc->ps = ns;
   sc->pz = nz;
+  if (sc->gb_prod) {      // a new system: these gaps in columns 1 (r, w) and 0 (s, z)
+    sc->pr_rR = sc->fr; sc->pr_rW = sc->dw; sc->pr_rS = sc->ds_prev; sc->pr_rZ = sc->dz_prev;
+    sc->pr_op |= PR_RESET;
+  }
 }
 
 // Slots each final mode reduces.  GLRED 2 in automated mode adds the norms
@@ -703,16 +735,18 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
             nm.g = sqrt(v[9]); nm.s = sqrt(v[10]); nm.l = sqrt(v[11]); nm.z = sqrt(v[12]);
             nm.q = sqrt(v[13]); nm.y = sqrt(v[14]); nm.x = sqrt(v[15]); nm.u = sqrt(v[16]);
             nm.n = sqrt(v[17]); nm.v = sqrt(v[18]); nm.r = sc->rn;
-            gap_bound_step(sc, fabs(sc->alpha), fabs(sc->beta), fabs(sc->omega),
-                           fabs(sc->omega_prev), nm);
+            gap_bound_step(sc, sc->alpha, sc->beta, sc->omega, sc->omega_prev, nm);
           }
           if (sc->rr_hit) {
             gap_bound_reset(sc, sqrt(v[19]), sqrt(v[20]), sqrt(v[9]), sqrt(v[21]), sqrt(v[22]),
                             sqrt(v[23]));
             sc->rr_hit = 0;
           }
-          if (sc->bound_history && its >= 1 && its <= sc->bound_len)
+          if (sc->gb_prod) {
+            sc->pr_its = its;     // k_bound_products logs f^r and applies eq:criterion
+          } else if (sc->bound_history && its >= 1 && its <= sc->bound_len) {
             sc->bound_history[its - 1] = sc->fr;
+          }
         }
         const double v5[5] = {rho1, rw, rs, rz, rr};
         // after a forced replacement the replaced residual is not tested against
@@ -727,7 +761,10 @@ __device__ inline void run_final(int mode, DevScalars* __restrict__ sc, const do
           if (g.outcome == G2_CONVERGED) {
             sc->done = RECURSIVE_CONVERGED;          // the host confirms with ||b - A x||
           } else {
-            if (sc->rr_auto) {                       // eq:criterion for the next step
+            if (sc->rr_auto && sc->gb_prod) {        // eq:criterion, after k_bound_products
+              sc->pr_rn = g.rn;
+              sc->pr_op |= PR_CRIT;
+            } else if (sc->rr_auto) {                // eq:criterion for the next step
               const int f_ok = sc->fr <= sc->tau * g.rn;
               sc->rr_next = sc->f_ok_prev && !f_ok;
               sc->f_ok_prev = f_ok;

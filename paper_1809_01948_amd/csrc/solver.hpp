@@ -92,6 +92,7 @@ struct Solver {
   int64_t lds_cap = 0;          // bytes of LDS one block may use (device attribute)
   int lds_blocks = 0;           // blocks of the LDS-window product (0: from the window size)
   const double* rhat_in = nullptr;  // the solve's caller shadow vector (null: r_0)
+  bool bound_prod = false;      // the solve's gap bound takes the products reading
   bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
   bool march_phase = true;      // phase kernels visit a 3D grid's tiles plane by plane (TileSeq)
   int march_zlen = 0;           // planes per work item of k_spmv_st3m (0: sized to the grid)
@@ -152,6 +153,7 @@ int fused_kind(Solver& S, bool transpose);
 int phase_march_planes(Solver& S, bool transpose);
 // a GLRED final on its own (one block, or one block per sum beyond eight)
 void launch_fin(Solver& S, int fin_mode, hipStream_t st);
+void launch_bound_products(Solver& S, hipStream_t st);
 void launch_init_res(Solver& S, bool tr, hipStream_t st);
 // out = A M^-1 in; with `pre` the input already holds M^-1 applied (V_PM)
 void launch_spmv(Solver& S, bool tr, const void* in, void* out, int fin_mode, bool dot_rhat,

@@ -191,6 +191,10 @@ class Solver:
             o.rr_auto = 1
         elif rr_auto == "estimate":
             o.rr_auto = 2
+        elif rr_auto == "products":
+            o.rr_auto = 3
+        elif rr_auto == "products-estimate":
+            o.rr_auto = 4
         else:   # True: the worst-case bound in FP64, the estimate with FP32 recurrences
             o.rr_auto = 1 if self.precision == "fp64" else 2
         o.rr_eps = rr_eps
@@ -211,8 +215,12 @@ class Solver:
 
         method: 'pipelined' (Algorithm 2 with residual replacement: every
         ``rr_period`` iterations, or automated with ``rr_auto``) or 'classic'
-        (Algorithm 1).  ``rhat``: a fixed shadow vector in place of r_0 (not
-        in the paper; None keeps r_0)."""
+        (Algorithm 1).  ``rr_auto``: False, True (the bound in FP64, its
+        estimate with FP32 storage), 'bound', 'estimate' (eq:DDr_bound as
+        printed), 'products', 'products-estimate' (the moduli of the products
+        of the error propagation matrices; the binding allocates the state
+        the library needs).  ``rhat``: a fixed shadow vector in place of r_0
+        (not in the paper; None keeps r_0)."""
         lib = L.load()
         b = _dev_vec(b, self.n, "b")
         rhat = None if rhat is None else _dev_vec(rhat, self.n, "rhat")
@@ -228,6 +236,11 @@ class Solver:
                        gap_history, use_graph, rr_auto, rr_eps, bound_history, restarts)
         if rhat is not None:
             o.rhat = rhat.data_ptr()
+        state = None
+        if o.rr_auto >= 3:      # the products reading's per-iteration state
+            state = torch.empty(16 * (maxit + 2), dtype=torch.float64, device=b.device)
+            o.bound_state = state.data_ptr()
+            o.bound_state_len = state.numel()
         st = L.Stats()
         fn = lib.pbicgstab_solve if method == "pipelined" else lib.classic_bicgstab_solve
         code = fn(self._h, _ptr(b), _ptr(out), ctypes.byref(o), ctypes.byref(st))

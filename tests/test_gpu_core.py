@@ -428,17 +428,22 @@ def test_automated_replacement_c1(Solver, form):
 
 
 @pytest.mark.parametrize("case,variant", [("c1", "bound"), ("c1", "estimate"),
-                                          ("poisson-200", "bound"), ("poisson-200", "estimate")])
+                                          ("poisson-200", "bound"), ("poisson-200", "estimate"),
+                                          ("c1", "products"), ("c1", "products-estimate"),
+                                          ("poisson-200", "products"),
+                                          ("poisson-200", "products-estimate")])
 def test_automated_bound_trace(Solver, case, variant):
     """The running bound f^r of eq:DDr_bound, logged per iteration, equals the
     oracle's over the first iterations (it is a function of the iteration's
-    scalars and vector norms, which agree to ~1e-13 there)."""
+    scalars and vector norms, which agree to ~1e-13 there), in both readings
+    (products: the state per error source advanced by k_bound_products)."""
     from workloads import poisson2d_c2
     p = convdiff2d_c1(32) if case == "c1" else poisson2d_c2(200)
     A, ops = oracle_ops(p)
     k = 12
     ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, rr_mode="auto",
-                             rr_estimate=variant == "estimate")
+                             rr_estimate=variant.endswith("estimate"),
+                             rr_reading="products" if variant.startswith("products") else "nested")
     S = Solver.from_problem(p, form="csr" if case == "c1" else "stencil")
     bh = torch.zeros(k, dtype=torch.float64, device="cuda")
     x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto=variant, bound_history=bh)
@@ -446,6 +451,60 @@ def test_automated_bound_trace(Solver, case, variant):
     assert st["iterations"] == k and len(ref.fr) == k
     assert np.all(rel(fr, np.array(ref.fr)) <= 1e-9), (fr, ref.fr)
     assert st["replacements"] == ref.replacements
+    S.close()
+
+
+@pytest.mark.parametrize("reading", ["nested", "products"])
+def test_automated_bound_through_replacements(Solver, reading):
+    """TP2 100^2 (no preconditioner): the bound of either reading equals the
+    oracle's through the first automated replacement (iteration 20: the
+    bound restarts from the recomputation's rounding errors, and the products
+    reading starts a new system of sources) and the three iterations after
+    it.  Tolerances from the oracle against itself with correctly rounded
+    dots: <= 2e-12 up to the replacement, then <= 6e-7 (the replaced r = b -
+    A x carries the last-bit differences of x relative to the small r), so
+    1e-9 and 1e-5 here."""
+    from workloads import tp2_unsymmetric
+    p = tp2_unsymmetric(100)
+    A, ops = oracle_ops(p, "none")
+    k = 24
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, rr_mode="auto", rr_reading=reading)
+    assert ref.rr_iters == [20], ref.rr_iters
+    S = Solver.from_problem(p, form="stencil", precond="none")
+    bh = torch.zeros(k, dtype=torch.float64, device="cuda")
+    variant = "bound" if reading == "nested" else "products"
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto=variant, bound_history=bh)
+    assert st["iterations"] == k and st["replacements"] == 1
+    d = rel(host(bh), np.array(ref.fr))
+    assert np.all(d[:21] <= 1e-9), d
+    assert np.all(d[21:] <= 1e-5), d
+    S.close()
+
+
+def test_products_bound_state_is_required(Solver):
+    """rr_auto 3 through the C ABI without (or with too small) a state buffer
+    is an invalid argument; with it the solve runs."""
+    import ctypes
+    from paper_1809_01948_amd import PbcgError
+    from paper_1809_01948_amd import _lib as L
+    p = convdiff2d_c1(16)
+    S = Solver.from_problem(p, form="csr", precond="none")
+    b = dev(p.b)
+    x = torch.zeros_like(b)
+    lib = L.load()
+    for length in (0, 16 * (50 + 2) - 1):
+        o = L.Opts()
+        lib.pbicgstab_default_opts(ctypes.byref(o))
+        o.maxit, o.rr_auto = 50, 3
+        state = torch.empty(max(length, 1), dtype=torch.float64, device="cuda")
+        if length:
+            o.bound_state, o.bound_state_len = state.data_ptr(), length
+        st = L.Stats()
+        code = lib.pbicgstab_solve(S._h, b.data_ptr(), x.data_ptr(), ctypes.byref(o),
+                                   ctypes.byref(st))
+        assert code == -1
+    x2, st2 = S.solve(b, tol=1e-10, maxit=50, rr_auto="products")
+    assert st2["status"] in (0, 1)
     S.close()
 
 
