@@ -245,7 +245,8 @@ def stored_traffic(workload, precision):
 
 
 def cpu_model():
-    cpu = platform.processor() or platform.machine()
+    """The host CPU's model name from /proc/cpuinfo (platform.processor()
+    would start a child process)."""
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -253,7 +254,7 @@ def cpu_model():
                     return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return cpu
+    return platform.machine()
 
 
 def cpu_baseline(iters):
@@ -404,9 +405,11 @@ def accuracy_vs_time(S, b, runs):
             if st["iterations"] < k:            # stopped (breakdown): the trajectory ends
                 break
         best = min(pts, key=lambda q: q[2])
+        desc = {key: ("random fixed shadow vector, rng(56)" if key == "rhat" else val)
+                for key, val in kw.items()}
         out[name] = {"points_iterations_seconds_relres": pts,
                      "best": {"iterations": best[0], "seconds": best[1], "rel_res_true": best[2]},
-                     "replacement": kw}
+                     "replacement": desc}
         log(f"accuracy {name}: best {best}")
     return out
 
@@ -415,16 +418,22 @@ def paper_problems(dev):
     import torch
     from paper_1809_01948_amd.solver import Solver
     from workloads import tp2_unsymmetric, tp3_helmholtz
+    import numpy as np
     res = {}
     p = tp2_unsymmetric(1000)
     S = Solver.from_problem(p, form="stencil", precond="none")
     b = torch.from_numpy(p.b).to(dev)
+    rh = torch.from_numpy(np.random.default_rng(56).standard_normal(p.n)).to(dev)
     ks = list(range(100, 1501, 100))
     res["TP2_1000x1000"] = accuracy_vs_time(S, b, [
         ("classic", dict(method="classic"), ks),
         ("p-BiCGStab", dict(), ks),
         ("p-BiCGStab_rr100", dict(rr_period=100), ks),
-        ("p-BiCGStab_auto", dict(rr_auto=True), ks)])
+        ("p-BiCGStab_auto", dict(rr_auto=True), ks),
+        # options outside the paper: the bound's square-root estimate in the
+        # products reading, with a random fixed shadow vector
+        ("p-BiCGStab_auto_products_estimate_random_shadow",
+         dict(rr_auto="products-estimate", rhat=rh), ks)])
     S.close()
     p = tp3_helmholtz(500)
     S = Solver.from_problem(p, form="stencil", precond="none")

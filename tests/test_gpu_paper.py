@@ -118,23 +118,38 @@ def test_tp2_automated_replacement(solver, tp2):
 def test_tp2_automated_estimate_random_shadow(solver, tp2, variant):
     """The automated strategy with the square-root estimate of the bound
     (Section 3.6), in either reading, and a random fixed shadow vector (an
-    option outside the paper) reaches classic BiCGStab's accuracy on TP2:
-    every run here -- two shadow vectors, two rounding-perturbed right-hand
-    sides -- converges to a 1e-13 true residual (Section 4.5 reports about
-    ten replacements and ~1e-13; here 12 to ~110 replacements).  With the
-    worst-case bound, or with r_0 as the shadow vector, the outcome is
-    rounding-sensitive (see test_tp2_automated_replacement)."""
+    option outside the paper), on two shadow vectors and two rounding-
+    perturbed right-hand sides.
+
+    * The criterion alone (no stopping test: the same run sampled every 100
+      iterations up to 1,500) keeps the true residual down: best <= 5e-11
+      (1e-11 with the nested reading) and <= 1e-8 after 1,500 iterations (or
+      where the run stops at a rho' = 0 breakdown once its recursive residual
+      has reached the rounding level), where p-BiCGStab without replacement
+      has grown to ~1e-2 (Section 4.5:
+      the automated strategy's accuracy is comparable to classic's, 1.4e-13
+      here; measured 1.2e-13 to 3e-12 with the nested reading).
+    * A solve to 1e-13 converges: the stopping test's confirm-and-replace
+      (at most three replacements) closes the rest."""
     for seed in (56, 57):
         rh = dev(np.random.default_rng(seed).standard_normal(tp2.n))
         for j in range(2):
             b = dev(tp2.b * (1.0 + j * 1e-15))
+            traj = []
+            for k in range(300, 1501, 100):
+                _, st = solver.solve(b, tol=0.0, maxit=k, rr_auto=variant, rhat=rh)
+                traj.append(st["rel_res_true"])
+                if st["iterations"] < k:    # a rho' = 0 stop at the noise floor ends it
+                    break
             _, st = solver.solve(b, tol=1e-13, maxit=3000, rr_auto=variant, rhat=rh)
-            print(f"{variant} shadow {seed} draw {j}: {st['status_name']} "
+            print(f"{variant} shadow {seed} draw {j}: criterion alone best {min(traj):.2e}, "
+                  f"at the end {traj[-1]:.2e}; to 1e-13: {st['status_name']} "
                   f"{st['iterations']} iterations, {st['replacements']} replacements, "
                   f"true {st['rel_res_true']:.2e}", flush=True)
+            assert min(traj) <= (1e-11 if variant == "estimate" else 5e-11)
+            assert traj[-1] <= 1e-8
             assert st["status"] == 0 and st["rel_res_true"] <= 1e-13
-            assert 5 <= st["replacements"] <= 150
-            assert st["iterations"] <= 1500
+            assert 5 <= st["replacements"] <= 150 and st["iterations"] <= 1500
 
 
 # -----------------------------------------------------------------------------
