@@ -137,17 +137,20 @@ def test_mixed_periodic_replacement_trace(Solver):
     S.close()
 
 
-def test_mixed_automated_bound_trace(Solver):
+@pytest.mark.parametrize("reading", ["nested", "products"])
+def test_mixed_automated_bound_trace(Solver, reading):
     """The automated bound with FP32 recurrences (square-root estimate,
     epsilon 2^-24, restart with 2^-53, tau 2^-12) logged per iteration
-    equals the oracle's."""
+    equals the oracle's, in both readings of the bound."""
     p = poisson2d_c2(64)
     A = p.scipy_csr()
     k = 20
-    ref = pipelined_bicgstab_lowprec(A, p.b, jacobi=True, tol=0.0, maxit=k, rr_mode="auto")
+    ref = pipelined_bicgstab_lowprec(A, p.b, jacobi=True, tol=0.0, maxit=k, rr_mode="auto",
+                                     rr_reading=reading)
     S = Solver.from_problem(p, form="stencil", precision="mixed", precond="jacobi")
     bh = torch.zeros(k, dtype=torch.float64, device="cuda")
-    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto=True, bound_history=bh)
+    variant = True if reading == "nested" else "products-estimate"
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto=variant, bound_history=bh)
     assert st["replacements"] == ref.replacements
     assert np.all(rel(host(bh), np.array(ref.fr)) <= 1e-9)
     S.close()
