@@ -455,7 +455,9 @@ def paper_problems(dev):
 def c1_latency(dev):
     """32^2 convection-diffusion (N = 1024): launch-bound; iterations per
     second of full solves to 1e-10, classic (Algorithm 1, 7 launches per
-    iteration) and pipelined (Algorithm 2 from HIP graphs)."""
+    iteration), pipelined (Algorithm 2 from HIP graphs) and pipelined as one
+    kernel in one workgroup (every vector in LDS, no launches or host polls
+    inside the solve)."""
     import torch
     from paper_1809_01948_amd.solver import Solver
     from workloads import convdiff2d_c1
@@ -466,7 +468,10 @@ def c1_latency(dev):
         S = Solver.from_problem(p, form=form, precond="none")
         for name, kw in (("classic", dict(method="classic")),
                          ("pipelined_graph", dict(use_graph=True)),
-                         ("pipelined_rr50_graph", dict(use_graph=True, rr_period=50))):
+                         ("pipelined_rr50_graph", dict(use_graph=True, rr_period=50)),
+                         ("pipelined_single_kernel", dict(single_kernel=True)),
+                         ("pipelined_rr50_single_kernel", dict(single_kernel=True,
+                                                               rr_period=50))):
             S.solve(b, tol=1e-10, maxit=2000, **kw)
             ts, its = [], 0
             for _ in range(20):
@@ -476,7 +481,9 @@ def c1_latency(dev):
             ts.sort()
             med = ts[len(ts) // 2]
             out[f"{form}_{name}"] = {"iterations": its, "median_seconds": med,
-                                     "iter_per_s": its / med, "status": st["status_name"]}
+                                     "iter_per_s": its / med, "status": st["status_name"],
+                                     "device_ms": st["elapsed_ms"],
+                                     "single_kernel": st["single_kernel"]}
         S.close()
     log(f"c1 latency: {json.dumps(out)}")
     return out

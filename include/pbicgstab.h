@@ -166,6 +166,17 @@ typedef struct {
                             16 * (maxit + 2) doubles (PBCG_ERR_INVALID_ARG otherwise); contents
                             on entry are ignored, on return unspecified */
   int64_t bound_state_len; /* doubles in bound_state */
+  int32_t single_kernel; /* nonzero: run the whole of Algorithm 2 as one kernel in one workgroup
+                            (every vector in LDS, the global reductions as workgroup
+                            reductions, no host polls) when the system allows it: at most
+                            1024 rows, FP64, rr_auto 0, gap_every 0, restarts 0, not
+                            transposed, not block-Jacobi, and a device with 112 KiB of LDS
+                            per workgroup; otherwise ignored.  Same arithmetic per row and the
+                            same stopping rules as the multi-kernel path; the sums of the
+                            reductions are taken in another order (results agree to
+                            rounding).  For small systems, whose solve is bound by kernel
+                            launches and host polls. */
+  int32_t pad1_;
 } pbcg_opts;
 
 typedef struct {
@@ -179,12 +190,12 @@ typedef struct {
   double rnorm0;             /* ||r_0|| */
   double bnorm;              /* ||b|| */
   int32_t restarts;          /* restarts performed (pbcg_opts.restarts) */
-  int32_t pad_;
+  int32_t single_kernel;     /* 1: the solve ran as the one-workgroup kernel (pbcg_opts.single_kernel) */
 } pbcg_stats;
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
  * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
- * rr_eps 0, no bound history, restarts 0, rhat NULL, no bound state. */
+ * rr_eps 0, no bound history, restarts 0, rhat NULL, no bound state, single_kernel 0. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

@@ -69,6 +69,8 @@ class Opts(ctypes.Structure):
         ("rhat", _P),
         ("bound_state", _P),
         ("bound_state_len", _c.c_int64),
+        ("single_kernel", _c.c_int32),
+        ("pad1_", _c.c_int32),
     ]
 
 
@@ -84,7 +86,7 @@ class Stats(ctypes.Structure):
         ("rnorm0", _c.c_double),
         ("bnorm", _c.c_double),
         ("restarts", _c.c_int32),
-        ("pad_", _c.c_int32),
+        ("single_kernel", _c.c_int32),
     ]
 
     def as_dict(self):

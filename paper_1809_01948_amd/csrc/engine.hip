@@ -848,6 +848,7 @@ int finish_stats(Solver& S, bool tr, const DevScalars& d, int status, pbcg_stats
     st->rel_res_recursive = d.nb > 0 ? d.rn / d.nb : 0.0;
     st->rel_res_true = d.nb > 0 ? tr_norm / d.nb : 0.0;
     st->elapsed_ms = ms;
+    st->single_kernel = 0;
   }
   (void)tr;
   return status;
@@ -871,6 +872,21 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
   if (tr) build_transpose(S);
   hipStream_t cs = (hipStream_t)o.stream;
   begin_solve(S, b, x, o, cs);
+  hipError_t sk_err = hipSuccess;
+  if (o.single_kernel && launch_small_solve(S, o, S.s1, &sk_err)) {
+    hipck(sk_err, "single-kernel solve: hipFuncSetAttribute");
+    hipck(hipGetLastError(), "single-kernel solve launch");
+    const double trn = true_residual(S, tr);
+    const DevScalars d = read_scalars(S);
+    const int spmvs = 3 + 2 * d.iter + 4 * d.rr_count + 1;
+    end_solve(S, x, cs);
+    const int rc = finish_stats(S, tr, d, d.status, st, trn, spmvs);
+    if (st) {
+      st->restarts = 0;
+      st->single_kernel = 1;
+    }
+    return rc;
+  }
   // Algorithm 2 initialisation
   launch_init_res(S, tr, S.s1);
   launch_spmv(S, tr, S.vec[V_R], S.vec[V_W], FIN_NONE, true, S.s1);

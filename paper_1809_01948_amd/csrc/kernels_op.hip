@@ -1181,4 +1181,396 @@ void launch_dia5_transpose(Solver& S, hipStream_t st) {
                        (const float*)S.A.dia, (float*)S.AT.dia, nx, ny, S.npad);
 }
 
+// ----------------------------------------------------------------------------
+// Algorithm 2 for small systems in one workgroup
+// ----------------------------------------------------------------------------
+//
+// A solve of a few hundred rows is bound by kernel launches and host polls,
+// not by memory.  For N <= kSmallRows (FP64) one block of kSmallRows threads
+// holds every vector of the iteration in LDS (row i in thread i) and runs
+// Algorithm 2 to its end in one launch: phase A and phase B with the
+// expressions of k_phaseA / k_phaseB, the products through the operator's
+// own row visitor (the same terms in the same order), periodic residual
+// replacement (eq:rr) in FP64 with the saved pre-replacement z, and the
+// termination rule: true-residual confirmation, at most three forced
+// replacements, no tolerance test right after one.
+//
+// Two barriers per iteration.  Each global reduction stores one partial per
+// wave (an xor butterfly over the wave) before a barrier that the iteration
+// needs anyway, and after it every wave adds the 16 partials with the same
+// 16-lane butterfly, so every thread holds the same bits without a second
+// barrier; the two products read M^-1 z and M^-1 w from arrays of their own,
+// which the following phase does not write.  A sliced-ELL row of at most
+// kSmallCache stored entries is held in registers for the whole solve.
+
+constexpr int kSmallRows = 1024;
+constexpr int kSmallWaves = kSmallRows / 64;
+static_assert(kSmallWaves == 16, "the reductions finish with a 16-lane butterfly");
+constexpr int kSmallCache = 8;
+enum : int {
+  SB_RH = 0, SB_R, SB_G, SB_S, SB_L, SB_Z, SB_K, SB_W, SB_T, SB_V, SB_ZS, SB_X, SB_B,
+  SB_NZ,      // M^-1 z_i, the input of v_i = A M^-1 z_i (also M^-1 r_0 at the start)
+  SB_MW,      // M^-1 w, the input of t = A M^-1 w
+  SB_COUNT
+};
+constexpr size_t kSmallLds = (size_t)SB_COUNT * kSmallRows * sizeof(double);
+constexpr int kSmallRed = 3;          // partial buffers: GLRED 1, GLRED 2, the others
+constexpr size_t kSmallStatic = (size_t)kSmallRed * 5 * kSmallWaves * sizeof(double);
+
+struct SmallArgs {
+  int n;
+  const double* dinv;
+  double ds;
+  double* x;                 // x_0 in, the last iterate out
+  const double* b;
+  const double* rhat_in;     // a fixed shadow vector, or null (r_0)
+  double* out[11];           // r^, r, g, s, l, z, k, w, t, v, saved z: written back at the end
+  double tol, tau;
+  int maxit, rr_period;
+  double* history;
+  int hist_len;
+  DevScalars* sc;
+};
+
+// one partial per wave of each of NS sums
+template <int NS>
+__device__ __forceinline__ void small_part(const double (&v)[NS], double (*buf)[kSmallWaves]) {
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    const double t = wave_sum(v[d]);
+    if ((threadIdx.x & 63) == 0) buf[d][threadIdx.x >> 6] = t;
+  }
+}
+
+// the sums of the wave partials (after a barrier): the same tree in every
+// wave, so every thread receives the same bits
+template <int NS>
+__device__ __forceinline__ void small_total(double (&v)[NS], const double (*buf)[kSmallWaves]) {
+  const int l = threadIdx.x & (kSmallWaves - 1);
+#pragma unroll
+  for (int d = 0; d < NS; ++d) {
+    double t = buf[d][l];
+    t += lane_xor<8>(t);
+    t += lane_xor<4>(t);
+    t += lane_xor<2>(t);
+    t += lane_xor<1>(t);
+    v[d] = t;
+  }
+}
+
+// A sliced-ELL row of at most kSmallCache stored entries, in registers; the
+// visit adds the entries in SellOp::row's order (ascending slot, padding
+// skipped), so the sums are the same.
+struct SellRowRegs {
+  int32_t c[kSmallCache];
+  double a[kSmallCache];
+  __device__ __forceinline__ void load(const SellOp<double>& op, int i) {
+    const int64_t s = i >> 6;
+    const int lane = i & 63;
+    const int64_t off = op.sptr[s];
+    const int w = (int)((op.sptr[s + 1] - off) >> 6);
+#pragma unroll
+    for (int j = 0; j < kSmallCache; ++j) {
+      const bool in = j < w;
+      c[j] = in ? op.col[off + (int64_t)j * kSellC + lane] : -1;
+      a[j] = in ? op.val[off + (int64_t)j * kSellC + lane] : 0.0;
+    }
+  }
+  template <class Vis>
+  __device__ __forceinline__ void row(Vis& vis) const {
+#pragma unroll
+    for (int j = 0; j < kSmallCache; ++j)
+      if (c[j] >= 0) vis.add(a[j], vis.load(c[j]));
+  }
+};
+
+template <int PC, class Op, bool CACHE>
+__global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) {
+  extern __shared__ double sm[];
+  __shared__ double red[kSmallRed][5][kSmallWaves];
+  double* const rh = sm + SB_RH * kSmallRows;
+  double* const r = sm + SB_R * kSmallRows;
+  double* const g = sm + SB_G * kSmallRows;
+  double* const s = sm + SB_S * kSmallRows;
+  double* const l = sm + SB_L * kSmallRows;
+  double* const z = sm + SB_Z * kSmallRows;
+  double* const k = sm + SB_K * kSmallRows;
+  double* const w = sm + SB_W * kSmallRows;
+  double* const t = sm + SB_T * kSmallRows;
+  double* const v = sm + SB_V * kSmallRows;
+  double* const zs = sm + SB_ZS * kSmallRows;
+  double* const x = sm + SB_X * kSmallRows;
+  double* const b = sm + SB_B * kSmallRows;
+  double* const nz = sm + SB_NZ * kSmallRows;
+  double* const mw = sm + SB_MW * kSmallRows;
+  const int i = threadIdx.x;
+  const bool own = i < a.n;
+  // M^-1 u for row i (prec1's product, with the diagonal kept in a register)
+  const double di = (PC == PC_VECTOR && own) ? a.dinv[i] : 0.0;
+  auto prec = [&](double u) {
+    if (PC == PC_NONE) return u;
+    if (PC == PC_SCALAR) return a.ds * u;
+    return di * u;
+  };
+  SellRowRegs rows;
+  if constexpr (CACHE) {
+    if (own) rows.load(op, i);
+  }
+  auto visit = [&](auto& vis) {
+    if constexpr (CACHE) rows.row(vis);
+    else op.row(i, vis);
+  };
+  // sum_j a_ij in_j
+  auto product = [&](const double* in) {
+    LdsVis<double> vis{in, 0, 0.0};
+    visit(vis);
+    return vis.sum;
+  };
+
+  // Algorithm 2 initialisation
+  if (own) {
+    x[i] = a.x[i];
+    b[i] = a.b[i];
+  }
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (own) {
+    ResVis<double> vis{x, 0.0};
+    visit(vis);
+    const double ri = b[i] - vis.sum;
+    const double hi = a.rhat_in ? a.rhat_in[i] : ri;
+    const double ki = prec(ri);
+    r[i] = ri; rh[i] = hi; k[i] = ki;
+    g[i] = 0.0; s[i] = 0.0; l[i] = 0.0; z[i] = 0.0; v[i] = 0.0; zs[i] = 0.0;
+    nz[i] = ki;
+    acc[0] = hi * ri;
+    acc[1] = ri * ri;
+    acc[2] = b[i] * b[i];
+  }
+  __syncthreads();
+  if (own) {
+    const double wi = product(nz);             // w_0 = A M^-1 r_0
+    w[i] = wi;
+    mw[i] = prec(wi);
+    acc[3] = rh[i] * wi;
+  }
+  small_part<4>(acc, red[2]);
+  __syncthreads();
+  if (own) t[i] = product(mw);                 // t_0 = A M^-1 w_0
+  small_total<4>(acc, red[2]);
+  double rho = acc[0];
+  const double rn0 = sqrt(acc[1]), nb = sqrt(acc[2]), rw = acc[3];
+  double rn = rn0, alpha = 0.0, beta = 0.0, omega = 0.0, omega_prev = 0.0;
+  int status = -1, iter = 0, rr_count = 0, forced = 0, n_saved = 0;
+  if (nb == 0.0) {
+    status = ST_CONVERGED;
+    if (own) x[i] = 0.0;
+  } else if (rn0 <= a.tol * nb) {
+    status = ST_CONVERGED;
+  } else if (!finite(rho) || !finite(rw)) {
+    status = ST_NONFINITE;
+  } else if (rw == 0.0) {
+    status = ST_BREAKDOWN_RHO;
+  } else {
+    alpha = rho / rw;
+  }
+
+  // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again; w (and
+  // M^-1 w) of the row are written at once: the second product reads k, l
+  auto replace = [&](bool save_z, double (&d)[5]) {
+    __syncthreads();                           // x and g of every row, no reader of k, l
+    if (own) {
+      Res2Vis<double, double, double> vis{x, g, 0.0, 0.0};
+      visit(vis);
+      const double ri = b[i] - vis.sx;
+      const double si = vis.sy;
+      r[i] = ri; s[i] = si; k[i] = prec(ri); l[i] = prec(si);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 5; ++e) d[e] = 0.0;
+    if (own) {
+      Res2Vis<double, double, double> vis{k, l, 0.0, 0.0};
+      visit(vis);
+      const double wi = vis.sx, zi = vis.sy;
+      if (save_z) zs[i] = z[i];
+      w[i] = wi; z[i] = zi; mw[i] = prec(wi);
+      d[0] = rh[i] * r[i]; d[1] = rh[i] * wi; d[2] = rh[i] * s[i]; d[3] = rh[i] * zi;
+      d[4] = r[i] * r[i];
+    }
+    rr_count += 1;
+    n_saved = 1;
+  };
+
+  while (status < 0) {
+    // phase A: g, s, l, z, M^-1 z and the GLRED 1 terms
+    double d2[2] = {0.0, 0.0};
+    if (own) {
+      const double zprev = n_saved ? zs[i] : z[i];
+      const double np = prec(zprev);
+      const double m = mw[i];
+      const double gn = k[i] + beta * (g[i] - omega_prev * l[i]);
+      const double sn = w[i] + beta * (s[i] - omega_prev * z[i]);
+      const double ln = m + beta * (l[i] - omega_prev * np);
+      const double zn = t[i] + beta * (z[i] - omega_prev * v[i]);
+      const double q = r[i] - alpha * sn;
+      const double y = w[i] - alpha * zn;
+      d2[0] = q * y;
+      d2[1] = y * y;
+      g[i] = gn; s[i] = sn; l[i] = ln; z[i] = zn;
+      nz[i] = prec(zn);
+    }
+    small_part<2>(d2, red[0]);
+    __syncthreads();
+    if (own) v[i] = product(nz);               // v_i = A M^-1 z_i
+    small_total<2>(d2, red[0]);                // GLRED 1
+    n_saved = 0;
+    if (!finite(d2[0]) || !finite(d2[1])) {
+      status = ST_NONFINITE;
+      break;
+    }
+    omega = d2[1] != 0.0 ? d2[0] / d2[1] : 0.0;
+    // phase B: x, r, k, w, M^-1 w and the GLRED 2 terms
+    double d5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (own) {
+      const double m = mw[i];
+      const double n_i = nz[i];
+      const double q = r[i] - alpha * s[i];
+      const double u = k[i] - alpha * l[i];
+      const double y = w[i] - alpha * z[i];
+      x[i] = (x[i] + alpha * g[i]) + omega * u;
+      const double rn_ = q - omega * y;
+      const double kn = u - omega * (m - alpha * n_i);
+      const double wn = y - omega * (t[i] - alpha * v[i]);
+      r[i] = rn_; k[i] = kn; w[i] = wn;
+      mw[i] = prec(wn);
+      d5[0] = rh[i] * rn_; d5[1] = rh[i] * wn; d5[2] = rh[i] * s[i]; d5[3] = rh[i] * z[i];
+      d5[4] = rn_ * rn_;
+    }
+    if (a.rr_period > 0 && (iter + 1) % a.rr_period == 0 && rn >= a.tau * rn0)
+      replace(true, d5);
+    small_part<5>(d5, red[1]);
+    __syncthreads();
+    if (own) t[i] = product(mw);               // t_{i+1} = A M^-1 w_{i+1}
+    small_total<5>(d5, red[1]);                // GLRED 2
+    const int its = ++iter;
+    double* hrow = (a.history && its <= a.hist_len) ? a.history + 4 * (int64_t)(its - 1) : nullptr;
+    if (hrow && i == 0) { hrow[1] = alpha; hrow[2] = omega; hrow[3] = 0.0; }
+    bool test_tol = true;
+    for (;;) {
+      const G2Step st = glred2_step(d5, alpha, omega, rho, a.tol, nb, test_tol);
+      if (st.outcome == G2_NONFINITE) {
+        status = ST_NONFINITE;
+        break;
+      }
+      rn = st.rn;
+      if (hrow && i == 0) hrow[0] = rn;
+      if (st.outcome == G2_CONVERGED) {
+        // confirm on the true residual ||b - A x|| (FP64; x of every row is
+        // written: phase B is behind the last barrier)
+        double tr2[1] = {0.0};
+        if (own) {
+          ResVis<double> vis{x, 0.0};
+          visit(vis);
+          const double e = b[i] - vis.sum;
+          tr2[0] = e * e;
+        }
+        small_part<1>(tr2, red[2]);
+        __syncthreads();
+        small_total<1>(tr2, red[2]);
+        if (sqrt(tr2[0]) <= a.tol * nb) {
+          status = ST_CONVERGED;
+        } else if (a.rr_period <= 0 || forced >= 3) {
+          status = ST_TRUE_RES_NOT_MET;
+        } else {
+          // replace and go on without testing the replaced residual
+          ++forced;
+          replace(n_saved == 0, d5);
+          small_part<5>(d5, red[1]);
+          __syncthreads();
+          if (own) t[i] = product(mw);
+          small_total<5>(d5, red[1]);
+          test_tol = false;
+          continue;
+        }
+      } else if (st.outcome == G2_BREAKDOWN_OMEGA) {
+        status = ST_BREAKDOWN_OMEGA;
+      } else if (st.outcome == G2_BREAKDOWN_RHO) {
+        status = ST_BREAKDOWN_RHO;
+      } else {
+        beta = st.beta;
+        if (hrow && i == 0) hrow[3] = beta;
+        alpha = st.alpha;
+        rho = d5[0];
+        omega_prev = omega;
+        if (its >= a.maxit) status = ST_MAXIT;
+      }
+      break;
+    }
+  }
+
+  // write the state back (each thread its own row): vectors, x, scalars
+  if (own) {
+    a.out[0][i] = rh[i]; a.out[1][i] = r[i]; a.out[2][i] = g[i]; a.out[3][i] = s[i];
+    a.out[4][i] = l[i]; a.out[5][i] = z[i]; a.out[6][i] = k[i]; a.out[7][i] = w[i];
+    a.out[8][i] = t[i]; a.out[9][i] = v[i]; a.out[10][i] = zs[i];
+    a.x[i] = x[i];
+  }
+  if (i == 0) {
+    DevScalars* sc = a.sc;
+    sc->done = STOPPED;
+    sc->status = status;
+    sc->iter = iter;
+    sc->rr_count = rr_count;
+    sc->rn = rn; sc->rn0 = rn0; sc->nb = nb; sc->rho = rho;
+    sc->alpha = alpha; sc->beta = beta; sc->omega = omega; sc->omega_prev = omega_prev;
+    sc->n_saved = n_saved;
+  }
+}
+
+template <int PC, class Op, bool CACHE>
+static hipError_t launch_small(const Op& op, const SmallArgs& a, hipStream_t st) {
+  const hipError_t e = hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kSmallLds);
+  if (e == hipSuccess)
+    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE>), dim3(1), dim3(kSmallRows), kSmallLds, st,
+                       op, a);
+  return e;
+}
+
+bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_t* err) {
+  if (S.n > kSmallRows || S.precision != 0 || o.transpose || o.rr_auto || o.gap_every > 0 ||
+      o.restarts > 0 || S.block || (size_t)S.lds_cap < kSmallLds + kSmallStatic)
+    return false;
+  SmallArgs a{};
+  a.n = (int)S.n;
+  a.dinv = (const double*)S.dinv;
+  a.ds = S.dinv_s;
+  a.x = S.x;
+  a.b = S.b;
+  a.rhat_in = o.rhat;
+  const int ids[11] = {V_RHAT, V_R, V_G, V_S, V_L, V_Z, V_K, V_W, V_T, V_V, V_TMP};
+  for (int c = 0; c < 11; ++c) a.out[c] = (double*)S.vec[ids[c]];
+  a.tol = o.tol;
+  a.tau = o.rr_tau > 0 ? o.rr_tau : std::sqrt(std::ldexp(1.0, -53));
+  a.maxit = o.maxit;
+  a.rr_period = o.rr_period;
+  a.history = o.history;
+  a.hist_len = o.history ? o.history_len : 0;
+  a.sc = S.sc;
+  // rows of the sliced-ELL operator short enough to stay in registers
+  const bool cache = S.mu_row <= kSmallCache;
+  with_op(S, false, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    if constexpr (std::is_same_v<T, double>) {
+      if constexpr (std::is_same_v<Op, SellOp<double>>) {
+        *err = cache ? launch_small<PC, Op, true>(op, a, st) : launch_small<PC, Op, false>(op, a, st);
+      } else {
+        *err = launch_small<PC, Op, false>(op, a, st);
+      }
+    }
+  });
+  return true;
+}
+
 }  // namespace pbcg

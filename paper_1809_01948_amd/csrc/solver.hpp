@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/pbicgstab.h"
 #include "common.hpp"
 #include "ops.hpp"
 
@@ -132,6 +133,10 @@ inline StParams<T> st_params(const Solver& S, const OpData& o) {
 // runs the GLRED 1 final in its prologue, and phase A with `pro` the
 // previous iteration's GLRED 2 final (fused operators, periodic strategy),
 // staging the scalars for the phase B launched with `staged`
+// the whole solve in one workgroup (small FP64 systems); false when the
+// system or the options do not allow it (nothing launched then); *err
+// receives the status of the kernel's LDS-size attribute call
+bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_t* err);
 void launch_phaseA(Solver& S, bool tr, bool pro, hipStream_t st);
 void launch_phaseB(Solver& S, bool tr, bool staged, hipStream_t st);
 void launch_final(Solver& S, int mode, int aux, hipStream_t st, bool force = false);

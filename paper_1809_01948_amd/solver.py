@@ -167,7 +167,7 @@ class Solver:
     # ---- solves ---------------------------------------------------------
     def _opts(self, tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
               gap_history, use_graph, rr_auto=False, rr_eps=0.0, bound_history=None,
-              restarts=0):
+              restarts=0, single_kernel=False):
         o = L.Opts()
         L.load().pbicgstab_default_opts(ctypes.byref(o))
         o.tol = tol
@@ -202,6 +202,7 @@ class Solver:
             o.bound_history = bound_history.data_ptr()
             o.bound_len = bound_history.numel()
         o.restarts = restarts
+        o.single_kernel = 1 if single_kernel else 0
         return o
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, *, tol=1e-10,
@@ -210,7 +211,7 @@ class Solver:
               gap_history: Optional[torch.Tensor] = None, use_graph=False,
               method="pipelined", out: Optional[torch.Tensor] = None, rr_auto=False,
               rr_eps=0.0, bound_history: Optional[torch.Tensor] = None, restarts=0,
-              rhat: Optional[torch.Tensor] = None):
+              rhat: Optional[torch.Tensor] = None, single_kernel=False):
         """Solve A x = b (A^T x = b with transpose).  Returns (x, stats dict).
 
         method: 'pipelined' (Algorithm 2 with residual replacement: every
@@ -220,7 +221,10 @@ class Solver:
         printed), 'products', 'products-estimate' (the moduli of the products
         of the error propagation matrices; the binding allocates the state
         the library needs).  ``rhat``: a fixed shadow vector in place of r_0
-        (not in the paper; None keeps r_0)."""
+        (not in the paper; None keeps r_0).  ``single_kernel``: run the whole
+        solve as one kernel in one workgroup when the system allows it (FP64,
+        at most 1024 rows, periodic or no replacement; stats
+        ``single_kernel`` says whether it did)."""
         lib = L.load()
         b = _dev_vec(b, self.n, "b")
         rhat = None if rhat is None else _dev_vec(rhat, self.n, "rhat")
@@ -233,7 +237,8 @@ class Solver:
             if t is not None and (not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous()):
                 raise TypeError(f"{nm} must be a contiguous CUDA float64 tensor")
         o = self._opts(tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
-                       gap_history, use_graph, rr_auto, rr_eps, bound_history, restarts)
+                       gap_history, use_graph, rr_auto, rr_eps, bound_history, restarts,
+                       single_kernel)
         if rhat is not None:
             o.rhat = rhat.data_ptr()
         state = None

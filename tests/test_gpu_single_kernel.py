@@ -1,0 +1,263 @@
+"""Algorithm 2 in one workgroup (pbcg_opts.single_kernel) against the oracle
+and against the multi-kernel path.
+
+* Traces (alpha, omega, beta, ||r||) to 1e-10 and the vectors element-wise
+  (x to 1e-12 of its largest term; the replaced r, w, s, z to that times
+  ||A||^2) with periodic replacement every 4 iterations, over the iterations
+  in which the oracle against itself with correctly rounded dots stays within
+  1e-12.  Operators: CSR without and with a Jacobi vector, the 2D stencil
+  with its scalar Jacobi, DIA5, the 3D stencil, a dense 37 x 37 CSR (one
+  partial wave) and the 31^2 grid (961 rows: a partial last wave); the
+  32^2 grid is the largest system the kernel takes (1024 rows).  Also with
+  a random shadow vector.
+* Full solves to 1e-10 on the 32^2 convection-diffusion problem: status as
+  the oracle's, x as the multi-kernel path's and the exact solution's to
+  the tolerance.  Without replacement the residual of this problem jumps by
+  factors of ten from one iteration to the next near the tolerance, so a
+  rounding difference moves the stopping iteration by a few (oracle 81,
+  multi-kernel path 76): the iteration count is held to a tenth of the
+  oracle's.
+* Termination: the recursive residual under a tolerance that the true
+  residual misses -- with replacement enabled a forced replacement and
+  convergence, without it TRUE_RES_NOT_MET, as in the oracle; b = 0, an
+  exact x_0, maxit, a 1 x 1 system.
+* Systems the kernel does not take (more than 1024 rows, FP32 storage, the
+  automated strategy, the transpose) run the multi-kernel path, bit for bit
+  as without the option; the allocation-free entry point gives the same
+  bits as pbicgstab_solve; two runs give the same bits.
+"""
+
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from gpu_util import dev, history_buffer, host, oracle_ops, rel, split_history
+from oracle import STATUS, Float64Ops, pipelined_bicgstab
+from workloads import (convdiff2d_c1, convdiff3d_c3, inverse_problem_c5, poisson2d_c2,
+                       random_dense_system)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    from paper_1809_01948_amd.solver import Solver as S
+    return S
+
+
+class _FsumOps(Float64Ops):
+    """The oracle's arithmetic with correctly rounded dot products."""
+
+    def dot(self, v, w):
+        return math.fsum(np.asarray(v) * np.asarray(w))
+
+
+def _horizon(A, b, dinv, rh, kw, cap):
+    runs = [pipelined_bicgstab(cls(A, dinv), b, tol=0.0, maxit=cap + 1, rhat=rh, **kw)
+            for cls in (Float64Ops, _FsumOps)]
+    a, f = runs
+    n = min(a.iterations, f.iterations)
+    d = np.zeros(n)
+    for x, y in ((a.alpha, f.alpha), (a.omega, f.omega), (a.rnorm, f.rnorm), (a.beta, f.beta)):
+        d = np.maximum(d, rel(x[:n], y[:n]))
+    bad = np.nonzero(d > 1e-12)[0]
+    return max(2, min(cap, int(bad[0]) if len(bad) else n))
+
+
+_CASES = [
+    ("c1-32-csr", lambda: convdiff2d_c1(32), "csr", "none"),
+    ("c1-32-csr-jacobi", lambda: convdiff2d_c1(32), "csr", "jacobi"),
+    ("c1-32-stencil-jacobi", lambda: convdiff2d_c1(32), "stencil", "jacobi"),
+    ("c1-31-stencil", lambda: convdiff2d_c1(31), "stencil", "none"),
+    ("dia5-24", lambda: inverse_problem_c5(24, sigma=1.0, with_csr=True), "dia5", "jacobi"),
+    ("3d7-10", lambda: convdiff3d_c3(10, with_csr=True), "stencil", "jacobi"),
+    ("dense-37", lambda: random_dense_system(37, 3, shift=8.0), "csr", "none"),
+]
+
+
+@pytest.mark.parametrize("shadow", [False, True], ids=["r0", "random-shadow"])
+@pytest.mark.parametrize("name,make,form,pc", _CASES, ids=[c[0] for c in _CASES])
+def test_single_kernel_trace_and_vectors(Solver, name, make, form, pc, shadow):
+    p = make()
+    A, ops = oracle_ops(p, pc)
+    rh = np.random.default_rng(57).standard_normal(p.n) if shadow else None
+    kw = dict(rr_period=4, rr_tau=0.0)
+    k = _horizon(A, p.b, ops.dinv, rh, kw, cap=8 if shadow else 24)
+    print(f"{name} shadow={shadow}: trace horizon {k} iterations", flush=True)
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, record=True, rhat=rh, **kw)
+    S = Solver.from_problem(p, form=form, precond=pc)
+    hist = history_buffer(k)
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, history=hist, rr_period=4, rr_tau=1e-300,
+                    rhat=None if rh is None else dev(rh), single_kernel=True)
+    assert st["single_kernel"] == 1
+    assert st["iterations"] == k and st["status"] == STATUS["MAXIT"]
+    assert st["replacements"] == ref.replacements == k // 4
+    rn, al, om, be = split_history(hist, k)
+    assert np.all(rel(al, ref.alpha) <= 1e-10)
+    assert np.all(rel(om, ref.omega) <= 1e-10)
+    assert np.all(rel(rn, ref.rnorm) <= 1e-10)
+    assert np.all(rel(be[:k - 1], ref.beta[:k - 1]) <= 1e-10)
+
+    def amax(v):
+        return float(np.max(np.abs(np.asarray(v, dtype=float))))
+    term_x, term = 0.0, 0.0
+    for j, snap in enumerate(ref.snapshots):
+        term_x = max(term_x, amax(snap["x1"]), abs(ref.alpha[j]) * amax(snap["g"]),
+                     abs(ref.omega[j]) * amax(snap["u"]))
+        sc = [1.0, abs(ref.alpha[j]), abs(ref.omega[j]), abs(ref.alpha[j] * ref.omega[j]),
+              abs(snap["beta"]), abs(snap["beta"] * snap["omega_prev"])]
+        vmax = max(amax(v) for v in snap.values() if isinstance(v, np.ndarray))
+        term = max(term, max(sc) * vmax)
+    assert np.max(np.abs(host(x) - ref.x)) <= 1e-12 * term_x
+    # the state written back to the workspace: the vectors of the last step
+    sn = ref.snapshots[-1]
+    nA = float(np.max(np.asarray(abs(A).sum(axis=1)).ravel()))
+    if pc == "jacobi":
+        nA *= float(np.max(np.abs(1.0 / A.diagonal())))
+    floor = 1e-12 * term * max(nA, 1.0) ** 2
+    for vname, want in {"r": sn["r1"], "w": sn["w1"], "s": sn["s"], "z": sn["z"],
+                        "g": sn["g"]}.items():
+        got = host(S.get_vector(vname))
+        assert np.max(np.abs(got - want)) <= floor, vname
+    want_rh = p.b if rh is None else rh          # x_0 = 0: r_0 = b
+    assert np.array_equal(host(S.get_vector("rhat")), want_rh)
+    S.close()
+
+
+@pytest.mark.parametrize("form,pc", [("csr", "none"), ("stencil", "none"), ("csr", "jacobi")])
+@pytest.mark.parametrize("period", [0, 50])
+def test_single_kernel_full_solve(Solver, form, pc, period):
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, pc)
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000, rr_period=period)
+    assert ref.status == 0
+    S = Solver.from_problem(p, form=form, precond=pc)
+    b = dev(p.b)
+    xs, ss = S.solve(b, tol=1e-10, maxit=2000, rr_period=period, single_kernel=True)
+    xm, sm = S.solve(b, tol=1e-10, maxit=2000, rr_period=period)
+    print(f"{form}/{pc} P={period}: oracle {ref.iterations} its, single kernel "
+          f"{ss['iterations']}, multi-kernel {sm['iterations']}", flush=True)
+    assert ss["single_kernel"] == 1 and sm["single_kernel"] == 0
+    assert ss["status"] == sm["status"] == 0
+    assert abs(ss["iterations"] - ref.iterations) <= max(2, ref.iterations // 10)
+    assert abs(ss["replacements"] - ref.replacements) <= 1
+    assert ss["rel_res_true"] <= 1e-10
+    assert ss["spmvs"] == 3 + 2 * ss["iterations"] + 4 * ss["replacements"] + 1
+    xs, xm = host(xs), host(xm)
+    # two solutions that both meet the tolerance: within cond(A) * 1e-10
+    assert np.max(np.abs(xs - xm)) <= 1e-6 * np.max(np.abs(xm))
+    assert np.max(np.abs(xs - p.x_exact)) <= 1e-6 * np.max(np.abs(p.x_exact))
+    S.close()
+
+
+def test_single_kernel_forced_replacement_and_true_residual(Solver):
+    """tol 1e-14 on the 32^2 problem is under what the recursive residual
+    reaches but not the true one: with replacement enabled (a period that
+    never comes round) a forced replacement, then convergence; without
+    replacement TRUE_RES_NOT_MET -- in the oracle and in the kernel."""
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, "none")
+    S = Solver.from_problem(p, form="csr", precond="none")
+    b = dev(p.b)
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-14, maxit=2000, rr_period=100000)
+    assert ref.status == 0 and ref.replacements == 1
+    x, st = S.solve(b, tol=1e-14, maxit=2000, rr_period=100000, single_kernel=True)
+    print(f"forced: oracle {ref.iterations} its {ref.rr_iters}, kernel {st['iterations']} its "
+          f"{st['replacements']} replacements", flush=True)
+    assert st["single_kernel"] == 1
+    assert st["status"] == 0 and 1 <= st["replacements"] <= 3
+    assert st["rel_res_true"] <= 1e-14
+    ref0 = pipelined_bicgstab(ops, p.b, tol=1e-14, maxit=2000, rr_period=0)
+    assert ref0.status == STATUS["TRUE_RES_NOT_MET"]
+    x, st = S.solve(b, tol=1e-14, maxit=2000, single_kernel=True)
+    assert st["status"] == STATUS["TRUE_RES_NOT_MET"] and st["replacements"] == 0
+    assert abs(st["iterations"] - ref0.iterations) <= max(2, ref0.iterations // 10)
+    assert st["rel_res_recursive"] <= 1e-14 < st["rel_res_true"]
+    S.close()
+
+
+def test_single_kernel_edge_cases(Solver):
+    p = convdiff2d_c1(32)
+    S = Solver.from_problem(p, form="csr", precond="none")
+    b = dev(p.b)
+    # b = 0: x = 0 whatever x_0, no iteration
+    x, st = S.solve(torch.zeros_like(b), x0=torch.ones_like(b), single_kernel=True)
+    assert st["single_kernel"] == 1 and st["status"] == 0 and st["iterations"] == 0
+    assert not torch.any(x).item()
+    # x_0 = the exact solution (b = A x_ex): converged before the first iteration
+    xe = S.apply(dev(p.x_exact))
+    x, st = S.solve(xe, x0=dev(p.x_exact), single_kernel=True)
+    assert st["status"] == 0 and st["iterations"] == 0
+    assert np.array_equal(host(x), p.x_exact)
+    # maxit: three iterations, three history rows, as the multi-kernel path
+    hs, hm = history_buffer(3), history_buffer(3)
+    xs, ss = S.solve(b, maxit=3, history=hs, single_kernel=True)
+    xm, sm = S.solve(b, maxit=3, history=hm)
+    assert ss["status"] == sm["status"] == STATUS["MAXIT"] and ss["iterations"] == 3
+    assert np.all(rel(host(hs), host(hm)) <= 1e-12)
+    S.close()
+    # a 1 x 1 system: x = b / a after one iteration ((y, y) = 0 gives omega = 0)
+    A = sp.csr_matrix(np.array([[2.0]]))
+    S1 = Solver.from_csr(A.indptr, A.indices, A.data, precond="none")
+    ref = pipelined_bicgstab(Float64Ops(A), np.array([4.0]), tol=1e-12, maxit=10)
+    x, st = S1.solve(dev([4.0]), tol=1e-12, maxit=10, single_kernel=True)
+    assert st["single_kernel"] == 1
+    assert st["status"] == ref.status == 0 and st["iterations"] == ref.iterations
+    assert host(x)[0] == 2.0
+    S1.close()
+
+
+def test_single_kernel_ineligible_runs_the_multi_kernel_path(Solver):
+    cases = [
+        (poisson2d_c2(33), dict(form="stencil", precond="jacobi"), {}),          # 1089 rows
+        (convdiff2d_c1(32), dict(form="csr", precision="mixed", precond="none"), {}),
+        (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(rr_auto="bound")),
+        (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(transpose=True)),
+    ]
+    for p, make_kw, solve_kw in cases:
+        S = Solver.from_problem(p, **make_kw)
+        b = dev(p.b)
+        xs, ss = S.solve(b, tol=1e-10, maxit=3000, single_kernel=True, **solve_kw)
+        xm, sm = S.solve(b, tol=1e-10, maxit=3000, **solve_kw)
+        assert ss["single_kernel"] == 0
+        for key in ("status", "iterations", "replacements", "rel_res_true"):
+            assert ss[key] == sm[key], key
+        assert np.array_equal(host(xs), host(xm))
+        S.close()
+
+
+def _abi_solve(L, fn, S, b, **kw):
+    o = L.Opts()
+    L.load().pbicgstab_default_opts(ctypes.byref(o))
+    o.tol = kw.get("tol", 1e-10)
+    o.maxit = kw.get("maxit", 3000)
+    o.rr_period = kw.get("rr_period", 0)
+    o.single_kernel = 1
+    o.stream = torch.cuda.current_stream().cuda_stream
+    x = torch.zeros_like(b)
+    st = L.Stats()
+    L.check(getattr(L.load(), fn)(S._h, ctypes.c_void_p(b.data_ptr()),
+                                  ctypes.c_void_p(x.data_ptr()), ctypes.byref(o),
+                                  ctypes.byref(st)))
+    torch.cuda.synchronize()
+    return host(x), st.as_dict()
+
+
+def test_single_kernel_noalloc_and_repeatable(Solver):
+    from paper_1809_01948_amd import _lib as L
+    p = convdiff2d_c1(32)
+    S = Solver.from_problem(p, form="csr", precond="jacobi")
+    b = dev(p.b)
+    runs = [_abi_solve(L, "pbicgstab_solve", S, b, rr_period=50),
+            _abi_solve(L, "pbicgstab_solve_noalloc", S, b, rr_period=50),
+            _abi_solve(L, "pbicgstab_solve", S, b, rr_period=50)]
+    for x, st in runs:
+        assert st["single_kernel"] == 1 and st["status"] == 0
+        for key in ("iterations", "replacements", "rel_res_recursive", "rel_res_true"):
+            assert st[key] == runs[0][1][key], key
+        assert np.array_equal(x, runs[0][0])
+    S.close()
