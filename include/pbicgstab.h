@@ -167,11 +167,13 @@ typedef struct {
                             on entry are ignored, on return unspecified */
   int64_t bound_state_len; /* doubles in bound_state */
   int32_t single_kernel; /* nonzero: run the whole of Algorithm 2 as one kernel in one workgroup
-                            (every vector in LDS, the global reductions as workgroup
-                            reductions, no host polls) when the system allows it: at most
-                            1024 rows, FP64, rr_auto 0, gap_every 0, restarts 0, not
-                            transposed, not block-Jacobi, and a device with 112 KiB of LDS
-                            per workgroup; otherwise ignored.  Same arithmetic per row and the
+                            (row i of every vector in the registers of thread i, the
+                            inputs of the products in LDS, the global reductions as
+                            workgroup reductions, no host polls) when the system allows it:
+                            at most 1024 rows, FP64, rr_auto 0, gap_every 0, restarts 0, not
+                            transposed, not block-Jacobi, and a device with 50 KiB of LDS
+                            per workgroup; otherwise ignored (pbcg_stats.single_kernel
+                            tells which ran).  Same arithmetic per row and the
                             same stopping rules as the multi-kernel path; the sums of the
                             reductions are taken in another order (results agree to
                             rounding).  For small systems, whose solve is bound by kernel
@@ -219,8 +221,10 @@ void pbicgstab_default_opts(pbcg_opts* opt);
  *                         block's column window in LDS (when it fits)
  *   PBCG_LDS_BLOCKS=n     blocks of that product (0: 256 per window that takes
  *                         more than half a block's LDS, else 512)
- * None changes a result bit except PBCG_NBLK and PBCG_MARCH_PHASE, which set
- * the order in which the dot products are summed.
+ *   PBCG_SMALL_RPT=1|2|4  rows per thread of the single-workgroup solve
+ *                         (opt single_kernel; default 2)
+ * None changes a result bit except PBCG_NBLK, PBCG_MARCH_PHASE and
+ * PBCG_SMALL_RPT, which set the order in which the dot products are summed.
  */
 
 /*

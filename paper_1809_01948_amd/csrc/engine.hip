@@ -220,6 +220,10 @@ void common_setup(Solver& S, int precision, int precond, void* workspace, size_t
   if (const char* env = std::getenv("PBCG_PREMULT")) S.premult = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_SELL_LDS")) S.sell_lds = std::atoi(env) != 0;
   if (const char* env = std::getenv("PBCG_LDS_BLOCKS")) S.lds_blocks = std::atoi(env);
+  if (const char* env = std::getenv("PBCG_SMALL_RPT")) {
+    const int v = std::atoi(env);
+    S.small_rpt = (v == 1 || v == 4) ? v : 2;
+  }
   {
     int dev = 0, cap = 0;
     hipck(hipGetDevice(&dev), "hipGetDevice");

@@ -1187,8 +1187,9 @@ void launch_dia5_transpose(Solver& S, hipStream_t st) {
 //
 // A solve of a few hundred rows is bound by kernel launches and host polls,
 // not by memory.  For N <= kSmallRows (FP64) one block of kSmallRows threads
-// holds every vector of the iteration in LDS (row i in thread i) and runs
-// Algorithm 2 to its end in one launch: phase A and phase B with the
+// holds the iteration vectors (row i in the registers of thread i; the
+// inputs of the products, whose neighbours' entries are read, also in LDS)
+// and runs Algorithm 2 to its end in one launch: phase A and phase B with the
 // expressions of k_phaseA / k_phaseB, the products through the operator's
 // own row visitor (the same terms in the same order), periodic residual
 // replacement (eq:rr) in FP64 with the saved pre-replacement z, and the
@@ -1208,9 +1209,9 @@ constexpr int kSmallWaves = kSmallRows / 64;
 static_assert(kSmallWaves == 16, "the reductions finish with a 16-lane butterfly");
 constexpr int kSmallCache = 8;
 enum : int {
-  SB_RH = 0, SB_R, SB_G, SB_S, SB_L, SB_Z, SB_K, SB_W, SB_T, SB_V, SB_ZS, SB_X, SB_B,
-  SB_NZ,      // M^-1 z_i, the input of v_i = A M^-1 z_i (also M^-1 r_0 at the start)
+  SB_NZ = 0,  // M^-1 z_i, the input of v_i = A M^-1 z_i (also M^-1 r_0 at the start)
   SB_MW,      // M^-1 w, the input of t = A M^-1 w
+  SB_PX, SB_PG, SB_PK, SB_PL,   // x, g, k, l for the products of a replacement
   SB_COUNT
 };
 constexpr size_t kSmallLds = (size_t)SB_COUNT * kSmallRows * sizeof(double);
@@ -1245,11 +1246,12 @@ __device__ __forceinline__ void small_part(const double (&v)[NS], double (*buf)[
 // the sums of the wave partials (after a barrier): the same tree in every
 // wave, so every thread receives the same bits
 template <int NS>
-__device__ __forceinline__ void small_total(double (&v)[NS], const double (*buf)[kSmallWaves]) {
+__device__ __forceinline__ void small_total(double (&v)[NS], const double (*buf)[kSmallWaves],
+                                            int nwaves) {
   const int l = threadIdx.x & (kSmallWaves - 1);
 #pragma unroll
   for (int d = 0; d < NS; ++d) {
-    double t = buf[d][l];
+    double t = l < nwaves ? buf[d][l] : 0.0;
     t += lane_xor<8>(t);
     t += lane_xor<4>(t);
     t += lane_xor<2>(t);
@@ -1284,87 +1286,131 @@ struct SellRowRegs {
   }
 };
 
-template <int PC, class Op, bool CACHE>
-__global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) {
+// A sliced-ELL row of any length read from memory one entry after another,
+// in SellOp::row's order; fewer registers than SellOp::row's grouped loads,
+// which the register-resident vectors of k_small_solve leave no room for.
+template <class Vis>
+__device__ __forceinline__ void sell_row_serial(const SellOp<double>& op, int i, Vis& vis) {
+  const int64_t sl = i >> 6;
+  const int lane = i & 63;
+  const int64_t off = op.sptr[sl];
+  const int w = (int)((op.sptr[sl + 1] - off) >> 6);
+  const int32_t* c = op.col + off + lane;
+  const double* v = op.val + off + lane;
+#pragma unroll 4
+  for (int j = 0; j < w; ++j) {
+    const int32_t cj = c[(int64_t)j * kSellC];
+    const double aj = v[(int64_t)j * kSellC];
+    if (cj >= 0) vis.add(aj, vis.load(cj));
+  }
+}
+
+// RPT rows per thread: rows tid, tid + T, ... (T = kSmallRows / RPT threads),
+// so that a wave's lanes hold consecutive rows.
+template <int PC, class Op, bool CACHE, int RPT>
+__global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallArgs a) {
+  constexpr int T = kSmallRows / RPT;
   extern __shared__ double sm[];
   __shared__ double red[kSmallRed][5][kSmallWaves];
-  double* const rh = sm + SB_RH * kSmallRows;
-  double* const r = sm + SB_R * kSmallRows;
-  double* const g = sm + SB_G * kSmallRows;
-  double* const s = sm + SB_S * kSmallRows;
-  double* const l = sm + SB_L * kSmallRows;
-  double* const z = sm + SB_Z * kSmallRows;
-  double* const k = sm + SB_K * kSmallRows;
-  double* const w = sm + SB_W * kSmallRows;
-  double* const t = sm + SB_T * kSmallRows;
-  double* const v = sm + SB_V * kSmallRows;
-  double* const zs = sm + SB_ZS * kSmallRows;
-  double* const x = sm + SB_X * kSmallRows;
-  double* const b = sm + SB_B * kSmallRows;
   double* const nz = sm + SB_NZ * kSmallRows;
   double* const mw = sm + SB_MW * kSmallRows;
-  const int i = threadIdx.x;
-  const bool own = i < a.n;
-  // M^-1 u for row i (prec1's product, with the diagonal kept in a register)
-  const double di = (PC == PC_VECTOR && own) ? a.dinv[i] : 0.0;
-  auto prec = [&](double u) {
+  double* const px = sm + SB_PX * kSmallRows;
+  double* const pg = sm + SB_PG * kSmallRows;
+  double* const pk = sm + SB_PK * kSmallRows;
+  double* const pl = sm + SB_PL * kSmallRows;
+  const int tid = threadIdx.x;
+  const int nw = T / 64;
+  int row[RPT];
+  bool own[RPT];
+  double di[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    row[j] = tid + j * T;
+    own[j] = row[j] < a.n;
+    di[j] = (PC == PC_VECTOR && own[j]) ? a.dinv[row[j]] : 0.0;
+  }
+  // M^-1 u for row j of the thread (prec1's product, the diagonal in a register)
+  auto prec = [&](int j, double u) {
     if (PC == PC_NONE) return u;
     if (PC == PC_SCALAR) return a.ds * u;
-    return di * u;
+    return di[j] * u;
   };
-  SellRowRegs rows;
+  SellRowRegs rows[RPT];
   if constexpr (CACHE) {
-    if (own) rows.load(op, i);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+      if (own[j]) rows[j].load(op, row[j]);
   }
-  auto visit = [&](auto& vis) {
-    if constexpr (CACHE) rows.row(vis);
-    else op.row(i, vis);
+  auto visit = [&](int j, auto& vis) {
+    if constexpr (CACHE) rows[j].row(vis);
+    else if constexpr (std::is_same_v<Op, SellOp<double>>) sell_row_serial(op, row[j], vis);
+    else op.row(row[j], vis);
   };
-  // sum_j a_ij in_j
-  auto product = [&](const double* in) {
+  // sum_c a_rc in_c for row j
+  auto product = [&](int j, const double* in) {
     LdsVis<double> vis{in, 0, 0.0};
-    visit(vis);
+    visit(j, vis);
     return vis.sum;
   };
+  // the rows' entries of the iteration vectors (0 where a thread has no row);
+  // m = M^-1 w and n = M^-1 z as stored for the products
+  double x[RPT], bi[RPT], rh[RPT], r[RPT], g[RPT], s[RPT], l[RPT], z[RPT], k[RPT];
+  double w[RPT], t[RPT], v[RPT], zs[RPT], m[RPT], n[RPT];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    x[j] = bi[j] = rh[j] = r[j] = g[j] = s[j] = l[j] = z[j] = k[j] = 0.0;
+    w[j] = t[j] = v[j] = zs[j] = m[j] = n[j] = 0.0;
+  }
 
   // Algorithm 2 initialisation
-  if (own) {
-    x[i] = a.x[i];
-    b[i] = a.b[i];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    if (own[j]) {
+      x[j] = a.x[row[j]];
+      bi[j] = a.b[row[j]];
+      px[row[j]] = x[j];
+    }
   }
   __syncthreads();
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (own) {
-    ResVis<double> vis{x, 0.0};
-    visit(vis);
-    const double ri = b[i] - vis.sum;
-    const double hi = a.rhat_in ? a.rhat_in[i] : ri;
-    const double ki = prec(ri);
-    r[i] = ri; rh[i] = hi; k[i] = ki;
-    g[i] = 0.0; s[i] = 0.0; l[i] = 0.0; z[i] = 0.0; v[i] = 0.0; zs[i] = 0.0;
-    nz[i] = ki;
-    acc[0] = hi * ri;
-    acc[1] = ri * ri;
-    acc[2] = b[i] * b[i];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    if (own[j]) {
+      ResVis<double> vis{px, 0.0};
+      visit(j, vis);
+      r[j] = bi[j] - vis.sum;
+      rh[j] = a.rhat_in ? a.rhat_in[row[j]] : r[j];
+      k[j] = prec(j, r[j]);
+      nz[row[j]] = k[j];
+      acc[0] += rh[j] * r[j];
+      acc[1] += r[j] * r[j];
+      acc[2] += bi[j] * bi[j];
+    }
   }
   __syncthreads();
-  if (own) {
-    const double wi = product(nz);             // w_0 = A M^-1 r_0
-    w[i] = wi;
-    mw[i] = prec(wi);
-    acc[3] = rh[i] * wi;
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    if (own[j]) {
+      w[j] = product(j, nz);                   // w_0 = A M^-1 r_0
+      m[j] = prec(j, w[j]);
+      mw[row[j]] = m[j];
+      acc[3] += rh[j] * w[j];
+    }
   }
   small_part<4>(acc, red[2]);
   __syncthreads();
-  if (own) t[i] = product(mw);                 // t_0 = A M^-1 w_0
-  small_total<4>(acc, red[2]);
+#pragma unroll
+  for (int j = 0; j < RPT; ++j)
+    if (own[j]) t[j] = product(j, mw);         // t_0 = A M^-1 w_0
+  small_total<4>(acc, red[2], nw);
   double rho = acc[0];
   const double rn0 = sqrt(acc[1]), nb = sqrt(acc[2]), rw = acc[3];
   double rn = rn0, alpha = 0.0, beta = 0.0, omega = 0.0, omega_prev = 0.0;
   int status = -1, iter = 0, rr_count = 0, forced = 0, n_saved = 0;
   if (nb == 0.0) {
     status = ST_CONVERGED;
-    if (own) x[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) x[j] = 0.0;
   } else if (rn0 <= a.tol * nb) {
     status = ST_CONVERGED;
   } else if (!finite(rho) || !finite(rw)) {
@@ -1375,28 +1421,50 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
     alpha = rho / rw;
   }
 
-  // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again; w (and
-  // M^-1 w) of the row are written at once: the second product reads k, l
+  // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again.  x, g,
+  // then k, l go through LDS arrays of their own (the neighbours' entries);
+  // their previous readers are behind at least one barrier.
   auto replace = [&](bool save_z, double (&d)[5]) {
-    __syncthreads();                           // x and g of every row, no reader of k, l
-    if (own) {
-      Res2Vis<double, double, double> vis{x, g, 0.0, 0.0};
-      visit(vis);
-      const double ri = b[i] - vis.sx;
-      const double si = vis.sy;
-      r[i] = ri; s[i] = si; k[i] = prec(ri); l[i] = prec(si);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      if (own[j]) {
+        px[row[j]] = x[j];
+        pg[row[j]] = g[j];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      if (own[j]) {
+        Res2Vis<double, double, double> vis{px, pg, 0.0, 0.0};
+        visit(j, vis);
+        r[j] = bi[j] - vis.sx;
+        s[j] = vis.sy;
+        k[j] = prec(j, r[j]);
+        l[j] = prec(j, s[j]);
+        pk[row[j]] = k[j];
+        pl[row[j]] = l[j];
+      }
     }
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 5; ++e) d[e] = 0.0;
-    if (own) {
-      Res2Vis<double, double, double> vis{k, l, 0.0, 0.0};
-      visit(vis);
-      const double wi = vis.sx, zi = vis.sy;
-      if (save_z) zs[i] = z[i];
-      w[i] = wi; z[i] = zi; mw[i] = prec(wi);
-      d[0] = rh[i] * r[i]; d[1] = rh[i] * wi; d[2] = rh[i] * s[i]; d[3] = rh[i] * zi;
-      d[4] = r[i] * r[i];
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      if (own[j]) {
+        Res2Vis<double, double, double> vis{pk, pl, 0.0, 0.0};
+        visit(j, vis);
+        if (save_z) zs[j] = z[j];
+        w[j] = vis.sx;
+        z[j] = vis.sy;
+        m[j] = prec(j, w[j]);
+        mw[row[j]] = m[j];
+        d[0] += rh[j] * r[j];
+        d[1] += rh[j] * w[j];
+        d[2] += rh[j] * s[j];
+        d[3] += rh[j] * z[j];
+        d[4] += r[j] * r[j];
+      }
     }
     rr_count += 1;
     n_saved = 1;
@@ -1405,25 +1473,29 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
   while (status < 0) {
     // phase A: g, s, l, z, M^-1 z and the GLRED 1 terms
     double d2[2] = {0.0, 0.0};
-    if (own) {
-      const double zprev = n_saved ? zs[i] : z[i];
-      const double np = prec(zprev);
-      const double m = mw[i];
-      const double gn = k[i] + beta * (g[i] - omega_prev * l[i]);
-      const double sn = w[i] + beta * (s[i] - omega_prev * z[i]);
-      const double ln = m + beta * (l[i] - omega_prev * np);
-      const double zn = t[i] + beta * (z[i] - omega_prev * v[i]);
-      const double q = r[i] - alpha * sn;
-      const double y = w[i] - alpha * zn;
-      d2[0] = q * y;
-      d2[1] = y * y;
-      g[i] = gn; s[i] = sn; l[i] = ln; z[i] = zn;
-      nz[i] = prec(zn);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      if (own[j]) {
+        const double np = prec(j, n_saved ? zs[j] : z[j]);
+        const double gn = k[j] + beta * (g[j] - omega_prev * l[j]);
+        const double sn = w[j] + beta * (s[j] - omega_prev * z[j]);
+        const double ln = m[j] + beta * (l[j] - omega_prev * np);
+        const double zn = t[j] + beta * (z[j] - omega_prev * v[j]);
+        const double q = r[j] - alpha * sn;
+        const double y = w[j] - alpha * zn;
+        d2[0] += q * y;
+        d2[1] += y * y;
+        g[j] = gn; s[j] = sn; l[j] = ln; z[j] = zn;
+        n[j] = prec(j, zn);
+        nz[row[j]] = n[j];
+      }
     }
     small_part<2>(d2, red[0]);
     __syncthreads();
-    if (own) v[i] = product(nz);               // v_i = A M^-1 z_i
-    small_total<2>(d2, red[0]);                // GLRED 1
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+      if (own[j]) v[j] = product(j, nz);       // v_i = A M^-1 z_i
+    small_total<2>(d2, red[0], nw);            // GLRED 1
     n_saved = 0;
     if (!finite(d2[0]) || !finite(d2[1])) {
       status = ST_NONFINITE;
@@ -1432,30 +1504,37 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
     omega = d2[1] != 0.0 ? d2[0] / d2[1] : 0.0;
     // phase B: x, r, k, w, M^-1 w and the GLRED 2 terms
     double d5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (own) {
-      const double m = mw[i];
-      const double n_i = nz[i];
-      const double q = r[i] - alpha * s[i];
-      const double u = k[i] - alpha * l[i];
-      const double y = w[i] - alpha * z[i];
-      x[i] = (x[i] + alpha * g[i]) + omega * u;
-      const double rn_ = q - omega * y;
-      const double kn = u - omega * (m - alpha * n_i);
-      const double wn = y - omega * (t[i] - alpha * v[i]);
-      r[i] = rn_; k[i] = kn; w[i] = wn;
-      mw[i] = prec(wn);
-      d5[0] = rh[i] * rn_; d5[1] = rh[i] * wn; d5[2] = rh[i] * s[i]; d5[3] = rh[i] * z[i];
-      d5[4] = rn_ * rn_;
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      if (own[j]) {
+        const double q = r[j] - alpha * s[j];
+        const double u = k[j] - alpha * l[j];
+        const double y = w[j] - alpha * z[j];
+        x[j] = (x[j] + alpha * g[j]) + omega * u;
+        const double rn_ = q - omega * y;
+        const double kn = u - omega * (m[j] - alpha * n[j]);
+        const double wn = y - omega * (t[j] - alpha * v[j]);
+        r[j] = rn_; k[j] = kn; w[j] = wn;
+        m[j] = prec(j, wn);
+        mw[row[j]] = m[j];
+        d5[0] += rh[j] * rn_;
+        d5[1] += rh[j] * wn;
+        d5[2] += rh[j] * s[j];
+        d5[3] += rh[j] * z[j];
+        d5[4] += rn_ * rn_;
+      }
     }
     if (a.rr_period > 0 && (iter + 1) % a.rr_period == 0 && rn >= a.tau * rn0)
       replace(true, d5);
     small_part<5>(d5, red[1]);
     __syncthreads();
-    if (own) t[i] = product(mw);               // t_{i+1} = A M^-1 w_{i+1}
-    small_total<5>(d5, red[1]);                // GLRED 2
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+      if (own[j]) t[j] = product(j, mw);       // t_{i+1} = A M^-1 w_{i+1}
+    small_total<5>(d5, red[1], nw);            // GLRED 2
     const int its = ++iter;
     double* hrow = (a.history && its <= a.hist_len) ? a.history + 4 * (int64_t)(its - 1) : nullptr;
-    if (hrow && i == 0) { hrow[1] = alpha; hrow[2] = omega; hrow[3] = 0.0; }
+    if (hrow && tid == 0) { hrow[1] = alpha; hrow[2] = omega; hrow[3] = 0.0; }
     bool test_tol = true;
     for (;;) {
       const G2Step st = glred2_step(d5, alpha, omega, rho, a.tol, nb, test_tol);
@@ -1464,20 +1543,26 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
         break;
       }
       rn = st.rn;
-      if (hrow && i == 0) hrow[0] = rn;
+      if (hrow && tid == 0) hrow[0] = rn;
       if (st.outcome == G2_CONVERGED) {
-        // confirm on the true residual ||b - A x|| (FP64; x of every row is
-        // written: phase B is behind the last barrier)
+        // confirm on the true residual ||b - A x|| (FP64)
+#pragma unroll
+        for (int j = 0; j < RPT; ++j)
+          if (own[j]) px[row[j]] = x[j];
+        __syncthreads();
         double tr2[1] = {0.0};
-        if (own) {
-          ResVis<double> vis{x, 0.0};
-          visit(vis);
-          const double e = b[i] - vis.sum;
-          tr2[0] = e * e;
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          if (own[j]) {
+            ResVis<double> vis{px, 0.0};
+            visit(j, vis);
+            const double e = bi[j] - vis.sum;
+            tr2[0] += e * e;
+          }
         }
         small_part<1>(tr2, red[2]);
         __syncthreads();
-        small_total<1>(tr2, red[2]);
+        small_total<1>(tr2, red[2], nw);
         if (sqrt(tr2[0]) <= a.tol * nb) {
           status = ST_CONVERGED;
         } else if (a.rr_period <= 0 || forced >= 3) {
@@ -1488,8 +1573,10 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
           replace(n_saved == 0, d5);
           small_part<5>(d5, red[1]);
           __syncthreads();
-          if (own) t[i] = product(mw);
-          small_total<5>(d5, red[1]);
+#pragma unroll
+          for (int j = 0; j < RPT; ++j)
+            if (own[j]) t[j] = product(j, mw);
+          small_total<5>(d5, red[1], nw);
           test_tol = false;
           continue;
         }
@@ -1499,7 +1586,7 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
         status = ST_BREAKDOWN_RHO;
       } else {
         beta = st.beta;
-        if (hrow && i == 0) hrow[3] = beta;
+        if (hrow && tid == 0) hrow[3] = beta;
         alpha = st.alpha;
         rho = d5[0];
         omega_prev = omega;
@@ -1509,14 +1596,18 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
     }
   }
 
-  // write the state back (each thread its own row): vectors, x, scalars
-  if (own) {
-    a.out[0][i] = rh[i]; a.out[1][i] = r[i]; a.out[2][i] = g[i]; a.out[3][i] = s[i];
-    a.out[4][i] = l[i]; a.out[5][i] = z[i]; a.out[6][i] = k[i]; a.out[7][i] = w[i];
-    a.out[8][i] = t[i]; a.out[9][i] = v[i]; a.out[10][i] = zs[i];
-    a.x[i] = x[i];
+  // write the state back: vectors, x, scalars
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    if (own[j]) {
+      const int i = row[j];
+      a.out[0][i] = rh[j]; a.out[1][i] = r[j]; a.out[2][i] = g[j]; a.out[3][i] = s[j];
+      a.out[4][i] = l[j]; a.out[5][i] = z[j]; a.out[6][i] = k[j]; a.out[7][i] = w[j];
+      a.out[8][i] = t[j]; a.out[9][i] = v[j]; a.out[10][i] = zs[j];
+      a.x[i] = x[j];
+    }
   }
-  if (i == 0) {
+  if (tid == 0) {
     DevScalars* sc = a.sc;
     sc->done = STOPPED;
     sc->status = status;
@@ -1528,15 +1619,22 @@ __global__ __launch_bounds__(kSmallRows) void k_small_solve(Op op, SmallArgs a) 
   }
 }
 
-template <int PC, class Op, bool CACHE>
-static hipError_t launch_small(const Op& op, const SmallArgs& a, hipStream_t st) {
-  const hipError_t e = hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE>,
+template <int PC, class Op, bool CACHE, int RPT>
+static hipError_t launch_small_rpt(const Op& op, const SmallArgs& a, hipStream_t st) {
+  const hipError_t e = hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE, RPT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)kSmallLds);
   if (e == hipSuccess)
-    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE>), dim3(1), dim3(kSmallRows), kSmallLds, st,
-                       op, a);
+    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE, RPT>), dim3(1), dim3(kSmallRows / RPT),
+                       kSmallLds, st, op, a);
   return e;
+}
+
+template <int PC, class Op, bool CACHE>
+static hipError_t launch_small(const Op& op, const SmallArgs& a, int rpt, hipStream_t st) {
+  if (rpt == 1) return launch_small_rpt<PC, Op, CACHE, 1>(op, a, st);
+  if (rpt == 4) return launch_small_rpt<PC, Op, CACHE, 4>(op, a, st);
+  return launch_small_rpt<PC, Op, CACHE, 2>(op, a, st);
 }
 
 bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_t* err) {
@@ -1561,12 +1659,14 @@ bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_
   a.sc = S.sc;
   // rows of the sliced-ELL operator short enough to stay in registers
   const bool cache = S.mu_row <= kSmallCache;
+  const int rpt = S.small_rpt;
   with_op(S, false, true, [&]<typename T, int PC, class Op>(const Op& op) {
     if constexpr (std::is_same_v<T, double>) {
       if constexpr (std::is_same_v<Op, SellOp<double>>) {
-        *err = cache ? launch_small<PC, Op, true>(op, a, st) : launch_small<PC, Op, false>(op, a, st);
+        *err = cache ? launch_small<PC, Op, true>(op, a, rpt, st)
+                     : launch_small<PC, Op, false>(op, a, rpt, st);
       } else {
-        *err = launch_small<PC, Op, false>(op, a, st);
+        *err = launch_small<PC, Op, false>(op, a, rpt, st);
       }
     }
   });

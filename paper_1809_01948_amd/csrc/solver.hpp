@@ -92,6 +92,7 @@ struct Solver {
   bool sell_lds = true;         // sliced-ELL iteration products stage their column window in LDS
   int64_t lds_cap = 0;          // bytes of LDS one block may use (device attribute)
   int lds_blocks = 0;           // blocks of the LDS-window product (0: from the window size)
+  int small_rpt = 2;            // rows per thread of the single-workgroup solve (1, 2 or 4)
   const double* rhat_in = nullptr;  // the solve's caller shadow vector (null: r_0)
   bool bound_prod = false;      // the solve's gap bound takes the products reading
   bool march3d = true;          // 3D stencil SPMVs march through the grid planes (k_spmv_st3m)
