@@ -158,7 +158,10 @@ def test_single_kernel_forced_replacement_and_true_residual(Solver):
     """tol 1e-14 on the 32^2 problem is under what the recursive residual
     reaches but not the true one: with replacement enabled (a period that
     never comes round) a forced replacement, then convergence; without
-    replacement TRUE_RES_NOT_MET -- in the oracle and in the kernel."""
+    replacement TRUE_RES_NOT_MET -- in the oracle and in the kernel.  The
+    recursive residual creeps along near 1e-14 before it crosses, so the
+    iteration of the crossing depends on rounding (the order of the sums) and
+    is not compared."""
     p = convdiff2d_c1(32)
     A, ops = oracle_ops(p, "none")
     S = Solver.from_problem(p, form="csr", precond="none")
@@ -175,7 +178,6 @@ def test_single_kernel_forced_replacement_and_true_residual(Solver):
     assert ref0.status == STATUS["TRUE_RES_NOT_MET"]
     x, st = S.solve(b, tol=1e-14, maxit=2000, single_kernel=True)
     assert st["status"] == STATUS["TRUE_RES_NOT_MET"] and st["replacements"] == 0
-    assert abs(st["iterations"] - ref0.iterations) <= max(2, ref0.iterations // 10)
     assert st["rel_res_recursive"] <= 1e-14 < st["rel_res_true"]
     S.close()
 
