@@ -106,6 +106,10 @@ def parse():
                          "per row (sliced ELL), or the 2048^2 variable-coefficient DIA5 operator "
                          "with its gradients")
     ap.add_argument("--kernels-precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--c1-only", action="store_true",
+                    help="only the 32^2 latency solves (classic, graphs, one workgroup): the "
+                         "short program that the rocprofv3 trace of the single-workgroup "
+                         "solve profiles; one JSON line")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "--kernels-only into the traffic summary under profiles/")
@@ -656,6 +660,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.kernels_only:
         kernels_only(args, dev)
+        return
+    if args.c1_only:
+        print(json.dumps({"c1_latency": c1_latency(dev)}), flush=True)
         return
     graph = bool(args.graph)
     log("generating the 200^3 convection-diffusion workload")
