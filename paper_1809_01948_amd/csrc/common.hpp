@@ -184,18 +184,85 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Wave sums of several values at once, packed four to a register.  gfx950's
+// permlane32 swap of two registers leaves, after one add, the pair sums
+// (lanes l, l + 32) of one value in the lower half-wave and of the other in
+// the upper half; the permlane16 swap of two such results leaves four
+// values by 16-lane row (pairs of rows added); DPP rotations within the
+// rows (by 8 and 4, then the quad swaps 2 and 1) finish all four rows.  Two
+// moves and an add per value pair and step instead of a full butterfly per
+// value, and no LDS-pipe swizzle.  Row r of pack p holds value
+// 4 p + kRowVal[r]; every value goes through the same adds in the same
+// order whatever its place in a pack, and after the row steps all lanes of a
+// row hold the same bits (each step adds partners that form the same pair in
+// either order).
+constexpr int kRowVal[4] = {0, 2, 1, 3};
+constexpr int kValLane[4] = {0, 32, 16, 48};   // first lane of the row holding value j
+
+__device__ __forceinline__ double pair_swap32_sum(double a, double b) {
+  // lanes 0-31: a_l + a_{l+32}; lanes 32-63: b_{l-32} + b_l
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+__device__ __forceinline__ double pair_swap16_sum(double a, double b) {
+  // rows 0, 2: a_r + a_{r+1}; rows 1, 3: b_{r-1} + b_r
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_f64<0x128>(v);   // row_ror:8
+  v += dpp_f64<0x124>(v);   // row_ror:4
+  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+  return v;
+}
+
+// the wave sum of each of NS values; store(d, sum) runs in the first lane of
+// the row that holds value d
+template <int NS, class F>
+__device__ __forceinline__ void wave_sums_packed(const double (&v)[NS], F&& store) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int p = 0; p < (NS + 3) / 4; ++p) {
+    const int b0 = 4 * p;
+    const double a = v[b0];
+    const double b = b0 + 1 < NS ? v[b0 + 1 < NS ? b0 + 1 : b0] : 0.0;
+    const double P = pair_swap32_sum(a, b);
+    double Q = 0.0;
+    if (b0 + 2 < NS) {
+      const double c = v[b0 + 2 < NS ? b0 + 2 : b0];
+      const double d = b0 + 3 < NS ? v[b0 + 3 < NS ? b0 + 3 : b0] : 0.0;
+      Q = pair_swap32_sum(c, d);
+    }
+    const double R = row16_sum(pair_swap16_sum(P, Q));
+    const int vi = b0 + kRowVal[lane >> 4];
+    if ((lane & 15) == 0 && vi < NS) store(vi, R);
+  }
+}
+
 // Block-level sum of ND per-thread accumulators; thread d < ND writes the
 // block's partial of dot d into partials[slot[d] * kMaxPartials + blk].
 template <int ND>
 __device__ __forceinline__ void block_partials(double (&acc)[ND], const int (&slot)[ND],
                                                double* __restrict__ partials, int blk) {
   __shared__ double red[ND][kWaves];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    double v = wave_sum(acc[d]);
-    if (lane == 0) red[d][wid] = v;
-  }
+  const int wid = threadIdx.x >> 6;
+  wave_sums_packed<ND>(acc, [&](int d, double v) { red[d][wid] = v; });
   __syncthreads();
   if (threadIdx.x < ND) {
     const int d = threadIdx.x;
@@ -245,12 +312,8 @@ __device__ __forceinline__ void slot_thread_sums(const double (&p)[NS][kSlotStri
 template <int NS>
 __device__ __forceinline__ void block_tree(const double (&s)[NS], double (&out)[NS]) {
   __shared__ double red[NS][kWaves];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 0; d < NS; ++d) {
-    const double v = wave_sum(s[d]);
-    if (lane == 0) red[d][wid] = v;
-  }
+  const int wid = threadIdx.x >> 6;
+  wave_sums_packed<NS>(s, [&](int d, double v) { red[d][wid] = v; });
   __syncthreads();
 #pragma unroll
   for (int d = 0; d < NS; ++d) {

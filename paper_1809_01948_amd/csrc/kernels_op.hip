@@ -1233,78 +1233,20 @@ struct SmallArgs {
   DevScalars* sc;
 };
 
-// Workgroup sums of several values at once.  The wave stage packs four
-// values into one register before it reduces: gfx950's permlane32 swap of
-// two registers leaves, after one add, the pair sums of one value in the
-// lower half-wave and of another in the upper half; the permlane16 swap of
-// two such registers leaves four values by 16-lane row; DPP rotations
-// within the rows (by 8 and 4, then the quad swaps 2 and 1) finish the
-// sums.  That is 2 moves and an add per value pair and step instead of a
-// full butterfly per value, with no LDS-pipe swizzle.  After the row steps
-// all lanes of a row hold the same bits (each step adds partners that form
-// the same pair in either order).  Row r of a pack holds value kRowVal[r].
-constexpr int kRowVal[4] = {0, 2, 1, 3};
-constexpr int kValLane[4] = {0, 32, 16, 48};   // the first lane of the row holding value j
-
-__device__ __forceinline__ double pair_swap32_sum(double a, double b) {
-  // lanes 0-31: a_l + a_{l+32}; lanes 32-63: b_{l-32} + b_l
-  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false,
-                                                   false);
-  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false,
-                                                   false);
-  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
-}
-
-__device__ __forceinline__ double pair_swap16_sum(double a, double b) {
-  // rows 0, 2: a_r + a_{r+1}; rows 1, 3: b_{r-1} + b_r
-  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false,
-                                                   false);
-  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false,
-                                                   false);
-  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false),
-                          __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_f64<0x128>(v);   // row_ror:8
-  v += dpp_f64<0x124>(v);   // row_ror:4
-  v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-  return v;
-}
-
+// Workgroup sums of the single-workgroup solve: the packed wave sums of
+// wave_sums_packed, one partial per wave in LDS, and after the barrier every
+// wave loads the partials packed the same way, sums the rows and reads each
+// total from its row (readlane), so every thread receives the same bits.
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
                           __builtin_amdgcn_readlane(__double2loint(v), lane));
 }
 
-// one partial per wave of each of NS sums, stored by the first lane of the
-// row that holds it
+// one partial per wave of each of NS sums
 template <int NS>
 __device__ __forceinline__ void small_part(const double (&v)[NS], double (*buf)[kSmallWaves]) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int p = 0; p < (NS + 3) / 4; ++p) {
-    const int b0 = 4 * p;
-    const double a = v[b0];
-    const double b = b0 + 1 < NS ? v[b0 + 1 < NS ? b0 + 1 : b0] : 0.0;
-    const double P = pair_swap32_sum(a, b);
-    double Q = 0.0;
-    if (b0 + 2 < NS) {
-      const double c = v[b0 + 2 < NS ? b0 + 2 : b0];
-      const double d = b0 + 3 < NS ? v[b0 + 3 < NS ? b0 + 3 : b0] : 0.0;
-      Q = pair_swap32_sum(c, d);
-    }
-    const double R = row16_sum(pair_swap16_sum(P, Q));
-    const int vi = b0 + kRowVal[lane >> 4];
-    if ((lane & 15) == 0 && vi < NS) buf[vi][wv] = R;
-  }
+  const int wv = threadIdx.x >> 6;
+  wave_sums_packed<NS>(v, [&](int d, double x) { buf[d][wv] = x; });
 }
 
 // the sums of the nwaves wave partials (after a barrier): every wave loads
