@@ -178,7 +178,12 @@ typedef struct {
                             reductions are taken in another order (results agree to
                             rounding).  For small systems, whose solve is bound by kernel
                             launches and host polls. */
-  int32_t pad1_;
+  int32_t rr_nv;         /* not in the paper: nonzero: every residual replacement (periodic,
+                            automated or forced) also recomputes n_i := M^-1 z_i and
+                            v_i := A n_i from the replaced z_i (one more SpMV and PREC per
+                            replacement), so that the next iteration's l and z recurrences
+                            use n_i and v_i of the same z_i.  0 (default): the six quantities
+                            of eq:rr only, n_i and v_i keep their pre-replacement values. */
 } pbcg_opts;
 
 typedef struct {
@@ -197,7 +202,8 @@ typedef struct {
 
 /* Fills `opt` with defaults: tol 1e-10, maxit 10000, rr_period 0, rr_tau 0,
  * check_every 0, transpose 0, no history, use_graph 0, stream NULL, rr_auto 0,
- * rr_eps 0, no bound history, restarts 0, rhat NULL, no bound state, single_kernel 0. */
+ * rr_eps 0, no bound history, restarts 0, rhat NULL, no bound state, single_kernel 0,
+ * rr_nv 0. */
 void pbicgstab_default_opts(pbcg_opts* opt);
 
 /*

@@ -596,7 +596,8 @@ class _GapBoundProducts(_GapBound):
 
 def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                        rr_tau=None, rr_mode="periodic", rr_eps=None, rr_estimate=False,
-                       rr_reading="nested", restarts=0, record=False, rhat=None):
+                       rr_reading="nested", restarts=0, record=False, rhat=None,
+                       rr_nv=False):
     """Algorithm 2 (preconditioned p-BiCGStab), Section 3, with residual
     replacement (Section 3.6, eq:rr):
 
@@ -631,7 +632,14 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
     restart.  BiCGStab admits any such vector with (rhat, r_0) != 0; r_0
     itself breaks down when the operator's column sums vanish and r_0 is a
     constant vector, since (1, b - A x_i) then depends on the boundary
-    values of x_i alone and tends to zero long before r_i does."""
+    values of x_i alone and tends to zero long before r_i does.
+
+    ``rr_nv`` (not in the paper, default False): a replacement also
+    recomputes n_i := M^-1 z_i and v_i := A n_i from the replaced z_i, the
+    definitions eq:auxvars gives them; the next iteration's l and z
+    recurrences then combine n_i, v_i and z_i of the same z_i.  By default
+    only the six quantities of eq:rr are recomputed and n_i, v_i keep the
+    values computed from the recursive z_i before the replacement."""
     auto = rr_mode == "auto"
     rhat_in = None if rhat is None else ops.copy(rhat)
     if rr_mode not in ("periodic", "auto"):
@@ -730,11 +738,14 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                (rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0))
         if due:
             r, k, w, s, l, z = replace(x, g)           # eq:rr, right after the w-update
+            if rr_nv:
+                n = ops.prec(z)                        # n_i, v_i of the replaced z_i
+                v = ops.spmv(n)
             res.replacements += 1
             res.rr_iters.append(i)
             replaced = True
             if snap is not None:
-                snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z)
+                snap["rep"] = dict(r=r, k=k, w=w, s=s, l=l, z=z, n=n, v=v)
             if auto:
                 f_next = gb.reset(ops.norm(x), ops.norm(k), ops.norm(g), ops.norm(l),
                                   ops.norm(s), ops.norm(z))
@@ -766,6 +777,9 @@ def pipelined_bicgstab(ops, b, x0=None, *, tol=1e-10, maxit=1000, rr_period=0,
                     res.fr.append(f_next)
                 return _finish(res, x, STATUS["TRUE_RES_NOT_MET"], i + 1, ops, b)
             r, k, w, s, l, z = replace(x, g)           # confirm failed: replace and go on
+            if rr_nv:
+                n = ops.prec(z)
+                v = ops.spmv(n)
             forced += 1
             res.replacements += 1
             res.rr_iters.append(i)

@@ -43,7 +43,7 @@ from .krylov import MAX_FORCED_REPLACEMENTS, STATUS, SolveResult, _GapBound, _Ga
 def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None, tol=1e-10,
                                maxit=1000, rr_period=0, rr_tau=None, rr_mode="periodic",
                                rr_estimate=None, record=False, dot_order="blas", rhat=None,
-                               rr_reading="nested"):
+                               rr_reading="nested", rr_nv=False):
     """Algorithm 2 with `store`-precision vectors (see the module docstring).
 
     A: scipy CSR (FP64 values, rounded here to `store`); b, x0: FP64.
@@ -52,6 +52,9 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
     products, for measuring how fast rounding-order differences grow.
     ``rhat``: a fixed shadow vector in place of r_0 (not in the paper; see
     krylov.pipelined_bicgstab), stored in the storage precision.
+    ``rr_nv``: a replacement also recomputes n_i and v_i from the replaced
+    z_i (not in the paper; see krylov.pipelined_bicgstab), with the
+    storage-type PREC and SPMV of the iteration.
     Returns a ``krylov.SolveResult`` (x in FP64)."""
     S = np.dtype(store).type
     f64 = np.float64
@@ -169,6 +172,9 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
                (rr_period > 0 and (i + 1) % rr_period == 0 and rn >= tau * rn0))
         if due:
             r, k, w, s, l, z = replace(x, g)
+            if rr_nv:
+                nv = prec(z)
+                v = spmv(nv)
             res.replacements += 1
             res.rr_iters.append(i)
             replaced = True
@@ -199,6 +205,9 @@ def pipelined_bicgstab_lowprec(A, b, *, jacobi=False, store=np.float32, x0=None,
                 st = "CONVERGED" if tr <= tol * nb else "TRUE_RES_NOT_MET"
                 return _done(res, x, STATUS[st], i + 1, A_w, b)
             r, k, w, s, l, z = replace(x, g)           # confirmation failed: replace, go on
+            if rr_nv:
+                nv = prec(z)
+                v = spmv(nv)
             forced += 1
             res.replacements += 1
             res.rr_iters.append(i)

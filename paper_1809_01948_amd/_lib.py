@@ -70,7 +70,7 @@ class Opts(ctypes.Structure):
         ("bound_state", _P),
         ("bound_state_len", _c.c_int64),
         ("single_kernel", _c.c_int32),
-        ("pad1_", _c.c_int32),
+        ("rr_nv", _c.c_int32),
     ]
 
 

@@ -737,7 +737,8 @@ bool enqueue_iteration(Solver& S, bool tr, int i, const pbcg_opts& o, hipStream_
   launch_phaseB(S, tr, pending, st);
   if (o.rr_auto || (o.rr_period > 0 && (i + 1) % o.rr_period == 0)) {
     launch_rr1(S, tr, false, st);      // predicated on the device (eq:criterion or the period)
-    launch_rr2(S, tr, false, st);
+    launch_rr2(S, tr, false, st, true, !o.rr_nv);
+    if (o.rr_nv) launch_rr3(S, tr, false, st);
   }
   if (!fused) launch_iter_spmv(S, tr, V_W, V_T, FIN_BETA, st);
   else if (!defer) launch_fin(S, FIN_BETA, st);
@@ -762,7 +763,7 @@ hipGraphExec_t chunk_graph(Solver& S, bool tr, int start, int len, const pbcg_op
                           std::to_string(len) + "/" +
                           std::to_string(off) + "/" + std::to_string(o.rr_period) + "/" +
                           std::to_string(o.gap_every > 0 ? start % o.gap_every : 0) + "/" +
-                          std::to_string(o.gap_every);
+                          std::to_string(o.gap_every) + "/" + std::to_string(o.rr_nv ? 1 : 0);
   auto it = S.graphs.find(key);
   if (it != S.graphs.end()) return it->second;
   hipGraph_t g = nullptr;
@@ -882,7 +883,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
     hipck(hipGetLastError(), "single-kernel solve launch");
     const double trn = true_residual(S, tr);
     const DevScalars d = read_scalars(S);
-    const int spmvs = 3 + 2 * d.iter + 4 * d.rr_count + 1;
+    const int spmvs = 3 + 2 * d.iter + (o.rr_nv ? 5 : 4) * d.rr_count + 1;
     end_solve(S, x, cs);
     const int rc = finish_stats(S, tr, d, d.status, st, trn, spmvs);
     if (st) {
@@ -961,7 +962,8 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
     const bool save_z = d.n_saved == 0;
     launch_set_done(S, RUNNING, S.s1);
     launch_rr1(S, tr, true, S.s1);
-    launch_rr2(S, tr, true, S.s1, save_z);
+    launch_rr2(S, tr, true, S.s1, save_z, !o.rr_nv);
+    if (o.rr_nv) launch_rr3(S, tr, true, S.s1);
     launch_spmv(S, tr, S.vec[V_W], S.vec[V_T], FIN_REDO, false, S.s1);
     launch_bound_products(S, S.s1);
     hipck(hipGetLastError(), "replacement launch");
@@ -978,7 +980,7 @@ int solve_pipelined(Solver& S, const double* b, double* x, const pbcg_opts& o, p
   }
   trn = true_residual(S, tr);
   d = read_scalars(S);
-  const int spmvs = 3 * (1 + restarts) + 2 * d.iter + 4 * d.rr_count + 1;
+  const int spmvs = 3 * (1 + restarts) + 2 * d.iter + (o.rr_nv ? 5 : 4) * d.rr_count + 1;
   end_solve(S, x, cs);
   const int rc = finish_stats(S, tr, d, status, st, trn, spmvs);
   if (st) st->restarts = restarts;

@@ -411,8 +411,11 @@ __global__ __launch_bounds__(kBlock) void k_rr1(Op op, const double* __restrict_
 // quantities of eq:rr are), and v_i = A n_i keeps its value; so the
 // pre-replacement z_i is kept in `zsave` for the next phase A, which forms
 // n_i from it (`save_z` = 0 when an earlier replacement of the same iteration
-// has saved it already).  With `pm`, also M^-1 w (dinv a vector) for the next
-// product.  Also the partial of ||z||^2 for the automated bound.
+// has saved it already).  With `keep_n` = 0 (option rr_nv, outside the
+// paper) n_i and v_i are refreshed from the replaced z_i instead (k_rr3):
+// nothing is saved and the next phase A forms n_i from z_i.  With `pm`, also
+// M^-1 w (dinv a vector) for the next product.  Also the partial of ||z||^2
+// for the automated bound.
 template <typename T, int PC, class Op>
 __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, const T* __restrict__ l,
                                                 T* __restrict__ w, T* __restrict__ z,
@@ -422,9 +425,9 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
                                                 const T* __restrict__ s, int64_t n, int64_t ntiles,
                                                 int nwork, DevScalars* __restrict__ sc,
                                                 double* __restrict__ partials, int force,
-                                                int npart, int save_z) {
+                                                int npart, int save_z, int keep_n) {
   if (!force && !rr_due(sc)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc->n_saved = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && keep_n) sc->n_saved = 1;
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (XcdWalk wk(ntiles, blockIdx.x, nwork); wk.t < wk.end; wk.t += wk.step) {
     const int64_t i = wk.t * kBlock + threadIdx.x;
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
       op.row(i, vis);
       const T wi = (T)vis.sx;
       const T zi = (T)vis.sy;
-      if (save_z) zsave[i] = z[i];
+      if (save_z && keep_n) zsave[i] = z[i];
       w[i] = wi;
       z[i] = zi;
       if (pm) pm[i] = dinv[i] * wi;
@@ -449,6 +452,26 @@ __global__ __launch_bounds__(kBlock) void k_rr2(Op op, const T* __restrict__ k, 
   const int slots[6] = {SL_RR0, SL_RW0, SL_RS0, SL_RZ0, SL_RR, SL_RZ2};
   block_partials<6>(acc, slots, partials, blockIdx.x);
   zero_partials<6>(slots, partials, npart);
+}
+
+// Option rr_nv (outside the paper): after a replacement, v_i = A M^-1 z_i
+// from the replaced z_i, so that the next iteration's l and z recurrences
+// use n_i = M^-1 z_i and v_i = A n_i of the same z_i (the next phase A forms
+// n_i from z_i itself).  Predicated like k_rr1 and k_rr2.
+template <typename T, int PC, class Op>
+__global__ __launch_bounds__(kBlock) void k_rr3(Op op, const T* __restrict__ z, T* __restrict__ v,
+                                                const T* __restrict__ dinv, T ds, int64_t n,
+                                                int64_t ntiles, int nwork,
+                                                const DevScalars* __restrict__ sc, int force) {
+  if (!force && !rr_due(sc)) return;
+  for (XcdWalk wk(ntiles, blockIdx.x, nwork); wk.t < wk.end; wk.t += wk.step) {
+    const int64_t i = wk.t * kBlock + threadIdx.x;
+    if (i < n) {
+      SpmvVis<T, PC> vis{z, dinv, ds, T(0)};
+      op.row(i, vis);
+      v[i] = vis.sum;
+    }
+  }
 }
 
 // partial of ||b - A x||^2 (FP64)
@@ -1027,14 +1050,24 @@ void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st) {
   });
 }
 
-void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z) {
+void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z, bool keep_n) {
   with_op(S, tr, false, [&]<typename T, int PC, class Op>(const Op& op) {
     const int g = rr_grid(S);
     hipLaunchKernelGGL((k_rr2<T, PC, Op>), dim3(g), dim3(kBlock), 0, st, op, (const T*)S.vec[V_K],
                        (const T*)S.vec[V_L], (T*)S.vec[V_W], (T*)S.vec[V_Z], (T*)S.vec[V_TMP],
                        pre_multiplied(S, tr) ? (T*)S.vec[V_PM] : (T*)nullptr,
                        (const T*)S.dinv, (const T*)S.vec[V_RHAT], (const T*)S.vec[V_R], (const T*)S.vec[V_S], S.n,
-                       S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk, save_z ? 1 : 0);
+                       S.rtiles, g, S.sc, S.partials, force ? 1 : 0, S.nblk, save_z ? 1 : 0,
+                       keep_n ? 1 : 0);
+  });
+}
+
+void launch_rr3(Solver& S, bool tr, bool force, hipStream_t st) {
+  with_op(S, tr, true, [&]<typename T, int PC, class Op>(const Op& op) {
+    const int g = rr_grid(S);
+    hipLaunchKernelGGL((k_rr3<T, PC, Op>), dim3(g), dim3(kBlock), 0, st, op, (const T*)S.vec[V_Z],
+                       (T*)S.vec[V_V], (const T*)S.dinv, (T)S.dinv_s, S.n, S.rtiles, g, S.sc,
+                       force ? 1 : 0);
   });
 }
 
@@ -1228,6 +1261,7 @@ struct SmallArgs {
   double* out[11];           // r^, r, g, s, l, z, k, w, t, v, saved z: written back at the end
   double tol, tau;
   int maxit, rr_period;
+  int rr_nv;                 // a replacement also refreshes n = M^-1 z and v = A n
   double* history;
   int hist_len;
   DevScalars* sc;
@@ -1460,7 +1494,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
       if (own[j]) {
         Res2Vis<double, double, double> vis{pk, pl, 0.0, 0.0};
         visit(j, vis);
-        if (save_z) zs[j] = z[j];
+        if (save_z && !a.rr_nv) zs[j] = z[j];
         w[j] = vis.sx;
         z[j] = vis.sy;
         m[j] = prec(j, w[j]);
@@ -1470,10 +1504,23 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
         d[2] += rh[j] * s[j];
         d[3] += rh[j] * z[j];
         d[4] += r[j] * r[j];
+        if (a.rr_nv) {
+          n[j] = prec(j, z[j]);
+          nz[row[j]] = n[j];
+        }
       }
     }
     rr_count += 1;
-    n_saved = 1;
+    n_saved = a.rr_nv ? 0 : 1;
+    if (a.rr_nv) {
+      // option rr_nv: v = A M^-1 z from the replaced z (the product reads the
+      // rows of nz written above; the last reader of nz, the v product of this
+      // iteration, is behind the barriers at the top)
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < RPT; ++j)
+        if (own[j]) v[j] = product(j, nz);
+    }
   };
 
   while (status < 0) {
@@ -1660,6 +1707,7 @@ bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_
   a.tau = o.rr_tau > 0 ? o.rr_tau : std::sqrt(std::ldexp(1.0, -53));
   a.maxit = o.maxit;
   a.rr_period = o.rr_period;
+  a.rr_nv = o.rr_nv ? 1 : 0;
   a.history = o.history;
   a.hist_len = o.history ? o.history_len : 0;
   a.sc = S.sc;

@@ -105,7 +105,8 @@ struct Solver {
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
 
-  // captured iteration chunks: key = (transpose, chunk length, start offset mod P, P)
+  // captured iteration chunks: key = (transpose, automated mode, chunk length, start offset
+  // mod P, P, gap offset and period, n/v refresh on replacement)
   std::map<std::string, hipGraphExec_t> graphs;
 };
 
@@ -174,7 +175,10 @@ bool pre_multiplied(Solver& S, bool transpose);
 // the iteration's product on z (V_Z -> V_V) or w (V_W -> V_T)
 void launch_iter_spmv(Solver& S, bool tr, int in_vec, int out_vec, int fin_mode, hipStream_t st);
 void launch_rr1(Solver& S, bool tr, bool force, hipStream_t st);
-void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z = true);
+void launch_rr2(Solver& S, bool tr, bool force, hipStream_t st, bool save_z = true,
+                bool keep_n = true);
+// option rr_nv: v = A M^-1 z from the replaced z (predicated like rr1, rr2)
+void launch_rr3(Solver& S, bool tr, bool force, hipStream_t st);
 void launch_apply_op(Solver& S, const OpData& o, const double* x, double* y, hipStream_t st);
 bool sell_lds_ok(const Solver& S, const OpData& o);
 void launch_true_res(Solver& S, bool tr, hipStream_t st);

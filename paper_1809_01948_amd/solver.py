@@ -167,7 +167,7 @@ class Solver:
     # ---- solves ---------------------------------------------------------
     def _opts(self, tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
               gap_history, use_graph, rr_auto=False, rr_eps=0.0, bound_history=None,
-              restarts=0, single_kernel=False):
+              restarts=0, single_kernel=False, rr_nv=False):
         o = L.Opts()
         L.load().pbicgstab_default_opts(ctypes.byref(o))
         o.tol = tol
@@ -203,6 +203,7 @@ class Solver:
             o.bound_len = bound_history.numel()
         o.restarts = restarts
         o.single_kernel = 1 if single_kernel else 0
+        o.rr_nv = 1 if rr_nv else 0
         return o
 
     def solve(self, b: torch.Tensor, x0: Optional[torch.Tensor] = None, *, tol=1e-10,
@@ -211,7 +212,7 @@ class Solver:
               gap_history: Optional[torch.Tensor] = None, use_graph=False,
               method="pipelined", out: Optional[torch.Tensor] = None, rr_auto=False,
               rr_eps=0.0, bound_history: Optional[torch.Tensor] = None, restarts=0,
-              rhat: Optional[torch.Tensor] = None, single_kernel=False):
+              rhat: Optional[torch.Tensor] = None, single_kernel=False, rr_nv=False):
         """Solve A x = b (A^T x = b with transpose).  Returns (x, stats dict).
 
         method: 'pipelined' (Algorithm 2 with residual replacement: every
@@ -224,7 +225,9 @@ class Solver:
         (not in the paper; None keeps r_0).  ``single_kernel``: run the whole
         solve as one kernel in one workgroup when the system allows it (FP64,
         at most 1024 rows, periodic or no replacement; stats
-        ``single_kernel`` says whether it did)."""
+        ``single_kernel`` says whether it did).  ``rr_nv``: every replacement
+        also recomputes n = M^-1 z and v = A n from the replaced z (not in the
+        paper, which replaces the six quantities of eq:rr only)."""
         lib = L.load()
         b = _dev_vec(b, self.n, "b")
         rhat = None if rhat is None else _dev_vec(rhat, self.n, "rhat")
@@ -238,7 +241,7 @@ class Solver:
                 raise TypeError(f"{nm} must be a contiguous CUDA float64 tensor")
         o = self._opts(tol, maxit, rr_period, rr_tau, check_every, transpose, history, gap_every,
                        gap_history, use_graph, rr_auto, rr_eps, bound_history, restarts,
-                       single_kernel)
+                       single_kernel, rr_nv)
         if rhat is not None:
             o.rhat = rhat.data_ptr()
         state = None

@@ -374,14 +374,33 @@ def test_c5_full_size_forward_adjoint_classic(Solver):
     option outside the paper): with r_0 = b = h^2 1 the operator's vanishing
     interior column sums drive (r_0, r_i) to zero long before r_i (a
     rho' = 0 breakdown or a stall above the tolerance).  Pipelined BiCGStab
-    does not reach 1e-6 at this size with either shadow vector: without
-    replacement its residual gap stalls the true residual, and every
-    replacement variant ends in a breakdown (the oracle shows the same trend
-    on the 1024^2 instance)."""
+    with the six quantities of eq:rr does not reach 1e-6 at this size with
+    either shadow vector: without replacement its residual gap stalls the
+    true residual, and every replacement variant ends in a breakdown (the
+    oracle shows the same trend on the 1024^2 instance); with the n/v
+    refresh it converges (test_c5_full_size_forward_adjoint_pipelined_nv)."""
     import torch
     n = 2048
     rh = torch.from_numpy(np.random.default_rng(56).standard_normal(n * n)).cuda()
     gd, fd = _kappa_fd_check(Solver, n, dict(tol=1e-7, maxit=30000, method="classic", rhat=rh))
+    assert abs(fd - gd) <= 1e-2 * abs(gd)
+
+
+def test_c5_full_size_forward_adjoint_pipelined_nv(Solver):
+    """The 2048^2 coefficient-field workflow with pipelined BiCGStab:
+    replacement every 200 iterations with the n/v refresh (pbcg_opts.rr_nv)
+    and a random fixed shadow vector (both options outside the paper),
+    forward + adjoint to a 1e-7 relative residual, dL/dkappa along a random
+    direction against central differences.  With the six quantities of
+    eq:rr alone the forward and adjoint solves break down at every period
+    tried and with the automated criterion; with the refresh the forward
+    solves converge with r_0 too, the adjoint (transposed) solve only with
+    another shadow vector (with r_0 it breaks down, (r_0, r_i) -> 0)."""
+    import torch
+    n = 2048
+    rh = torch.from_numpy(np.random.default_rng(56).standard_normal(n * n)).cuda()
+    gd, fd = _kappa_fd_check(Solver, n, dict(tol=1e-7, maxit=30000, rr_period=200,
+                                             rr_nv=True, rhat=rh))
     assert abs(fd - gd) <= 1e-2 * abs(gd)
 
 
@@ -390,7 +409,8 @@ def test_c5_pipelined_forward_adjoint_256(Solver):
     scaled with the grid) with pipelined BiCGStab and automated residual
     replacement for the forward and the adjoint solves.  From 512^2 on the
     pipelined method's residual gap and rho' = 0 breakdowns stop it on this
-    problem, in the oracle as on the GPU."""
+    problem, in the oracle as on the GPU, unless the replacements also
+    refresh n and v (test_c5_full_size_forward_adjoint_pipelined_nv)."""
     gd, fd = _kappa_fd_check(Solver, 256, dict(tol=1e-6, maxit=30000, rr_auto=True))
     assert abs(fd - gd) <= 1e-2 * abs(gd)
 

@@ -21,7 +21,7 @@ import scipy.sparse.linalg as spla
 
 from oracle import (STATUS, ExactOps, Float64Ops, classic_bicgstab,
                     pipelined_bicgstab, unit_roundoff)
-from workloads import (Stencil, convdiff2d_c1, random_dense_system,
+from workloads import (Stencil, convdiff2d_c1, inverse_problem_c5, random_dense_system,
                        stencil_to_csr)
 
 
@@ -119,6 +119,66 @@ def test_exact_classic_equals_pipelined(case):
     assert rr.replacements >= 2
     assert list(rr.x) == list(rp.x)
     assert rr.alpha == rp.alpha and rr.omega == rp.omega
+
+
+@pytest.mark.parametrize("case", ["dense6", "stencil4x4"])
+def test_exact_replacement_with_nv_refresh_is_a_no_op(case):
+    """Option outside the paper (rr_nv): a replacement that also recomputes
+    n_i = M^-1 z_i and v_i = A n_i from the replaced z_i leaves exact iterates
+    unchanged, as eq:rr's six quantities alone do (on exact iterates every
+    recomputed quantity equals its recurrence); a refresh from a wrong
+    vector (z without M^-1, or the previous iteration's z) would not."""
+    A, b, dinv, xex = _exact_case(case)
+    its = 6 if case == "dense6" else 5
+    ops = ExactOps(A, dinv)
+    rp = pipelined_bicgstab(ops, b, tol=0.0, maxit=its)
+    rr = pipelined_bicgstab(ops, b, tol=0.0, maxit=its, rr_period=2, rr_tau=0.0, rr_nv=True)
+    assert rr.replacements >= 2
+    assert list(rr.x) == list(rp.x)
+    assert rr.alpha == rp.alpha and rr.omega == rp.omega and rr.beta == rp.beta
+
+
+def test_nv_refresh_values():
+    """With rr_nv the n and v that the next iteration uses are M^-1 and
+    A M^-1 of the replaced z (FP64, the oracle's own PREC and SPMV)."""
+    p = convdiff2d_c1(10)
+    A = p.scipy_csr()
+    dinv = 1.0 / A.diagonal()
+    ops = Float64Ops(A, dinv)
+    res = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=12, rr_period=4, rr_tau=0.0,
+                             rr_nv=True, record=True)
+    reps = [sn["rep"] for sn in res.snapshots if sn["replaced"]]
+    assert len(reps) == 3
+    for rep in reps:
+        assert np.array_equal(rep["n"], dinv * rep["z"])
+        assert np.array_equal(rep["v"], A @ rep["n"])
+    # without the option n, v stay those of the recursive z of the iteration
+    lit = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=12, rr_period=4, rr_tau=0.0,
+                             record=True)
+    for sn in lit.snapshots:
+        if sn["replaced"]:
+            assert np.array_equal(sn["rep"]["n"], sn["n"])
+            assert np.array_equal(sn["rep"]["v"], sn["v"])
+            assert not np.array_equal(sn["rep"]["z"], sn["z"])
+
+
+def test_nv_refresh_on_the_coefficient_field_problem():
+    """Observation (FP64 oracle, an option outside the paper): on the 384^2
+    coefficient-field operator with Jacobi and replacement every 50
+    iterations, refreshing n and v at each replacement converges to 1e-6 in
+    under 1000 iterations.  With the six quantities of eq:rr alone the same
+    solve is at the mercy of rounding here (v_i = A M^-1 z_i of the
+    recursive z_i enters the next z recurrence beside the replaced z_i, an
+    error of |beta omega| ||A M^-1 (z_replaced - z_i)|| injected at every
+    replacement): it stalls at 3e-3 after 1200 iterations with one BLAS
+    summation order and converges with another; at 512^2 it diverges, and on
+    the GPU at 2048^2 it breaks down at every period."""
+    p = inverse_problem_c5(384, with_csr=True)
+    A = p.scipy_csr()
+    ops = Float64Ops(A, 1.0 / A.diagonal())
+    nv = pipelined_bicgstab(ops, p.b, tol=1e-6, maxit=1200, rr_period=50, rr_nv=True)
+    assert nv.status == STATUS["CONVERGED"] and nv.iterations < 1000
+    assert np.linalg.norm(p.b - A @ nv.x) <= 1e-6 * np.linalg.norm(p.b)
 
 
 def test_exact_finite_termination():
