@@ -586,8 +586,10 @@ def c5_full_size(dev):
     Classic BiCGStab and p-BiCGStab with automated replacement, each with the
     paper's shadow residual r_0 and with a random fixed shadow vector (an
     option outside the paper: with b = h^2 1 the operator's vanishing
-    interior column sums drive (r_0, r_i) to zero).  Reported, not asserted:
-    p-BiCGStab breaks down on this operator at full size."""
+    interior column sums drive (r_0, r_i) to zero), and p-BiCGStab with
+    periodic replacement that also refreshes n and v (rr_nv, another option
+    outside the paper).  Reported, not asserted: with the six quantities of
+    eq:rr alone p-BiCGStab breaks down on this operator at full size."""
     import torch
     from paper_1809_01948_amd.solver import Solver
     from workloads import dia5_from_kappa, inverse_problem_c5
@@ -603,7 +605,10 @@ def c5_full_size(dev):
     for name, kw in (("classic_r0", dict(method="classic", tol=1e-6)),
                      ("pipelined_auto_r0", dict(rr_auto=True, tol=1e-6)),
                      ("classic_random_shadow", dict(method="classic", tol=1e-7, rhat=rh)),
-                     ("pipelined_auto_random_shadow", dict(rr_auto=True, tol=1e-6, rhat=rh))):
+                     ("pipelined_auto_random_shadow", dict(rr_auto=True, tol=1e-6, rhat=rh)),
+                     ("pipelined_rr50_nv_r0", dict(rr_period=50, rr_nv=True, tol=1e-6)),
+                     ("pipelined_rr200_nv_random_shadow",
+                      dict(rr_period=200, rr_nv=True, tol=1e-7, rhat=rh))):
         ut, st_t, s_t = solve_timed(S_t, b, maxit=20000, **kw)
         u, st_f, s_f = solve_timed(S, b, maxit=20000, **kw)
         g = 2.0 * (u - ut)
