@@ -437,7 +437,11 @@ def paper_problems(dev):
         # options outside the paper: the bound's square-root estimate in the
         # products reading, with a random fixed shadow vector
         ("p-BiCGStab_auto_products_estimate_random_shadow",
-         dict(rr_auto="products-estimate", rhat=rh), ks)])
+         dict(rr_auto="products-estimate", rhat=rh), ks),
+        # another option outside the paper: every replacement also refreshes
+        # n = M^-1 z and v = A n from the replaced z (with the paper's r_0)
+        ("p-BiCGStab_rr100_nv", dict(rr_period=100, rr_nv=True), ks),
+        ("p-BiCGStab_auto_estimate_nv", dict(rr_auto="estimate", rr_nv=True), ks)])
     S.close()
     p = tp3_helmholtz(500)
     S = Solver.from_problem(p, form="stencil", precond="none")
@@ -446,7 +450,8 @@ def paper_problems(dev):
     res["TP3_500x500"] = accuracy_vs_time(S, b, [
         ("classic", dict(method="classic"), ks),
         ("p-BiCGStab", dict(), ks),
-        ("p-BiCGStab_rr200", dict(rr_period=200), ks)])
+        ("p-BiCGStab_rr200", dict(rr_period=200), ks),
+        ("p-BiCGStab_rr200_nv", dict(rr_period=200, rr_nv=True), ks)])
     S.close()
     res["note"] = ("the paper's TP2/TP3 (Table tab:specs, ||A||_2 = 1, b = A 1/sqrt(N), no "
                    "preconditioner, FP64); paper (120 ranks): TP2 classic ~1e-13 at ~600 "

@@ -381,6 +381,27 @@ def test_automated_replacement_paper_tp2():
     assert max(res.rr_iters[:-1]) < 150
 
 
+@pytest.mark.parametrize("reading", ["nested", "products"])
+@pytest.mark.parametrize("estimate", [False, True], ids=["bound", "estimate"])
+def test_automated_replacement_tp2_with_nv_refresh(reading, estimate):
+    """TP2 200^2 with the automated criterion in every variant (both
+    readings of eq:DDr_bound, worst case and square-root estimate) when each
+    replacement also refreshes n and v (rr_nv, an option outside the paper):
+    every variant reaches 1e-13 with a handful of replacements, as Section
+    4.5 reports (about ten); with the six quantities of eq:rr alone the
+    products reading breaks down here (rho' = 0 after ~940 and ~1,560
+    iterations, one BLAS thread), and at 1000^2 every variant fails, while
+    with the refresh all four converge there too (589-846 iterations, 8-21
+    replacements, 4.8e-14-9.7e-14)."""
+    from workloads import tp2_unsymmetric
+    p = tp2_unsymmetric(200)
+    ops = Float64Ops(p.scipy_csr())
+    res = pipelined_bicgstab(ops, p.b, tol=1e-13, maxit=3000, rr_mode="auto",
+                             rr_estimate=estimate, rr_reading=reading, rr_nv=True)
+    assert res.status == STATUS["CONVERGED"] and res.true_rel_res <= 1e-13
+    assert 3 <= res.replacements <= 30
+
+
 _BD_A = np.array([[-2.0, -2.0, -2.0], [-2.0, -2.0, -1.0], [-2.0, 2.0, -1.0]])
 _BD_B = np.array([0.0, -1.0, 0.0])
 
