@@ -1219,23 +1219,24 @@ void launch_dia5_transpose(Solver& S, hipStream_t st) {
 // ----------------------------------------------------------------------------
 //
 // A solve of a few hundred rows is bound by kernel launches and host polls,
-// not by memory.  For N <= kSmallRows (FP64) one block of kSmallRows threads
-// holds the iteration vectors (row i in the registers of thread i; the
-// inputs of the products, whose neighbours' entries are read, also in LDS)
-// and runs Algorithm 2 to its end in one launch: phase A and phase B with the
-// expressions of k_phaseA / k_phaseB, the products through the operator's
-// own row visitor (the same terms in the same order), periodic residual
-// replacement (eq:rr) in FP64 with the saved pre-replacement z, and the
+// not by memory.  For N <= kSmallRows (FP64) one block of kSmallRows / RPT
+// threads (RPT rows per thread) holds the iteration vectors (the rows of a
+// thread in its registers; the inputs of the products, whose neighbours'
+// entries are read, also in LDS) and runs Algorithm 2 to its end in one
+// launch: phase A and phase B with the expressions of k_phaseA / k_phaseB,
+// the products through the operator's own row visitor (the same terms in
+// the same order), periodic residual replacement (eq:rr) in FP64 with the
+// saved pre-replacement z (or with n and v refreshed, option rr_nv), and the
 // termination rule: true-residual confirmation, at most three forced
 // replacements, no tolerance test right after one.
 //
 // Two barriers per iteration.  Each global reduction stores one partial per
-// wave (an xor butterfly over the wave) before a barrier that the iteration
-// needs anyway, and after it every wave adds the 16 partials with the same
-// 16-lane butterfly, so every thread holds the same bits without a second
-// barrier; the two products read M^-1 z and M^-1 w from arrays of their own,
-// which the following phase does not write.  A sliced-ELL row of at most
-// kSmallCache stored entries is held in registers for the whole solve.
+// wave (wave_sums_packed) before a barrier that the iteration needs anyway,
+// and after it every wave adds the partials with the same moves, so every
+// thread holds the same bits without a second barrier; the two products
+// read M^-1 z and M^-1 w from arrays of their own, which the following
+// phase does not write.  A sliced-ELL row of at most kSmallCache stored
+// entries is held in registers for the whole solve.
 
 constexpr int kSmallRows = 1024;
 constexpr int kSmallWaves = kSmallRows / 64;
