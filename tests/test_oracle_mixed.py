@@ -25,17 +25,20 @@ def _cases():
 
 
 @pytest.mark.parametrize("name,p,jacobi", _cases(), ids=[c[0] for c in _cases()])
-@pytest.mark.parametrize("mode", ["periodic", "auto", "auto-products"])
+@pytest.mark.parametrize("mode", ["periodic", "auto", "auto-products", "periodic-nv",
+                                  "auto-nv"])
 def test_float64_storage_is_the_fp64_oracle(name, p, jacobi, mode):
     A = p.scipy_csr()
     ops = Float64Ops(A, 1.0 / A.diagonal() if jacobi else None)
     kw = dict(tol=1e-12, maxit=300)
-    if mode == "periodic":
+    if mode.startswith("periodic"):
         kw["rr_period"] = 7
     else:
         kw["rr_mode"] = "auto"
         if mode == "auto-products":
             kw["rr_reading"] = "products"
+    if mode.endswith("-nv"):
+        kw["rr_nv"] = True              # the n/v refresh (an option outside the paper)
     ref = pipelined_bicgstab(ops, p.b, **kw)
     got = pipelined_bicgstab_lowprec(A, p.b, jacobi=jacobi, store=np.float64, **kw)
     assert got.status == ref.status and got.iterations == ref.iterations
