@@ -10,7 +10,8 @@ outside the paper) on the GPU against the oracle with the same option.
   the phase kernels), DIA5 (fused), the 3D stencil (plane-marching product),
   and the single-workgroup solve.
 * After a replacement in the last iteration the stored v is A M^-1 of the
-  stored (replaced) z.
+  stored (replaced) z; also for the transposed (adjoint) solve, against the
+  oracle on A^T.
 * FP32 storage: the stored vectors bit for bit after the refresh and a few
   more iterations, and the trace over its horizon (the FP32 oracle with two
   summation orders of the dot products).
@@ -103,6 +104,39 @@ def test_nv_refresh_trace(Solver, name, make, form, pc, single):
     # and it is the oracle's refreshed v (z agrees to the trace's accuracy)
     rep = ref.snapshots[-1]["rep"]
     assert np.max(np.abs(v - rep["v"])) <= 1e-9 * np.max(np.abs(rep["v"]))
+    S.close()
+
+
+@pytest.mark.parametrize("name,make,form", [
+    ("c1-csr-jacobi", lambda: convdiff2d_c1(32), "csr"),
+    ("dia5-48", lambda: inverse_problem_c5(48, sigma=1.0, with_csr=True), "dia5")],
+    ids=["c1-csr-jacobi", "dia5-48"])
+def test_nv_refresh_transposed_trace(Solver, name, make, form):
+    """The adjoint solve A^T x = b with the refresh against the oracle on
+    A^T (same Jacobi diagonal), replacement every 4 iterations."""
+    import scipy.sparse as sp
+    p = make()
+    A = sp.csr_matrix(p.scipy_csr().T)
+    dinv = 1.0 / A.diagonal()
+    kw = dict(rr_period=4, rr_tau=0.0, rr_nv=True)
+    k = _horizon(A, p.b, dinv, kw)
+    k -= k % 4
+    assert k >= 4
+    print(f"{name} transposed: trace horizon {k} iterations", flush=True)
+    ref = pipelined_bicgstab(Float64Ops(A, dinv), p.b, tol=0.0, maxit=k, **kw)
+    S = Solver.from_problem(p, form=form, precond="jacobi")
+    hist = history_buffer(k)
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, history=hist, rr_period=4, rr_tau=1e-300,
+                    rr_nv=True, transpose=True)
+    assert st["iterations"] == k and st["replacements"] == ref.replacements == k // 4
+    rn, al, om, be = split_history(hist, k)
+    assert np.all(rel(al, ref.alpha) <= 1e-10)
+    assert np.all(rel(om, ref.omega) <= 1e-10)
+    assert np.all(rel(rn, ref.rnorm) <= 1e-10)
+    z = host(S.get_vector("z"))
+    v = host(S.get_vector("v"))
+    want = A @ (dinv * z)
+    assert np.max(np.abs(v - want)) <= 1e-13 * np.max(np.abs(want))
     S.close()
 
 
