@@ -465,8 +465,8 @@ def c1_latency(dev):
     """32^2 convection-diffusion (N = 1024): launch-bound; iterations per
     second of full solves to 1e-10, classic (Algorithm 1, 7 launches per
     iteration), pipelined (Algorithm 2 from HIP graphs) and pipelined as one
-    kernel in one workgroup (every vector in LDS, no launches or host polls
-    inside the solve)."""
+    kernel in one workgroup (no launches or host polls inside the solve);
+    without replacement, every 50 iterations and the automated strategy."""
     import torch
     from paper_1809_01948_amd.solver import Solver
     from workloads import convdiff2d_c1
@@ -478,9 +478,12 @@ def c1_latency(dev):
         for name, kw in (("classic", dict(method="classic")),
                          ("pipelined_graph", dict(use_graph=True)),
                          ("pipelined_rr50_graph", dict(use_graph=True, rr_period=50)),
+                         ("pipelined_auto_graph", dict(use_graph=True, rr_auto=True)),
                          ("pipelined_single_kernel", dict(single_kernel=True)),
                          ("pipelined_rr50_single_kernel", dict(single_kernel=True,
-                                                               rr_period=50))):
+                                                               rr_period=50)),
+                         ("pipelined_auto_single_kernel", dict(single_kernel=True,
+                                                               rr_auto=True))):
             S.solve(b, tol=1e-10, maxit=2000, **kw)
             ts, its = [], 0
             for _ in range(20):

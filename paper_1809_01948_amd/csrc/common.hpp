@@ -84,6 +84,7 @@ enum Status : int {
 // first, in one 64-byte line: a kernel that tests `done` and then reads the
 // scalars finds them in the line the test has already brought in.
 struct alignas(64) DevScalars {
+  static constexpr bool kProducts = true;   // carries the products reading's state
   int32_t done;                    // Done
   int32_t n_saved;                 // 1: the iteration's pre-replacement z is in the spare vector
   int32_t rr_auto;                 // 1: automated replacement strategy instead of the period

@@ -1249,8 +1249,11 @@ enum : int {
   SB_COUNT
 };
 constexpr size_t kSmallLds = (size_t)SB_COUNT * kSmallRows * sizeof(double);
-constexpr int kSmallRed = 3;          // partial buffers: GLRED 1, GLRED 2, the others
-constexpr size_t kSmallStatic = (size_t)kSmallRed * 5 * kSmallWaves * sizeof(double);
+constexpr int kSmallRed = 4;          // partial buffers: GLRED 1, GLRED 2, the others, and
+                                      // GLRED 1 of odd iterations (automated strategy)
+constexpr int kSmallSums = 14;        // sums per buffer (automated strategy: GLRED 2 with the
+                                      // norms of phase B and of a replacement)
+constexpr size_t kSmallStatic = (size_t)kSmallRed * kSmallSums * kSmallWaves * sizeof(double);
 
 struct SmallArgs {
   int n;
@@ -1265,7 +1268,9 @@ struct SmallArgs {
   int rr_nv;                 // a replacement also refreshes n = M^-1 z and v = A n
   double* history;
   int hist_len;
-  DevScalars* sc;
+  double* bound_history;     // automated strategy: f^r per iteration, or null
+  int bound_len;
+  DevScalars* sc;            // the solve's scalars (the bound's constants are read from it)
 };
 
 // Workgroup sums of the single-workgroup solve: the packed wave sums of
@@ -1347,12 +1352,21 @@ __device__ __forceinline__ void sell_row_serial(const SellOp<double>& op, int i,
 }
 
 // RPT rows per thread: rows tid, tid + T, ... (T = kSmallRows / RPT threads),
-// so that a wave's lanes hold consecutive rows.
-template <int PC, class Op, bool CACHE, int RPT>
+// so that a wave's lanes hold consecutive rows.  AUTO: the automated strategy
+// (Section 3.6, nested reading: the worst-case bound or the estimate); the
+// reductions carry the norms of the bound (phase A ten, phase B four, a
+// replacement five), and every thread advances the same bound state
+// (GapState) from the same totals, so eq:criterion needs no broadcast.
+template <int PC, class Op, bool CACHE, int RPT, bool AUTO>
 __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallArgs a) {
   constexpr int T = kSmallRows / RPT;
+  constexpr int NI = AUTO ? 6 : 4;    // sums of the initialisation
+  constexpr int NA = AUTO ? 12 : 2;   // GLRED 1 (+ norms)
+  constexpr int NB = AUTO ? 9 : 5;    // GLRED 2 (+ norms of phase B)
+  constexpr int NR = AUTO ? 14 : 5;   // GLRED 2 after a replacement (+ its norms)
+  static_assert(NR <= kSmallSums && NA <= kSmallSums, "partial buffers");
   extern __shared__ double sm[];
-  __shared__ double red[kSmallRed][5][kSmallWaves];
+  __shared__ double red[kSmallRed][kSmallSums][kSmallWaves];
   double* const nz = sm + SB_NZ * kSmallRows;
   double* const mw = sm + SB_MW * kSmallRows;
   double* const px = sm + SB_PX * kSmallRows;
@@ -1413,7 +1427,9 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     }
   }
   __syncthreads();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[NI];
+#pragma unroll
+  for (int e = 0; e < NI; ++e) acc[e] = 0.0;
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     if (own[j]) {
@@ -1426,6 +1442,10 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
       acc[0] += rh[j] * r[j];
       acc[1] += r[j] * r[j];
       acc[2] += bi[j] * bi[j];
+      if constexpr (AUTO) {
+        acc[4] += x[j] * x[j];
+        acc[5] += k[j] * k[j];
+      }
     }
   }
   __syncthreads();
@@ -1438,12 +1458,12 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
       acc[3] += rh[j] * w[j];
     }
   }
-  small_part<4>(acc, red[2]);
+  small_part<NI>(acc, red[2]);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < RPT; ++j)
     if (own[j]) t[j] = product(j, mw);         // t_0 = A M^-1 w_0
-  small_total<4>(acc, red[2], nw);
+  small_total<NI>(acc, red[2], nw);
   double rho = acc[0];
   const double rn0 = sqrt(acc[1]), nb = sqrt(acc[2]), rw = acc[3];
   double rn = rn0, alpha = 0.0, beta = 0.0, omega = 0.0, omega_prev = 0.0;
@@ -1461,11 +1481,21 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   } else {
     alpha = rho / rw;
   }
+  // the bound of Section 3.2 at the start, and eq:criterion's previous test
+  GapState gs;
+  bool f_ok_prev = false, rr_next = false;
+  if constexpr (AUTO) {
+    gs.load(a.sc);
+    gs.nb = nb;
+    gap_bound_start(&gs, sqrt(acc[4]), sqrt(acc[5]));
+    f_ok_prev = gs.fr <= a.tau * rn0;
+  }
 
-  // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again.  x, g,
+  // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again (with
+  // AUTO also the norms that restart the bound: x, k, l, s, z in d[9..13]).  x, g,
   // then k, l go through LDS arrays of their own (the neighbours' entries);
   // their previous readers are behind at least one barrier.
-  auto replace = [&](bool save_z, double (&d)[5]) {
+  auto replace = [&](bool save_z, double (&d)[NR]) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       if (own[j]) {
@@ -1490,6 +1520,10 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 5; ++e) d[e] = 0.0;
+    if constexpr (AUTO) {
+#pragma unroll
+      for (int e = 9; e < 14; ++e) d[e] = 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       if (own[j]) {
@@ -1505,6 +1539,13 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
         d[2] += rh[j] * s[j];
         d[3] += rh[j] * z[j];
         d[4] += r[j] * r[j];
+        if constexpr (AUTO) {
+          d[9] += x[j] * x[j];
+          d[10] += k[j] * k[j];
+          d[11] += l[j] * l[j];
+          d[12] += s[j] * s[j];
+          d[13] += z[j] * z[j];
+        }
         if (a.rr_nv) {
           n[j] = prec(j, z[j]);
           nz[row[j]] = n[j];
@@ -1524,9 +1565,35 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     }
   };
 
+  // the GLRED 2 sums (after a replacement with its norms), with the product
+  // t_{i+1} = A M^-1 w_{i+1} between the partials and the totals
+  // (the norms' partials stay in red[1]: the bound step sums them)
+  auto glred2_sums = [&](double (&d)[NR], bool replaced) {
+    constexpr int NS = AUTO ? NB : 5;
+    if (replaced && AUTO) {
+      small_part<NR>(d, red[1]);
+    } else {
+      double p[NS];
+#pragma unroll
+      for (int e = 0; e < NS; ++e) p[e] = d[e];
+      small_part<NS>(p, red[1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RPT; ++j)
+      if (own[j]) t[j] = product(j, mw);
+    double g2[5];
+    small_total<5>(g2, red[1], nw);
+#pragma unroll
+    for (int e = 0; e < 5; ++e) d[e] = g2[e];
+  };
+
   while (status < 0) {
-    // phase A: g, s, l, z, M^-1 z and the GLRED 1 terms
-    double d2[2] = {0.0, 0.0};
+    // phase A: g, s, l, z, M^-1 z and the GLRED 1 terms (with AUTO the norms
+    // of k, w, t, m before and of g, s, l, z, q, y after the update)
+    double d2[NA];
+#pragma unroll
+    for (int e = 0; e < NA; ++e) d2[e] = 0.0;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       if (own[j]) {
@@ -1539,31 +1606,59 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
         const double y = w[j] - alpha * zn;
         d2[0] += q * y;
         d2[1] += y * y;
+        if constexpr (AUTO) {
+          d2[2] += k[j] * k[j];
+          d2[3] += w[j] * w[j];
+          d2[4] += t[j] * t[j];
+          d2[5] += m[j] * m[j];
+          d2[6] += gn * gn;
+          d2[7] += sn * sn;
+          d2[8] += ln * ln;
+          d2[9] += zn * zn;
+          d2[10] += q * q;
+          d2[11] += y * y;
+        }
         g[j] = gn; s[j] = sn; l[j] = ln; z[j] = zn;
         n[j] = prec(j, zn);
         nz[row[j]] = n[j];
       }
     }
-    small_part<2>(d2, red[0]);
+    // With AUTO the norms' partials stay in the buffer until the bound step
+    // at the end of the iteration, which no barrier separates from the next
+    // phase A: consecutive iterations use two buffers.
+    double (*const ra)[kSmallWaves] = (AUTO && (iter & 1)) ? red[3] : red[0];
+    small_part<NA>(d2, ra);
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
       if (own[j]) v[j] = product(j, nz);       // v_i = A M^-1 z_i
-    small_total<2>(d2, red[0], nw);            // GLRED 1
+    double g1[2];
+    small_total<2>(g1, ra, nw);                // GLRED 1
+    d2[0] = g1[0];
+    d2[1] = g1[1];
     n_saved = 0;
     if (!finite(d2[0]) || !finite(d2[1])) {
       status = ST_NONFINITE;
       break;
     }
     omega = d2[1] != 0.0 ? d2[0] / d2[1] : 0.0;
-    // phase B: x, r, k, w, M^-1 w and the GLRED 2 terms
-    double d5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // phase B: x, r, k, w, M^-1 w and the GLRED 2 terms (with AUTO the norms
+    // of x before the update, u, n, v in d5[5..8])
+    double d5[NR];
+#pragma unroll
+    for (int e = 0; e < NR; ++e) d5[e] = 0.0;
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       if (own[j]) {
         const double q = r[j] - alpha * s[j];
         const double u = k[j] - alpha * l[j];
         const double y = w[j] - alpha * z[j];
+        if constexpr (AUTO) {
+          d5[5] += x[j] * x[j];
+          d5[6] += u * u;
+          d5[7] += n[j] * n[j];
+          d5[8] += v[j] * v[j];
+        }
         x[j] = (x[j] + alpha * g[j]) + omega * u;
         const double rn_ = q - omega * y;
         const double kn = u - omega * (m[j] - alpha * n[j]);
@@ -1578,20 +1673,43 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
         d5[4] += rn_ * rn_;
       }
     }
-    if (a.rr_period > 0 && (iter + 1) % a.rr_period == 0 && rn >= a.tau * rn0)
-      replace(true, d5);
-    small_part<5>(d5, red[1]);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < RPT; ++j)
-      if (own[j]) t[j] = product(j, mw);       // t_{i+1} = A M^-1 w_{i+1}
-    small_total<5>(d5, red[1], nw);            // GLRED 2
+    // a replacement: eq:criterion's decision of the previous iteration, or the period
+    const bool due = AUTO ? rr_next
+                          : (a.rr_period > 0 && (iter + 1) % a.rr_period == 0 && rn >= a.tau * rn0);
+    if (due) replace(true, d5);
+    glred2_sums(d5, due);                      // GLRED 2
+    bool hit = due;                            // the bound restarts after this step
     const int its = ++iter;
     double* hrow = (a.history && its <= a.hist_len) ? a.history + 4 * (int64_t)(its - 1) : nullptr;
     if (hrow && tid == 0) { hrow[1] = alpha; hrow[2] = omega; hrow[3] = 0.0; }
     bool test_tol = true;
     for (;;) {
-      const G2Step st = glred2_step(d5, alpha, omega, rho, a.tol, nb, test_tol);
+      if constexpr (AUTO) {
+        // the norms from the partials left in ra (phase A) and red[1]
+        // (phase B, a replacement)
+        double na[10];
+        small_total<10>(na, ra + 2, nw);
+        if (test_tol) {                        // the bound step of this iteration
+          double nbv[4];
+          small_total<4>(nbv, red[1] + 5, nw);
+          IterNorms nm;
+          nm.k = sqrt(na[0]); nm.w = sqrt(na[1]); nm.t = sqrt(na[2]); nm.m = sqrt(na[3]);
+          nm.g = sqrt(na[4]); nm.s = sqrt(na[5]); nm.l = sqrt(na[6]); nm.z = sqrt(na[7]);
+          nm.q = sqrt(na[8]); nm.y = sqrt(na[9]); nm.x = sqrt(nbv[0]); nm.u = sqrt(nbv[1]);
+          nm.n = sqrt(nbv[2]); nm.v = sqrt(nbv[3]); nm.r = rn;
+          gap_bound_step(&gs, alpha, beta, omega, omega_prev, nm);
+        }
+        if (hit) {
+          double nr[5];
+          small_total<5>(nr, red[1] + 9, nw);
+          gap_bound_reset(&gs, sqrt(nr[0]), sqrt(nr[1]), sqrt(na[4]), sqrt(nr[2]), sqrt(nr[3]),
+                          sqrt(nr[4]));
+          hit = false;
+        }
+        if (tid == 0 && a.bound_history && its <= a.bound_len) a.bound_history[its - 1] = gs.fr;
+      }
+      const double g5[5] = {d5[0], d5[1], d5[2], d5[3], d5[4]};
+      const G2Step st = glred2_step(g5, alpha, omega, rho, a.tol, nb, test_tol);
       if (st.outcome == G2_NONFINITE) {
         status = ST_NONFINITE;
         break;
@@ -1619,32 +1737,35 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
         small_total<1>(tr2, red[2], nw);
         if (sqrt(tr2[0]) <= a.tol * nb) {
           status = ST_CONVERGED;
-        } else if (a.rr_period <= 0 || forced >= 3) {
+        } else if ((!AUTO && a.rr_period <= 0) || forced >= 3) {
           status = ST_TRUE_RES_NOT_MET;
         } else {
           // replace and go on without testing the replaced residual
           ++forced;
           replace(n_saved == 0, d5);
-          small_part<5>(d5, red[1]);
-          __syncthreads();
-#pragma unroll
-          for (int j = 0; j < RPT; ++j)
-            if (own[j]) t[j] = product(j, mw);
-          small_total<5>(d5, red[1], nw);
+          glred2_sums(d5, true);
+          hit = true;
           test_tol = false;
           continue;
         }
-      } else if (st.outcome == G2_BREAKDOWN_OMEGA) {
-        status = ST_BREAKDOWN_OMEGA;
-      } else if (st.outcome == G2_BREAKDOWN_RHO) {
-        status = ST_BREAKDOWN_RHO;
       } else {
-        beta = st.beta;
-        if (hrow && tid == 0) hrow[3] = beta;
-        alpha = st.alpha;
-        rho = d5[0];
-        omega_prev = omega;
-        if (its >= a.maxit) status = ST_MAXIT;
+        if constexpr (AUTO) {                  // eq:criterion for the next iteration
+          const bool f_ok = gs.fr <= a.tau * st.rn;
+          rr_next = f_ok_prev && !f_ok;
+          f_ok_prev = f_ok;
+        }
+        if (st.outcome == G2_BREAKDOWN_OMEGA) {
+          status = ST_BREAKDOWN_OMEGA;
+        } else if (st.outcome == G2_BREAKDOWN_RHO) {
+          status = ST_BREAKDOWN_RHO;
+        } else {
+          beta = st.beta;
+          if (hrow && tid == 0) hrow[3] = beta;
+          alpha = st.alpha;
+          rho = d5[0];
+          omega_prev = omega;
+          if (its >= a.maxit) status = ST_MAXIT;
+        }
       }
       break;
     }
@@ -1673,26 +1794,31 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   }
 }
 
-template <int PC, class Op, bool CACHE, int RPT>
+template <int PC, class Op, bool CACHE, int RPT, bool AUTO>
 static hipError_t launch_small_rpt(const Op& op, const SmallArgs& a, hipStream_t st) {
-  const hipError_t e = hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE, RPT>,
+  const hipError_t e = hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE, RPT, AUTO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)kSmallLds);
   if (e == hipSuccess)
-    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE, RPT>), dim3(1), dim3(kSmallRows / RPT),
-                       kSmallLds, st, op, a);
+    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE, RPT, AUTO>), dim3(1),
+                       dim3(kSmallRows / RPT), kSmallLds, st, op, a);
   return e;
 }
 
+// the automated strategy runs with two rows per thread
 template <int PC, class Op, bool CACHE>
-static hipError_t launch_small(const Op& op, const SmallArgs& a, int rpt, hipStream_t st) {
-  if (rpt == 1) return launch_small_rpt<PC, Op, CACHE, 1>(op, a, st);
-  if (rpt == 4) return launch_small_rpt<PC, Op, CACHE, 4>(op, a, st);
-  return launch_small_rpt<PC, Op, CACHE, 2>(op, a, st);
+static hipError_t launch_small(const Op& op, const SmallArgs& a, int rpt, bool automated,
+                               hipStream_t st) {
+  if (automated) return launch_small_rpt<PC, Op, CACHE, 2, true>(op, a, st);
+  if (rpt == 1) return launch_small_rpt<PC, Op, CACHE, 1, false>(op, a, st);
+  if (rpt == 4) return launch_small_rpt<PC, Op, CACHE, 4, false>(op, a, st);
+  return launch_small_rpt<PC, Op, CACHE, 2, false>(op, a, st);
 }
 
 bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_t* err) {
-  if (S.n > kSmallRows || S.precision != 0 || o.transpose || o.rr_auto || o.gap_every > 0 ||
+  // the products reading of the automated strategy (rr_auto 3, 4) keeps a
+  // state per error source in a caller's buffer: not here
+  if (S.n > kSmallRows || S.precision != 0 || o.transpose || o.rr_auto > 2 || o.gap_every > 0 ||
       o.restarts > 0 || S.block || (size_t)S.lds_cap < kSmallLds + kSmallStatic)
     return false;
   SmallArgs a{};
@@ -1705,12 +1831,14 @@ bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_
   const int ids[11] = {V_RHAT, V_R, V_G, V_S, V_L, V_Z, V_K, V_W, V_T, V_V, V_TMP};
   for (int c = 0; c < 11; ++c) a.out[c] = (double*)S.vec[ids[c]];
   a.tol = o.tol;
-  a.tau = o.rr_tau > 0 ? o.rr_tau : std::sqrt(std::ldexp(1.0, -53));
+  a.tau = S.h_sc[2].tau;      // the scalars begin_solve uploaded (automated: sqrt(eps))
   a.maxit = o.maxit;
   a.rr_period = o.rr_period;
   a.rr_nv = o.rr_nv ? 1 : 0;
   a.history = o.history;
   a.hist_len = o.history ? o.history_len : 0;
+  a.bound_history = o.rr_auto ? o.bound_history : nullptr;
+  a.bound_len = a.bound_history ? o.bound_len : 0;
   a.sc = S.sc;
   // rows of the sliced-ELL operator short enough to stay in registers
   const bool cache = S.mu_row <= kSmallCache;
@@ -1718,10 +1846,10 @@ bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_
   with_op(S, false, true, [&]<typename T, int PC, class Op>(const Op& op) {
     if constexpr (std::is_same_v<T, double>) {
       if constexpr (std::is_same_v<Op, SellOp<double>>) {
-        *err = cache ? launch_small<PC, Op, true>(op, a, rpt, st)
-                     : launch_small<PC, Op, false>(op, a, rpt, st);
+        *err = cache ? launch_small<PC, Op, true>(op, a, rpt, o.rr_auto != 0, st)
+                     : launch_small<PC, Op, false>(op, a, rpt, o.rr_auto != 0, st);
       } else {
-        *err = launch_small<PC, Op, false>(op, a, rpt, st);
+        *err = launch_small<PC, Op, false>(op, a, rpt, o.rr_auto != 0, st);
       }
     }
   });

@@ -455,7 +455,11 @@ struct IterNorms {
 struct LocalBounds {
   double x, r, q, u, y, g, s, l, z, k, w;
 };
-__device__ inline LocalBounds gap_local_bounds(const DevScalars* sc, double a, double b, double w,
+// The bound functions take the scalar struct or any state with the same
+// fields (the single-workgroup solve keeps one in registers; St::kProducts
+// false: the nested reading only).
+template <class St>
+__device__ inline LocalBounds gap_local_bounds(const St* sc, double a, double b, double w,
                                                double wp, const IterNorms& nm) {
   const double e = sc->eps_b, nA = sc->nA;
   const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
@@ -481,21 +485,26 @@ __device__ inline LocalBounds gap_local_bounds(const DevScalars* sc, double a, d
 // gap-norm bounds (eq:DDr_bound as printed).  Products reading: the bounds of
 // the local error groups entering the r, w, s and z gaps (eq:Dr, eq:Dw,
 // eq:Ds, eq:Dz) and the signed scalars are handed to k_bound_products.
-__device__ inline void gap_bound_step(DevScalars* sc, double as, double bs, double ws,
+template <class St>
+__device__ inline void gap_bound_step(St* sc, double as, double bs, double ws,
                                       double wps, const IterNorms& nm) {
   const double a = fabs(as), b = fabs(bs), w = fabs(ws), wp = fabs(wps);
   const LocalBounds d = gap_local_bounds(sc, a, b, w, wp, nm);
   const double e = sc->eps_b, nA = sc->nA;
   const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
-  if (sc->gb_prod) {
-    sc->pr_a = as; sc->pr_b = bs; sc->pr_w = ws; sc->pr_wp = wps;
-    sc->pr_R = nA * d.x + d.r + w * nA * d.u + d.q + w * d.y;
-    sc->pr_W = nA * d.k + d.w + nA * d.u + d.y;
-    sc->pr_S = nA * d.g + d.s;
-    sc->pr_Z = nA * d.l + d.z;
-    sc->pr_S0 = smu * nm.g * e;
-    sc->pr_Z0 = smu * nm.l * e;
-    sc->pr_op |= PR_STEP;
+  bool prod = false;
+  if constexpr (St::kProducts) prod = sc->gb_prod;
+  if (prod) {
+    if constexpr (St::kProducts) {
+      sc->pr_a = as; sc->pr_b = bs; sc->pr_w = ws; sc->pr_wp = wps;
+      sc->pr_R = nA * d.x + d.r + w * nA * d.u + d.q + w * d.y;
+      sc->pr_W = nA * d.k + d.w + nA * d.u + d.y;
+      sc->pr_S = nA * d.g + d.s;
+      sc->pr_Z = nA * d.l + d.z;
+      sc->pr_S0 = smu * nm.g * e;
+      sc->pr_Z0 = smu * nm.l * e;
+      sc->pr_op |= PR_STEP;
+    }
   } else {
     double dz, ds;
     if (sc->gb_first) {   // Delta^s_0, Delta^z_0: the initial gaps of Section 3.2 (g_0 = k_0, l_0 = m_0)
@@ -517,7 +526,8 @@ __device__ inline void gap_bound_step(DevScalars* sc, double as, double bs, doub
 // Bounds at the start of Algorithm 2 (Section 3.2): ||Delta^r_0|| <=
 // ((mu sqrt(N) + 1) ||A|| ||x_0|| + ||b||) eps, ||Delta^w_0|| <= mu sqrt(N)
 // ||A|| ||k_0|| eps; the s and z gaps of iteration 0 are set by its step.
-__device__ inline void gap_bound_start(DevScalars* sc, double nx, double nk) {
+template <class St>
+__device__ inline void gap_bound_start(St* sc, double nx, double nk) {
   const double e = sc->eps_b;
   const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
   sc->fr = ((cmu + 1.0) * sc->nA * nx + sc->nb) * e;
@@ -525,13 +535,15 @@ __device__ inline void gap_bound_start(DevScalars* sc, double nx, double nk) {
   sc->ds_prev = sc->dz_prev = 0.0;
   sc->gb_first = 1;
   sc->pg = sc->ps = sc->pl = sc->pz = sc->pn = sc->pv = 0.0;
-  if (sc->gb_prod) sc->pr_op = PR_START;    // column 0: the initial r and w gaps (fr, dw)
+  if constexpr (St::kProducts)
+    if (sc->gb_prod) sc->pr_op = PR_START;  // column 0: the initial r and w gaps (fr, dw)
 }
 
 // bounds right after an explicit recomputation of r, k, w from x and s, l, z
 // from g, in the arithmetic of the recomputation (FP64: eps_r); the next
 // step's local bounds use the replaced s, l, z
-__device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, double ng, double nl,
+template <class St>
+__device__ inline void gap_bound_reset(St* sc, double nx, double nk, double ng, double nl,
                                        double ns, double nz) {
   const double e = sc->eps_r;
   const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
@@ -544,11 +556,32 @@ __device__ inline void gap_bound_reset(DevScalars* sc, double nx, double nk, dou
   sc->pl = nl;
   sc->ps = ns;
   sc->pz = nz;
-  if (sc->gb_prod) {      // a new system: these gaps in columns 1 (r, w) and 0 (s, z)
-    sc->pr_rR = sc->fr; sc->pr_rW = sc->dw; sc->pr_rS = sc->ds_prev; sc->pr_rZ = sc->dz_prev;
-    sc->pr_op |= PR_RESET;
+  if constexpr (St::kProducts) {
+    if (sc->gb_prod) {    // a new system: these gaps in columns 1 (r, w) and 0 (s, z)
+      sc->pr_rR = sc->fr; sc->pr_rW = sc->dw; sc->pr_rS = sc->ds_prev; sc->pr_rZ = sc->dz_prev;
+      sc->pr_op |= PR_RESET;
+    }
   }
 }
+
+// The nested reading's state and constants, for a solve that keeps them in
+// registers (every thread the same values).
+struct GapState {
+  static constexpr bool kProducts = false;
+  int rr_est, gb_first;
+  double eps_b, eps_r, nA, nM, mu, nN, nb;
+  double fr, dw, ds_prev, dz_prev;
+  double pg, ps, pl, pz, pn, pv;
+  __device__ void load(const DevScalars* s) {
+    rr_est = s->rr_est;
+    gb_first = 1;
+    eps_b = s->eps_b; eps_r = s->eps_r;
+    nA = s->nA; nM = s->nM; mu = s->mu; nN = s->nN;
+    nb = 0.0;
+    fr = dw = ds_prev = dz_prev = 0.0;
+    pg = ps = pl = pz = pn = pv = 0.0;
+  }
+};
 
 // Slots each final mode reduces.  GLRED 2 in automated mode adds the norms
 // of the gap bound; FIN_SUM reduces slots 0 .. aux-1.

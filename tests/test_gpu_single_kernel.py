@@ -21,10 +21,16 @@ and against the multi-kernel path.
   residual misses -- with replacement enabled a forced replacement and
   convergence, without it TRUE_RES_NOT_MET, as in the oracle; b = 0, an
   exact x_0, maxit, a 1 x 1 system.
+* The automated strategy (Section 3.6, nested reading, worst-case bound and
+  estimate): the logged bound f^r to 1e-9 of the oracle's over the first
+  iterations, and through the first automated replacement (iteration 23 of
+  the 32^2 problem) to 1e-8, then 1e-5, as far as the oracle against itself
+  with correctly rounded dots agrees; full solves as the oracle's.
 * Systems the kernel does not take (more than 1024 rows, FP32 storage, the
-  automated strategy, the transpose) run the multi-kernel path, bit for bit
-  as without the option; the allocation-free entry point gives the same
-  bits as pbicgstab_solve; two runs give the same bits.
+  products reading of the automated strategy, the transpose) run the
+  multi-kernel path, bit for bit as without the option; the allocation-free
+  entry point gives the same bits as pbicgstab_solve; two runs give the same
+  bits.
 """
 
 import ctypes
@@ -213,11 +219,110 @@ def test_single_kernel_edge_cases(Solver):
     S1.close()
 
 
+# -----------------------------------------------------------------------------
+# the automated strategy (Section 3.6, nested reading)
+# -----------------------------------------------------------------------------
+
+_AUTO_CASES = [
+    ("c1-32-csr", lambda: convdiff2d_c1(32), "csr", "none"),
+    ("c1-32-csr-jacobi", lambda: convdiff2d_c1(32), "csr", "jacobi"),
+    ("c1-32-stencil-jacobi", lambda: convdiff2d_c1(32), "stencil", "jacobi"),
+    ("dia5-24", lambda: inverse_problem_c5(24, sigma=1.0, with_csr=True), "dia5", "jacobi"),
+    ("3d7-10", lambda: convdiff3d_c3(10, with_csr=True), "stencil", "jacobi"),
+]
+
+
+@pytest.mark.parametrize("variant", ["bound", "estimate"])
+@pytest.mark.parametrize("name,make,form,pc", _AUTO_CASES, ids=[c[0] for c in _AUTO_CASES])
+def test_single_kernel_automated_bound_trace(Solver, name, make, form, pc, variant):
+    """The bound f^r of eq:DDr_bound logged per iteration, to 1e-9 of the
+    oracle's over up to 12 iterations -- as far as the oracle against itself
+    with correctly rounded dots agrees to 1e-11 (all 12 on the 2D problems, 5
+    on the 3D one) --, the scalar trace over the oracle's own horizon, and
+    the same replacements."""
+    p = make()
+    A, ops = oracle_ops(p, pc)
+    kw = dict(rr_mode="auto", rr_estimate=variant == "estimate")
+    runs = [pipelined_bicgstab(cls(A, ops.dinv), p.b, tol=0.0, maxit=12, **kw)
+            for cls in (Float64Ops, _FsumOps)]
+    bad = np.nonzero(rel(np.array(runs[0].fr), np.array(runs[1].fr)) > 1e-11)[0]
+    k = int(bad[0]) if len(bad) else 12
+    assert k >= 4
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, **kw)
+    h = _horizon(A, p.b, ops.dinv, None, kw, k)
+    S = Solver.from_problem(p, form=form, precond=pc)
+    bh = torch.zeros(k, dtype=torch.float64, device="cuda")
+    hist = history_buffer(k)
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto=variant, bound_history=bh,
+                    history=hist, single_kernel=True)
+    assert st["single_kernel"] == 1
+    assert st["iterations"] == k and len(ref.fr) == k
+    assert np.all(rel(host(bh), np.array(ref.fr)) <= 1e-9), (host(bh), ref.fr)
+    assert st["replacements"] == ref.replacements
+    rn, al, om, be = split_history(hist, h)
+    assert np.all(rel(al, ref.alpha[:h]) <= 1e-10)
+    assert np.all(rel(om, ref.omega[:h]) <= 1e-10)
+    assert np.all(rel(rn, ref.rnorm[:h]) <= 1e-10)
+    S.close()
+
+
+@pytest.mark.parametrize("form", ["csr", "stencil"])
+def test_single_kernel_automated_through_replacement(Solver, form):
+    """The 32^2 problem without preconditioner: the criterion replaces in
+    iteration 23, in the oracle and in the kernel; the bound restarts there
+    from the recomputation's rounding errors.  The oracle against itself with
+    correctly rounded dots: <= 2.1e-10 up to the replacement, then 1.7e-8 and
+    5.9e-7 in the two iterations after it, so 1e-8 and 1e-5 here."""
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, "none")
+    k = 26
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, rr_mode="auto")
+    assert ref.rr_iters == [23], ref.rr_iters
+    S = Solver.from_problem(p, form=form, precond="none")
+    bh = torch.zeros(k, dtype=torch.float64, device="cuda")
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto="bound", bound_history=bh,
+                    single_kernel=True)
+    assert st["single_kernel"] == 1
+    assert st["iterations"] == k and st["replacements"] == 1
+    assert st["spmvs"] == 3 + 2 * k + 4 + 1
+    d = rel(host(bh), np.array(ref.fr))
+    assert np.all(d[:24] <= 1e-8), d
+    assert np.all(d[24:] <= 1e-5), d
+    S.close()
+
+
+@pytest.mark.parametrize("variant", ["bound", "estimate"])
+@pytest.mark.parametrize("form,pc", [("csr", "none"), ("stencil", "jacobi"), ("csr", "jacobi")])
+def test_single_kernel_automated_full_solve(Solver, form, pc, variant):
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, pc)
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=2000, rr_mode="auto",
+                             rr_estimate=variant == "estimate")
+    assert ref.status == 0
+    S = Solver.from_problem(p, form=form, precond=pc)
+    b = dev(p.b)
+    xs, ss = S.solve(b, tol=1e-10, maxit=2000, rr_auto=variant, single_kernel=True)
+    xm, sm = S.solve(b, tol=1e-10, maxit=2000, rr_auto=variant)
+    print(f"{form}/{pc} {variant}: oracle {ref.iterations} its {ref.rr_iters}, single kernel "
+          f"{ss['iterations']} its {ss['replacements']} rr, multi-kernel {sm['iterations']} its "
+          f"{sm['replacements']} rr", flush=True)
+    assert ss["single_kernel"] == 1 and sm["single_kernel"] == 0
+    assert ss["status"] == sm["status"] == 0
+    assert abs(ss["iterations"] - ref.iterations) <= max(2, ref.iterations // 10)
+    assert abs(ss["replacements"] - ref.replacements) <= 2
+    assert ss["rel_res_true"] <= 1e-10
+    assert ss["spmvs"] == 3 + 2 * ss["iterations"] + 4 * ss["replacements"] + 1
+    xs, xm = host(xs), host(xm)
+    assert np.max(np.abs(xs - xm)) <= 1e-6 * np.max(np.abs(xm))
+    assert np.max(np.abs(xs - p.x_exact)) <= 1e-6 * np.max(np.abs(p.x_exact))
+    S.close()
+
+
 def test_single_kernel_ineligible_runs_the_multi_kernel_path(Solver):
     cases = [
         (poisson2d_c2(33), dict(form="stencil", precond="jacobi"), {}),          # 1089 rows
         (convdiff2d_c1(32), dict(form="csr", precision="mixed", precond="none"), {}),
-        (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(rr_auto="bound")),
+        (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(rr_auto="products")),
         (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(transpose=True)),
     ]
     for p, make_kw, solve_kw in cases:
