@@ -1355,8 +1355,8 @@ __device__ __forceinline__ void sell_row_serial(const SellOp<double>& op, int i,
 // so that a wave's lanes hold consecutive rows.  AUTO: the automated strategy
 // (Section 3.6, nested reading: the worst-case bound or the estimate); the
 // reductions carry the norms of the bound (phase A ten, phase B four, a
-// replacement five), and every thread advances the same bound state
-// (GapState) from the same totals, so eq:criterion needs no broadcast.
+// replacement five); wave 0 alone advances the bound state (GapState) and
+// passes eq:criterion's decision to the other waves through LDS.
 template <int PC, class Op, bool CACHE, int RPT, bool AUTO>
 __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallArgs a) {
   constexpr int T = kSmallRows / RPT;
@@ -1367,6 +1367,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   static_assert(NR <= kSmallSums && NA <= kSmallSums, "partial buffers");
   extern __shared__ double sm[];
   __shared__ double red[kSmallRed][kSmallSums][kSmallWaves];
+  __shared__ int rr_flag;             // AUTO: eq:criterion's decision for the next iteration
   double* const nz = sm + SB_NZ * kSmallRows;
   double* const mw = sm + SB_MW * kSmallRows;
   double* const px = sm + SB_PX * kSmallRows;
@@ -1482,13 +1483,18 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     alpha = rho / rw;
   }
   // the bound of Section 3.2 at the start, and eq:criterion's previous test
+  // (wave 0; its first write of rr_flag is behind the next barrier)
+  const bool bw = tid < 64;
   GapState gs;
-  bool f_ok_prev = false, rr_next = false;
+  bool f_ok_prev = false;
   if constexpr (AUTO) {
-    gs.load(a.sc);
-    gs.nb = nb;
-    gap_bound_start(&gs, sqrt(acc[4]), sqrt(acc[5]));
-    f_ok_prev = gs.fr <= a.tau * rn0;
+    if (bw) {
+      gs.load(a.sc);
+      gs.nb = nb;
+      gap_bound_start(&gs, sqrt(acc[4]), sqrt(acc[5]));
+      f_ok_prev = gs.fr <= a.tau * rn0;
+      if (tid == 0) rr_flag = 0;
+    }
   }
 
   // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again (with
@@ -1565,10 +1571,10 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     }
   };
 
-  // the GLRED 2 sums (after a replacement with its norms), with the product
-  // t_{i+1} = A M^-1 w_{i+1} between the partials and the totals
-  // (the norms' partials stay in red[1]: the bound step sums them)
-  auto glred2_sums = [&](double (&d)[NR], bool replaced) {
+  // the GLRED 2 sums (after a replacement with its norms), with `mid` and the
+  // product t_{i+1} = A M^-1 w_{i+1} between the partials and the totals (the
+  // norms' partials stay in red[1] for the bound)
+  auto glred2_sums = [&](double (&d)[NR], bool replaced, auto&& mid) {
     constexpr int NS = AUTO ? NB : 5;
     if (replaced && AUTO) {
       small_part<NR>(d, red[1]);
@@ -1579,6 +1585,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
       small_part<NS>(p, red[1]);
     }
     __syncthreads();
+    mid();
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
       if (own[j]) t[j] = product(j, mw);
@@ -1586,6 +1593,36 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     small_total<5>(g2, red[1], nw);
 #pragma unroll
     for (int e = 0; e < 5; ++e) d[e] = g2[e];
+  };
+
+  // AUTO: the bound step of the iteration (eq:DDr_bound, with the norms
+  // summed from the partials that phase A left in `ra` and phase B in red[1])
+  // and, after a replacement, its restart from the recomputation's errors.
+  // It needs alpha_i, beta_i, omega_i, omega_{i-1} and ||r_i||, not the
+  // GLRED 2 totals, so it runs before the product t_{i+1} (their latencies
+  // overlap); eq:criterion follows the totals.
+  auto bound_update = [&](double (*rb)[kSmallWaves], bool step, bool reset) {
+    if constexpr (AUTO) {
+      if (!bw) return;
+      double na[10];
+      small_total<10>(na, rb + 2, nw);
+      if (step) {
+        double nbv[4];
+        small_total<4>(nbv, red[1] + 5, nw);
+        IterNorms nm;
+        nm.k = sqrt(na[0]); nm.w = sqrt(na[1]); nm.t = sqrt(na[2]); nm.m = sqrt(na[3]);
+        nm.g = sqrt(na[4]); nm.s = sqrt(na[5]); nm.l = sqrt(na[6]); nm.z = sqrt(na[7]);
+        nm.q = sqrt(na[8]); nm.y = sqrt(na[9]); nm.x = sqrt(nbv[0]); nm.u = sqrt(nbv[1]);
+        nm.n = sqrt(nbv[2]); nm.v = sqrt(nbv[3]); nm.r = rn;
+        gap_bound_step(&gs, alpha, beta, omega, omega_prev, nm);
+      }
+      if (reset) {
+        double nr[5];
+        small_total<5>(nr, red[1] + 9, nw);
+        gap_bound_reset(&gs, sqrt(nr[0]), sqrt(nr[1]), sqrt(na[4]), sqrt(nr[2]), sqrt(nr[3]),
+                        sqrt(nr[4]));
+      }
+    }
   };
 
   while (status < 0) {
@@ -1674,40 +1711,20 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
       }
     }
     // a replacement: eq:criterion's decision of the previous iteration, or the period
-    const bool due = AUTO ? rr_next
+    // (rr_flag was written before the last barrier, and is next written after
+    // the barrier that follows this read)
+    const bool due = AUTO ? rr_flag != 0
                           : (a.rr_period > 0 && (iter + 1) % a.rr_period == 0 && rn >= a.tau * rn0);
     if (due) replace(true, d5);
-    glred2_sums(d5, due);                      // GLRED 2
-    bool hit = due;                            // the bound restarts after this step
+    glred2_sums(d5, due, [&] { bound_update(ra, true, due); });   // GLRED 2
     const int its = ++iter;
     double* hrow = (a.history && its <= a.hist_len) ? a.history + 4 * (int64_t)(its - 1) : nullptr;
     if (hrow && tid == 0) { hrow[1] = alpha; hrow[2] = omega; hrow[3] = 0.0; }
     bool test_tol = true;
     for (;;) {
-      if constexpr (AUTO) {
-        // the norms from the partials left in ra (phase A) and red[1]
-        // (phase B, a replacement)
-        double na[10];
-        small_total<10>(na, ra + 2, nw);
-        if (test_tol) {                        // the bound step of this iteration
-          double nbv[4];
-          small_total<4>(nbv, red[1] + 5, nw);
-          IterNorms nm;
-          nm.k = sqrt(na[0]); nm.w = sqrt(na[1]); nm.t = sqrt(na[2]); nm.m = sqrt(na[3]);
-          nm.g = sqrt(na[4]); nm.s = sqrt(na[5]); nm.l = sqrt(na[6]); nm.z = sqrt(na[7]);
-          nm.q = sqrt(na[8]); nm.y = sqrt(na[9]); nm.x = sqrt(nbv[0]); nm.u = sqrt(nbv[1]);
-          nm.n = sqrt(nbv[2]); nm.v = sqrt(nbv[3]); nm.r = rn;
-          gap_bound_step(&gs, alpha, beta, omega, omega_prev, nm);
-        }
-        if (hit) {
-          double nr[5];
-          small_total<5>(nr, red[1] + 9, nw);
-          gap_bound_reset(&gs, sqrt(nr[0]), sqrt(nr[1]), sqrt(na[4]), sqrt(nr[2]), sqrt(nr[3]),
-                          sqrt(nr[4]));
-          hit = false;
-        }
+      if constexpr (AUTO)
         if (tid == 0 && a.bound_history && its <= a.bound_len) a.bound_history[its - 1] = gs.fr;
-      }
+      // (wave 0's gs and f_ok_prev only: the other waves' copies are unused)
       const double g5[5] = {d5[0], d5[1], d5[2], d5[3], d5[4]};
       const G2Step st = glred2_step(g5, alpha, omega, rho, a.tol, nb, test_tol);
       if (st.outcome == G2_NONFINITE) {
@@ -1743,16 +1760,17 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
           // replace and go on without testing the replaced residual
           ++forced;
           replace(n_saved == 0, d5);
-          glred2_sums(d5, true);
-          hit = true;
+          glred2_sums(d5, true, [&] { bound_update(ra, false, true); });
           test_tol = false;
           continue;
         }
       } else {
         if constexpr (AUTO) {                  // eq:criterion for the next iteration
-          const bool f_ok = gs.fr <= a.tau * st.rn;
-          rr_next = f_ok_prev && !f_ok;
-          f_ok_prev = f_ok;
+          if (bw) {
+            const bool f_ok = gs.fr <= a.tau * st.rn;
+            if (tid == 0) rr_flag = (f_ok_prev && !f_ok) ? 1 : 0;
+            f_ok_prev = f_ok;
+          }
         }
         if (st.outcome == G2_BREAKDOWN_OMEGA) {
           status = ST_BREAKDOWN_OMEGA;

@@ -457,13 +457,26 @@ struct LocalBounds {
 };
 // The bound functions take the scalar struct or any state with the same
 // fields (the single-workgroup solve keeps one in registers; St::kProducts
-// false: the nested reading only).
+// false: the nested reading only).  The factors of the products' rounding
+// errors, mu sqrt(N) (worst case) or sqrt(mu) (estimate) and 1 or sqrt(N):
+// a state that holds them (cmu, cnu) gives them, else they are computed.
+template <class St>
+__device__ inline double gap_cmu(const St* sc) {
+  if constexpr (requires { sc->cmu; }) return sc->cmu;
+  else return sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
+}
+template <class St>
+__device__ inline double gap_cnu(const St* sc) {
+  if constexpr (requires { sc->cnu; }) return sc->cnu;
+  else return sc->rr_est ? 1.0 : sqrt(sc->nN);
+}
+
 template <class St>
 __device__ inline LocalBounds gap_local_bounds(const St* sc, double a, double b, double w,
                                                double wp, const IterNorms& nm) {
   const double e = sc->eps_b, nA = sc->nA;
-  const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
-  const double smut = (sc->rr_est ? 1.0 : sqrt(sc->nN)) * sc->nM;
+  const double smu = gap_cmu(sc) * nA;
+  const double smut = gap_cnu(sc) * sc->nM;
   LocalBounds d;
   d.x = (2 * nm.x + 3 * a * nm.g + 2 * w * nm.u) * e;
   d.r = (nm.q + 2 * w * nm.y) * e;
@@ -491,7 +504,7 @@ __device__ inline void gap_bound_step(St* sc, double as, double bs, double ws,
   const double a = fabs(as), b = fabs(bs), w = fabs(ws), wp = fabs(wps);
   const LocalBounds d = gap_local_bounds(sc, a, b, w, wp, nm);
   const double e = sc->eps_b, nA = sc->nA;
-  const double smu = (sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN)) * nA;
+  const double smu = gap_cmu(sc) * nA;
   bool prod = false;
   if constexpr (St::kProducts) prod = sc->gb_prod;
   if (prod) {
@@ -529,7 +542,7 @@ __device__ inline void gap_bound_step(St* sc, double as, double bs, double ws,
 template <class St>
 __device__ inline void gap_bound_start(St* sc, double nx, double nk) {
   const double e = sc->eps_b;
-  const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
+  const double cmu = gap_cmu(sc);
   sc->fr = ((cmu + 1.0) * sc->nA * nx + sc->nb) * e;
   sc->dw = cmu * sc->nA * nk * e;
   sc->ds_prev = sc->dz_prev = 0.0;
@@ -546,7 +559,7 @@ template <class St>
 __device__ inline void gap_bound_reset(St* sc, double nx, double nk, double ng, double nl,
                                        double ns, double nz) {
   const double e = sc->eps_r;
-  const double cmu = sc->rr_est ? sqrt(sc->mu) : sc->mu * sqrt(sc->nN);
+  const double cmu = gap_cmu(sc);
   const double smu = cmu * sc->nA;
   sc->fr = ((cmu + 1.0) * sc->nA * nx + sc->nb) * e;
   sc->dw = smu * nk * e;
@@ -570,6 +583,7 @@ struct GapState {
   static constexpr bool kProducts = false;
   int rr_est, gb_first;
   double eps_b, eps_r, nA, nM, mu, nN, nb;
+  double cmu, cnu;                 // gap_cmu, gap_cnu of the constants above
   double fr, dw, ds_prev, dz_prev;
   double pg, ps, pl, pz, pn, pv;
   __device__ void load(const DevScalars* s) {
@@ -577,6 +591,8 @@ struct GapState {
     gb_first = 1;
     eps_b = s->eps_b; eps_r = s->eps_r;
     nA = s->nA; nM = s->nM; mu = s->mu; nN = s->nN;
+    cmu = rr_est ? sqrt(mu) : mu * sqrt(nN);
+    cnu = rr_est ? 1.0 : sqrt(nN);
     nb = 0.0;
     fr = dw = ds_prev = dz_prev = 0.0;
     pg = ps = pl = pz = pn = pv = 0.0;
