@@ -318,6 +318,40 @@ def test_single_kernel_automated_full_solve(Solver, form, pc, variant):
     S.close()
 
 
+@pytest.mark.parametrize("variant", ["bound", "estimate"])
+def test_single_kernel_automated_forced_replacements(Solver, variant):
+    """tol 1e-15 on the 32^2 problem: the recursive residual gets there, the
+    true one does not; after the criterion's own replacements the solve
+    forces three (the bound restarts after each) and ends TRUE_RES_NOT_MET --
+    in the oracle, the multi-kernel path and the kernel.  Where the
+    recursive residual crosses 1e-15 depends on the order of the sums, so
+    iteration counts are not compared."""
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, "none")
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-15, maxit=2000, rr_mode="auto",
+                             rr_estimate=variant == "estimate")
+    assert ref.status == STATUS["TRUE_RES_NOT_MET"] and ref.replacements >= 3
+    S = Solver.from_problem(p, form="csr", precond="none")
+    b = dev(p.b)
+    bh = torch.zeros(2000, dtype=torch.float64, device="cuda")
+    xs, ss = S.solve(b, tol=1e-15, maxit=2000, rr_auto=variant, single_kernel=True,
+                     bound_history=bh)
+    xm, sm = S.solve(b, tol=1e-15, maxit=2000, rr_auto=variant)
+    print(f"{variant}: oracle {ref.iterations} its {ref.rr_iters}; kernel {ss['iterations']} its "
+          f"{ss['replacements']} rr; multi-kernel {sm['iterations']} its {sm['replacements']} rr",
+          flush=True)
+    assert ss["single_kernel"] == 1
+    for st in (ss, sm):
+        assert st["status"] == STATUS["TRUE_RES_NOT_MET"]
+        assert st["replacements"] >= 3
+        assert st["rel_res_recursive"] <= 1e-15 < st["rel_res_true"]
+        assert st["rel_res_true"] <= 1e-13
+    # the bound was logged for every iteration, finite and positive
+    fr = host(bh)[:ss["iterations"]]
+    assert np.all(np.isfinite(fr)) and np.all(fr > 0)
+    S.close()
+
+
 def test_single_kernel_ineligible_runs_the_multi_kernel_path(Solver):
     cases = [
         (poisson2d_c2(33), dict(form="stencil", precond="jacobi"), {}),          # 1089 rows
@@ -343,6 +377,7 @@ def _abi_solve(L, fn, S, b, **kw):
     o.tol = kw.get("tol", 1e-10)
     o.maxit = kw.get("maxit", 3000)
     o.rr_period = kw.get("rr_period", 0)
+    o.rr_auto = kw.get("rr_auto", 0)
     o.single_kernel = 1
     o.stream = torch.cuda.current_stream().cuda_stream
     x = torch.zeros_like(b)
@@ -354,14 +389,16 @@ def _abi_solve(L, fn, S, b, **kw):
     return host(x), st.as_dict()
 
 
-def test_single_kernel_noalloc_and_repeatable(Solver):
+@pytest.mark.parametrize("kw", [dict(rr_period=50), dict(rr_auto=1), dict(rr_auto=2)],
+                         ids=["period-50", "auto-bound", "auto-estimate"])
+def test_single_kernel_noalloc_and_repeatable(Solver, kw):
     from paper_1809_01948_amd import _lib as L
     p = convdiff2d_c1(32)
     S = Solver.from_problem(p, form="csr", precond="jacobi")
     b = dev(p.b)
-    runs = [_abi_solve(L, "pbicgstab_solve", S, b, rr_period=50),
-            _abi_solve(L, "pbicgstab_solve_noalloc", S, b, rr_period=50),
-            _abi_solve(L, "pbicgstab_solve", S, b, rr_period=50)]
+    runs = [_abi_solve(L, "pbicgstab_solve", S, b, **kw),
+            _abi_solve(L, "pbicgstab_solve_noalloc", S, b, **kw),
+            _abi_solve(L, "pbicgstab_solve", S, b, **kw)]
     for x, st in runs:
         assert st["single_kernel"] == 1 and st["status"] == 0
         for key in ("iterations", "replacements", "rel_res_recursive", "rel_res_true"):
