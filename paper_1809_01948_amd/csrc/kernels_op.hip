@@ -1251,7 +1251,7 @@ enum : int {
 constexpr size_t kSmallLds = (size_t)SB_COUNT * kSmallRows * sizeof(double);
 constexpr int kSmallRed = 4;          // partial buffers: GLRED 1, GLRED 2, the others, and
                                       // GLRED 1 of odd iterations (automated strategy)
-constexpr int kSmallSums = 14;        // sums per buffer (automated strategy: GLRED 2 with the
+constexpr int kSmallSums = 17;        // sums per buffer (automated strategy: GLRED 2 with the
                                       // norms of phase B and of a replacement)
 constexpr size_t kSmallStatic = (size_t)kSmallRed * kSmallSums * kSmallWaves * sizeof(double);
 
@@ -1354,16 +1354,17 @@ __device__ __forceinline__ void sell_row_serial(const SellOp<double>& op, int i,
 // RPT rows per thread: rows tid, tid + T, ... (T = kSmallRows / RPT threads),
 // so that a wave's lanes hold consecutive rows.  AUTO: the automated strategy
 // (Section 3.6, nested reading: the worst-case bound or the estimate); the
-// reductions carry the norms of the bound (phase A ten, phase B four, a
-// replacement five); wave 0 alone advances the bound state (GapState) and
+// reductions carry the norms of the bound (phase A six, phase B seven, a
+// replacement five; ||y|| is GLRED 1's (y, y)); wave 0 alone advances the
+// bound state (GapState) and
 // passes eq:criterion's decision to the other waves through LDS.
 template <int PC, class Op, bool CACHE, int RPT, bool AUTO>
 __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallArgs a) {
   constexpr int T = kSmallRows / RPT;
   constexpr int NI = AUTO ? 6 : 4;    // sums of the initialisation
-  constexpr int NA = AUTO ? 12 : 2;   // GLRED 1 (+ norms)
-  constexpr int NB = AUTO ? 9 : 5;    // GLRED 2 (+ norms of phase B)
-  constexpr int NR = AUTO ? 14 : 5;   // GLRED 2 after a replacement (+ its norms)
+  constexpr int NA = AUTO ? 8 : 2;    // GLRED 1 (+ norms), two groups of four
+  constexpr int NB = AUTO ? 12 : 5;   // GLRED 2 (+ norms), three groups of four
+  constexpr int NR = AUTO ? 17 : 5;   // GLRED 2 after a replacement (+ its norms)
   static_assert(NR <= kSmallSums && NA <= kSmallSums, "partial buffers");
   extern __shared__ double sm[];
   __shared__ double red[kSmallRed][kSmallSums][kSmallWaves];
@@ -1498,7 +1499,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   }
 
   // eq:rr from x_{i+1} and g_i in FP64, and the GLRED 2 terms again (with
-  // AUTO also the norms that restart the bound: x, k, l, s, z in d[9..13]).  x, g,
+  // AUTO also the norms that restart the bound: x, k, l, s, z in d[12..16]).  x, g,
   // then k, l go through LDS arrays of their own (the neighbours' entries);
   // their previous readers are behind at least one barrier.
   auto replace = [&](bool save_z, double (&d)[NR]) {
@@ -1528,7 +1529,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     for (int e = 0; e < 5; ++e) d[e] = 0.0;
     if constexpr (AUTO) {
 #pragma unroll
-      for (int e = 9; e < 14; ++e) d[e] = 0.0;
+      for (int e = 12; e < 17; ++e) d[e] = 0.0;
     }
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
@@ -1546,11 +1547,11 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
         d[3] += rh[j] * z[j];
         d[4] += r[j] * r[j];
         if constexpr (AUTO) {
-          d[9] += x[j] * x[j];
-          d[10] += k[j] * k[j];
-          d[11] += l[j] * l[j];
-          d[12] += s[j] * s[j];
-          d[13] += z[j] * z[j];
+          d[12] += x[j] * x[j];
+          d[13] += k[j] * k[j];
+          d[14] += l[j] * l[j];
+          d[15] += s[j] * s[j];
+          d[16] += z[j] * z[j];
         }
         if (a.rr_nv) {
           n[j] = prec(j, z[j]);
@@ -1596,30 +1597,31 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   };
 
   // AUTO: the bound step of the iteration (eq:DDr_bound, with the norms
-  // summed from the partials that phase A left in `ra` and phase B in red[1])
+  // summed from the partials that phase A left in `ra` and phase B in red[1];
+  // ||y||^2 is GLRED 1's (y, y), the same sum)
   // and, after a replacement, its restart from the recomputation's errors.
   // It needs alpha_i, beta_i, omega_i, omega_{i-1} and ||r_i||, not the
   // GLRED 2 totals, so it runs before the product t_{i+1} (their latencies
   // overlap); eq:criterion follows the totals.
-  auto bound_update = [&](double (*rb)[kSmallWaves], bool step, bool reset) {
+  auto bound_update = [&](double (*rb)[kSmallWaves], double yy, bool step, bool reset) {
     if constexpr (AUTO) {
       if (!bw) return;
-      double na[10];
-      small_total<10>(na, rb + 2, nw);
+      double nbv[7];                           // x, u, n, v, g, s, q
+      small_total<7>(nbv, red[1] + 5, nw);
       if (step) {
-        double nbv[4];
-        small_total<4>(nbv, red[1] + 5, nw);
+        double na[6];                          // k, w, t, m, l, z
+        small_total<6>(na, rb + 2, nw);
         IterNorms nm;
         nm.k = sqrt(na[0]); nm.w = sqrt(na[1]); nm.t = sqrt(na[2]); nm.m = sqrt(na[3]);
-        nm.g = sqrt(na[4]); nm.s = sqrt(na[5]); nm.l = sqrt(na[6]); nm.z = sqrt(na[7]);
-        nm.q = sqrt(na[8]); nm.y = sqrt(na[9]); nm.x = sqrt(nbv[0]); nm.u = sqrt(nbv[1]);
-        nm.n = sqrt(nbv[2]); nm.v = sqrt(nbv[3]); nm.r = rn;
+        nm.l = sqrt(na[4]); nm.z = sqrt(na[5]); nm.x = sqrt(nbv[0]); nm.u = sqrt(nbv[1]);
+        nm.n = sqrt(nbv[2]); nm.v = sqrt(nbv[3]); nm.g = sqrt(nbv[4]); nm.s = sqrt(nbv[5]);
+        nm.q = sqrt(nbv[6]); nm.y = sqrt(yy); nm.r = rn;
         gap_bound_step(&gs, alpha, beta, omega, omega_prev, nm);
       }
       if (reset) {
         double nr[5];
-        small_total<5>(nr, red[1] + 9, nw);
-        gap_bound_reset(&gs, sqrt(nr[0]), sqrt(nr[1]), sqrt(na[4]), sqrt(nr[2]), sqrt(nr[3]),
+        small_total<5>(nr, red[1] + 12, nw);
+        gap_bound_reset(&gs, sqrt(nr[0]), sqrt(nr[1]), sqrt(nbv[4]), sqrt(nr[2]), sqrt(nr[3]),
                         sqrt(nr[4]));
       }
     }
@@ -1627,7 +1629,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
 
   while (status < 0) {
     // phase A: g, s, l, z, M^-1 z and the GLRED 1 terms (with AUTO the norms
-    // of k, w, t, m before and of g, s, l, z, q, y after the update)
+    // of k, w, t, m before and of l, z after the update)
     double d2[NA];
 #pragma unroll
     for (int e = 0; e < NA; ++e) d2[e] = 0.0;
@@ -1648,12 +1650,8 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
           d2[3] += w[j] * w[j];
           d2[4] += t[j] * t[j];
           d2[5] += m[j] * m[j];
-          d2[6] += gn * gn;
-          d2[7] += sn * sn;
-          d2[8] += ln * ln;
-          d2[9] += zn * zn;
-          d2[10] += q * q;
-          d2[11] += y * y;
+          d2[6] += ln * ln;
+          d2[7] += zn * zn;
         }
         g[j] = gn; s[j] = sn; l[j] = ln; z[j] = zn;
         n[j] = prec(j, zn);
@@ -1680,7 +1678,8 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     }
     omega = d2[1] != 0.0 ? d2[0] / d2[1] : 0.0;
     // phase B: x, r, k, w, M^-1 w and the GLRED 2 terms (with AUTO the norms
-    // of x before the update, u, n, v in d5[5..8])
+    // of x before the update, u, n, v, and of phase A's g, s, q in d5[5..11];
+    // q is phase A's q, the same expression of the same values)
     double d5[NR];
 #pragma unroll
     for (int e = 0; e < NR; ++e) d5[e] = 0.0;
@@ -1695,6 +1694,9 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
           d5[6] += u * u;
           d5[7] += n[j] * n[j];
           d5[8] += v[j] * v[j];
+          d5[9] += g[j] * g[j];
+          d5[10] += s[j] * s[j];
+          d5[11] += q * q;
         }
         x[j] = (x[j] + alpha * g[j]) + omega * u;
         const double rn_ = q - omega * y;
@@ -1716,7 +1718,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     const bool due = AUTO ? rr_flag != 0
                           : (a.rr_period > 0 && (iter + 1) % a.rr_period == 0 && rn >= a.tau * rn0);
     if (due) replace(true, d5);
-    glred2_sums(d5, due, [&] { bound_update(ra, true, due); });   // GLRED 2
+    glred2_sums(d5, due, [&] { bound_update(ra, d2[1], true, due); });   // GLRED 2
     const int its = ++iter;
     double* hrow = (a.history && its <= a.hist_len) ? a.history + 4 * (int64_t)(its - 1) : nullptr;
     if (hrow && tid == 0) { hrow[1] = alpha; hrow[2] = omega; hrow[3] = 0.0; }
@@ -1760,7 +1762,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
           // replace and go on without testing the replaced residual
           ++forced;
           replace(n_saved == 0, d5);
-          glred2_sums(d5, true, [&] { bound_update(ra, false, true); });
+          glred2_sums(d5, true, [&] { bound_update(ra, d2[1], false, true); });
           test_tol = false;
           continue;
         }
