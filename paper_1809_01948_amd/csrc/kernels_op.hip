@@ -1484,7 +1484,8 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     alpha = rho / rw;
   }
   // the bound of Section 3.2 at the start, and eq:criterion's previous test
-  // (wave 0; its first write of rr_flag is behind the next barrier)
+  // (wave 0 holds the bound state, the other waves' gs and f_ok_prev are
+  // unused; its first write of rr_flag is behind the next barrier)
   const bool bw = tid < 64;
   GapState gs;
   bool f_ok_prev = false;
@@ -1726,7 +1727,6 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     for (;;) {
       if constexpr (AUTO)
         if (tid == 0 && a.bound_history && its <= a.bound_len) a.bound_history[its - 1] = gs.fr;
-      // (wave 0's gs and f_ok_prev only: the other waves' copies are unused)
       const double g5[5] = {d5[0], d5[1], d5[2], d5[3], d5[4]};
       const G2Step st = glred2_step(g5, alpha, omega, rho, a.tol, nb, test_tol);
       if (st.outcome == G2_NONFINITE) {
