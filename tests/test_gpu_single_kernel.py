@@ -291,6 +291,34 @@ def test_single_kernel_automated_through_replacement(Solver, form):
     S.close()
 
 
+@pytest.mark.parametrize("form,pc", [("csr", "none"), ("stencil", "jacobi")])
+def test_single_kernel_automated_random_shadow(Solver, form, pc):
+    """With a random shadow vector the criterion replaces in iteration 7 of
+    the 32^2 problem (oracle and kernel).  The oracle against itself with
+    correctly rounded dots: <= 9.3e-11 up to the replacement, 1.5e-10 and
+    3.0e-10 in the two iterations after it, so 1e-8 and 1e-6 here."""
+    p = convdiff2d_c1(32)
+    A, ops = oracle_ops(p, pc)
+    rh = np.random.default_rng(57).standard_normal(p.n)
+    k = 10
+    ref = pipelined_bicgstab(ops, p.b, tol=0.0, maxit=k, rr_mode="auto", rhat=rh)
+    assert ref.rr_iters == [7], ref.rr_iters
+    S = Solver.from_problem(p, form=form, precond=pc)
+    bh = torch.zeros(k, dtype=torch.float64, device="cuda")
+    hist = history_buffer(k)
+    x, st = S.solve(dev(p.b), tol=0.0, maxit=k, rr_auto="bound", bound_history=bh,
+                    history=hist, rhat=dev(rh), single_kernel=True)
+    assert st["single_kernel"] == 1
+    assert st["iterations"] == k and st["replacements"] == 1
+    d = rel(host(bh), np.array(ref.fr))
+    assert np.all(d[:8] <= 1e-8), d
+    assert np.all(d[8:] <= 1e-6), d
+    rn, al, om, be = split_history(hist, 7)
+    assert np.all(rel(al, ref.alpha[:7]) <= 1e-10)
+    assert np.all(rel(rn, ref.rnorm[:7]) <= 1e-10)
+    S.close()
+
+
 @pytest.mark.parametrize("variant", ["bound", "estimate"])
 @pytest.mark.parametrize("form,pc", [("csr", "none"), ("stencil", "jacobi"), ("csr", "jacobi")])
 def test_single_kernel_automated_full_solve(Solver, form, pc, variant):
