@@ -24,8 +24,10 @@ and against the multi-kernel path.
 * The automated strategy (Section 3.6, nested reading, worst-case bound and
   estimate): the logged bound f^r to 1e-9 of the oracle's over the first
   iterations, and through the first automated replacement (iteration 23 of
-  the 32^2 problem) to 1e-8, then 1e-5, as far as the oracle against itself
-  with correctly rounded dots agrees; full solves as the oracle's.
+  the 32^2 problem; iteration 7 with a random shadow vector) to 1e-8, then
+  1e-5 (1e-6), as far as the oracle against itself with correctly rounded
+  dots agrees; full solves as the oracle's; forced replacements ending
+  TRUE_RES_NOT_MET; the allocation-free entry point.
 * Systems the kernel does not take (more than 1024 rows, FP32 storage, the
   products reading of the automated strategy, the transpose) run the
   multi-kernel path, bit for bit as without the option; the allocation-free
