@@ -173,7 +173,7 @@ typedef struct {
                             at most 1024 rows, FP64, rr_auto 0, 1 or 2 (the automated
                             strategy's nested reading, its bound kept in registers; the
                             bound history is written), gap_every 0, restarts 0, not
-                            transposed, not block-Jacobi, and a device with 56 KiB of LDS
+                            transposed, not block-Jacobi, and a device with 57 KiB of LDS
                             per workgroup; otherwise ignored (pbcg_stats.single_kernel
                             tells which ran).  Same arithmetic per row and the
                             same stopping rules as the multi-kernel path; the sums of the
