@@ -466,7 +466,8 @@ def c1_latency(dev):
     second of full solves to 1e-10, classic (Algorithm 1, 7 launches per
     iteration), pipelined (Algorithm 2 from HIP graphs) and pipelined as one
     kernel in one workgroup (no launches or host polls inside the solve);
-    without replacement, every 50 iterations and the automated strategy."""
+    without replacement, every 50 iterations and the automated strategy.
+    Also the 45^2 grid (2025 rows), graphs against one workgroup."""
     import torch
     from paper_1809_01948_amd.solver import Solver
     from workloads import convdiff2d_c1
@@ -496,6 +497,26 @@ def c1_latency(dev):
                                      "iter_per_s": its / med, "status": st["status_name"],
                                      "device_ms": st["elapsed_ms"],
                                      "single_kernel": st["single_kernel"]}
+        S.close()
+    # the 45^2 grid (2025 rows): one workgroup with four rows per thread
+    p45 = convdiff2d_c1(45)
+    b45 = torch.from_numpy(p45.b).to(dev)
+    for form in ("csr", "stencil"):
+        S = Solver.from_problem(p45, form=form, precond="none")
+        for name, kw in (("pipelined_graph", dict(use_graph=True)),
+                         ("pipelined_single_kernel", dict(single_kernel=True))):
+            S.solve(b45, tol=1e-10, maxit=3000, **kw)
+            ts = []
+            for _ in range(20):
+                _, st, sec = solve_timed(S, b45, tol=1e-10, maxit=3000, **kw)
+                ts.append(sec)
+            ts.sort()
+            med = ts[len(ts) // 2]
+            out[f"n2025_{form}_{name}"] = {"iterations": st["iterations"], "median_seconds": med,
+                                           "iter_per_s": st["iterations"] / med,
+                                           "status": st["status_name"],
+                                           "device_ms": st["elapsed_ms"],
+                                           "single_kernel": st["single_kernel"]}
         S.close()
     log(f"c1 latency: {json.dumps(out)}")
     return out

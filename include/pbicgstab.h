@@ -170,11 +170,12 @@ typedef struct {
                             (row i of every vector in the registers of thread i, the
                             inputs of the products in LDS, the global reductions as
                             workgroup reductions, no host polls) when the system allows it:
-                            at most 1024 rows, FP64, rr_auto 0, 1 or 2 (the automated
+                            at most 2048 rows (above 1024 four rows per thread), FP64,
+                            rr_auto 0, or 1 or 2 up to 1024 rows (the automated
                             strategy's nested reading, its bound kept in registers; the
                             bound history is written), gap_every 0, restarts 0, not
-                            transposed, not block-Jacobi, and a device with 57 KiB of LDS
-                            per workgroup; otherwise ignored (pbcg_stats.single_kernel
+                            transposed, not block-Jacobi, and a device with 57 KiB (105 KiB
+                            above 1024 rows) of LDS per workgroup; otherwise ignored (pbcg_stats.single_kernel
                             tells which ran).  Same arithmetic per row and the
                             same stopping rules as the multi-kernel path; the sums of the
                             reductions are taken in another order (results agree to
@@ -231,7 +232,8 @@ void pbicgstab_default_opts(pbcg_opts* opt);
  *                         more than half a block's LDS, else 512)
  *   PBCG_SMALL_RPT=1|2|4  rows per thread of the single-workgroup solve
  *                         (opt single_kernel; default 2; the automated
- *                         strategy always runs with 2)
+ *                         strategy always runs with 2, more than 1024 rows
+ *                         with 4)
  * None changes a result bit except PBCG_NBLK, PBCG_MARCH_PHASE and
  * PBCG_SMALL_RPT, which set the order in which the dot products are summed.
  */

@@ -1219,8 +1219,9 @@ void launch_dia5_transpose(Solver& S, hipStream_t st) {
 // ----------------------------------------------------------------------------
 //
 // A solve of a few hundred rows is bound by kernel launches and host polls,
-// not by memory.  For N <= kSmallRows (FP64) one block of kSmallRows / RPT
-// threads (RPT rows per thread) holds the iteration vectors (the rows of a
+// not by memory.  For N <= ROWS (FP64; 1024, or 2048 with four rows per
+// thread) one block of ROWS / RPT threads (RPT rows per thread) holds the
+// iteration vectors (the rows of a
 // thread in its registers; the inputs of the products, whose neighbours'
 // entries are read, also in LDS) and runs Algorithm 2 to its end in one
 // launch: phase A and phase B with the expressions of k_phaseA / k_phaseB,
@@ -1235,20 +1236,23 @@ void launch_dia5_transpose(Solver& S, hipStream_t st) {
 // and after it every wave adds the partials with the same moves, so every
 // thread holds the same bits without a second barrier; the two products
 // read M^-1 z and M^-1 w from arrays of their own, which the following
-// phase does not write.  A sliced-ELL row of at most kSmallCache stored
+// phase does not write.  A sliced-ELL row of at most kSmallCache (with
+// four rows per thread kSmallCache2k) stored
 // entries is held in registers for the whole solve.
 
 constexpr int kSmallRows = 1024;
-constexpr int kSmallWaves = kSmallRows / 64;
+constexpr int kSmallRowsMax = 2048;   // four rows per thread, 512 threads
+constexpr int kSmallWaves = 16;       // most waves of a block (1024 threads)
 static_assert(kSmallWaves == 16, "the wave partials fit one 16-lane row");
 constexpr int kSmallCache = 8;
+constexpr int kSmallCache2k = 5;      // with four rows per thread (2048 rows)
 enum : int {
   SB_NZ = 0,  // M^-1 z_i, the input of v_i = A M^-1 z_i (also M^-1 r_0 at the start)
   SB_MW,      // M^-1 w, the input of t = A M^-1 w
   SB_PX, SB_PG, SB_PK, SB_PL,   // x, g, k, l for the products of a replacement
   SB_COUNT
 };
-constexpr size_t kSmallLds = (size_t)SB_COUNT * kSmallRows * sizeof(double);
+constexpr size_t small_lds(int rows) { return (size_t)SB_COUNT * rows * sizeof(double); }
 constexpr int kSmallRed = 4;          // partial buffers: GLRED 1, GLRED 2, the others, and
                                       // GLRED 1 of odd iterations (automated strategy)
 constexpr int kSmallSums = 17;        // sums per buffer (automated strategy: GLRED 2 with the
@@ -1306,19 +1310,20 @@ __device__ __forceinline__ void small_total(double (&v)[NS], const double (*buf)
   }
 }
 
-// A sliced-ELL row of at most kSmallCache stored entries, in registers; the
+// A sliced-ELL row of at most NC stored entries, in registers; the
 // visit adds the entries in SellOp::row's order (ascending slot, padding
 // skipped), so the sums are the same.
+template <int NC>
 struct SellRowRegs {
-  int32_t c[kSmallCache];
-  double a[kSmallCache];
+  int32_t c[NC];
+  double a[NC];
   __device__ __forceinline__ void load(const SellOp<double>& op, int i) {
     const int64_t s = i >> 6;
     const int lane = i & 63;
     const int64_t off = op.sptr[s];
     const int w = (int)((op.sptr[s + 1] - off) >> 6);
 #pragma unroll
-    for (int j = 0; j < kSmallCache; ++j) {
+    for (int j = 0; j < NC; ++j) {
       const bool in = j < w;
       c[j] = in ? op.col[off + (int64_t)j * kSellC + lane] : -1;
       a[j] = in ? op.val[off + (int64_t)j * kSellC + lane] : 0.0;
@@ -1327,7 +1332,7 @@ struct SellRowRegs {
   template <class Vis>
   __device__ __forceinline__ void row(Vis& vis) const {
 #pragma unroll
-    for (int j = 0; j < kSmallCache; ++j)
+    for (int j = 0; j < NC; ++j)
       if (c[j] >= 0) vis.add(a[j], vis.load(c[j]));
   }
 };
@@ -1351,16 +1356,17 @@ __device__ __forceinline__ void sell_row_serial(const SellOp<double>& op, int i,
   }
 }
 
-// RPT rows per thread: rows tid, tid + T, ... (T = kSmallRows / RPT threads),
-// so that a wave's lanes hold consecutive rows.  AUTO: the automated strategy
+// RPT rows per thread: rows tid, tid + T, ... (T = ROWS / RPT threads), so
+// that a wave's lanes hold consecutive rows.  AUTO: the automated strategy
 // (Section 3.6, nested reading: the worst-case bound or the estimate); the
 // reductions carry the norms of the bound (phase A six, phase B seven, a
 // replacement five; ||y|| is GLRED 1's (y, y)); wave 0 alone advances the
 // bound state (GapState) and
 // passes eq:criterion's decision to the other waves through LDS.
-template <int PC, class Op, bool CACHE, int RPT, bool AUTO>
-__global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallArgs a) {
-  constexpr int T = kSmallRows / RPT;
+template <int PC, class Op, bool CACHE, int RPT, bool AUTO, int ROWS>
+__global__ __launch_bounds__(ROWS / RPT) void k_small_solve(Op op, SmallArgs a) {
+  constexpr int T = ROWS / RPT;
+  static_assert(T % 64 == 0 && T / 64 <= kSmallWaves, "waves of the block");
   constexpr int NI = AUTO ? 6 : 4;    // sums of the initialisation
   constexpr int NA = AUTO ? 8 : 2;    // GLRED 1 (+ norms), two groups of four
   constexpr int NB = AUTO ? 12 : 5;   // GLRED 2 (+ norms), three groups of four
@@ -1369,12 +1375,12 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   extern __shared__ double sm[];
   __shared__ double red[kSmallRed][kSmallSums][kSmallWaves];
   __shared__ int rr_flag;             // AUTO: eq:criterion's decision for the next iteration
-  double* const nz = sm + SB_NZ * kSmallRows;
-  double* const mw = sm + SB_MW * kSmallRows;
-  double* const px = sm + SB_PX * kSmallRows;
-  double* const pg = sm + SB_PG * kSmallRows;
-  double* const pk = sm + SB_PK * kSmallRows;
-  double* const pl = sm + SB_PL * kSmallRows;
+  double* const nz = sm + SB_NZ * ROWS;
+  double* const mw = sm + SB_MW * ROWS;
+  double* const px = sm + SB_PX * ROWS;
+  double* const pg = sm + SB_PG * ROWS;
+  double* const pk = sm + SB_PK * ROWS;
+  double* const pl = sm + SB_PL * ROWS;
   const int tid = threadIdx.x;
   const int nw = T / 64;
   int row[RPT];
@@ -1392,7 +1398,7 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
     if (PC == PC_SCALAR) return a.ds * u;
     return di[j] * u;
   };
-  SellRowRegs rows[RPT];
+  SellRowRegs<(ROWS > kSmallRows) ? kSmallCache2k : kSmallCache> rows[RPT];
   if constexpr (CACHE) {
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
@@ -1814,21 +1820,24 @@ __global__ __launch_bounds__(kSmallRows / RPT) void k_small_solve(Op op, SmallAr
   }
 }
 
-template <int PC, class Op, bool CACHE, int RPT, bool AUTO>
+template <int PC, class Op, bool CACHE, int RPT, bool AUTO, int ROWS = kSmallRows>
 static hipError_t launch_small_rpt(const Op& op, const SmallArgs& a, hipStream_t st) {
-  const hipError_t e = hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE, RPT, AUTO>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kSmallLds);
+  const hipError_t e =
+      hipFuncSetAttribute((const void*)k_small_solve<PC, Op, CACHE, RPT, AUTO, ROWS>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)small_lds(ROWS));
   if (e == hipSuccess)
-    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE, RPT, AUTO>), dim3(1),
-                       dim3(kSmallRows / RPT), kSmallLds, st, op, a);
+    hipLaunchKernelGGL((k_small_solve<PC, Op, CACHE, RPT, AUTO, ROWS>), dim3(1),
+                       dim3(ROWS / RPT), small_lds(ROWS), st, op, a);
   return e;
 }
 
-// the automated strategy runs with two rows per thread
+// the automated strategy runs with two rows per thread; more than 1024 rows
+// with four (512 threads, the registers of two waves per SIMD; sliced-ELL
+// rows of at most kSmallCache2k entries in registers)
 template <int PC, class Op, bool CACHE>
 static hipError_t launch_small(const Op& op, const SmallArgs& a, int rpt, bool automated,
                                hipStream_t st) {
+  if (a.n > kSmallRows) return launch_small_rpt<PC, Op, CACHE, 4, false, kSmallRowsMax>(op, a, st);
   if (automated) return launch_small_rpt<PC, Op, CACHE, 2, true>(op, a, st);
   if (rpt == 1) return launch_small_rpt<PC, Op, CACHE, 1, false>(op, a, st);
   if (rpt == 4) return launch_small_rpt<PC, Op, CACHE, 4, false>(op, a, st);
@@ -1837,9 +1846,12 @@ static hipError_t launch_small(const Op& op, const SmallArgs& a, int rpt, bool a
 
 bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_t* err) {
   // the products reading of the automated strategy (rr_auto 3, 4) keeps a
-  // state per error source in a caller's buffer: not here
-  if (S.n > kSmallRows || S.precision != 0 || o.transpose || o.rr_auto > 2 || o.gap_every > 0 ||
-      o.restarts > 0 || S.block || (size_t)S.lds_cap < kSmallLds + kSmallStatic)
+  // state per error source in a caller's buffer: not here; nor the automated
+  // strategy above 1024 rows (its registers with four rows per thread)
+  const int rows = S.n > kSmallRows ? kSmallRowsMax : kSmallRows;
+  if (S.n > kSmallRowsMax || (S.n > kSmallRows && o.rr_auto) || S.precision != 0 ||
+      o.transpose || o.rr_auto > 2 || o.gap_every > 0 || o.restarts > 0 || S.block ||
+      (size_t)S.lds_cap < small_lds(rows) + kSmallStatic)
     return false;
   SmallArgs a{};
   a.n = (int)S.n;
@@ -1861,7 +1873,7 @@ bool launch_small_solve(Solver& S, const pbcg_opts& o, hipStream_t st, hipError_
   a.bound_len = a.bound_history ? o.bound_len : 0;
   a.sc = S.sc;
   // rows of the sliced-ELL operator short enough to stay in registers
-  const bool cache = S.mu_row <= kSmallCache;
+  const bool cache = S.mu_row <= (S.n > kSmallRows ? kSmallCache2k : kSmallCache);
   const int rpt = S.small_rpt;
   with_op(S, false, true, [&]<typename T, int PC, class Op>(const Op& op) {
     if constexpr (std::is_same_v<T, double>) {

@@ -224,8 +224,9 @@ class Solver:
         the library needs).  ``rhat``: a fixed shadow vector in place of r_0
         (not in the paper; None keeps r_0).  ``single_kernel``: run the whole
         solve as one kernel in one workgroup when the system allows it (FP64,
-        at most 1024 rows, no, periodic or automated replacement -- not the
-        'products' readings; stats ``single_kernel`` says whether it did).  ``rr_nv``: every replacement
+        at most 2048 rows, no or periodic replacement, or up to 1024 rows the
+        automated one -- not the 'products' readings; stats
+        ``single_kernel`` says whether it did).  ``rr_nv``: every replacement
         also recomputes n = M^-1 z and v = A n from the replaced z (not in the
         paper, which replaces the six quantities of eq:rr only)."""
         lib = L.load()

@@ -8,8 +8,9 @@ and against the multi-kernel path.
   1e-12.  Operators: CSR without and with a Jacobi vector, the 2D stencil
   with its scalar Jacobi, DIA5, the 3D stencil, a dense 37 x 37 CSR (one
   partial wave) and the 31^2 grid (961 rows: a partial last wave); the
-  32^2 grid is the largest system the kernel takes (1024 rows).  Also with
-  a random shadow vector.
+  32^2 grid is the largest system with two rows per thread (1024 rows);
+  the 45^2 grid (2025 rows) and the 12^3 grid (1728 rows) take four rows
+  per thread (at most 2048 rows).  Also with a random shadow vector.
 * Full solves to 1e-10 on the 32^2 convection-diffusion problem: status as
   the oracle's, x as the multi-kernel path's and the exact solution's to
   the tolerance.  Without replacement the residual of this problem jumps by
@@ -28,8 +29,9 @@ and against the multi-kernel path.
   1e-5 (1e-6), as far as the oracle against itself with correctly rounded
   dots agrees; full solves as the oracle's; forced replacements ending
   TRUE_RES_NOT_MET; the allocation-free entry point.
-* Systems the kernel does not take (more than 1024 rows, FP32 storage, the
-  products reading of the automated strategy, the transpose) run the
+* Systems the kernel does not take (more than 2048 rows, FP32 storage, the
+  products reading of the automated strategy, the automated strategy above
+  1024 rows, the transpose) run the
   multi-kernel path, bit for bit as without the option; the allocation-free
   entry point gives the same bits as pbicgstab_solve; two runs give the same
   bits.
@@ -84,6 +86,9 @@ _CASES = [
     ("dia5-24", lambda: inverse_problem_c5(24, sigma=1.0, with_csr=True), "dia5", "jacobi"),
     ("3d7-10", lambda: convdiff3d_c3(10, with_csr=True), "stencil", "jacobi"),
     ("dense-37", lambda: random_dense_system(37, 3, shift=8.0), "csr", "none"),
+    ("c1-45-csr", lambda: convdiff2d_c1(45), "csr", "none"),
+    ("c1-45-stencil-jacobi", lambda: convdiff2d_c1(45), "stencil", "jacobi"),
+    ("3d7-12", lambda: convdiff3d_c3(12, with_csr=True), "stencil", "jacobi"),
 ]
 
 
@@ -157,6 +162,32 @@ def test_single_kernel_full_solve(Solver, form, pc, period):
     assert ss["spmvs"] == 3 + 2 * ss["iterations"] + 4 * ss["replacements"] + 1
     xs, xm = host(xs), host(xm)
     # two solutions that both meet the tolerance: within cond(A) * 1e-10
+    assert np.max(np.abs(xs - xm)) <= 1e-6 * np.max(np.abs(xm))
+    assert np.max(np.abs(xs - p.x_exact)) <= 1e-6 * np.max(np.abs(p.x_exact))
+    S.close()
+
+
+@pytest.mark.parametrize("form,pc", [("csr", "none"), ("stencil", "jacobi")])
+@pytest.mark.parametrize("period", [0, 50])
+def test_single_kernel_full_solve_2048(Solver, form, pc, period):
+    """The 45^2 grid (2025 rows, four rows per thread): as the oracle's and
+    the multi-kernel path's solve."""
+    p = convdiff2d_c1(45)
+    A, ops = oracle_ops(p, pc)
+    ref = pipelined_bicgstab(ops, p.b, tol=1e-10, maxit=3000, rr_period=period)
+    assert ref.status == 0
+    S = Solver.from_problem(p, form=form, precond=pc)
+    b = dev(p.b)
+    xs, ss = S.solve(b, tol=1e-10, maxit=3000, rr_period=period, single_kernel=True)
+    xm, sm = S.solve(b, tol=1e-10, maxit=3000, rr_period=period)
+    print(f"45^2 {form}/{pc} P={period}: oracle {ref.iterations} its, single kernel "
+          f"{ss['iterations']}, multi-kernel {sm['iterations']}", flush=True)
+    assert ss["single_kernel"] == 1 and sm["single_kernel"] == 0
+    assert ss["status"] == sm["status"] == 0
+    assert abs(ss["iterations"] - ref.iterations) <= max(2, ref.iterations // 10)
+    assert abs(ss["replacements"] - ref.replacements) <= 1
+    assert ss["rel_res_true"] <= 1e-10
+    xs, xm = host(xs), host(xm)
     assert np.max(np.abs(xs - xm)) <= 1e-6 * np.max(np.abs(xm))
     assert np.max(np.abs(xs - p.x_exact)) <= 1e-6 * np.max(np.abs(p.x_exact))
     S.close()
@@ -384,7 +415,8 @@ def test_single_kernel_automated_forced_replacements(Solver, variant):
 
 def test_single_kernel_ineligible_runs_the_multi_kernel_path(Solver):
     cases = [
-        (poisson2d_c2(33), dict(form="stencil", precond="jacobi"), {}),          # 1089 rows
+        (poisson2d_c2(46), dict(form="stencil", precond="jacobi"), {}),          # 2116 rows
+        (convdiff2d_c1(40), dict(form="csr", precond="none"), dict(rr_auto="bound")),  # 1600
         (convdiff2d_c1(32), dict(form="csr", precision="mixed", precond="none"), {}),
         (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(rr_auto="products")),
         (convdiff2d_c1(32), dict(form="csr", precond="none"), dict(transpose=True)),
