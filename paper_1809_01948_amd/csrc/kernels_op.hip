@@ -986,12 +986,13 @@ static void launch_spmv_lds(Solver& S, bool tr, const void* in, void* out, int f
   const int nwork = (int)std::max<int64_t>(kXcds, nw / kXcds * kXcds);
   with_op(S, tr, !pre, [&]<typename T, int PC, class Op>(const Op& op) {
     if constexpr (std::is_same_v<Op, SellOp<T>>) {
+      // (if the attribute is refused, the launch below fails and the
+      // caller's launch check reports it)
       static bool attr = false;
-      if (!attr) {
-        hipFuncSetAttribute((const void*)k_spmv_sell_lds<T, PC>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)S.lds_cap);
-        attr = true;
-      }
+      if (!attr)
+        attr = hipFuncSetAttribute((const void*)k_spmv_sell_lds<T, PC>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)S.lds_cap) == hipSuccess;
       hipLaunchKernelGGL((k_spmv_sell_lds<T, PC>), dim3(nwork), dim3(kLdsRows), shmem, st, op,
                          o.win_lo, o.win_len, (const T*)in, (T*)out, (const T*)S.dinv,
                          (T)S.dinv_s, S.n, o.nlb, nwork, S.sc);
